@@ -1,0 +1,64 @@
+"""Seeded synthetic input matrices for RBGS QR.
+
+This module only builds inputs; it contains none of the method's arithmetic
+and is shared by the tests, the benchmark and the smoke check.  All matrices are
+returned in FP64, column-major (Fortran order), so that column j is contiguous.
+
+* `svd_matrix(n, m, sigma, seed)`: W = U diag(sigma) V^T with U the
+  orthonormal factor of a seeded n x m Gaussian matrix and V that of a seeded
+  m x m Gaussian matrix (both sign-fixed so the factor is unique); cond(W) is
+  sigma[0] / sigma[-1].  With n = 10 000, m = 64 and sigma = logspace(0, -8, 64)
+  this is the small FP64 single-QR workload.
+* `oscillatory_matrix(n, m, seed)`: w_ij = sin(10 (mu_j x_i + 1)) /
+  (cos(100 mu_j x_i - 100 mu_j) + 1.1), x_i = i / (n - 1), mu_j ~ U[0, 1]
+  drawn from a seeded generator.  A smooth parametric family, numerically
+  rank-deficient, which stands in for the matrix of the paper's first numerical
+  example (Section 5.1), whose exact generator differs; with n = 10^6 and
+  m = 256 this is the large single-QR workload.
+"""
+import numpy as np
+
+
+def _orthonormal(rng, n, m):
+    G = rng.standard_normal((n, m))
+    U, Rg = np.linalg.qr(G)
+    d = np.sign(np.diag(Rg))
+    d[d == 0] = 1.0
+    return U * d[None, :]
+
+
+def svd_matrix(n, m, sigma, seed):
+    rng = np.random.default_rng(seed)
+    U = _orthonormal(rng, n, m)
+    V = _orthonormal(rng, m, m)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    return np.asfortranarray((U * sigma[None, :]) @ V.T)
+
+
+def small_single_qr(seed=0xDA7A00, n=10_000, m=64, decades=8.0):
+    """The small FP64 single-QR workload (cond(W) = 10^decades)."""
+    return svd_matrix(n, m, np.logspace(0.0, -decades, m), seed)
+
+
+def oscillatory_matrix(n, m, seed, dtype=np.float64, chunk=1 << 17):
+    rng = np.random.default_rng(seed)
+    mu = rng.random(m)
+    W = np.empty((n, m), dtype=dtype, order="F")
+    denom_n = max(n - 1, 1)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        x = np.arange(r0, r1, dtype=np.float64)[:, None] / denom_n
+        mx = mu[None, :] * x
+        W[r0:r1, :] = np.sin(10.0 * (mx + 1.0)) / (np.cos(100.0 * mx - 100.0 * mu[None, :]) + 1.1)
+    return W
+
+
+def large_single_qr(seed=0xDA7A01, n=1_000_000, m=256, dtype=np.float64):
+    """The large single-QR workload (n = 10^6, m = 256)."""
+    return oscillatory_matrix(n, m, seed, dtype=dtype)
+
+
+# Default seeds of the sketching operators for each workload.
+THETA_SEED_SMALL = 0x2111146410
+THETA_SEED_LARGE = 0x2111146411
+THETA_SEED_MIXED = 0x2111146412
