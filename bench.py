@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of RBGS QR on one MI355X.
+
+Workload (the large single-QR case): W is n = 10^6 x m = 256 with
+w_ij = sin(10 (mu_j x_i + 1)) / (cos(100 mu_j x_i - 100 mu_j) + 1.1), block
+width p = 16, sketch dimension k = 1024.  One step is one complete RBGS QR
+(all blocks: sketches, least squares, update, QR of the sketch, substitution,
+re-sketch) with W already resident in HBM.
+
+The headline form stores W and Q in FP32 (step 3 on FP32 matrix cores, all
+small factors and sketch accumulation in FP64) with the sparse-sign sketch and
+the low-synchronization variant.  The FP64 form and the Gaussian-sketch forms
+are timed on the same matrix and reported beside it, each with its accuracy
+(||W - QR||_F / ||W||_F, cond2(Q), Delta, Delta~).
+
+`value` is algorithmic HBM throughput in GB/s: n s m ((N-1)/2 + 2) bytes per
+QR (N = m/p blocks, s = bytes per element; each block reads Q_(1:i-1) and W_(i)
+once and writes Q_(i) once) divided by the measured time per QR.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RBGS QR time & HBM GB/s at n=1e6 m=256: FP32/BF16x3 vs FP64 at equal error"
+HBM_PEAK_GBS = 8000.0
+LS_ITERS = 4   # Richardson sweeps of the least-squares step
+
+
+def alg_bytes(n, m, p, s):
+    N = -(-m // p)
+    # sum over blocks of (K + 2 bw) n s with K = i*p
+    tot = 0
+    for c0 in range(0, m, p):
+        bw = min(p, m - c0)
+        tot += (c0 + 2 * bw) * n * s
+    return float(tot)
+
+
+def accuracy(W, Q, R, cert):
+    import torch
+    Wd = W.double()
+    Qd = Q.double()
+    E = Wd - Qd @ R
+    err = (torch.linalg.norm(E) / torch.linalg.norm(Wd)).item()
+    G = (Qd.t() @ Qd).cpu().numpy()
+    import numpy as np
+    ev = np.linalg.eigvalsh(G)
+    cond = float(np.sqrt(ev[-1] / ev[0])) if ev[0] > 0 else float("inf")
+    return dict(rel_err=err, cond2_Q=cond, delta=cert["delta"], delta_tilde=cert["delta_tilde"])
+
+
+def time_form(W, p, kind, k, seed, variant, steps, warmup, profile=False, math="f64"):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    n, m = W.shape
+    Q = B.colmajor(n, m, W.dtype, W.device)
+    R = B.colmajor(m, m, torch.float64, W.device)
+    # accuracy run (with certificate) outside the timed region
+    _, _, _, cert = B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, want_cert=True, math=math)
+    acc = accuracy(W, Q, R, cert)
+    for _ in range(warmup):
+        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+    torch.cuda.synchronize()
+    if profile:
+        B.profile_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    prof = None
+    if profile:
+        prof = {name: B.profile_get(name) for name in ("update", "sketch", "reduce", "small", "trsm")}
+        B.profile_enable(False)
+    s = 4 if W.dtype == torch.float32 else 8
+    gbs = alg_bytes(n, m, p, s) / (ms * 1e-3) / 1e9
+    return dict(ms=ms, alg_GBps=gbs, **acc), prof
+
+
+def cpu_baseline(W64_host, p, k, seed, target_s=15.0):
+    """The FP64 oracle timed on a row sample of the same workload (sparse sign,
+    low-sync), scaled to GB/s with the same algorithmic byte count (FP64)."""
+    import numpy as np
+    import oracle.rbgs as orb
+    from oracle.theta import Sketch
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    n_full, m = W64_host.shape
+    n_s = 62_500
+    while True:
+        Ws = np.asfortranarray(W64_host[:n_s])
+        th = Sketch("sparse", k, seed=seed).materialize(n_s)
+        t = time.perf_counter()
+        orb.rbgs(Ws, p, th, "lowsync", "householder")
+        dt = time.perf_counter() - t
+        if dt * 2 > target_s or n_s * 2 > n_full:
+            break
+        n_s *= 2
+    gbs = alg_bytes(n_s, m, p, 8) / dt / 1e9
+    return dict(value=gbs, unit="GB/s", cores=int(threads), kind="oracle",
+                sample=f"FP64 oracle, low-sync sparse-sign RBGS on the first {n_s} rows of the "
+                       f"workload (m={m}, p={p}, k={k}); one run, {dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--m", type=int, default=256)
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--k", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gaussian", action="store_true")
+    ap.add_argument("--forms", default="all", help="'headline' to time only the headline form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2111_14641_amd import binding as B
+    from paper_2111_14641_amd.workloads import large_single_qr, THETA_SEED_LARGE
+
+    torch.cuda.set_device(0)
+    n, m, p, k = args.n, args.m, args.p, args.k
+    print(f"[bench] generating W {n}x{m}", file=sys.stderr, flush=True)
+    W64h = large_single_qr(n=n, m=m)
+    W64 = B.colmajor(n, m, torch.float64)
+    W64.copy_(torch.from_numpy(W64h))
+    W32 = B.colmajor(n, m, torch.float32)
+    W32.copy_(W64)
+    torch.cuda.synchronize()
+
+    forms = {}
+    print("[bench] fp32 sparse lowsync (headline)", file=sys.stderr, flush=True)
+    head, prof = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync", args.steps,
+                           args.warmup, profile=True)
+    forms["f32_sparse_lowsync"] = head
+    if args.forms == "all":
+        print("[bench] fp64 sparse lowsync", file=sys.stderr, flush=True)
+        forms["f64_sparse_lowsync"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "lowsync",
+                                                   args.steps, args.warmup)
+        print("[bench] fp32 storage with fp32 arithmetic", file=sys.stderr, flush=True)
+        forms["f32_f32math_sparse_lowsync"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE,
+                                                           "lowsync", args.steps, args.warmup,
+                                                           math="f32")
+        print("[bench] fp32/fp64 sparse plain", file=sys.stderr, flush=True)
+        forms["f32_sparse_plain"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "plain",
+                                                 max(3, args.steps // 4), 1)
+        forms["f64_sparse_plain"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "plain",
+                                                 max(3, args.steps // 4), 1)
+        if not args.no_gaussian:
+            print("[bench] gaussian forms", file=sys.stderr, flush=True)
+            forms["f32_gauss_lowsync"], _ = time_form(W32, p, "gaussian", k, THETA_SEED_LARGE,
+                                                      "lowsync", max(2, args.steps // 10), 1)
+            forms["f64_gauss_lowsync"], _ = time_form(W64, p, "gaussian", k, THETA_SEED_LARGE,
+                                                      "lowsync", max(2, args.steps // 10), 1)
+    upd_ms, upd_cnt, upd_bytes = prof["update"]
+    achieved = upd_bytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="update_kernel<float,double,1> (step 3 + substitution, low-sync)",
+                    avg_launch_us=round(upd_ms / max(upd_cnt, 1) * 1e3, 2),
+                    share_of_step=round(upd_ms / args.steps / head["ms"], 3))
+    kernel_ms = {name: round(v[0] / args.steps, 4) for name, v in prof.items()}
+    speedup = None
+    if "f64_sparse_lowsync" in forms:
+        speedup = forms["f64_sparse_lowsync"]["ms"] / head["ms"]
+    out = {
+        "metric": METRIC,
+        "value": round(head["alg_GBps"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"oscillatory W n={n} m={m}, p={p}, k={k}, sparse-sign zeta=8, "
+                               "low-sync RBGS, FP32 storage with FP64 arithmetic",
+                   "n": n, "m": m, "p": p, "k": k, "parallelism": "single GPU"},
+        "speedup_f32_vs_f64": None if speedup is None else round(speedup, 3),
+        "forms": {name: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in f.items()}
+                  for name, f in forms.items()},
+        "kernel_ms_per_step": kernel_ms,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W64h, p, k, THETA_SEED_LARGE)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

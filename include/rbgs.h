@@ -1,0 +1,188 @@
+/*
+ * rbgs.h -- C ABI of the MI355X (gfx950) randomized block Gram-Schmidt library.
+ *
+ * The library computes the RBGS QR factorization W = Q R of a tall matrix W
+ * (n x m, m <= k << n) with respect to the sketched inner product
+ * <Theta x, Theta y>, where Theta (k x n) is a random sketching operator
+ * regenerated on the fly from a counter-based generator and never stored.
+ * Reference: O. Balabanov and L. Grigori, "Randomized block Gram-Schmidt
+ * process for the solution of linear systems and eigenvalue problems",
+ * arXiv 2111.14641: Section 2 (Algorithm "RBGS"), Section 2.1 (least-squares
+ * step), Section 2.2 (inter-block QR: RCholeskyQR and RCholeskyQR with
+ * postponed sketching), Section 3 (certificates Delta and Delta~).
+ *
+ * Conventions for every call below:
+ *  - Matrices are column-major.  "Device" pointers are HIP device memory
+ *    (e.g. allocated by PyTorch); "host" pointers are ordinary host memory.
+ *  - The caller owns every array it passes.  A handle owns only its internal
+ *    workspace, which grows on demand, is reused between calls and is freed by
+ *    rbgs_destroy.
+ *  - Work is enqueued on the stream given in the options (NULL = the null
+ *    stream) and the call returns without waiting, unless stated otherwise.
+ *  - Argument errors are detected on the host before anything is enqueued and
+ *    are reported as RBGS_EINVAL / RBGS_EUNSUPPORTED; nothing is written then.
+ *  - No call throws.  A handle must not be used by two threads at once.
+ *  - Results are bitwise reproducible for identical inputs, options and device:
+ *    every reduction runs in a fixed order and no floating-point atomics are
+ *    used.
+ */
+#ifndef RBGS_H
+#define RBGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbgs_handle_s* rbgs_handle;
+
+typedef enum {
+  RBGS_OK = 0,
+  RBGS_EINVAL = -1,        /* invalid argument (checked on the host)              */
+  RBGS_ENOMEM = -2,        /* device workspace allocation failed                 */
+  RBGS_EDEVICE = -3,       /* a HIP runtime call failed (see rbgs_last_error)    */
+  RBGS_EBREAKDOWN = -4,    /* a diagonal entry of R is zero or not finite        */
+  RBGS_ENOTCONV = -5,      /* reserved for iterative solvers                     */
+  RBGS_EUNSUPPORTED = -6   /* valid request outside what the kernels implement   */
+} rbgs_status;
+
+/* Element type of W and Q. */
+typedef enum { RBGS_STORE_F64 = 0, RBGS_STORE_F32 = 1 } rbgs_store;
+
+/* Arithmetic of the high-dimensional update Q'_(i) = W_(i) - Q_(1:i-1) R_(1:i-1,i)
+ * (step 3 of Algorithm RBGS, the "coarse" unit roundoff u_crs of Section 2).
+ *  F64  FP64 matrix-core products and accumulation; with FP32 storage the FP32
+ *       data are converted exactly and only the result Q'_(i) is rounded to
+ *       FP32.  Valid with either storage.
+ *  F32  FP32 matrix-core products with FP32 accumulation and R rounded to FP32;
+ *       FP32 storage only.  Its rounding errors, of size u32 ||W||, exceed Q'_(i)
+ *       itself once W is numerically rank deficient at FP32 level, and then the
+ *       sketched orthogonality is lost (the certificate Delta exposes it).
+ * The sketches, the least-squares problem, the QR of the sketch and the
+ * substitution always run in FP64 (the "fine" unit roundoff of Section 2). */
+typedef enum { RBGS_MATH_F64 = 0, RBGS_MATH_F32 = 1 } rbgs_math;
+
+/* Sketching operator Theta (Section 1.3).  Entries are defined from
+ * Philox-4x32-10 (key = seed; column r of Theta = row r of W):
+ *  GAUSSIAN    Theta = Z / sqrt(k), Z[4j+e][r] from counter (r_lo, r_hi, j,
+ *              0x47415553) through a single-precision Box-Muller transform;
+ *              k % 4 == 0.
+ *  SPARSE_SIGN Theta = B / sqrt(zeta): column r has zeta entries +-1, one in
+ *              each of the zeta segments of k/zeta rows, from counters
+ *              (r_lo, r_hi, c, 0x53504152), c = 0, 1; 1 <= zeta <= 8,
+ *              k % zeta == 0, k <= 2048.
+ *  IDENTITY    Theta = I, k == n (testing: RBGS then reduces to block
+ *              Gram-Schmidt with exact projections). */
+typedef enum {
+  RBGS_SKETCH_GAUSSIAN = 0,
+  RBGS_SKETCH_SPARSE_SIGN = 1,
+  RBGS_SKETCH_IDENTITY = 2
+} rbgs_sketch_kind;
+
+/* Inter-block QR in steps 4-5 (Section 2.2):
+ *  PLAIN    RCholeskyQR: S'_(i) = Theta Q'_(i) computed from Q'_(i).
+ *  LOWSYNC  RCholeskyQR with postponed sketching:
+ *           S'_(i) = P_(i) - S_(1:i-1) R_(1:i-1,i); the update and the
+ *           substitution are then one pass over the rows and each block needs
+ *           a single device-wide reduction (the sketch of Q_(i)). */
+typedef enum { RBGS_VARIANT_PLAIN = 0, RBGS_VARIANT_LOWSYNC = 1 } rbgs_variant;
+
+typedef struct {
+  int32_t kind;      /* rbgs_sketch_kind                                  */
+  int32_t zeta;      /* nonzeros per column of the sparse sign (1..8)     */
+  int64_t k;         /* sketch dimension (rows of Theta), m <= k <= n     */
+  uint64_t seed;     /* Philox key                                        */
+} rbgs_sketch;
+
+typedef struct {
+  int32_t store;     /* rbgs_store                                        */
+  int32_t math;      /* rbgs_math                                         */
+  int32_t variant;   /* rbgs_variant                                      */
+  int32_t ls_iters;  /* Richardson sweeps l >= 1 for the least-squares step
+                        (supplement, Section SM.1); error <= Delta^l |y|    */
+  void* stream;      /* hipStream_t or NULL                               */
+} rbgs_opts;
+
+/* A-posteriori certificate (step 6 of Algorithm RBGS). */
+typedef struct {
+  double delta;          /* ||I - S^T S||_F                                */
+  double delta_tilde;    /* ||P - S R||_F / ||P||_F                         */
+  int64_t breakdown_col; /* first column j with R_jj == 0 or not finite, -1 */
+  int32_t nonfinite;     /* 1 if any entry of R or S is not finite          */
+  int32_t reserved;
+} rbgs_cert;
+
+/* Create a handle bound to HIP device `device`.  No device memory is touched
+ * until the first computing call.  Returns RBGS_EINVAL if h is NULL or device
+ * is negative. */
+rbgs_status rbgs_create(rbgs_handle* h, int device);
+
+/* Free the handle's workspace (after waiting for its streams) and the handle.
+ * A NULL handle is accepted. */
+rbgs_status rbgs_destroy(rbgs_handle h);
+
+/* RBGS QR factorization (Algorithm RBGS of Section 2).
+ *   W    device, n x m (ld ldw >= n), element type opts->store; read only
+ *        unless Q == W.
+ *   p    block width (the paper's m_p); the blocks are columns [c0, c0+p);
+ *        the last block is narrower when p does not divide m.  1 <= p <= 32.
+ *   sk   host, the sketching operator; m <= sk->k <= n.
+ *   opts host.
+ *   Q    device, n x m (ld ldq >= n), element type opts->store.  Q == W (with
+ *        ldq == ldw) factorizes in place; any other overlap is invalid.
+ *   R    device, m x m FP64 (ld ldr >= m); upper triangular with positive
+ *        diagonal on return; the strictly lower part is set to zero.
+ *   S_out device or NULL, k x m FP64 (ld k): the sketch S = Theta Q.
+ *   cert host or NULL.  When given, the call also computes Delta and Delta~,
+ *        waits for the stream, and returns RBGS_EBREAKDOWN if a diagonal entry
+ *        of R is zero or not finite (cert->breakdown_col names it; Q and R are
+ *        valid up to the preceding block).  Without cert the call does not
+ *        wait and a breakdown shows up as non-finite entries of Q.
+ */
+rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
+                    const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
+                    double* R, int64_t ldr, double* S_out, rbgs_cert* cert);
+
+/* Sketch of a block of rows: out = Theta[:, row0:row0+n] X (Section 1.3), the
+ * operation of steps 1 and 5 of Algorithm RBGS.
+ *   X   device, n x c (ld ldx >= n), element type `store` (rbgs_store).
+ *   out device, k x c FP64 (ld ldo >= k), overwritten.
+ *   row0 global row index of the first row of X (Theta's columns are indexed
+ *        by global rows, so sketches of row ranges add up to the full sketch).
+ * Enqueued on `stream`. */
+rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t store, const void* X,
+                              int64_t ldx, int64_t n, int64_t c, int64_t row0, double* out,
+                              int64_t ldo, void* stream);
+
+/* Explicit unscaled sketching matrix, for brute-force checks of the
+ * definition above: out[t + k*(r - row0)] = Z[t][r] (Gaussian), B[t][r]
+ * (sparse sign, +-1 or 0) or I[t][r] (identity) for t < k, row0 <= r < row0+n.
+ *   out device, k x n float (ld k), overwritten.  Theta = scale * out with
+ *   scale = 1/sqrt(k) (Gaussian), 1/sqrt(zeta) (sparse sign), 1 (identity). */
+rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
+                             float* out, void* stream);
+
+/* Kernel timing for measurements.  With profiling enabled, the handle records
+ * HIP events around every launch of the kernels named below on the stream it
+ * enqueues them on.  rbgs_profile_get waits for the recorded events and
+ * returns, for kernel class `which`, the summed duration in milliseconds, the
+ * number of launches and the summed algorithmic bytes (the minimal HBM
+ * traffic of those launches: each input element read once, each output
+ * element written once).
+ *   which: 0 = update (steps 3 [+5 fused]), 1 = sketch partial products,
+ *          2 = sketch reduction, 3 = small FP64 factors, 4 = substitution
+ *          (plain variant). */
+rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable);
+rbgs_status rbgs_profile_get(rbgs_handle h, int32_t which, double* ms, int64_t* launches,
+                             double* bytes);
+
+const char* rbgs_status_string(rbgs_status s);
+/* Text of the last error detected on this handle ("" if none). */
+const char* rbgs_last_error(rbgs_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBGS_H */

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of the C ABI declared in include/rbgs.h.
+
+Only argument marshalling happens here: every step of the computation runs in
+the HIP kernels of librbgs.so.  PyTorch supplies device memory and the stream.
+If the library has not been built, importing functions from here raises
+immediately; there is no fallback implementation.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librbgs.so")
+
+# rbgs_status
+RBGS_OK, RBGS_EINVAL, RBGS_ENOMEM, RBGS_EDEVICE, RBGS_EBREAKDOWN, RBGS_ENOTCONV, RBGS_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+# rbgs_store / rbgs_math / rbgs_sketch_kind / rbgs_variant
+STORE = {"f64": 0, "f32": 1}
+MATH = {"f64": 0, "f32": 1}
+SKETCH = {"gaussian": 0, "sparse": 1, "identity": 2}
+VARIANT = {"plain": 0, "lowsync": 1}
+PROFILE = {"update": 0, "sketch": 1, "reduce": 2, "small": 3, "trsm": 4}
+
+
+class rbgs_sketch(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("zeta", ctypes.c_int32), ("k", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
+class rbgs_opts(ctypes.Structure):
+    _fields_ = [("store", ctypes.c_int32), ("math", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("ls_iters", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class rbgs_cert(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("delta_tilde", ctypes.c_double),
+                ("breakdown_col", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RbgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SIGNATURES = {
+    "rbgs_create": ([ctypes.POINTER(_P), ctypes.c_int], ctypes.c_int),
+    "rbgs_destroy": ([_P], ctypes.c_int),
+    "rbgs_qr": ([_P, _P, _I64, _I64, _I64, _I64, ctypes.POINTER(rbgs_sketch),
+                 ctypes.POINTER(rbgs_opts), _P, _I64, _P, _I64, _P, ctypes.POINTER(rbgs_cert)],
+                ctypes.c_int),
+    "rbgs_sketch_apply": ([_P, ctypes.POINTER(rbgs_sketch), _I32, _P, _I64, _I64, _I64, _I64, _P,
+                           _I64, _P], ctypes.c_int),
+    "rbgs_theta_dense": ([_P, ctypes.POINTER(rbgs_sketch), _I64, _I64, _P, _P], ctypes.c_int),
+    "rbgs_profile_enable": ([_P, _I32], ctypes.c_int),
+    "rbgs_profile_get": ([_P, _I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
+                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "rbgs_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "rbgs_last_error": ([_P], ctypes.c_char_p),
+}
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2111_14641_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+class Library:
+    """Process-wide library and one handle per device."""
+    _inst = None
+
+    def __init__(self):
+        self.lib = load_library()
+        self.handles = {}
+
+    @classmethod
+    def get(cls):
+        if cls._inst is None:
+            cls._inst = Library()
+        return cls._inst
+
+    def handle(self, device=0):
+        if device not in self.handles:
+            h = _P()
+            st = self.lib.rbgs_create(ctypes.byref(h), device)
+            if st != RBGS_OK:
+                raise RbgsError(st, "rbgs_create failed")
+            self.handles[device] = h
+        return self.handles[device]
+
+    def check(self, st, h):
+        if st != RBGS_OK:
+            msg = self.lib.rbgs_last_error(h).decode() or self.lib.rbgs_status_string(st).decode()
+            raise RbgsError(st, msg)
+
+    # -- raw C ABI (same names) -------------------------------------------
+    def rbgs_qr(self, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, cert):
+        return self.lib.rbgs_qr(h, W, ldw, n, m, p, ctypes.byref(sk), ctypes.byref(opts), Q, ldq,
+                                R, ldr, S_out, ctypes.byref(cert) if cert is not None else None)
+
+    def rbgs_sketch_apply(self, h, sk, store, X, ldx, n, c, row0, out, ldo, stream):
+        return self.lib.rbgs_sketch_apply(h, ctypes.byref(sk), store, X, ldx, n, c, row0, out,
+                                          ldo, stream)
+
+    def rbgs_theta_dense(self, h, sk, n, row0, out, stream):
+        return self.lib.rbgs_theta_dense(h, ctypes.byref(sk), n, row0, out, stream)
+
+    def rbgs_profile_enable(self, h, enable):
+        return self.lib.rbgs_profile_enable(h, int(enable))
+
+    def rbgs_profile_get(self, h, which):
+        ms, cnt, by = ctypes.c_double(), _I64(), ctypes.c_double()
+        st = self.lib.rbgs_profile_get(h, which, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by))
+        return st, ms.value, cnt.value, by.value
+
+
+# ---------------------------------------------------------------------------
+# torch-facing helpers (allocation and stream plumbing only)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(n, m, dtype, device="cuda"):
+    """An n x m column-major tensor (stride (1, n))."""
+    torch = _torch()
+    return torch.empty((m, n), dtype=dtype, device=device).t()
+
+
+def as_colmajor(X):
+    """(pointer, ld) of a 2-D column-major tensor; raises if X is not one."""
+    if X.dim() != 2 or X.stride(0) != 1 or (X.shape[1] > 1 and X.stride(1) < X.shape[0]):
+        raise ValueError("expected a column-major 2-D tensor (stride (1, ld), ld >= rows)")
+    return X.data_ptr(), max(X.stride(1), X.shape[0])
+
+
+def _stream_ptr(X):
+    torch = _torch()
+    return torch.cuda.current_stream(X.device).cuda_stream
+
+
+def make_sketch(kind, k, seed, zeta=8):
+    return rbgs_sketch(SKETCH[kind], int(zeta), int(k), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync", ls_iters=4,
+            Q=None, R=None, want_S=False, want_cert=False, math="f64"):
+    """RBGS QR of a column-major CUDA tensor W (n x m, float32 or float64).
+
+    math: arithmetic of the update (step 3): "f64" (default, any storage) or
+    "f32" (FP32 storage only).
+
+    Returns (Q, R, S, cert): Q like W (or the given Q, e.g. W itself for an
+    in-place factorization), R (m x m float64, column-major), S (k x m float64)
+    or None, and a dict with the certificates or None.
+    """
+    torch = _torch()
+    lib = Library.get()
+    n, m = W.shape
+    if W.dtype == torch.float64:
+        store = "f64"
+    elif W.dtype == torch.float32:
+        store = "f32"
+    else:
+        raise TypeError("W must be float32 or float64")
+    if k is None:
+        raise ValueError("sketch dimension k is required")
+    dev = W.device.index or 0
+    h = lib.handle(dev)
+    if Q is None:
+        Q = colmajor(n, m, W.dtype, W.device)
+    if R is None:
+        R = colmajor(m, m, torch.float64, W.device)
+    S = colmajor(k, m, torch.float64, W.device) if want_S else None
+    wp, ldw = as_colmajor(W)
+    qp, ldq = as_colmajor(Q)
+    rp, ldr = as_colmajor(R)
+    sk = make_sketch(kind, k, seed, zeta)
+    opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters), _stream_ptr(W))
+    cert = rbgs_cert() if want_cert else None
+    st = lib.rbgs_qr(h, wp, ldw, n, m, p, sk, opts, qp, ldq, rp, ldr,
+                     S.data_ptr() if S is not None else None, cert)
+    if st == RBGS_EBREAKDOWN and cert is not None:
+        return Q, R, S, dict(delta=cert.delta, delta_tilde=cert.delta_tilde,
+                             breakdown_col=cert.breakdown_col, nonfinite=cert.nonfinite,
+                             status=st)
+    lib.check(st, h)
+    cd = None
+    if cert is not None:
+        cd = dict(delta=cert.delta, delta_tilde=cert.delta_tilde,
+                  breakdown_col=cert.breakdown_col, nonfinite=cert.nonfinite, status=st)
+    return Q, R, S, cd
+
+
+def sketch_apply(X, kind, k, seed, zeta=8, row0=0, out=None):
+    """Theta[:, row0:row0+n] X for a column-major CUDA tensor X (n x c)."""
+    torch = _torch()
+    lib = Library.get()
+    n, c = X.shape
+    store = "f64" if X.dtype == torch.float64 else "f32"
+    h = lib.handle(X.device.index or 0)
+    if out is None:
+        out = colmajor(k, c, torch.float64, X.device)
+    xp, ldx = as_colmajor(X)
+    op, ldo = as_colmajor(out)
+    st = lib.rbgs_sketch_apply(h, make_sketch(kind, k, seed, zeta), STORE[store], xp, ldx, n, c,
+                               row0, op, ldo, _stream_ptr(X))
+    lib.check(st, h)
+    return out
+
+
+def theta_dense(kind, k, seed, n, row0=0, zeta=8, device="cuda"):
+    """Explicit unscaled Theta[:, row0:row0+n] (k x n float32, column-major)."""
+    torch = _torch()
+    lib = Library.get()
+    dev = torch.device(device)
+    h = lib.handle(dev.index or 0)
+    out = colmajor(k, n, torch.float32, dev)
+    st = lib.rbgs_theta_dense(h, make_sketch(kind, k, seed, zeta), n, row0, out.data_ptr(),
+                              torch.cuda.current_stream(dev).cuda_stream)
+    lib.check(st, h)
+    return out
+
+
+def profile_enable(enable=True, device=0):
+    lib = Library.get()
+    h = lib.handle(device)
+    lib.check(lib.rbgs_profile_enable(h, enable), h)
+
+
+def profile_get(which, device=0):
+    """(milliseconds, launches, algorithmic bytes) summed over the recorded launches."""
+    lib = Library.get()
+    h = lib.handle(device)
+    st, ms, cnt, by = lib.rbgs_profile_get(h, PROFILE[which])
+    lib.check(st, h)
+    return ms, cnt, by

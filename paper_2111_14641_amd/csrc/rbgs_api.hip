@@ -1,0 +1,494 @@
+// C ABI of the RBGS library: argument validation, workspace, and the block
+// loop of Algorithm RBGS (Section 2) for both inter-block variants of
+// Section 2.2.  Every step is enqueued on the caller's stream; nothing waits
+// on the host unless a certificate is requested.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rbgs.h"
+#include "rbgs_internal.h"
+
+using namespace rbgs;
+
+namespace {
+
+constexpr int kProfClasses = 5;
+enum ProfClass { kProfUpdate = 0, kProfSketch = 1, kProfReduce = 2, kProfSmall = 3, kProfTrsm = 4 };
+
+struct ProfRec {
+  int which;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct rbgs_handle_s {
+  int device = 0;
+  std::string last_error;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool profiling = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[kProfClasses] = {0};
+  int64_t prof_cnt[kProfClasses] = {0};
+  double prof_bytes[kProfClasses] = {0};
+  double* host_cert = nullptr;  // pinned, 4 doubles + flag
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+rbgs_status fail(rbgs_handle h, rbgs_status s, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+rbgs_status hip_fail(rbgs_handle h, hipError_t e, const char* where) {
+  std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(h, RBGS_EDEVICE, msg);
+}
+
+#define HIP_TRY(h, expr, where)                        \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return hip_fail(h, _e, where); \
+  } while (0)
+
+hipEvent_t take_event(rbgs_handle h) {
+  hipEvent_t e;
+  if (!h->pool.empty()) {
+    e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Wraps one kernel launch (or launch sequence) with profiling events.
+struct ProfScope {
+  rbgs_handle h;
+  int which;
+  double bytes;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(rbgs_handle h_, int which_, double bytes_, hipStream_t st_)
+      : h(h_), which(which_), bytes(bytes_), st(st_) {
+    if (h->profiling) {
+      a = take_event(h);
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = take_event(h);
+      if (b) {
+        (void)hipEventRecord(b, st);
+        h->recs.push_back({which, a, b, bytes});
+      } else {
+        h->pool.push_back(a);
+      }
+    }
+  }
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+rbgs_status ensure_ws(rbgs_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return RBGS_OK;
+  if (h->ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)1 << 20);
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, RBGS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  h->ws_bytes = want;
+  return RBGS_OK;
+}
+
+bool valid_sketch(const rbgs_sketch* sk, int64_t n, std::string& why) {
+  if (!sk) { why = "sketch descriptor is NULL"; return false; }
+  if (sk->k < 1) { why = "sketch dimension k must be >= 1"; return false; }
+  switch (sk->kind) {
+    case RBGS_SKETCH_GAUSSIAN:
+      if (sk->k % 4) { why = "Gaussian sketch needs k % 4 == 0"; return false; }
+      if (sk->k > (int64_t)1 << 20) { why = "k too large"; return false; }
+      return true;
+    case RBGS_SKETCH_SPARSE_SIGN:
+      if (sk->zeta < 1 || sk->zeta > 8) { why = "sparse sign needs 1 <= zeta <= 8"; return false; }
+      if (sk->k % sk->zeta) { why = "sparse sign needs k % zeta == 0"; return false; }
+      if (sk->k > 2048) { why = "sparse sign supports k <= 2048"; return false; }
+      return true;
+    case RBGS_SKETCH_IDENTITY:
+      if (sk->k != n) { why = "identity sketch needs k == n"; return false; }
+      return true;
+    default:
+      why = "unknown sketch kind";
+      return false;
+  }
+}
+
+SketchDesc make_desc(const rbgs_sketch* sk) {
+  SketchDesc d;
+  d.kind = sk->kind;
+  d.zeta = sk->zeta;
+  d.k = sk->k;
+  d.key0 = (uint32_t)(sk->seed & 0xFFFFFFFFull);
+  d.key1 = (uint32_t)(sk->seed >> 32);
+  return d;
+}
+
+double sketch_scale(const SketchDesc& d) {
+  if (d.kind == kGaussian) return 1.0 / sqrt((double)d.k);
+  if (d.kind == kSparse) return 1.0 / sqrt((double)d.zeta);
+  return 1.0;
+}
+
+size_t sketch_partial_doubles(const SketchDesc& d, int64_t n, int64_t ncols) {
+  if (d.kind == kIdentity) return 0;
+  return (size_t)sketch_num_partials(d, n, ncols) * (size_t)ncols * (size_t)d.k;
+}
+
+// out = Theta X (k x ncols, ld ldo)
+rbgs_status do_sketch(rbgs_handle h, const SketchDesc& d, bool f32, const void* X, int64_t ldx,
+                      int64_t n, int64_t ncols, int64_t row0, double* out, int64_t ldo,
+                      double* partial, hipStream_t st) {
+  const double s = f32 ? 4.0 : 8.0;
+  if (d.kind == kIdentity) {
+    ProfScope ps(h, kProfSketch, s * n * ncols + 8.0 * n * ncols, st);
+    HIP_TRY(h, launch_sketch_identity(f32, X, ldx, n, ncols, out, ldo, st), "sketch_identity");
+    return RBGS_OK;
+  }
+  const int G = sketch_num_partials(d, n, ncols);
+  {
+    ProfScope ps(h, kProfSketch, s * n * ncols, st);
+    HIP_TRY(h, launch_sketch_partials(d, f32, X, ldx, n, ncols, row0, partial, st), "sketch");
+  }
+  {
+    ProfScope ps(h, kProfReduce, 8.0 * d.k * ncols, st);
+    HIP_TRY(h, launch_sketch_reduce(partial, G, d.k, ncols, sketch_scale(d), out, ldo, st),
+            "sketch_reduce");
+  }
+  return RBGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbgs_status rbgs_create(rbgs_handle* h, int device) {
+  if (!h || device < 0) return RBGS_EINVAL;
+  rbgs_handle p = new (std::nothrow) rbgs_handle_s();
+  if (!p) return RBGS_ENOMEM;
+  p->device = device;
+  *h = p;
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_destroy(rbgs_handle h) {
+  if (!h) return RBGS_OK;
+  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert) {
+    DeviceGuard g(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto& r : h->recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->host_cert) (void)hipHostFree(h->host_cert);
+  }
+  delete h;
+  return RBGS_OK;
+}
+
+const char* rbgs_status_string(rbgs_status s) {
+  switch (s) {
+    case RBGS_OK: return "success";
+    case RBGS_EINVAL: return "invalid argument";
+    case RBGS_ENOMEM: return "out of device memory";
+    case RBGS_EDEVICE: return "HIP runtime error";
+    case RBGS_EBREAKDOWN: return "breakdown: zero or non-finite diagonal entry of R";
+    case RBGS_ENOTCONV: return "not converged";
+    case RBGS_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* rbgs_last_error(rbgs_handle h) { return h ? h->last_error.c_str() : ""; }
+
+rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
+                    const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
+                    double* R, int64_t ldr, double* S_out, rbgs_cert* cert) {
+  // ---- host-side validation (nothing is enqueued on failure) -------------
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  if (!W || !Q || !R) return fail(h, RBGS_EINVAL, "W, Q and R must be non-NULL");
+  if (!opts) return fail(h, RBGS_EINVAL, "options are NULL");
+  if (n < 1 || m < 1) return fail(h, RBGS_EINVAL, "n and m must be >= 1");
+  if (m > n) return fail(h, RBGS_EINVAL, "m must not exceed n");
+  if (p < 1) return fail(h, RBGS_EINVAL, "block width p must be >= 1");
+  if (ldw < n || ldq < n) return fail(h, RBGS_EINVAL, "leading dimensions of W and Q must be >= n");
+  if (ldr < m) return fail(h, RBGS_EINVAL, "leading dimension of R must be >= m");
+  std::string why;
+  if (!valid_sketch(sk, n, why)) return fail(h, RBGS_EINVAL, why);
+  if (sk->k < m) return fail(h, RBGS_EINVAL, "sketch dimension k must be >= m");
+  if (sk->k > n) return fail(h, RBGS_EINVAL, "sketch dimension k must be <= n");
+  if (opts->store != RBGS_STORE_F64 && opts->store != RBGS_STORE_F32)
+    return fail(h, RBGS_EINVAL, "unknown storage type");
+  if (opts->math != RBGS_MATH_F64 && opts->math != RBGS_MATH_F32)
+    return fail(h, RBGS_EINVAL, "unknown arithmetic");
+  if (opts->store == RBGS_STORE_F64 && opts->math != RBGS_MATH_F64)
+    return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
+  if (opts->variant != RBGS_VARIANT_PLAIN && opts->variant != RBGS_VARIANT_LOWSYNC)
+    return fail(h, RBGS_EINVAL, "unknown variant");
+  if (opts->ls_iters < 1 || opts->ls_iters > 16)
+    return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
+  if (p > 32) return fail(h, RBGS_EUNSUPPORTED, "block width p > 32 is not implemented");
+  const bool f32 = opts->store == RBGS_STORE_F32;
+  const bool f32_math = opts->math == RBGS_MATH_F32;
+  const size_t es = f32 ? 4 : 8;
+  {
+    // Q == W (same ld) is the in-place factorization; any other overlap is invalid.
+    const char* w0 = (const char*)W;
+    const char* w1 = w0 + es * (size_t)(ldw * (m - 1) + n);
+    const char* q0 = (const char*)Q;
+    const char* q1 = q0 + es * (size_t)(ldq * (m - 1) + n);
+    const bool same = (w0 == q0) && (ldw == ldq);
+    if (!same && q0 < w1 && w0 < q1) return fail(h, RBGS_EINVAL, "Q overlaps W (only Q == W is allowed)");
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + 8 * (size_t)(ldr * (m - 1) + m);
+    if ((r0 < w1 && w0 < r1) || (r0 < q1 && q0 < r1)) return fail(h, RBGS_EINVAL, "R overlaps W or Q");
+  }
+
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)opts->stream;
+  const SketchDesc d = make_desc(sk);
+  const int64_t k = d.k;
+  const int b = (int)p;
+
+  // ---- workspace ---------------------------------------------------------
+  size_t off = 0;
+  auto carve = [&](size_t doubles) {
+    size_t o = off;
+    off += ((doubles * 8 + 255) / 256) * 256;
+    return o;
+  };
+  const size_t o_S = S_out ? 0 : carve((size_t)k * m);
+  const size_t o_P = carve((size_t)k * m);
+  const size_t o_E = carve((size_t)k * b);
+  // partial sums for every sketch width used: all of W, a full block, the last block
+  size_t part_need = std::max(sketch_partial_doubles(d, n, m), sketch_partial_doubles(d, n, std::min<int64_t>(b, m)));
+  if (m % b) part_need = std::max(part_need, sketch_partial_doubles(d, n, m % b));
+  const size_t o_part = carve(part_need);
+  const size_t o_stack = carve(qr_stack_size(k, b));
+  const size_t o_flag = carve(1);
+  const size_t o_cs = carve(cert_scratch_size(k, m));
+  const size_t o_cout = carve(4);
+  rbgs_status rs = ensure_ws(h, off);
+  if (rs != RBGS_OK) return rs;
+  char* base = (char*)h->ws;
+  double* S = S_out ? S_out : (double*)(base + o_S);
+  double* P = (double*)(base + o_P);
+  double* E = (double*)(base + o_E);
+  double* part = (double*)(base + o_part);
+  double* stack = (double*)(base + o_stack);
+  int64_t* flag = (int64_t*)(base + o_flag);
+  double* cscratch = (double*)(base + o_cs);
+  double* cout = (double*)(base + o_cout);
+
+  HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
+  HIP_TRY(h, launch_set_i64(flag, -1, st), "flag");
+
+  // ---- step 1 for all blocks at once: P = Theta W (W is not modified before
+  // its block is reached, so hoisting the sketches of the blocks is exact) --
+  rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, st);
+  if (rs != RBGS_OK) return rs;
+
+  const char* Wb = (const char*)W;
+  char* Qb = (char*)Q;
+  const int l = opts->ls_iters;
+  for (int64_t c0 = 0; c0 < m; c0 += b) {
+    const int bw = (int)std::min<int64_t>(b, m - c0);
+    const int64_t K = c0;
+    const double* Pi = P + c0 * k;
+    double* Rk = R + c0 * ldr;            // R_(1:i-1,i): rows [0, K), columns [c0, c0+bw)
+    double* Rii = R + c0 + c0 * ldr;      // R_(i,i)
+    const void* Wi = Wb + es * (size_t)(c0 * ldw);
+    void* Qi = Qb + es * (size_t)(c0 * ldq);
+
+    // ---- step 2: sketched least squares by l Richardson sweeps ----------
+    if (K > 0) {
+      ProfScope ps(h, kProfSmall, 0.0, st);
+      HIP_TRY(h, launch_sty(S, k, Pi, k, Rk, ldr, k, K, bw, false, st), "richardson");
+      for (int it = 1; it < l; ++it) {
+        HIP_TRY(h, launch_resid(Pi, k, S, k, Rk, ldr, E, k, k, K, bw, st), "richardson");
+        HIP_TRY(h, launch_sty(S, k, E, k, Rk, ldr, k, K, bw, true, st), "richardson");
+      }
+    }
+    const double ub = (double)es * (double)n * (double)(K + 2 * bw);
+    if (opts->variant == RBGS_VARIANT_LOWSYNC) {
+      // ---- steps 4-5 with postponed sketching: S'_(i) = P_(i) - S R_(1:i-1,i)
+      {
+        ProfScope ps(h, kProfSmall, 0.0, st);
+        const double* Sp = Pi;
+        if (K > 0) {
+          HIP_TRY(h, launch_resid(Pi, k, S, k, Rk, ldr, E, k, k, K, bw, st), "S'");
+          Sp = E;
+        }
+        HIP_TRY(h, launch_qr_r(Sp, k, k, bw, Rii, ldr, stack, flag, c0, st), "qr of sketch");
+      }
+      // ---- step 3 + substitution in one pass --------------------------
+      {
+        ProfScope ps(h, kProfUpdate, ub, st);
+        HIP_TRY(h, launch_update(f32, f32_math, Wi, ldw, Q, ldq, Qi, ldq, Rk, Rii, ldr, n, K, bw, st),
+                "update");
+      }
+    } else {
+      // ---- step 3: Q'_(i), stored in Q_(i) ------------------------------
+      {
+        ProfScope ps(h, kProfUpdate, ub, st);
+        HIP_TRY(h, launch_update(f32, f32_math, Wi, ldw, Q, ldq, Qi, ldq, Rk, nullptr, ldr, n, K, bw, st),
+                "update");
+      }
+      // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution -----------
+      rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, E, k, part, st);
+      if (rs != RBGS_OK) return rs;
+      {
+        ProfScope ps(h, kProfSmall, 0.0, st);
+        HIP_TRY(h, launch_qr_r(E, k, k, bw, Rii, ldr, stack, flag, c0, st), "qr of sketch");
+      }
+      {
+        ProfScope ps(h, kProfTrsm, 2.0 * es * n * bw, st);
+        HIP_TRY(h, launch_trsm(f32, Qi, ldq, Rii, ldr, n, bw, st), "substitution");
+      }
+    }
+    // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------
+    rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, S + c0 * k, k, part, st);
+    if (rs != RBGS_OK) return rs;
+  }
+
+  if (!cert) return RBGS_OK;
+  // ---- step 6: certificates (host waits) ---------------------------------
+  HIP_TRY(h, launch_certificates(S, P, R, ldr, k, m, cscratch, cout, st), "certificates");
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert, cout, 4 * sizeof(double), hipMemcpyDeviceToHost, st),
+          "copy certificate");
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+          "copy flag");
+  HIP_TRY(h, hipStreamSynchronize(st), "stream synchronize");
+  const double* hc = h->host_cert;
+  int64_t bcol;
+  memcpy(&bcol, hc + 4, sizeof(int64_t));
+  const double pn2 = hc[2];
+  cert->delta = sqrt(hc[0]);
+  cert->delta_tilde = pn2 > 0 ? sqrt(hc[1] / pn2) : 0.0;
+  cert->breakdown_col = bcol;
+  cert->nonfinite = hc[3] != 0.0 ? 1 : 0;
+  cert->reserved = 0;
+  if (bcol >= 0) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "R(%lld,%lld) is zero or not finite", (long long)bcol, (long long)bcol);
+    return fail(h, RBGS_EBREAKDOWN, buf);
+  }
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t store, const void* X,
+                              int64_t ldx, int64_t n, int64_t c, int64_t row0, double* out,
+                              int64_t ldo, void* stream) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  if (!X || !out) return fail(h, RBGS_EINVAL, "X and out must be non-NULL");
+  if (n < 1 || c < 1 || ldx < n || row0 < 0) return fail(h, RBGS_EINVAL, "bad sizes");
+  if (store != RBGS_STORE_F64 && store != RBGS_STORE_F32) return fail(h, RBGS_EINVAL, "unknown storage type");
+  std::string why;
+  if (sk && sk->kind == RBGS_SKETCH_IDENTITY) {
+    if (sk->k != n || row0 != 0) return fail(h, RBGS_EINVAL, "identity sketch needs k == n and row0 == 0");
+  } else if (!valid_sketch(sk, n, why)) {
+    return fail(h, RBGS_EINVAL, why);
+  }
+  if (ldo < sk->k) return fail(h, RBGS_EINVAL, "ldo must be >= k");
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  const SketchDesc d = make_desc(sk);
+  rbgs_status rs = ensure_ws(h, sketch_partial_doubles(d, n, c) * 8 + 256);
+  if (rs != RBGS_OK) return rs;
+  return do_sketch(h, d, store == RBGS_STORE_F32, X, ldx, n, c, row0, out, ldo, (double*)h->ws,
+                   (hipStream_t)stream);
+}
+
+rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
+                             float* out, void* stream) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  if (!out || n < 1 || row0 < 0) return fail(h, RBGS_EINVAL, "bad arguments");
+  std::string why;
+  if (!sk) return fail(h, RBGS_EINVAL, "sketch descriptor is NULL");
+  if (sk->kind != RBGS_SKETCH_IDENTITY && !valid_sketch(sk, n, why)) return fail(h, RBGS_EINVAL, why);
+  if (sk->kind == RBGS_SKETCH_IDENTITY && sk->k < 1) return fail(h, RBGS_EINVAL, "k must be >= 1");
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  HIP_TRY(h, launch_theta_dense(make_desc(sk), n, row0, out, (hipStream_t)stream), "theta_dense");
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable) {
+  if (!h) return RBGS_EINVAL;
+  h->profiling = enable != 0;
+  for (int i = 0; i < kProfClasses; ++i) {
+    h->prof_ms[i] = 0;
+    h->prof_cnt[i] = 0;
+    h->prof_bytes[i] = 0;
+  }
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_profile_get(rbgs_handle h, int32_t which, double* ms, int64_t* launches,
+                             double* bytes) {
+  if (!h || which < 0 || which >= kProfClasses) return RBGS_EINVAL;
+  if (!h->recs.empty()) {
+    DeviceGuard guard(h->device);
+    for (auto& r : h->recs) {
+      HIP_TRY(h, hipEventSynchronize(r.b), "hipEventSynchronize");
+      float t = 0.f;
+      HIP_TRY(h, hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+      h->prof_ms[r.which] += t;
+      h->prof_cnt[r.which] += 1;
+      h->prof_bytes[r.which] += r.bytes;
+      h->pool.push_back(r.a);
+      h->pool.push_back(r.b);
+    }
+    h->recs.clear();
+  }
+  if (ms) *ms = h->prof_ms[which];
+  if (launches) *launches = h->prof_cnt[which];
+  if (bytes) *bytes = h->prof_bytes[which];
+  return RBGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// Internal declarations of the gfx950 RBGS library: device-side definition of
+// the sketching operators and the host launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace rbgs {
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
+// words 0 and 2 by the two Philox multipliers, swaps the high halves across,
+// and mixes in the key; the key advances by the Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+constexpr uint32_t kTagGauss = 0x47415553u;
+constexpr uint32_t kTagSparse = 0x53504152u;
+
+// fp32 constants by bit pattern (correctly rounded values of the named reals).
+__device__ __forceinline__ float f32c(uint32_t b) { return __uint_as_float(b); }
+
+// Natural logarithm of u = (2*(w >> 9) + 1) * 2^-24 in single precision:
+// write N = 2*(w>>9)+1 = f * 2^e with f in [sqrt(2)/2, sqrt(2)], then
+// ln u = (e - 24) ln 2 + 2 atanh(s), s = (f-1)/(f+1), using the odd series of
+// atanh to s^9.  Each operation is one correctly rounded IEEE fp32 operation
+// (no contraction), so the result is reproducible bit for bit.
+__device__ __forceinline__ float gauss_ln_u24(uint32_t w) {
+#pragma clang fp contract(off)
+  const uint32_t N = ((w >> 9) << 1) | 1u;
+  const uint32_t bits = __float_as_uint((float)N);
+  int e = (int)((bits >> 23) & 0xFFu) - 127;
+  float f = __uint_as_float((bits & 0x007FFFFFu) | 0x3F800000u);
+  if (f > f32c(0x3FB504F3u)) {  // sqrt(2)
+    f = f * 0.5f;
+    e += 1;
+  }
+  const float s = (f - 1.0f) / (f + 1.0f);
+  const float s2 = s * s;
+  float p = f32c(0x3E124925u) + s2 * f32c(0x3DE38E39u);  // 1/7 + s2/9
+  p = f32c(0x3E4CCCCDu) + s2 * p;                         // 1/5
+  p = f32c(0x3EAAAAABu) + s2 * p;                         // 1/3
+  const float t = 2.0f * s;
+  const float lnf = t + t * (s2 * p);
+  return (float)(e - 24) * f32c(0x3F317218u) + lnf;      // ln 2
+}
+
+// cos and sin of phi = (pi/2) (q + t), q = w >> 30, t = (2*((w>>7) & 0x7FFFFF)+1) 2^-24:
+// Taylor polynomials of sin a (to a^13) and cos a (to a^14) at a = t * pi/2,
+// Horner form, then q quarter turns.  Single-precision, no contraction.
+__device__ __forceinline__ void gauss_sincos(uint32_t w, float& c, float& s) {
+#pragma clang fp contract(off)
+  const uint32_t q = w >> 30;
+  const uint32_t v = (w >> 7) & 0x7FFFFFu;
+  const float t = (float)(2u * v + 1u) * 5.9604644775390625e-08f;  // 2^-24
+  const float a = t * f32c(0x3FC90FDBu);                             // pi/2
+  const float a2 = a * a;
+  float ps = f32c(0xB2D7322Bu) + a2 * f32c(0x2F309231u);  // -1/11! + a2/13!
+  ps = f32c(0x3638EF1Du) + a2 * ps;                         //  1/9!
+  ps = f32c(0xB9500D01u) + a2 * ps;                         // -1/7!
+  ps = f32c(0x3C088889u) + a2 * ps;                         //  1/5!
+  ps = f32c(0xBE2AAAABu) + a2 * ps;                         // -1/3!
+  const float sa = a + (a * a2) * ps;
+  float pc = f32c(0x310F76C7u) + a2 * f32c(0xAD49CBA5u);   //  1/12! - a2/14!
+  pc = f32c(0xB493F27Eu) + a2 * pc;                         // -1/10!
+  pc = f32c(0x37D00D01u) + a2 * pc;                         //  1/8!
+  pc = f32c(0xBAB60B61u) + a2 * pc;                         // -1/6!
+  pc = f32c(0x3D2AAAABu) + a2 * pc;                         //  1/4!
+  pc = f32c(0xBF000000u) + a2 * pc;                         // -1/2
+  const float ca = 1.0f + a2 * pc;
+  switch (q) {
+    case 0: c = ca; s = sa; break;
+    case 1: c = -sa; s = ca; break;
+    case 2: c = -ca; s = -sa; break;
+    default: c = sa; s = -ca; break;
+  }
+}
+
+// Box-Muller: radius word wr, angle word wa -> (rho cos phi, rho sin phi).
+__device__ __forceinline__ void gauss_pair(uint32_t wr, uint32_t wa, float& z0, float& z1) {
+#pragma clang fp contract(off)
+  const float rho = sqrtf(-2.0f * gauss_ln_u24(wr));
+  float c, s;
+  gauss_sincos(wa, c, s);
+  z0 = rho * c;
+  z1 = rho * s;
+}
+
+// Unscaled Gaussian entries Z[4j .. 4j+3][r].
+__device__ __forceinline__ void gauss4(uint64_t r, uint32_t j, uint32_t k0, uint32_t k1, float z[4]) {
+  const u32x4 x = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), j, kTagGauss, k0, k1);
+  gauss_pair(x.x, x.y, z[0], z[1]);
+  gauss_pair(x.z, x.w, z[2], z[3]);
+}
+
+// Row (target) of the nonzero of segment s of the sparse-sign column r:
+// s*L + (((w_s >> 1) * L) >> 31), sign bit = w_s & 1 (1 = negative).
+__device__ __forceinline__ uint32_t sparse_target(uint32_t w, uint32_t s, uint32_t L) {
+  return s * L + (uint32_t)((((uint64_t)(w >> 1)) * (uint64_t)L) >> 31);
+}
+
+// The eight words of column r of the sparse sign (two Philox calls).
+__device__ __forceinline__ void sparse_words(uint64_t r, uint32_t k0, uint32_t k1, uint32_t w[8]) {
+  const u32x4 a = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), 0u, kTagSparse, k0, k1);
+  const u32x4 b = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), 1u, kTagSparse, k0, k1);
+  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+  w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (all enqueue on `st`, return hipError_t of the launch).
+// ---------------------------------------------------------------------------
+enum SketchKind { kGaussian = 0, kSparse = 1, kIdentity = 2 };
+
+struct SketchDesc {
+  int kind;
+  int zeta;
+  int64_t k;
+  uint32_t key0, key1;
+};
+
+// Number of partial blocks (row ranges) the sketch kernels use for n rows.
+int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols);
+// Columns handled per partial block pass.
+constexpr int kSketchCols = 16;
+
+// partial[g][c][t] (g < G, c < ncols, t < k), G = sketch_num_partials(sk, n).
+hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
+                                  int64_t n, int64_t ncols, int64_t row0, double* partial,
+                                  hipStream_t st);
+// out[t + c*ldo] = scale * sum_g partial[g][c][t]
+hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
+                                double scale, double* out, int64_t ldo, hipStream_t st);
+// Identity sketch: out = X (converted to FP64).
+hipError_t launch_sketch_identity(bool f32, const void* X, int64_t ldx, int64_t n, int64_t ncols,
+                                  double* out, int64_t ldo, hipStream_t st);
+hipError_t launch_theta_dense(const SketchDesc& sk, int64_t n, int64_t row0, float* out,
+                              hipStream_t st);
+
+// Q'_(i) = W_(i) - Q_(1:i-1) R_(1:i-1,i)  [then Q_(i) = Q'_(i) R_(i,i)^{-1} if Rii != nullptr]
+//   Rk: R_(1:i-1,i) in the R array (column-major, ld ldr), K rows, bw columns.
+//   Rii: R_(i,i) in the R array (ld ldr), bw x bw, or nullptr.
+//   f32: storage of W/Q is FP32 (else FP64); f32_math: FP32 matrix-core arithmetic
+//   (only with FP32 storage), else FP64 matrix-core arithmetic.
+hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, const void* Q,
+                         int64_t ldq, void* Qout, int64_t ldqo, const double* Rk,
+                         const double* Rii, int64_t ldr, int64_t n, int64_t K, int bw,
+                         hipStream_t st);
+// In place Q_(i) = Q'_(i) R_(i,i)^{-1} (forward substitution per row).
+hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_t ldr, int64_t n,
+                       int bw, hipStream_t st);
+
+// Small FP64 factors (Section 2.1, 2.2).
+// Y (K x bw, ld ldy) (+)= S^T E,  S: k x K (ld lds), E: k x bw (ld lde)
+hipError_t launch_sty(const double* S, int64_t lds, const double* E, int64_t lde, double* Y,
+                      int64_t ldy, int64_t k, int64_t K, int bw, bool accumulate, hipStream_t st);
+// E = P - S Y   (k x bw)
+hipError_t launch_resid(const double* P, int64_t ldp, const double* S, int64_t lds,
+                        const double* Y, int64_t ldy, double* E, int64_t lde, int64_t k, int64_t K,
+                        int bw, hipStream_t st);
+// R (bw x bw, ld ldr) = positive-diagonal R factor of the Householder QR of
+// A (k x bw, ld lda).  `stack` is workspace of qr_stack_size(k, bw) doubles.
+// Sets flag[0] = first breakdown column (global index col0 + j) if a diagonal
+// entry is zero or not finite and flag[0] is still -1.
+size_t qr_stack_size(int64_t k, int bw);
+hipError_t launch_qr_r(const double* A, int64_t lda, int64_t k, int bw, double* R, int64_t ldr,
+                       double* stack, int64_t* flag, int64_t col0, hipStream_t st);
+// Fill an m x m column-major matrix (ld) with zeros.
+hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+// Certificates: out[0] = ||I - S^T S||_F^2, out[1] = ||P - S R||_F^2, out[2] = ||P||_F^2,
+// out[3] = 1 if any entry of R or S is not finite.  `scratch` >= cert_scratch_size(k, m).
+size_t cert_scratch_size(int64_t k, int64_t m);
+hipError_t launch_certificates(const double* S, const double* P, const double* R, int64_t ldr,
+                               int64_t k, int64_t m, double* scratch, double* out, hipStream_t st);
+
+}  // namespace rbgs

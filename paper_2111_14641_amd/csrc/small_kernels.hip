@@ -1,0 +1,332 @@
+// Small FP64 factors of Algorithm RBGS (k-dimensional work):
+//  * Richardson sweeps for the sketched least-squares problem of step 2
+//    (supplement SM.1): Y <- Y + S^T (P - S Y), built from two kernels,
+//    Y (+)= S^T E and E = P - S Y;
+//  * the residual sketch S'_(i) = P_(i) - S_(1:i-1) R_(1:i-1,i) of RCholeskyQR
+//    with postponed sketching (Section 2.2.3) -- the same E = P - S Y kernel;
+//  * R_(i,i) = R factor of the l2 (Householder) QR of S'_(i) with positive
+//    diagonal (Sections 2.2.2 and 2.2.3), as a tree of Householder QRs of row
+//    chunks held in LDS (the R factor of a stack of R factors is the R factor
+//    of the whole matrix, up to row signs);
+//  * the certificates of step 6, Delta = ||I - S^T S||_F and
+//    Delta~ = ||P - S R||_F / ||P||_F.
+// Every reduction runs in a fixed order.
+#include "rbgs_internal.h"
+
+namespace rbgs {
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Y[j + c ldy] (+)= sum_t S[t + j lds] E[t + c lde]; one wave per (j, c).
+__global__ __launch_bounds__(256) void sty_kernel(const double* __restrict__ S, int64_t lds,
+                                                  const double* __restrict__ E, int64_t lde,
+                                                  double* __restrict__ Y, int64_t ldy, int64_t k,
+                                                  int64_t K, int bw, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= K * bw) return;
+  const int64_t j = w % K, c = w / K;
+  const double* s = S + j * lds;
+  const double* e = E + c * lde;
+  double acc = 0.0;
+  for (int64_t t = lane; t < k; t += 64) acc = fma(s[t], e[t], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    double* y = Y + j + c * ldy;
+    *y = accumulate ? *y + acc : acc;
+  }
+}
+
+// E[t + c lde] = P[t + c ldp] - sum_{j<K} S[t + j lds] Y[j + c ldy]
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P, int64_t ldp,
+                                                    const double* __restrict__ S, int64_t lds,
+                                                    const double* __restrict__ Y, int64_t ldy,
+                                                    double* __restrict__ E, int64_t lde, int64_t k,
+                                                    int64_t K) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (t >= k) return;
+  const double* y = Y + c * ldy;
+  double acc = 0.0;
+  for (int64_t j = 0; j < K; ++j) acc = fma(S[t + j * lds], y[j], acc);
+  E[t + c * lde] = P[t + c * ldp] - acc;
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of a chunk held in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kQrThreads = 256;
+constexpr int kQrLds = 4096;  // doubles of LDS for the chunk (32 KB)
+constexpr int kQrMaxB = 32;
+
+__device__ __forceinline__ int qr_chunk_rows(int bw) {
+  // rows per chunk: as many as fit in LDS, at least 2*bw so the tree shrinks
+  return kQrLds / bw;
+}
+
+// In-place Householder triangularization of A (rows x bw, column-major, ld
+// rows) in LDS.  For column j: sigma = ||x||^2 with x = A[j:, j]; alpha =
+// -sign(x_0) ||x||; v = x - alpha e_1 (stored over x); every later column is
+// updated as a_c -= (2 / v^T v) (v^T a_c) v with v^T v = 2 ||x|| (||x|| + |x_0|);
+// then A[j][j] = alpha.  On return the upper triangle holds R (a zero column
+// gives R_jj = 0 and no reflection).
+__device__ void householder_lds(double* A, int rows, int bw, double* red /* [kQrMaxB+1] */) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double alpha_s, beta_s;
+  for (int j = 0; j < bw && j < rows; ++j) {
+    if (wave == 0) {
+      double acc = 0.0;
+      for (int r = j + lane; r < rows; r += 64) acc = fma(A[r + j * rows], A[r + j * rows], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        const double x0 = A[j + j * rows];
+        if (acc == 0.0) {
+          alpha_s = 0.0;
+          beta_s = 0.0;
+        } else {
+          const double nrm = sqrt(acc);
+          const double alpha = x0 >= 0.0 ? -nrm : nrm;
+          alpha_s = alpha;
+          beta_s = 2.0 / (2.0 * nrm * (nrm + fabs(x0)));
+          A[j + j * rows] = x0 - alpha;  // v_0
+        }
+      }
+    }
+    __syncthreads();
+    const double beta = beta_s;
+    if (beta != 0.0) {
+      for (int c = j + 1 + wave; c < bw; c += 4) {
+        double acc = 0.0;
+        for (int r = j + lane; r < rows; r += 64) acc = fma(A[r + j * rows], A[r + c * rows], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) red[c] = beta * acc;
+      }
+      __syncthreads();
+      const int ncols = bw - j - 1;
+      const int nrows = rows - j;
+      for (int e = tid; e < ncols * nrows; e += kQrThreads) {
+        const int c = j + 1 + e / nrows;
+        const int r = j + e % nrows;
+        A[r + c * rows] = fma(-red[c], A[r + j * rows], A[r + c * rows]);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) A[j + j * rows] = alpha_s;
+    __syncthreads();
+  }
+}
+
+// One level of the tree: chunk b of `src` (rows_in x bw, ld ld_in) -> its R
+// factor (bw x bw) written at rows [b*bw, b*bw+bw) of `dst` (ld ld_out).  When
+// final != 0 there is one chunk and R goes to the output with a positive
+// diagonal, zeros below it, and a breakdown check.
+__global__ __launch_bounds__(kQrThreads) void qr_level_kernel(const double* __restrict__ src,
+                                                              int64_t ld_in, int64_t rows_in,
+                                                              int bw, double* __restrict__ dst,
+                                                              int64_t ld_out, int final,
+                                                              int64_t* flag, int64_t col0) {
+  __shared__ double A[kQrLds];
+  __shared__ double red[kQrMaxB + 1];
+  const int CH = qr_chunk_rows(bw);
+  const int64_t r0 = (int64_t)blockIdx.x * CH;
+  const int rows = (int)min((int64_t)CH, rows_in - r0);
+  const int rows_p = max(rows, bw);  // pad short chunks with zero rows
+  for (int e = threadIdx.x; e < rows_p * bw; e += kQrThreads) {
+    const int r = e % rows_p, c = e / rows_p;
+    A[r + c * rows_p] = r < rows ? src[(r0 + r) + c * ld_in] : 0.0;
+  }
+  __syncthreads();
+  householder_lds(A, rows_p, bw, red);
+  if (!final) {
+    for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
+      const int r = e % bw, c = e / bw;
+      dst[((int64_t)blockIdx.x * bw + r) + c * ld_out] = r <= c ? A[r + c * rows_p] : 0.0;
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
+    const int r = e % bw, c = e / bw;
+    const double d = A[r + r * rows_p];
+    const double sgn = d < 0.0 ? -1.0 : 1.0;
+    dst[r + c * ld_out] = r <= c ? sgn * A[r + c * rows_p] : 0.0;
+  }
+  if (threadIdx.x == 0 && flag != nullptr) {
+    for (int j = 0; j < bw; ++j) {
+      const double d = A[j + j * rows_p];
+      if (!(d != 0.0) || !isfinite(d)) {
+        atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
+                  (unsigned long long)(col0 + j));
+        break;
+      }
+    }
+  }
+}
+
+size_t qr_stack_size(int64_t k, int bw) {
+  const int64_t CH = kQrLds / bw;
+  int64_t rows = k, total = 0;
+  while (rows > CH) {
+    const int64_t nch = ceil_div(rows, CH);
+    total += nch * bw;
+    rows = nch * bw;
+  }
+  return (size_t)total * bw + 1;
+}
+
+hipError_t launch_qr_r(const double* A, int64_t lda, int64_t k, int bw, double* R, int64_t ldr,
+                       double* stack, int64_t* flag, int64_t col0, hipStream_t st) {
+  if (bw > kQrMaxB) return hipErrorInvalidValue;
+  const int64_t CH = kQrLds / bw;
+  const double* src = A;
+  int64_t ld_in = lda, rows = k;
+  double* buf = stack;
+  while (rows > CH) {
+    const int64_t nch = ceil_div(rows, CH);
+    const int64_t out_rows = nch * bw;
+    hipLaunchKernelGGL(qr_level_kernel, dim3((unsigned)nch), dim3(kQrThreads), 0, st, src, ld_in,
+                       rows, bw, buf, out_rows, 0, (int64_t*)nullptr, (int64_t)0);
+    src = buf;
+    ld_in = out_rows;
+    rows = out_rows;
+    buf += out_rows * bw;
+  }
+  hipLaunchKernelGGL(qr_level_kernel, dim3(1), dim3(kQrThreads), 0, st, src, ld_in, rows, bw, R,
+                     ldr, 1, flag, col0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(double* A, int64_t ld, int64_t rows, int64_t cols) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  A[(idx % rows) + (idx / rows) * ld] = 0.0;
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st) {
+  const int64_t total = rows * cols;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, A, ld,
+                     rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_sty(const double* S, int64_t lds, const double* E, int64_t lde, double* Y,
+                      int64_t ldy, int64_t k, int64_t K, int bw, bool accumulate,
+                      hipStream_t st) {
+  const int64_t waves = K * bw;
+  if (waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(sty_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, st, S, lds, E,
+                     lde, Y, ldy, k, K, bw, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid(const double* P, int64_t ldp, const double* S, int64_t lds,
+                        const double* Y, int64_t ldy, double* E, int64_t lde, int64_t k, int64_t K,
+                        int bw, hipStream_t st) {
+  dim3 grid((unsigned)ceil_div(k, 256), (unsigned)bw);
+  hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, P, ldp, S, lds, Y, ldy, E, lde, k, K);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Certificates.
+// ---------------------------------------------------------------------------
+// scratch[a + m b] = (delta_ab - S_a . S_b)^2 ; one wave per (a, b)
+__global__ __launch_bounds__(256) void gram_defect_kernel(const double* __restrict__ S, int64_t k,
+                                                          int64_t m, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= m * m) return;
+  const int64_t a = w % m, b = w / m;
+  double acc = 0.0;
+  for (int64_t t = lane; t < k; t += 64) acc = fma(S[t + a * k], S[t + b * k], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const double d = (a == b ? 1.0 : 0.0) - acc;
+    out[w] = d * d;
+  }
+}
+
+// out[t + k c] = (P - S R)[t, c]^2 ; out2[t + k c] = P[t, c]^2
+__global__ __launch_bounds__(256) void sketch_resid_kernel(const double* __restrict__ S,
+                                                           const double* __restrict__ P,
+                                                           const double* __restrict__ R,
+                                                           int64_t ldr, int64_t k, int64_t m,
+                                                           double* __restrict__ out,
+                                                           double* __restrict__ out2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (t >= k) return;
+  double acc = 0.0;
+  for (int64_t j = 0; j <= c; ++j) acc = fma(S[t + j * k], R[j + c * ldr], acc);
+  const double p = P[t + c * k];
+  const double e = p - acc;
+  out[t + c * k] = e * e;
+  out2[t + c * k] = p * p;
+}
+
+__global__ __launch_bounds__(256) void finite_kernel(const double* __restrict__ S,
+                                                     const double* __restrict__ R, int64_t ldr,
+                                                     int64_t k, int64_t m,
+                                                     double* __restrict__ out) {
+  // out[idx] = 1 if the idx-th entry of S (k*m) or R (m*m) is not finite
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < k * m) {
+    out[idx] = isfinite(S[idx]) ? 0.0 : 1.0;
+  } else if (idx < k * m + m * m) {
+    const int64_t e = idx - k * m;
+    out[idx] = isfinite(R[(e % m) + (e / m) * ldr]) ? 0.0 : 1.0;
+  }
+}
+
+// single workgroup, fixed order: out = sum of v[0..len)
+__global__ __launch_bounds__(256) void sum_kernel(const double* __restrict__ v, int64_t len,
+                                                  double* __restrict__ out) {
+  __shared__ double part[4];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += 256) acc += v[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+size_t cert_scratch_size(int64_t k, int64_t m) { return (size_t)(m * m + 2 * k * m + m * m); }
+
+hipError_t launch_certificates(const double* S, const double* P, const double* R, int64_t ldr,
+                               int64_t k, int64_t m, double* scratch, double* out,
+                               hipStream_t st) {
+  double* g = scratch;
+  double* e = g + m * m;
+  double* p2 = e + k * m;
+  hipLaunchKernelGGL(gram_defect_kernel, dim3((unsigned)ceil_div(m * m, 4)), dim3(256), 0, st, S,
+                     k, m, g);
+  hipLaunchKernelGGL(sketch_resid_kernel, dim3((unsigned)ceil_div(k, 256), (unsigned)m), dim3(256),
+                     0, st, S, P, R, ldr, k, m, e, p2);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, g, m * m, out + 0);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, e, k * m, out + 1);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, p2, k * m, out + 2);
+  // non-finite entries: reuse the Gram area (already summed in stream order)
+  double* fin = e;  // k*m + m*m entries fit in e .. p2 + k*m
+  hipLaunchKernelGGL(finite_kernel, dim3((unsigned)ceil_div(k * m + m * m, 256)), dim3(256), 0, st,
+                     S, R, ldr, k, m, fin);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, fin, k * m + m * m, out + 3);
+  return hipGetLastError();
+}
+
+}  // namespace rbgs

@@ -1,0 +1,98 @@
+"""GPU sketching operators against the oracle's definition (bit-exact Theta,
+FP64-accurate sketches)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import theta as th
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def to_np(t):
+    return np.ascontiguousarray(t.detach().cpu().numpy())
+
+
+@pytest.mark.parametrize("k,n,row0,seed", [
+    (256, 1000, 0, 0x2111146410),
+    (64, 333, 12345, 7),
+    (1024, 300, 2**32 - 100, 99),      # crosses the 32-bit boundary of the row counter
+])
+def test_gaussian_theta_bit_exact(gpu_lib, k, n, row0, seed):
+    from paper_2111_14641_amd import binding as B
+    say("theta gaussian", k, n, row0, seed)
+    Zg = to_np(B.theta_dense("gaussian", k, seed, n, row0))
+    Zo = np.ascontiguousarray(th.gaussian_z(np.arange(row0, row0 + n, dtype=np.uint64), k, seed).T)
+    mism = np.count_nonzero(Zg.view(np.uint32) != Zo.view(np.uint32))
+    assert mism == 0, f"{mism} of {Zg.size} entries differ; max abs diff {np.max(np.abs(Zg - Zo))}"
+
+
+@pytest.mark.parametrize("k,zeta,n,row0,seed", [
+    (1024, 8, 2000, 0, 0x2111146411), (64, 8, 500, 777, 3), (60, 5, 100, 2**33, 5), (2048, 8, 300, 0, 1),
+])
+def test_sparse_theta_bit_exact(gpu_lib, k, zeta, n, row0, seed):
+    from paper_2111_14641_amd import binding as B
+    say("theta sparse", k, zeta, n, row0, seed)
+    Bg = to_np(B.theta_dense("sparse", k, seed, n, row0, zeta=zeta))
+    S = th.Sketch("sparse", k, seed=seed, zeta=zeta)
+    idx, sgn = th.sparse_sign_entries(np.arange(row0, row0 + n, dtype=np.uint64), k, zeta, seed)
+    Bo = np.zeros((k, n), dtype=np.float32)
+    Bo[idx.ravel(), np.repeat(np.arange(n), zeta)] = sgn.ravel()
+    assert np.array_equal(Bg, Bo)
+    assert S.scale == 1 / np.sqrt(zeta)
+
+
+def abs_sketch(kind, k, seed, X, row0, zeta=8):
+    """|Theta| |X| (the scale of the rounding-error bound of a sketch)."""
+    import scipy.sparse as sp
+    n = X.shape[0]
+    rows = np.arange(row0, row0 + n, dtype=np.uint64)
+    if kind == "gaussian":
+        out = np.zeros((k, X.shape[1]))
+        for r0 in range(0, n, 8192):
+            Z = th.gaussian_z(rows[r0:r0 + 8192], k, seed).astype(np.float64)
+            out += np.abs(Z).T @ np.abs(X[r0:r0 + 8192])
+        return out / np.sqrt(k)
+    idx, _ = th.sparse_sign_entries(rows, k, zeta, seed)
+    Bm = sp.csr_matrix((np.ones(idx.size), (idx.ravel().astype(np.int64), np.repeat(np.arange(n), zeta))),
+                       shape=(k, n))
+    return (Bm @ np.abs(X)) / np.sqrt(zeta)
+
+
+@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("gaussian", 100), ("sparse", 1024),
+                                    ("sparse", 2048), ("sparse", 64)])
+@pytest.mark.parametrize("n,c,row0", [(4097, 16, 0), (1000, 5, 31), (70000, 33, 1 << 20), (3, 1, 0)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sketch_apply_matches_oracle(gpu_lib, kind, k, n, c, row0, dtype):
+    """FP64 accumulation of exact products (fp32 entries of Z or +-1 times the
+    data): GPU and oracle differ by summation order only, within
+    c u sqrt(n) |Theta| |X| elementwise."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("sketch", kind, k, n, c, row0, dtype)
+    rng = np.random.default_rng(n + c + k)
+    X = rng.standard_normal((n, c))
+    if dtype == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Xt = B.colmajor(n, c, tdt)
+    Xt.copy_(torch.from_numpy(X))
+    got = to_np(B.sketch_apply(Xt, kind, k, seed=11, row0=row0))
+    ref = th.Sketch(kind, k, seed=11).apply(X, row0=row0)
+    tol = 1e-15 * (10 + np.sqrt(n)) * abs_sketch(kind, k, 11, X, row0)
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+def test_identity_sketch_copies(gpu_lib):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("sketch identity")
+    X = np.random.default_rng(0).standard_normal((50, 3))
+    Xt = B.colmajor(50, 3, torch.float64)
+    Xt.copy_(torch.from_numpy(X))
+    assert np.array_equal(to_np(B.sketch_apply(Xt, "identity", 50, seed=0)), X)
