@@ -191,11 +191,21 @@ class Sketch:
         else:
             raise ValueError(kind)
         self._dense = None
+        self._csr = None
+        self._csr_n = 0
 
     def materialize(self, n):
-        """Form Theta explicitly (k x n, FP64) once and apply it by a dense
-        product from then on; for small n only."""
-        self._dense = self.dense(n)
+        """Form Theta explicitly once and apply it by a product from then on:
+        a dense k x n FP64 matrix, or for the sparse sign a compressed sparse
+        row matrix of the unscaled +-1 entries (so large n stays cheap)."""
+        if self.kind == "sparse":
+            idx, sign = sparse_sign_entries(np.arange(n), self.k, self.zeta, self.seed)
+            cols = np.repeat(np.arange(n), self.zeta)
+            self._csr = sp.csr_matrix((sign.ravel().astype(np.float64),
+                                       (idx.ravel().astype(np.int64), cols)), shape=(self.k, n))
+            self._csr_n = n
+        else:
+            self._dense = self.dense(n)
         return self
 
     # -- explicit form -------------------------------------------------
@@ -226,6 +236,8 @@ class Sketch:
         n_loc, c = X.shape
         if self._dense is not None:
             return self._dense[:, row0:row0 + n_loc] @ X
+        if self._csr is not None and row0 == 0 and n_loc == self._csr_n:
+            return self.scale * (self._csr @ X)
         if self.kind == "identity":
             if row0 != 0 or n_loc != self.k:
                 raise ValueError("identity sketch needs k == n")
