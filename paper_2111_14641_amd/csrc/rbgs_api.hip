@@ -175,7 +175,7 @@ size_t sketch_partial_doubles(const SketchDesc& d, int64_t n, int64_t ncols) {
 // out = Theta X (k x ncols, ld ldo)
 rbgs_status do_sketch(rbgs_handle h, const SketchDesc& d, bool f32, const void* X, int64_t ldx,
                       int64_t n, int64_t ncols, int64_t row0, double* out, int64_t ldo,
-                      double* partial, hipStream_t st) {
+                      double* partial, const uint16_t* plan, hipStream_t st) {
   const double s = f32 ? 4.0 : 8.0;
   if (d.kind == kIdentity) {
     ProfScope ps(h, kProfSketch, s * n * ncols + 8.0 * n * ncols, st);
@@ -185,7 +185,7 @@ rbgs_status do_sketch(rbgs_handle h, const SketchDesc& d, bool f32, const void* 
   const int G = sketch_num_partials(d, n, ncols);
   {
     ProfScope ps(h, kProfSketch, s * n * ncols, st);
-    HIP_TRY(h, launch_sketch_partials(d, f32, X, ldx, n, ncols, row0, partial, st), "sketch");
+    HIP_TRY(h, launch_sketch_partials(d, f32, X, ldx, n, ncols, row0, partial, plan, st), "sketch");
   }
   {
     ProfScope ps(h, kProfReduce, 8.0 * d.k * ncols, st);
@@ -306,6 +306,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   if (m % b) part_need = std::max(part_need, sketch_partial_doubles(d, n, m % b));
   const size_t o_part = carve(part_need);
   const size_t o_stack = carve(qr_stack_size(k, b));
+  const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
   const size_t o_cs = carve(cert_scratch_size(k, m));
   const size_t o_cout = carve(4);
@@ -317,16 +318,21 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   double* E = (double*)(base + o_E);
   double* part = (double*)(base + o_part);
   double* stack = (double*)(base + o_stack);
+  uint16_t* plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
   int64_t* flag = (int64_t*)(base + o_flag);
   double* cscratch = (double*)(base + o_cs);
   double* cout = (double*)(base + o_cout);
 
   HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
   HIP_TRY(h, launch_set_i64(flag, -1, st), "flag");
+  if (plan) {
+    ProfScope ps(h, kProfSketch, 0.0, st);
+    HIP_TRY(h, launch_sparse_plan(d, n, 0, plan, st), "sketch plan");
+  }
 
   // ---- step 1 for all blocks at once: P = Theta W (W is not modified before
   // its block is reached, so hoisting the sketches of the blocks is exact) --
-  rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, st);
+  rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, plan, st);
   if (rs != RBGS_OK) return rs;
 
   const char* Wb = (const char*)W;
@@ -376,7 +382,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
                 "update");
       }
       // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution -----------
-      rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, E, k, part, st);
+      rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, E, k, part, plan, st);
       if (rs != RBGS_OK) return rs;
       {
         ProfScope ps(h, kProfSmall, 0.0, st);
@@ -388,7 +394,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
       }
     }
     // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------
-    rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, S + c0 * k, k, part, st);
+    rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, S + c0 * k, k, part, plan, st);
     if (rs != RBGS_OK) return rs;
   }
 
@@ -436,10 +442,15 @@ rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t stor
   DeviceGuard guard(h->device);
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
   const SketchDesc d = make_desc(sk);
-  rbgs_status rs = ensure_ws(h, sketch_partial_doubles(d, n, c) * 8 + 256);
+  const size_t part_bytes = ((sketch_partial_doubles(d, n, c) * 8 + 255) / 256) * 256;
+  const size_t plan_bytes = d.kind == kSparse ? sparse_plan_bytes(d, n) : 0;
+  rbgs_status rs = ensure_ws(h, part_bytes + plan_bytes + 256);
   if (rs != RBGS_OK) return rs;
+  hipStream_t st = (hipStream_t)stream;
+  uint16_t* plan = d.kind == kSparse ? (uint16_t*)((char*)h->ws + part_bytes) : nullptr;
+  if (plan) HIP_TRY(h, launch_sparse_plan(d, n, row0, plan, st), "sketch plan");
   return do_sketch(h, d, store == RBGS_STORE_F32, X, ldx, n, c, row0, out, ldo, (double*)h->ws,
-                   (hipStream_t)stream);
+                   plan, st);
 }
 
 rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,

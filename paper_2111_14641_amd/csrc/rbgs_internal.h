@@ -148,10 +148,16 @@ int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols);
 // Columns handled per partial block pass.
 constexpr int kSketchCols = 16;
 
-// partial[g][c][t] (g < G, c < ncols, t < k), G = sketch_num_partials(sk, n).
+// Sparse sign: bucket Theta's nonzeros by target once per factorization (the
+// "plan"; sparse_plan_bytes of workspace), for rows [row0, row0 + n).
+size_t sparse_plan_bytes(const SketchDesc& sk, int64_t n);
+hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uint16_t* plan,
+                              hipStream_t st);
+// partial[g][c][t] (g < G, c < ncols, t < k), G = sketch_num_partials(sk, n, ncols).
+// `plan` (sparse sign only) must have been built for the same rows.
 hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
-                                  hipStream_t st);
+                                  const uint16_t* plan, hipStream_t st);
 // out[t + c*ldo] = scale * sum_g partial[g][c][t]
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
                                 double scale, double* out, int64_t ldo, hipStream_t st);

@@ -25,7 +25,7 @@ __device__ __forceinline__ double to_f64(T x) {
 constexpr int kSpThreads = 1024;
 constexpr int kSpTile = 256;  // rows per tile
 constexpr int kSpMaxK = 2048;
-constexpr int kSpTPT = kSpMaxK / kSpThreads;
+constexpr int kSpLoads = kSketchCols * kSpTile / kSpThreads;  // prefetched elements per thread
 
 __device__ __forceinline__ void block_exclusive_scan_2048(int* cnt, int* off, int* cur, int k) {
   // Each thread scans two consecutive counters; wave prefix sums via shuffles;
@@ -58,99 +58,166 @@ __device__ __forceinline__ void block_exclusive_scan_2048(int* cnt, int* off, in
   if (i1 < k) { off[i1] = base + a; cur[i1] = base + a; }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
-    const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int64_t row0, int k, int zeta,
-    uint32_t key0, uint32_t key1, int64_t rows_per_wg, double* __restrict__ partial) {
-  __shared__ T xs[kSketchCols * kSpTile];     // [c][rr]
-  __shared__ uint16_t sorted[kSpTile * 8];    // (rr << 1) | sign, bucketed by target
+// Sketch plan: Theta is the same matrix for every sketch of one factorization,
+// so its nonzeros are bucketed once.  For each tile of kSpTile rows the plan
+// holds, sorted by target and, within a target, by row, the entries
+// (row-in-tile << 1) | sign_bit, and the offsets of every target's bucket.
+//   off: [ntiles][k + 1] uint16     ent: [ntiles][kSpTile * zeta] uint16
+__global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int64_t row0, int k,
+                                                                 int zeta, uint32_t key0,
+                                                                 uint32_t key1,
+                                                                 uint16_t* __restrict__ plan_off,
+                                                                 uint16_t* __restrict__ plan_ent) {
+  __shared__ uint16_t sorted[kSpTile * 8];
   __shared__ int cnt[kSpMaxK];
   __shared__ int off[kSpMaxK];
   __shared__ int cur[kSpMaxK];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  const int64_t tile0 = tile * kSpTile;
+  const int trows = (int)min((int64_t)kSpTile, n - tile0);
+  const uint32_t L = (uint32_t)(k / zeta);
+  for (int t = tid; t < k; t += kSpThreads) cnt[t] = 0;
+  __syncthreads();
+  uint32_t tgt[4], ent[4];
+  int nown = 0;
+  if (tid < 2 * kSpTile) {
+    const int rr = tid >> 1, half = tid & 1;
+    if (rr < trows && 4 * half < zeta) {
+      const uint64_t r = (uint64_t)(row0 + tile0 + rr);
+      const u32x4 w = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), (uint32_t)half, kTagSparse,
+                                    key0, key1);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int s = 4 * half + q;
+        if (s < zeta) {
+          tgt[q] = sparse_target(ws[q], (uint32_t)s, L);
+          ent[q] = ((uint32_t)rr << 1) | (ws[q] & 1u);
+          atomicAdd(&cnt[tgt[q]], 1);
+          nown = q + 1;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  block_exclusive_scan_2048(cnt, off, cur, k);
+  __syncthreads();
+  for (int q = 0; q < nown; ++q) {
+    const int pos = atomicAdd(&cur[tgt[q]], 1);
+    sorted[pos] = (uint16_t)ent[q];
+  }
+  __syncthreads();
+  uint16_t* po = plan_off + tile * (k + 1);
+  for (int t = tid; t < k; t += kSpThreads) {
+    const int b = off[t], e = b + cnt[t];
+    // bucket order: increasing row (each row appears once per target)
+    for (int i = b + 1; i < e; ++i) {
+      const uint16_t v = sorted[i];
+      int p = i - 1;
+      while (p >= b && sorted[p] > v) {
+        sorted[p + 1] = sorted[p];
+        --p;
+      }
+      sorted[p + 1] = v;
+    }
+    po[t] = (uint16_t)b;
+  }
+  if (tid == 0) po[k] = (uint16_t)(trows * zeta);
+  __syncthreads();
+  uint16_t* pe = plan_ent + tile * (int64_t)(kSpTile * zeta);
+  for (int i = tid; i < trows * zeta; i += kSpThreads) pe[i] = sorted[i];
+}
+
+// Sparse-sign partial sums from a plan.  A workgroup owns a range of tiles and
+// one group of up to 16 columns; thread t owns targets t (and t + 1024).  Per
+// tile the rows are staged in LDS as FP64 (row-major) and each thread sums its
+// bucket in row order with an exact sign (fma with +-1).  The next tile is
+// prefetched into registers while the current one is summed.
+template <typename T, int TPT>
+__global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
+    const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
+    const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
+    int64_t tiles_per_wg, double* __restrict__ partial) {
+  constexpr int XC = kSketchCols + 1;           // padded row of the staged tile
+  __shared__ double xs[kSpTile * XC];           // [rr][c]
+  __shared__ uint16_t ent[kSpTile * 8];
+  __shared__ uint16_t off[kSpMaxK + 1];
 
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
   const int col0 = blockIdx.y * kSketchCols;
   const int nc = min(kSketchCols, ncols - col0);
-  const int64_t rbeg = (int64_t)g * rows_per_wg;
-  const int64_t rend = min(n, rbeg + rows_per_wg);
-  const uint32_t L = (uint32_t)(k / zeta);
+  const int64_t ntiles = (n + kSpTile - 1) / kSpTile;
+  const int64_t tbeg = (int64_t)g * tiles_per_wg;
+  const int64_t tend = min(ntiles, tbeg + tiles_per_wg);
+  const int E = kSpTile * zeta;
 
-  double acc[kSpTPT][kSketchCols];
+  double acc[TPT][kSketchCols];
 #pragma unroll
-  for (int j = 0; j < kSpTPT; ++j)
+  for (int j = 0; j < TPT; ++j)
 #pragma unroll
     for (int c = 0; c < kSketchCols; ++c) acc[j][c] = 0.0;
 
-  for (int64_t tile0 = rbeg; tile0 < rend; tile0 += kSpTile) {
-    const int trows = (int)min((int64_t)kSpTile, rend - tile0);
-    for (int t = tid; t < k; t += kSpThreads) cnt[t] = 0;
-    for (int e = tid; e < kSketchCols * kSpTile; e += kSpThreads) {
+  T px[kSpLoads];
+  uint16_t pe[8 * kSpTile / kSpThreads];
+  uint16_t po[(kSpMaxK + 1 + kSpThreads - 1) / kSpThreads];
+  auto fetch = [&](int64_t tile) {
+    const int64_t r0 = tile * kSpTile;
+    const int trows = (int)min((int64_t)kSpTile, n - r0);
+#pragma unroll
+    for (int i = 0; i < kSpLoads; ++i) {
+      const int e = tid + i * kSpThreads;
       const int c = e / kSpTile, rr = e % kSpTile;
-      xs[e] = (rr < trows && c < nc) ? X[(tile0 + rr) + (int64_t)(col0 + c) * ldx] : (T)0;
+      px[i] = (rr < trows && c < nc) ? X[(r0 + rr) + (int64_t)(col0 + c) * ldx] : (T)0;
     }
-    __syncthreads();
-    // (row, target) pairs: thread handles row rr = tid/2, segments 4*(tid&1) .. +3
-    uint32_t tgt[4], ent[4];
-    int nown = 0;
-    if (tid < 2 * kSpTile) {
-      const int rr = tid >> 1, half = tid & 1;
-      if (rr < trows && 4 * half < zeta) {
-        const uint64_t r = (uint64_t)(row0 + tile0 + rr);
-        const u32x4 w = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), (uint32_t)half,
-                                      kTagSparse, key0, key1);
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    const uint16_t* se = plan_ent + tile * (int64_t)E;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int s = 4 * half + q;
-          if (s < zeta) {
-            tgt[q] = sparse_target(ws[q], (uint32_t)s, L);
-            ent[q] = ((uint32_t)rr << 1) | (ws[q] & 1u);
-            atomicAdd(&cnt[tgt[q]], 1);
-            nown = q + 1;
-          }
-        }
-      }
+    for (int i = 0; i < 8 * kSpTile / kSpThreads; ++i) {
+      const int e = tid + i * kSpThreads;
+      pe[i] = e < trows * zeta ? se[e] : (uint16_t)0;
     }
-    __syncthreads();
-    block_exclusive_scan_2048(cnt, off, cur, k);
-    __syncthreads();
-    for (int q = 0; q < nown; ++q) {
-      const int pos = atomicAdd(&cur[tgt[q]], 1);
-      sorted[pos] = (uint16_t)ent[q];
+    const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
+#pragma unroll
+    for (int i = 0; i < (kSpMaxK + 1 + kSpThreads - 1) / kSpThreads; ++i) {
+      const int t = tid + i * kSpThreads;
+      po[i] = t <= k ? so[t] : (uint16_t)0;
     }
+  };
+  if (tbeg < tend) fetch(tbeg);
+  for (int64_t tile = tbeg; tile < tend; ++tile) {
+#pragma unroll
+    for (int i = 0; i < kSpLoads; ++i) {
+      const int e = tid + i * kSpThreads;
+      xs[(e % kSpTile) * XC + e / kSpTile] = to_f64(px[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8 * kSpTile / kSpThreads; ++i) ent[tid + i * kSpThreads] = pe[i];
+#pragma unroll
+    for (int i = 0; i < (kSpMaxK + 1 + kSpThreads - 1) / kSpThreads; ++i) {
+      const int t = tid + i * kSpThreads;
+      if (t <= k) off[t] = po[i];
+    }
+    if (tile + 1 < tend) fetch(tile + 1);   // in flight while this tile is summed
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSpTPT; ++j) {
+    for (int j = 0; j < TPT; ++j) {
       const int t = tid + j * kSpThreads;
       if (t < k) {
-        const int b = off[t], e = b + cnt[t];
-        // insertion sort of the bucket by row (each row appears once per target)
-        for (int i = b + 1; i < e; ++i) {
-          const uint16_t v = sorted[i];
-          int p = i - 1;
-          while (p >= b && sorted[p] > v) {
-            sorted[p + 1] = sorted[p];
-            --p;
-          }
-          sorted[p + 1] = v;
-        }
+        const int b = off[t], e = off[t + 1];
         for (int i = b; i < e; ++i) {
-          const uint32_t v = sorted[i];
-          const int rr = (int)(v >> 1);
-          const bool neg = v & 1u;
+          const uint32_t v = ent[i];
+          const double* xr = xs + (v >> 1) * XC;
+          const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-          for (int c = 0; c < kSketchCols; ++c) {
-            const double x = to_f64(xs[c * kSpTile + rr]);
-            acc[j][c] += neg ? -x : x;
-          }
+          for (int c = 0; c < kSketchCols; ++c) acc[j][c] = fma(sg, xr[c], acc[j][c]);
         }
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int j = 0; j < kSpTPT; ++j) {
+  for (int j = 0; j < TPT; ++j) {
     const int t = tid + j * kSpThreads;
     if (t < k) {
 #pragma unroll
@@ -226,15 +293,33 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of the partial sums, scaled once in FP64.
 // ---------------------------------------------------------------------------
-__global__ void sketch_reduce_kernel(const double* __restrict__ partial, int G, int64_t k,
-                                     int64_t ncols, double scale, double* __restrict__ out,
-                                     int64_t ldo) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= k * ncols) return;
+// 8 lanes per output: lane q sums g = q, q+8, ... in order, then the eight
+// partial sums are combined by a fixed butterfly.
+constexpr int kRedLanes = 8;
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __restrict__ partial,
+                                                            int G, int64_t k, int64_t ncols,
+                                                            double scale, double* __restrict__ out,
+                                                            int64_t ldo) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = (int)(gid % kRedLanes);
+  const int64_t idx = gid / kRedLanes;
+  const bool ok = idx < k * ncols;
   const int64_t t = idx % k, c = idx / k;
-  double s = 0.0;
-  for (int g = 0; g < G; ++g) s += partial[((int64_t)g * ncols + c) * k + t];
-  out[t + c * ldo] = scale * s;
+  double s0 = 0.0, s1 = 0.0;
+  if (ok) {
+    const double* p = partial + c * k + t;
+    const int64_t stride = ncols * k;
+    int g = q;
+    for (; g + kRedLanes < G; g += 2 * kRedLanes) {
+      s0 += p[(int64_t)g * stride];
+      s1 += p[(int64_t)(g + kRedLanes) * stride];
+    }
+    if (g < G) s0 += p[(int64_t)g * stride];
+  }
+  double s = s0 + s1;
+#pragma unroll
+  for (int d = 1; d < kRedLanes; d <<= 1) s += __shfl_xor(s, d, 64);
+  if (ok && q == 0) out[t + c * ldo] = scale * s;
 }
 
 template <typename T>
@@ -281,36 +366,59 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols) {
-  // Aim for about 512 workgroups in the grid (two per CU) while keeping each
-  // row range at least one tile long.
+  // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
+  // over the column groups.  Gaussian: about 512 workgroups of 256 threads.
+  // Each row range is at least one tile long.
   const int64_t groups = ceil_div(ncols, kSketchCols);
-  int64_t per = 1;
-  int64_t tile = kSpTile;
+  int64_t G, tile;
   if (sk.kind == kGaussian) {
-    per = ceil_div(sk.k, 256);
+    G = ceil_div(512, groups * ceil_div(sk.k, 256));
     tile = kGaTile;
+  } else {
+    G = ceil_div(256, groups);
+    tile = kSpTile;
   }
-  int64_t G = ceil_div(512, groups * per);
   G = std::min<int64_t>(G, ceil_div(n, tile));
   return (int)std::max<int64_t>(1, G);
 }
 
+size_t sparse_plan_bytes(const SketchDesc& sk, int64_t n) {
+  const int64_t ntiles = ceil_div(n, kSpTile);
+  return (size_t)ntiles * (size_t)(sk.k + 1 + kSpTile * sk.zeta) * sizeof(uint16_t);
+}
+
+hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uint16_t* plan,
+                              hipStream_t st) {
+  const int64_t ntiles = ceil_div(n, kSpTile);
+  uint16_t* off = plan;
+  uint16_t* ent = plan + ntiles * (sk.k + 1);
+  hipLaunchKernelGGL(sparse_plan_kernel, dim3((unsigned)ntiles), dim3(kSpThreads), 0, st, n, row0,
+                     (int)sk.k, sk.zeta, sk.key0, sk.key1, off, ent);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
-                                  hipStream_t st) {
+                                  const uint16_t* plan, hipStream_t st) {
+  const uint16_t* plan_off = plan;
+  const uint16_t* plan_ent = plan ? plan + ceil_div(n, kSpTile) * (sk.k + 1) : nullptr;
   const int G = sketch_num_partials(sk, n, ncols);
   const int64_t groups = ceil_div(ncols, kSketchCols);
   if (sk.kind == kSparse) {
-    const int64_t rpw = ceil_div(ceil_div(n, G), kSpTile) * kSpTile;
+    if (plan_off == nullptr || plan_ent == nullptr) return hipErrorInvalidValue;
+    const int64_t ntiles = ceil_div(n, kSpTile);
+    const int64_t tpw = ceil_div(ntiles, G);
     dim3 grid(G, (unsigned)groups);
-    if (f32)
-      hipLaunchKernelGGL(sketch_sparse_kernel<float>, grid, dim3(kSpThreads), 0, st,
-                         (const float*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
-                         sk.key1, rpw, partial);
-    else
-      hipLaunchKernelGGL(sketch_sparse_kernel<double>, grid, dim3(kSpThreads), 0, st,
-                         (const double*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
-                         sk.key1, rpw, partial);
+    const bool two = sk.k > kSpThreads;
+#define RBGS_SP(T, TPT)                                                                          \
+  hipLaunchKernelGGL((sketch_sparse_kernel<T, TPT>), grid, dim3(kSpThreads), 0, st, (const T*)X, \
+                     ldx, n, (int)ncols, (int)sk.k, sk.zeta, plan_off, plan_ent, tpw, partial)
+    if (f32) {
+      if (two) RBGS_SP(float, 2); else RBGS_SP(float, 1);
+    } else {
+      if (two) RBGS_SP(double, 2); else RBGS_SP(double, 1);
+    }
+#undef RBGS_SP
   } else {
     const int64_t rpw = ceil_div(ceil_div(n, G), kGaTile) * kGaTile;
     dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)groups);
@@ -328,7 +436,7 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
 
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
                                 double scale, double* out, int64_t ldo, hipStream_t st) {
-  const int64_t total = k * ncols;
+  const int64_t total = k * ncols * kRedLanes;
   hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
                      partial, G, k, ncols, scale, out, ldo);
   return hipGetLastError();

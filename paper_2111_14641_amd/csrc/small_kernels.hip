@@ -53,9 +53,17 @@ __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P
   const int64_t c = blockIdx.y;
   if (t >= k) return;
   const double* y = Y + c * ldy;
-  double acc = 0.0;
-  for (int64_t j = 0; j < K; ++j) acc = fma(S[t + j * lds], y[j], acc);
-  E[t + c * lde] = P[t + c * ldp] - acc;
+  // four interleaved partial sums keep several loads in flight
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t j = 0;
+  for (; j + 4 <= K; j += 4) {
+    a0 = fma(S[t + j * lds], y[j], a0);
+    a1 = fma(S[t + (j + 1) * lds], y[j + 1], a1);
+    a2 = fma(S[t + (j + 2) * lds], y[j + 2], a2);
+    a3 = fma(S[t + (j + 3) * lds], y[j + 3], a3);
+  }
+  for (; j < K; ++j) a0 = fma(S[t + j * lds], y[j], a0);
+  E[t + c * lde] = P[t + c * ldp] - ((a0 + a1) + (a2 + a3));
 }
 
 // ---------------------------------------------------------------------------
@@ -71,55 +79,65 @@ __device__ __forceinline__ int qr_chunk_rows(int bw) {
 }
 
 // In-place Householder triangularization of A (rows x bw, column-major, ld
-// rows) in LDS.  For column j: sigma = ||x||^2 with x = A[j:, j]; alpha =
-// -sign(x_0) ||x||; v = x - alpha e_1 (stored over x); every later column is
-// updated as a_c -= (2 / v^T v) (v^T a_c) v with v^T v = 2 ||x|| (||x|| + |x_0|);
-// then A[j][j] = alpha.  On return the upper triangle holds R (a zero column
-// gives R_jj = 0 and no reflection).
+// rows) in LDS.  For column j: x = A[j:, j], alpha = -sign(x_0) ||x||,
+// v = x - alpha e_1, and every later column is updated as
+// a_c -= beta (v^T a_c) v with beta = 2 / (v^T v) = 1 / (||x|| (||x|| + |x_0|)).
+// All dots d_c = x^T a_c (c >= j; d_j = ||x||^2) come from one reduction pass:
+// thread (c, g) sums rows g, g + NG, g + 2 NG, ... of column c and the NG
+// threads of a column reduce by shuffles; then v^T a_c = d_c + (v_0 - x_0) a_jc.
+// On return the upper triangle holds R (a zero column gives R_jj = 0 and no
+// reflection).
+template <int BWP>
 __device__ void householder_lds(double* A, int rows, int bw, double* red /* [kQrMaxB+1] */) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double alpha_s, beta_s;
+  constexpr int NG = (kQrThreads / BWP) < 64 ? (kQrThreads / BWP) : 64;  // threads per column
+  const int tid = threadIdx.x;
+  const int c = tid / NG, g = tid % NG;
+  const bool active = tid < BWP * NG;
+  __shared__ double sc[4];  // alpha, beta, v0 - x0, flag
   for (int j = 0; j < bw && j < rows; ++j) {
-    if (wave == 0) {
-      double acc = 0.0;
-      for (int r = j + lane; r < rows; r += 64) acc = fma(A[r + j * rows], A[r + j * rows], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        const double x0 = A[j + j * rows];
-        if (acc == 0.0) {
-          alpha_s = 0.0;
-          beta_s = 0.0;
-        } else {
-          const double nrm = sqrt(acc);
-          const double alpha = x0 >= 0.0 ? -nrm : nrm;
-          alpha_s = alpha;
-          beta_s = 2.0 / (2.0 * nrm * (nrm + fabs(x0)));
-          A[j + j * rows] = x0 - alpha;  // v_0
-        }
+    double d = 0.0;
+    if (active && c >= j && c < bw) {
+      const double* aj = A + j * rows;
+      const double* ac = A + c * rows;
+      for (int r = j + g; r < rows; r += NG) d = fma(aj[r], ac[r], d);
+    }
+#pragma unroll
+    for (int o = 1; o < NG; o <<= 1) d += __shfl_xor(d, o, 64);
+    if (active && g == 0 && c < bw) red[c] = d;
+    // a_jc for this thread's column, read before any thread updates column c
+    const double ajc = (active && c > j && c < bw) ? A[j + c * rows] : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      const double sigma = red[j];
+      const double x0 = A[j + j * rows];
+      if (sigma == 0.0) {
+        sc[0] = 0.0;
+        sc[1] = 0.0;
+        sc[2] = 0.0;
+      } else {
+        const double nrm = sqrt(sigma);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        sc[0] = alpha;
+        sc[1] = 1.0 / (nrm * (nrm + fabs(x0)));
+        sc[2] = -alpha;  // v0 - x0
+        A[j + j * rows] = x0 - alpha;  // v_0
       }
     }
     __syncthreads();
-    const double beta = beta_s;
-    if (beta != 0.0) {
-      for (int c = j + 1 + wave; c < bw; c += 4) {
-        double acc = 0.0;
-        for (int r = j + lane; r < rows; r += 64) acc = fma(A[r + j * rows], A[r + c * rows], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) red[c] = beta * acc;
-      }
-      __syncthreads();
-      const int ncols = bw - j - 1;
-      const int nrows = rows - j;
-      for (int e = tid; e < ncols * nrows; e += kQrThreads) {
-        const int c = j + 1 + e / nrows;
-        const int r = j + e % nrows;
-        A[r + c * rows] = fma(-red[c], A[r + j * rows], A[r + c * rows]);
-      }
-      __syncthreads();
+    const double beta = sc[1];
+    if (beta != 0.0 && active && c > j && c < bw) {
+      // w_c = v^T a_c = d_c + (v0 - x0) a_jc
+      double* ac = A + c * rows;
+      const double* v = A + j * rows;
+      const double w = beta * (red[c] + sc[2] * ajc);
+      for (int r = j + g; r < rows; r += NG) ac[r] = fma(-w, v[r], ac[r]);
     }
-    if (tid == 0) A[j + j * rows] = alpha_s;
     __syncthreads();
+    if (tid == 0) A[j + j * rows] = sc[0];
+    // (the next iteration's reads of column j+1 start after the barrier above;
+    //  A[j][j] is not read again in this factorization)
   }
+  __syncthreads();
 }
 
 // One level of the tree: chunk b of `src` (rows_in x bw, ld ld_in) -> its R
@@ -142,7 +160,10 @@ __global__ __launch_bounds__(kQrThreads) void qr_level_kernel(const double* __re
     A[r + c * rows_p] = r < rows ? src[(r0 + r) + c * ld_in] : 0.0;
   }
   __syncthreads();
-  householder_lds(A, rows_p, bw, red);
+  if (bw <= 4) householder_lds<4>(A, rows_p, bw, red);
+  else if (bw <= 8) householder_lds<8>(A, rows_p, bw, red);
+  else if (bw <= 16) householder_lds<16>(A, rows_p, bw, red);
+  else householder_lds<32>(A, rows_p, bw, red);
   if (!final) {
     for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
       const int r = e % bw, c = e / bw;

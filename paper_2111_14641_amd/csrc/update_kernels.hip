@@ -21,7 +21,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kUpThreads = 256;
-constexpr int kKC = 64;       // rows of R per LDS chunk
+constexpr int kKC = 128;      // rows of R per LDS chunk
 constexpr int kUnroll = 8;    // K-steps whose loads are issued together
 constexpr int kMaxB = 32;
 
@@ -62,17 +62,18 @@ struct Vec16<double> {
   typedef f64x2 t;
 };
 
-// Forward substitution of one row: x R = q', R upper triangular (bw x bw) in
-// LDS (column-major, ld kMaxB).  FP64 arithmetic.
+// Forward substitution of one row: x R = q', R upper triangular (bw x bw,
+// bw <= NC) in LDS (column-major, ld NC).  FP64 arithmetic.
+template <int NC>
 __device__ __forceinline__ void row_substitute(double* x, const double* Rs, int bw) {
 #pragma unroll
-  for (int c = 0; c < kMaxB; ++c) {
+  for (int c = 0; c < NC; ++c) {
     if (c < bw) {
       double s = x[c];
 #pragma unroll
-      for (int l = 0; l < kMaxB; ++l)
-        if (l < c) s = fma(-x[l], Rs[l + c * kMaxB], s);
-      x[c] = s / Rs[c + c * kMaxB];
+      for (int l = 0; l < NC; ++l)
+        if (l < c) s = fma(-x[l], Rs[l + c * NC], s);
+      x[c] = s / Rs[c + c * NC];
     }
   }
 }
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
   constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(C);
   constexpr int U_BYTES = RS_BYTES > CT_BYTES ? RS_BYTES : CT_BYTES;
   __shared__ __attribute__((aligned(16))) unsigned char ubuf_raw[U_BYTES];  // R chunk, then product slab
-  __shared__ double Rd[kMaxB * kMaxB];                                        // R_(i,i)
+  __shared__ double Rd[NCOL * NCOL];                                          // R_(i,i)
   C* ubuf = reinterpret_cast<C*>(ubuf_raw);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -104,8 +105,8 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
   const bool afull = vec_ok && (arow + VEC <= n);
 
   if (Rii != nullptr) {
-    for (int e = threadIdx.x; e < kMaxB * kMaxB; e += kUpThreads) {
-      const int r = e % kMaxB, c = e / kMaxB;
+    for (int e = threadIdx.x; e < NCOL * NCOL; e += kUpThreads) {
+      const int r = e % NCOL, c = e / NCOL;
       Rd[e] = (r < bw && c < bw) ? Rii[r + (int64_t)c * ldr] : (r == c ? 1.0 : 0.0);
     }
   }
@@ -116,6 +117,37 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[v][nb] = (typename M::acc_t){0, 0, 0, 0};
 
+  // A operand group: kUnroll K-steps of 4 columns, one 16-byte load per step.
+  auto load_group = [&](T (&a)[kUnroll][VEC], int kc0, int kc, int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int col = kc0 + ks0 + 4 * u + kk;
+      const bool colok = (ks0 + 4 * u + kk) < kc;
+      const T* src = Q + arow + (int64_t)col * ldq;
+      if (colok && afull) {
+        typename Vec16<T>::t vv = *reinterpret_cast<const typename Vec16<T>::t*>(src);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[u][v] = vv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[u][v] = (colok && arow + v < n) ? src[v] : (T)0;
+      }
+    }
+  };
+  auto mma_group = [&](const T (&a)[kUnroll][VEC], int kc, int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ks0 + 4 * u < kc) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const C b = ubuf[(ks0 + 4 * u + kk) * NCOL + nb * 16 + li];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma((C)a[u][v], b, acc[v][nb]);
+        }
+      }
+    }
+  };
+
   for (int kc0 = 0; kc0 < K; kc0 += kKC) {
     const int kc = min(kKC, K - kc0);
     __syncthreads();
@@ -124,32 +156,16 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
       ubuf[e] = (r < kc && c < bw) ? (C)Rk[(kc0 + r) + (int64_t)c * ldr] : (C)0;
     }
     __syncthreads();
-    for (int ks0 = 0; ks0 < kc; ks0 += 4 * kUnroll) {
-      T a[kUnroll][VEC];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int col = kc0 + ks0 + 4 * u + kk;
-        const bool colok = (ks0 + 4 * u + kk) < kc;
-        const T* src = Q + arow + (int64_t)col * ldq;
-        if (colok && afull) {
-          typename Vec16<T>::t vv = *reinterpret_cast<const typename Vec16<T>::t*>(src);
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) a[u][v] = vv[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) a[u][v] = (colok && arow + v < n) ? src[v] : (T)0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        if (ks0 + 4 * u < kc) {
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const C b = ubuf[(ks0 + 4 * u + kk) * NCOL + nb * 16 + li];
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma((C)a[u][v], b, acc[v][nb]);
-          }
-        }
+    // ping-pong: the loads of group g+1 are in flight during the products of group g
+    constexpr int GS = 4 * kUnroll;
+    T a0[kUnroll][VEC], a1[kUnroll][VEC];
+    load_group(a0, kc0, kc, 0);
+    for (int ks0 = 0; ks0 < kc; ks0 += 2 * GS) {
+      if (ks0 + GS < kc) load_group(a1, kc0, kc, ks0 + GS);
+      mma_group(a0, kc, ks0);
+      if (ks0 + GS < kc) {
+        if (ks0 + 2 * GS < kc) load_group(a0, kc0, kc, ks0 + 2 * GS);
+        mma_group(a1, kc, ks0 + GS);
       }
     }
   }
@@ -158,9 +174,9 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
   C* ct = ubuf + wave * WROWS * CT_LD;
   const int64_t row = wrow0 + lane;
   const bool own = lane < WROWS && row < n;
-  double x[kMaxB];
+  double x[NCOL];
 #pragma unroll
-  for (int c = 0; c < kMaxB; ++c) x[c] = 0.0;
+  for (int c = 0; c < NCOL; ++c) x[c] = 0.0;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     __syncthreads();
@@ -182,9 +198,9 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
     }
   }
   if (own) {
-    if (Rii != nullptr) row_substitute(x, Rd, bw);
+    if (Rii != nullptr) row_substitute<NCOL>(x, Rd, bw);
 #pragma unroll
-    for (int c = 0; c < kMaxB; ++c)
+    for (int c = 0; c < NCOL; ++c)
       if (c < bw) Qout[row + (int64_t)c * ldqo] = (T)x[c];
   }
 }
@@ -205,7 +221,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t l
   double x[kMaxB];
 #pragma unroll
   for (int c = 0; c < kMaxB; ++c) x[c] = c < bw ? (double)Qb[row + (int64_t)c * ldq] : 0.0;
-  row_substitute(x, Rd, bw);
+  row_substitute<kMaxB>(x, Rd, bw);
 #pragma unroll
   for (int c = 0; c < kMaxB; ++c)
     if (c < bw) Qb[row + (int64_t)c * ldq] = (T)x[c];
