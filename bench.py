@@ -198,7 +198,8 @@ def main():
                                "low-sync RBGS, FP32 storage with FP64 arithmetic",
                    "n": n, "m": m, "p": p, "k": k, "parallelism": "single GPU"},
         "speedup_f32_vs_f64": None if speedup is None else round(speedup, 3),
-        "forms": {name: {kk: (round(v, 6) if isinstance(v, float) else v) for kk, v in f.items()}
+        "forms": {name: {kk: (float(f"{v:.4g}") if isinstance(v, float) else v)
+                         for kk, v in f.items()}
                   for name, f in forms.items()},
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,

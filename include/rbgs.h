@@ -35,6 +35,11 @@
 extern "C" {
 #endif
 
+/* Exported entry points (the library is built with hidden default visibility). */
+#ifndef RBGS_API
+#define RBGS_API __attribute__((visibility("default")))
+#endif
+
 typedef struct rbgs_handle_s* rbgs_handle;
 
 typedef enum {
@@ -116,11 +121,11 @@ typedef struct {
 /* Create a handle bound to HIP device `device`.  No device memory is touched
  * until the first computing call.  Returns RBGS_EINVAL if h is NULL or device
  * is negative. */
-rbgs_status rbgs_create(rbgs_handle* h, int device);
+RBGS_API rbgs_status rbgs_create(rbgs_handle* h, int device);
 
 /* Free the handle's workspace (after waiting for its streams) and the handle.
  * A NULL handle is accepted. */
-rbgs_status rbgs_destroy(rbgs_handle h);
+RBGS_API rbgs_status rbgs_destroy(rbgs_handle h);
 
 /* RBGS QR factorization (Algorithm RBGS of Section 2).
  *   W    device, n x m (ld ldw >= n), element type opts->store; read only
@@ -140,7 +145,7 @@ rbgs_status rbgs_destroy(rbgs_handle h);
  *        valid up to the preceding block).  Without cert the call does not
  *        wait and a breakdown shows up as non-finite entries of Q.
  */
-rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
+RBGS_API rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
                     const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
                     double* R, int64_t ldr, double* S_out, rbgs_cert* cert);
 
@@ -151,7 +156,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
  *   row0 global row index of the first row of X (Theta's columns are indexed
  *        by global rows, so sketches of row ranges add up to the full sketch).
  * Enqueued on `stream`. */
-rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t store, const void* X,
+RBGS_API rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t store, const void* X,
                               int64_t ldx, int64_t n, int64_t c, int64_t row0, double* out,
                               int64_t ldo, void* stream);
 
@@ -160,7 +165,7 @@ rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t stor
  * (sparse sign, +-1 or 0) or I[t][r] (identity) for t < k, row0 <= r < row0+n.
  *   out device, k x n float (ld k), overwritten.  Theta = scale * out with
  *   scale = 1/sqrt(k) (Gaussian), 1/sqrt(zeta) (sparse sign), 1 (identity). */
-rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
+RBGS_API rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
                              float* out, void* stream);
 
 /* Kernel timing for measurements.  With profiling enabled, the handle records
@@ -173,13 +178,13 @@ rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, in
  *   which: 0 = update (steps 3 [+5 fused]), 1 = sketch partial products,
  *          2 = sketch reduction, 3 = small FP64 factors, 4 = substitution
  *          (plain variant). */
-rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable);
-rbgs_status rbgs_profile_get(rbgs_handle h, int32_t which, double* ms, int64_t* launches,
+RBGS_API rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable);
+RBGS_API rbgs_status rbgs_profile_get(rbgs_handle h, int32_t which, double* ms, int64_t* launches,
                              double* bytes);
 
-const char* rbgs_status_string(rbgs_status s);
+RBGS_API const char* rbgs_status_string(rbgs_status s);
 /* Text of the last error detected on this handle ("" if none). */
-const char* rbgs_last_error(rbgs_handle h);
+RBGS_API const char* rbgs_last_error(rbgs_handle h);
 
 #ifdef __cplusplus
 }

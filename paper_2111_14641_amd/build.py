@@ -21,7 +21,7 @@ SOURCES = ["rbgs_api.hip", "sketch_kernels.hip", "update_kernels.hip", "small_ke
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-fvisibility=hidden",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

@@ -308,6 +308,10 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   const size_t o_stack = carve(qr_stack_size(k, b));
   const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
+  const size_t o_cnt = carve(1);
+  const size_t o_G = carve((size_t)m * m);   // Gram matrix S^T S of the blocks done
+  const size_t o_C = carve((size_t)m * b);   // c = S^T P_(i)
+  const size_t o_Y = carve((size_t)m * b);   // Richardson iterate
   const size_t o_cs = carve(cert_scratch_size(k, m));
   const size_t o_cout = carve(4);
   rbgs_status rs = ensure_ws(h, off);
@@ -320,11 +324,16 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   double* stack = (double*)(base + o_stack);
   uint16_t* plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
   int64_t* flag = (int64_t*)(base + o_flag);
+  unsigned* counters = (unsigned*)(base + o_cnt);  // [1]: QR tree arrivals
+  double* G = (double*)(base + o_G);
+  double* Cb = (double*)(base + o_C);
+  double* Yb = (double*)(base + o_Y);
   double* cscratch = (double*)(base + o_cs);
   double* cout = (double*)(base + o_cout);
 
   HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
   HIP_TRY(h, launch_set_i64(flag, -1, st), "flag");
+  HIP_TRY(h, launch_set_u32(counters, 2, 0u, st), "counters");
   if (plan) {
     ProfScope ps(h, kProfSketch, 0.0, st);
     HIP_TRY(h, launch_sparse_plan(d, n, 0, plan, st), "sketch plan");
@@ -348,12 +357,30 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
     void* Qi = Qb + es * (size_t)(c0 * ldq);
 
     // ---- step 2: sketched least squares by l Richardson sweeps ----------
+    // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
+    // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.
     if (K > 0) {
       ProfScope ps(h, kProfSmall, 0.0, st);
-      HIP_TRY(h, launch_sty(S, k, Pi, k, Rk, ldr, k, K, bw, false, st), "richardson");
+      const int bprev = b;  // width of block i-1 (only the last block can be narrower)
+      const double* Sprev = S + (K - bprev) * k;
+      double* Ccol = (l > 1) ? Cb : Rk;
+      const int64_t ldc = (l > 1) ? K : ldr;
+      HIP_TRY(h, launch_gram_sty(S, k, K, Pi, bw, Sprev, bprev, Ccol, ldc, G + (K - bprev) * m, m,
+                                 G + (K - bprev), m, st),
+              "least squares: sketch products");
+      // sweeps: Y_1 = c, Y_{s+1} = Y_s + c - G Y_s.  Targets alternate between
+      // R_(1:i-1,i) and Yb so that the last sweep lands in R and no sweep
+      // writes its own input.
+      const double* Ycur = Cb;
+      int64_t ldycur = K;
       for (int it = 1; it < l; ++it) {
-        HIP_TRY(h, launch_resid(Pi, k, S, k, Rk, ldr, E, k, k, K, bw, st), "richardson");
-        HIP_TRY(h, launch_sty(S, k, E, k, Rk, ldr, k, K, bw, true, st), "richardson");
+        const bool toR = ((l - 1 - it) & 1) == 0;
+        double* Ynext = toR ? Rk : Yb;
+        const int64_t ldn = toR ? ldr : K;
+        HIP_TRY(h, launch_gram_sweep(G, m, K, Cb, Ycur, ldycur, Ynext, ldn, bw, st),
+                "least squares: sweep");
+        Ycur = Ynext;
+        ldycur = ldn;
       }
     }
     const double ub = (double)es * (double)n * (double)(K + 2 * bw);
@@ -363,10 +390,11 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
         ProfScope ps(h, kProfSmall, 0.0, st);
         const double* Sp = Pi;
         if (K > 0) {
-          HIP_TRY(h, launch_resid(Pi, k, S, k, Rk, ldr, E, k, k, K, bw, st), "S'");
+          HIP_TRY(h, launch_resid(Pi, S, k, K, Rk, ldr, E, bw, st), "S'");
           Sp = E;
         }
-        HIP_TRY(h, launch_qr_r(Sp, k, k, bw, Rii, ldr, stack, flag, c0, st), "qr of sketch");
+        HIP_TRY(h, launch_qr_fused(Sp, k, bw, stack, counters + 1, Rii, ldr, flag, c0, st),
+                "qr of sketch");
       }
       // ---- step 3 + substitution in one pass --------------------------
       {
@@ -386,7 +414,8 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
       if (rs != RBGS_OK) return rs;
       {
         ProfScope ps(h, kProfSmall, 0.0, st);
-        HIP_TRY(h, launch_qr_r(E, k, k, bw, Rii, ldr, stack, flag, c0, st), "qr of sketch");
+        HIP_TRY(h, launch_qr_fused(E, k, bw, stack, counters + 1, Rii, ldr, flag, c0, st),
+                "qr of sketch");
       }
       {
         ProfScope ps(h, kProfTrsm, 2.0 * es * n * bw, st);

@@ -180,21 +180,29 @@ hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, co
 hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_t ldr, int64_t n,
                        int bw, hipStream_t st);
 
-// Small FP64 factors (Section 2.1, 2.2).
-// Y (K x bw, ld ldy) (+)= S^T E,  S: k x K (ld lds), E: k x bw (ld lde)
-hipError_t launch_sty(const double* S, int64_t lds, const double* E, int64_t lde, double* Y,
-                      int64_t ldy, int64_t k, int64_t K, int bw, bool accumulate, hipStream_t st);
-// E = P - S Y   (k x bw)
-hipError_t launch_resid(const double* P, int64_t ldp, const double* S, int64_t lds,
-                        const double* Y, int64_t ldy, double* E, int64_t lde, int64_t k, int64_t K,
-                        int bw, hipStream_t st);
-// R (bw x bw, ld ldr) = positive-diagonal R factor of the Householder QR of
-// A (k x bw, ld lda).  `stack` is workspace of qr_stack_size(k, bw) doubles.
-// Sets flag[0] = first breakdown column (global index col0 + j) if a diagonal
-// entry is zero or not finite and flag[0] is still -1.
+// Small FP64 factors (Sections 2.1 and 2.2).  Workspace for the QR tree of a k x bw matrix.
 size_t qr_stack_size(int64_t k, int bw);
-hipError_t launch_qr_r(const double* A, int64_t lda, int64_t k, int bw, double* R, int64_t ldr,
-                       double* stack, int64_t* flag, int64_t col0, hipStream_t st);
+// out0 (K x n0, ld ldo0) = S^T X0, out1 (K x n1, ld ldo1) = S^T X1 and, if
+// out1t is not null, out1t (n1 x K, ld ldo1t) = (S^T X1)^T.  S: k x K (ld k);
+// X0, X1: k x n0, k x n1 (ld k).
+hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* X0, int n0,
+                           const double* X1, int n1, double* out0, int64_t ldo0, double* out1,
+                           int64_t ldo1, double* out1t, int64_t ldo1t, hipStream_t st);
+// One Richardson sweep in Gram form: Ynew = Y + C - G Y (G: K x K, ld ldg;
+// C: K x bw, ld K).  Ynew must not alias Y.
+hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const double* C,
+                             const double* Y, int64_t ldy, double* Ynew, int64_t ldyn, int bw,
+                             hipStream_t st);
+// E = P - S Y (k x bw, ld k; S: k x K, ld k; Y: K x bw, ld ldy).
+hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
+                        int64_t ldy, double* E, int bw, hipStream_t st);
+// R_(i,i) (positive diagonal) of src (k x bw, ld k) in one launch (tree of
+// Householder QRs; *counter must be 0 and is left at 0; stack:
+// qr_stack_size(k, bw) doubles; flag[0] is set to the first column col0 + j whose
+// diagonal entry is zero or not finite, if it is still -1).
+hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
+                           double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st);
+hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 // Fill an m x m column-major matrix (ld) with zeros.
 hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);

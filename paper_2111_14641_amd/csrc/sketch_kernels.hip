@@ -162,6 +162,8 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
   T px[kSpLoads];
   uint16_t pe[8 * kSpTile / kSpThreads];
   uint16_t po[(kSpMaxK + 1 + kSpThreads - 1) / kSpThreads];
+  // All loads are unconditional (indices clamped into range, values masked
+  // afterwards), so none of them waits on a branch.
   auto fetch = [&](int64_t tile) {
     const int64_t r0 = tile * kSpTile;
     const int trows = (int)min((int64_t)kSpTile, n - r0);
@@ -169,19 +171,24 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
     for (int i = 0; i < kSpLoads; ++i) {
       const int e = tid + i * kSpThreads;
       const int c = e / kSpTile, rr = e % kSpTile;
-      px[i] = (rr < trows && c < nc) ? X[(r0 + rr) + (int64_t)(col0 + c) * ldx] : (T)0;
+      const bool in = rr < trows && c < nc;
+      const T v = X[(r0 + (rr < trows ? rr : trows - 1)) + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+      px[i] = in ? v : (T)0;
     }
     const uint16_t* se = plan_ent + tile * (int64_t)E;
+    const int ne = trows * zeta;
 #pragma unroll
     for (int i = 0; i < 8 * kSpTile / kSpThreads; ++i) {
       const int e = tid + i * kSpThreads;
-      pe[i] = e < trows * zeta ? se[e] : (uint16_t)0;
+      const uint16_t v = se[e < ne ? e : ne - 1];
+      pe[i] = e < ne ? v : (uint16_t)0;
     }
     const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
 #pragma unroll
     for (int i = 0; i < (kSpMaxK + 1 + kSpThreads - 1) / kSpThreads; ++i) {
       const int t = tid + i * kSpThreads;
-      po[i] = t <= k ? so[t] : (uint16_t)0;
+      const uint16_t v = so[t <= k ? t : k];
+      po[i] = t <= k ? v : (uint16_t)0;
     }
   };
   if (tbeg < tend) fetch(tbeg);

@@ -23,49 +23,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Y[j + c ldy] (+)= sum_t S[t + j lds] E[t + c lde]; one wave per (j, c).
-__global__ __launch_bounds__(256) void sty_kernel(const double* __restrict__ S, int64_t lds,
-                                                  const double* __restrict__ E, int64_t lde,
-                                                  double* __restrict__ Y, int64_t ldy, int64_t k,
-                                                  int64_t K, int bw, int accumulate) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= K * bw) return;
-  const int64_t j = w % K, c = w / K;
-  const double* s = S + j * lds;
-  const double* e = E + c * lde;
-  double acc = 0.0;
-  for (int64_t t = lane; t < k; t += 64) acc = fma(s[t], e[t], acc);
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    double* y = Y + j + c * ldy;
-    *y = accumulate ? *y + acc : acc;
-  }
-}
-
-// E[t + c lde] = P[t + c ldp] - sum_{j<K} S[t + j lds] Y[j + c ldy]
-__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P, int64_t ldp,
-                                                    const double* __restrict__ S, int64_t lds,
-                                                    const double* __restrict__ Y, int64_t ldy,
-                                                    double* __restrict__ E, int64_t lde, int64_t k,
-                                                    int64_t K) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (t >= k) return;
-  const double* y = Y + c * ldy;
-  // four interleaved partial sums keep several loads in flight
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t j = 0;
-  for (; j + 4 <= K; j += 4) {
-    a0 = fma(S[t + j * lds], y[j], a0);
-    a1 = fma(S[t + (j + 1) * lds], y[j + 1], a1);
-    a2 = fma(S[t + (j + 2) * lds], y[j + 2], a2);
-    a3 = fma(S[t + (j + 3) * lds], y[j + 3], a3);
-  }
-  for (; j < K; ++j) a0 = fma(S[t + j * lds], y[j], a0);
-  E[t + c * lde] = P[t + c * ldp] - ((a0 + a1) + (a2 + a3));
-}
-
 // ---------------------------------------------------------------------------
 // Householder QR of a chunk held in LDS.
 // ---------------------------------------------------------------------------
@@ -140,24 +97,34 @@ __device__ void householder_lds(double* A, int rows, int bw, double* red /* [kQr
   __syncthreads();
 }
 
-// One level of the tree: chunk b of `src` (rows_in x bw, ld ld_in) -> its R
-// factor (bw x bw) written at rows [b*bw, b*bw+bw) of `dst` (ld ld_out).  When
+// One chunk of one level of the tree: chunk b of `src` (rows_in x bw, ld ld_in)
+// -> its R factor (bw x bw) at rows [b*bw, b*bw+bw) of `dst` (ld ld_out).  With
 // final != 0 there is one chunk and R goes to the output with a positive
-// diagonal, zeros below it, and a breakdown check.
-__global__ __launch_bounds__(kQrThreads) void qr_level_kernel(const double* __restrict__ src,
-                                                              int64_t ld_in, int64_t rows_in,
-                                                              int bw, double* __restrict__ dst,
-                                                              int64_t ld_out, int final,
-                                                              int64_t* flag, int64_t col0) {
-  __shared__ double A[kQrLds];
-  __shared__ double red[kQrMaxB + 1];
+// diagonal, zeros below it, and a breakdown check.  A: kQrLds doubles of LDS.
+__device__ void qr_chunk(const double* __restrict__ src, int64_t ld_in, int64_t rows_in, int bw,
+                         double* __restrict__ dst, int64_t ld_out, int final, int64_t* flag,
+                         int64_t col0, int64_t b, double* A, double* red) {
   const int CH = qr_chunk_rows(bw);
-  const int64_t r0 = (int64_t)blockIdx.x * CH;
+  const int64_t r0 = b * CH;
   const int rows = (int)min((int64_t)CH, rows_in - r0);
   const int rows_p = max(rows, bw);  // pad short chunks with zero rows
-  for (int e = threadIdx.x; e < rows_p * bw; e += kQrThreads) {
+  // element e = r + c rows_p of the padded chunk; every load is issued before
+  // the first is used (clamped index, then select)
+  constexpr int PER = kQrLds / kQrThreads;
+  const int tot = rows_p * bw;
+  double v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * kQrThreads;
     const int r = e % rows_p, c = e / rows_p;
-    A[r + c * rows_p] = r < rows ? src[(r0 + r) + c * ld_in] : 0.0;
+    const bool ok = e < tot && r < rows;
+    const double x = src[ok ? (r0 + r) + c * ld_in : 0];
+    v[i] = ok ? x : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * kQrThreads;
+    if (e < tot) A[e] = v[i];
   }
   __syncthreads();
   if (bw <= 4) householder_lds<4>(A, rows_p, bw, red);
@@ -167,26 +134,27 @@ __global__ __launch_bounds__(kQrThreads) void qr_level_kernel(const double* __re
   if (!final) {
     for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
       const int r = e % bw, c = e / bw;
-      dst[((int64_t)blockIdx.x * bw + r) + c * ld_out] = r <= c ? A[r + c * rows_p] : 0.0;
+      dst[(b * bw + r) + c * ld_out] = r <= c ? A[r + c * rows_p] : 0.0;
     }
-    return;
-  }
-  for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
-    const int r = e % bw, c = e / bw;
-    const double d = A[r + r * rows_p];
-    const double sgn = d < 0.0 ? -1.0 : 1.0;
-    dst[r + c * ld_out] = r <= c ? sgn * A[r + c * rows_p] : 0.0;
-  }
-  if (threadIdx.x == 0 && flag != nullptr) {
-    for (int j = 0; j < bw; ++j) {
-      const double d = A[j + j * rows_p];
-      if (!(d != 0.0) || !isfinite(d)) {
-        atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
-                  (unsigned long long)(col0 + j));
-        break;
+  } else {
+    for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
+      const int r = e % bw, c = e / bw;
+      const double d = A[r + r * rows_p];
+      const double sgn = d < 0.0 ? -1.0 : 1.0;
+      dst[r + c * ld_out] = r <= c ? sgn * A[r + c * rows_p] : 0.0;
+    }
+    if (threadIdx.x == 0 && flag != nullptr) {
+      for (int j = 0; j < bw; ++j) {
+        const double d = A[j + j * rows_p];
+        if (!(d != 0.0) || !isfinite(d)) {
+          atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
+                    (unsigned long long)(col0 + j));
+          break;
+        }
       }
     }
   }
+  __syncthreads();
 }
 
 size_t qr_stack_size(int64_t k, int bw) {
@@ -198,28 +166,6 @@ size_t qr_stack_size(int64_t k, int bw) {
     rows = nch * bw;
   }
   return (size_t)total * bw + 1;
-}
-
-hipError_t launch_qr_r(const double* A, int64_t lda, int64_t k, int bw, double* R, int64_t ldr,
-                       double* stack, int64_t* flag, int64_t col0, hipStream_t st) {
-  if (bw > kQrMaxB) return hipErrorInvalidValue;
-  const int64_t CH = kQrLds / bw;
-  const double* src = A;
-  int64_t ld_in = lda, rows = k;
-  double* buf = stack;
-  while (rows > CH) {
-    const int64_t nch = ceil_div(rows, CH);
-    const int64_t out_rows = nch * bw;
-    hipLaunchKernelGGL(qr_level_kernel, dim3((unsigned)nch), dim3(kQrThreads), 0, st, src, ld_in,
-                       rows, bw, buf, out_rows, 0, (int64_t*)nullptr, (int64_t)0);
-    src = buf;
-    ld_in = out_rows;
-    rows = out_rows;
-    buf += out_rows * bw;
-  }
-  hipLaunchKernelGGL(qr_level_kernel, dim3(1), dim3(kQrThreads), 0, st, src, ld_in, rows, bw, R,
-                     ldr, 1, flag, col0);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -241,26 +187,213 @@ hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStr
   return hipGetLastError();
 }
 
+__global__ void set_u32_kernel(unsigned* p, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
+  hipLaunchKernelGGL(set_u32_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
   hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, st, p, v);
   return hipGetLastError();
 }
 
-hipError_t launch_sty(const double* S, int64_t lds, const double* E, int64_t lde, double* Y,
-                      int64_t ldy, int64_t k, int64_t K, int bw, bool accumulate,
-                      hipStream_t st) {
-  const int64_t waves = K * bw;
-  if (waves == 0) return hipSuccess;
-  hipLaunchKernelGGL(sty_kernel, dim3((unsigned)ceil_div(waves, 4)), dim3(256), 0, st, S, lds, E,
-                     lde, Y, ldy, k, K, bw, accumulate ? 1 : 0);
+// ---------------------------------------------------------------------------
+// Least squares of step 2 by Richardson sweeps (supplement SM.1),
+//   Y_1 = S^T P,   Y_{s+1} = Y_s + S^T (P - S Y_s) = Y_s + c - G Y_s,
+// with c = S^T P and the Gram matrix G = S^T S of the sketch.  G is kept up to
+// date block by block, so one pass over the k x K sketch per block gives both c
+// and the new block column of G, and every further sweep only touches the
+// K x K Gram matrix.  (Same iterates as the residual form in exact arithmetic;
+// the limiting accuracy, u cond(S)^2, equals u up to the small factor
+// (1 + Delta)^2 because S is nearly orthonormal.)
+// ---------------------------------------------------------------------------
+
+// out0[j][c] = sum_t S[t][j] X0[t][c] (c < n0), out1[j][c] = sum_t S[t][j] X1[t][c]
+// (c < n1), j < K.  16 lanes per output (t strided by 16), shuffle reduction.
+__global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict__ S, int64_t k,
+                                                       int64_t K, const double* __restrict__ X0,
+                                                       int n0, const double* __restrict__ X1,
+                                                       int n1, double* __restrict__ out0,
+                                                       int64_t ldo0, double* __restrict__ out1,
+                                                       int64_t ldo1, double* __restrict__ out1t,
+                                                       int64_t ldo1t) {
+  const int q = threadIdx.x & 15;
+  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;  // output index
+  const int ncol = n0 + n1;
+  const bool ok = o < K * ncol;
+  const int64_t j = ok ? o % K : 0;
+  const int col = ok ? (int)(o / K) : 0;
+  const double* x = col < n0 ? X0 + (int64_t)col * k : X1 + (int64_t)(col - n0) * k;
+  const double* sj = S + j * k;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t t = q;
+  for (; t + 48 < k; t += 64) {
+    a0 = fma(sj[t], x[t], a0);
+    a1 = fma(sj[t + 16], x[t + 16], a1);
+    a2 = fma(sj[t + 32], x[t + 32], a2);
+    a3 = fma(sj[t + 48], x[t + 48], a3);
+  }
+  for (; t < k; t += 16) a0 = fma(sj[t], x[t], a0);
+  double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) v += __shfl_xor(v, d, 64);
+  if (ok && q == 0) {
+    if (col < n0) {
+      out0[j + (int64_t)col * ldo0] = v;
+    } else {
+      const int c = col - n0;
+      out1[j + (int64_t)c * ldo1] = v;
+      if (out1t) out1t[c + j * ldo1t] = v;  // symmetric half of the Gram matrix
+    }
+  }
+}
+
+// Ynew[j][c] = Y[j][c] + C[j][c] - sum_l G[j][l] Y[l][c].  4 lanes per output
+// split l in quarters; lanes (jl, q) = (lane % 16, lane / 16) in each wave.
+__global__ __launch_bounds__(256) void gram_sweep_kernel(const double* __restrict__ G, int64_t ldg,
+                                                         int64_t K, const double* __restrict__ C,
+                                                         const double* __restrict__ Y,
+                                                         int64_t ldy, double* __restrict__ Ynew,
+                                                         int64_t ldyn, int bw) {
+  const int lane = threadIdx.x & 63;
+  const int jl = lane & 15, q = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // wave index
+  const int64_t jblocks = (K + 15) / 16;
+  const bool okw = w < jblocks * bw;
+  const int64_t jb = okw ? w % jblocks : 0;
+  const int c = okw ? (int)(w / jblocks) : 0;
+  const int64_t j = jb * 16 + jl;
+  const bool ok = okw && j < K;
+  const int64_t jc = ok ? j : 0;
+  const int64_t l0 = (K * q) / 4, l1 = (K * (q + 1)) / 4;
+  const double* yc = Y + (int64_t)c * ldy;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t l = l0;
+  for (; l + 1 < l1; l += 2) {
+    a0 = fma(G[jc + l * ldg], yc[l], a0);
+    a1 = fma(G[jc + (l + 1) * ldg], yc[l + 1], a1);
+  }
+  if (l < l1) a0 = fma(G[jc + l * ldg], yc[l], a0);
+  double v = a0 + a1;
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  if (ok && q == 0) Ynew[j + (int64_t)c * ldyn] = yc[j] + (C[j + (int64_t)c * K] - v);
+}
+
+// E[t][c] = P[t][c] - sum_j S[t][j] Y[j][c].  4 lanes per output split j in
+// quarters; lanes (tl, q) = (lane % 16, lane / 16).
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P,
+                                                    const double* __restrict__ S, int64_t k,
+                                                    int64_t K, const double* __restrict__ Y,
+                                                    int64_t ldy, double* __restrict__ E, int bw) {
+  const int lane = threadIdx.x & 63;
+  const int tl = lane & 15, q = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t tblocks = (k + 15) / 16;
+  const bool okw = w < tblocks * bw;
+  const int64_t tb = okw ? w % tblocks : 0;
+  const int c = okw ? (int)(w / tblocks) : 0;
+  const int64_t t = tb * 16 + tl;
+  const bool ok = okw && t < k;
+  const int64_t tc = ok ? t : 0;
+  const int64_t j0 = (K * q) / 4, j1 = (K * (q + 1)) / 4;
+  const double* yc = Y + (int64_t)c * ldy;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t j = j0;
+  for (; j + 1 < j1; j += 2) {
+    a0 = fma(S[tc + j * k], yc[j], a0);
+    a1 = fma(S[tc + (j + 1) * k], yc[j + 1], a1);
+  }
+  if (j < j1) a0 = fma(S[tc + j * k], yc[j], a0);
+  double v = a0 + a1;
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  if (ok && q == 0) E[t + (int64_t)c * k] = P[t + (int64_t)c * k] - v;
+}
+
+__device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned total) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == total - 1;
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// R_(i,i) (positive diagonal) of the k x bw matrix src (ld k): workgroup g
+// factors chunk g in LDS; the last workgroup factors the stack of chunk R
+// factors (all remaining levels of the tree) and writes R_(i,i).
+__global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
+    const double* __restrict__ src, int64_t k, int bw, double* __restrict__ stack,
+    unsigned* counter, double* __restrict__ Rii, int64_t ldr, int64_t* flag, int64_t col0) {
+  __shared__ double A[kQrLds];
+  __shared__ double red[kQrMaxB + 1];
+  const int CH = qr_chunk_rows(bw);
+  const int64_t nch = (k + CH - 1) / CH;
+  if (nch == 1) {
+    qr_chunk(src, k, k, bw, Rii, ldr, 1, flag, col0, 0, A, red);
+    return;
+  }
+  const int64_t ld1 = nch * bw;
+  qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, blockIdx.x, A, red);
+  if (!last_block_arrives(counter, (unsigned)nch)) return;
+  // remaining levels in this workgroup
+  const double* lsrc = stack;
+  int64_t ld_in = ld1, lrows = ld1;
+  double* buf = stack + ld1 * bw;
+  while (lrows > CH) {
+    const int64_t n2 = (lrows + CH - 1) / CH;
+    const int64_t out_rows = n2 * bw;
+    for (int64_t b2 = 0; b2 < n2; ++b2)
+      qr_chunk(lsrc, ld_in, lrows, bw, buf, out_rows, 0, nullptr, 0, b2, A, red);
+    lsrc = buf;
+    ld_in = out_rows;
+    lrows = out_rows;
+    buf += out_rows * bw;
+  }
+  qr_chunk(lsrc, ld_in, lrows, bw, Rii, ldr, 1, flag, col0, 0, A, red);
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* X0, int n0,
+                           const double* X1, int n1, double* out0, int64_t ldo0, double* out1,
+                           int64_t ldo1, double* out1t, int64_t ldo1t, hipStream_t st) {
+  const int64_t threads = K * (n0 + n1) * 16;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(gram_sty_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st, S,
+                     k, K, X0, n0, X1, n1, out0, ldo0, out1, ldo1, out1t, ldo1t);
   return hipGetLastError();
 }
 
-hipError_t launch_resid(const double* P, int64_t ldp, const double* S, int64_t lds,
-                        const double* Y, int64_t ldy, double* E, int64_t lde, int64_t k, int64_t K,
-                        int bw, hipStream_t st) {
-  dim3 grid((unsigned)ceil_div(k, 256), (unsigned)bw);
-  hipLaunchKernelGGL(resid_kernel, grid, dim3(256), 0, st, P, ldp, S, lds, Y, ldy, E, lde, k, K);
+hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const double* C,
+                             const double* Y, int64_t ldy, double* Ynew, int64_t ldyn, int bw,
+                             hipStream_t st) {
+  const int64_t waves = ceil_div(K, 16) * bw;
+  hipLaunchKernelGGL(gram_sweep_kernel, dim3((unsigned)ceil_div(waves * 64, 256)), dim3(256), 0, st,
+                     G, ldg, K, C, Y, ldy, Ynew, ldyn, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
+                        int64_t ldy, double* E, int bw, hipStream_t st) {
+  const int64_t waves = ceil_div(k, 16) * bw;
+  hipLaunchKernelGGL(resid_kernel, dim3((unsigned)ceil_div(waves * 64, 256)), dim3(256), 0, st, P,
+                     S, k, K, Y, ldy, E, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
+                           double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st) {
+  if (bw > kQrMaxB) return hipErrorInvalidValue;
+  const int64_t CH = kQrLds / bw;
+  hipLaunchKernelGGL(qr_fused_kernel, dim3((unsigned)ceil_div(k, CH)), dim3(kQrThreads), 0, st, src,
+                     k, bw, stack, counter, Rii, ldr, flag, col0);
   return hipGetLastError();
 }
 

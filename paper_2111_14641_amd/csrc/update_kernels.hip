@@ -20,9 +20,15 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+#ifndef RBGS_UP_UNROLL
+#define RBGS_UP_UNROLL 8
+#endif
+#ifndef RBGS_UP_PINGPONG
+#define RBGS_UP_PINGPONG 1
+#endif
 constexpr int kUpThreads = 256;
-constexpr int kKC = 128;      // rows of R per LDS chunk
-constexpr int kUnroll = 8;    // K-steps whose loads are issued together
+constexpr int kKC = 128;                  // rows of R per LDS chunk
+constexpr int kUnroll = RBGS_UP_UNROLL;   // K-steps whose loads are issued together
 constexpr int kMaxB = 32;
 
 // Matrix-core operations by compute type.  Output layout of the 16x16x4
@@ -81,33 +87,56 @@ __device__ __forceinline__ void row_substitute(double* x, const double* Rs, int 
 // T: storage type of W and Q; C: arithmetic of the product (float: FP32
 // matrix cores with FP32 accumulation; double: FP64 matrix cores, FP32 data
 // converted exactly).  NB: 16-column blocks of R_(1:i-1,i) (1 or 2).
+// TAIL = false: every row of the workgroup's 4*WROWS-row tile exists and the
+// 16-byte vector loads are aligned; all loads are unconditional (columns past
+// K are clamped and meet zero rows of R), so no load waits on a branch.
+// TAIL = true: guarded element loads, for the last partial tile or unaligned Q.
 template <typename T, typename C, int NB>
-__global__ __launch_bounds__(kUpThreads) void update_kernel(
+struct UpdateShape {
+  static constexpr int VEC = Vec16<T>::N;
+  static constexpr int WROWS = 16 * VEC;  // rows per wave
+  static constexpr int TILE = 4 * WROWS;  // rows per workgroup
+  static constexpr int NCOL = 16 * NB;
+  static constexpr int CT_LD = 17;        // one 16-column slab of the product per pass
+  static constexpr int RS_BYTES = kKC * NCOL * sizeof(C);
+  static constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(C);
+  static constexpr int U_BYTES = RS_BYTES > CT_BYTES ? RS_BYTES : CT_BYTES;
+};
+
+template <typename T, typename C, int NB, bool TAIL>
+__device__ __forceinline__ void update_tile(
     const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
-    const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t n, int K,
-    int bw, int vec_ok) {
+    const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t tile_row0,
+    int64_t n, int K, int bw, unsigned char* ubuf_raw, double* Rd) {
   typedef Mfma<C> M;
-  constexpr int VEC = Vec16<T>::N;
-  constexpr int WROWS = 16 * VEC;  // rows per wave
-  constexpr int NCOL = 16 * NB;
-  constexpr int CT_LD = 17;        // one 16-column slab of the product per pass
-  constexpr int RS_BYTES = kKC * NCOL * sizeof(C);
-  constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(C);
-  constexpr int U_BYTES = RS_BYTES > CT_BYTES ? RS_BYTES : CT_BYTES;
-  __shared__ __attribute__((aligned(16))) unsigned char ubuf_raw[U_BYTES];  // R chunk, then product slab
-  __shared__ double Rd[NCOL * NCOL];                                          // R_(i,i)
+  typedef UpdateShape<T, C, NB> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int WROWS = Sh::WROWS;
+  constexpr int NCOL = Sh::NCOL;
+  constexpr int CT_LD = Sh::CT_LD;
   C* ubuf = reinterpret_cast<C*>(ubuf_raw);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t wrow0 = ((int64_t)blockIdx.x * 4 + wave) * WROWS;
+  const int64_t wrow0 = tile_row0 + (int64_t)wave * WROWS;
   const int kk = lane >> 4, li = lane & 15;
   const int64_t arow = wrow0 + (int64_t)VEC * li;   // first row of this lane's A vector
-  const bool afull = vec_ok && (arow + VEC <= n);
+  const int64_t row = wrow0 + lane;                  // row owned in the epilogue (lane < WROWS)
+  const bool own = lane < WROWS && (!TAIL || row < n);
+  const int bwc = bw - 1;
 
+  // W_(i) row of this lane, loaded first so its latency overlaps the product
+  T wrow[NCOL];
+  {
+    const int64_t rr = TAIL ? (row < n ? row : n - 1) : (lane < WROWS ? row : wrow0);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) wrow[c] = W[rr + (int64_t)(c < bw ? c : bwc) * ldw];
+  }
   if (Rii != nullptr) {
     for (int e = threadIdx.x; e < NCOL * NCOL; e += kUpThreads) {
       const int r = e % NCOL, c = e / NCOL;
-      Rd[e] = (r < bw && c < bw) ? Rii[r + (int64_t)c * ldr] : (r == c ? 1.0 : 0.0);
+      const bool in = r < bw && c < bw;
+      const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
+      Rd[e] = in ? v : (r == c ? 1.0 : 0.0);
     }
   }
 
@@ -118,19 +147,23 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
     for (int nb = 0; nb < NB; ++nb) acc[v][nb] = (typename M::acc_t){0, 0, 0, 0};
 
   // A operand group: kUnroll K-steps of 4 columns, one 16-byte load per step.
-  auto load_group = [&](T (&a)[kUnroll][VEC], int kc0, int kc, int ks0) {
+  auto load_group = [&](T (&a)[kUnroll][VEC], int kc0, int ks0) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int col = kc0 + ks0 + 4 * u + kk;
-      const bool colok = (ks0 + 4 * u + kk) < kc;
+      int col = kc0 + ks0 + 4 * u + kk;
+      col = col < K ? col : K - 1;  // padded steps meet zero rows of R
       const T* src = Q + arow + (int64_t)col * ldq;
-      if (colok && afull) {
+      if (!TAIL) {
         typename Vec16<T>::t vv = *reinterpret_cast<const typename Vec16<T>::t*>(src);
 #pragma unroll
         for (int v = 0; v < VEC; ++v) a[u][v] = vv[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) a[u][v] = (colok && arow + v < n) ? src[v] : (T)0;
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const T x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
+          a[u][v] = in ? x : (T)0;
+        }
       }
     }
   };
@@ -153,30 +186,36 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
     __syncthreads();
     for (int e = threadIdx.x; e < kKC * NCOL; e += kUpThreads) {
       const int r = e / NCOL, c = e % NCOL;
-      ubuf[e] = (r < kc && c < bw) ? (C)Rk[(kc0 + r) + (int64_t)c * ldr] : (C)0;
+      const bool in = r < kc && c < bw;
+      const double v = Rk[(kc0 + (in ? r : 0)) + (int64_t)(in ? c : 0) * ldr];
+      ubuf[e] = in ? (C)v : (C)0;
     }
     __syncthreads();
-    // ping-pong: the loads of group g+1 are in flight during the products of group g
     constexpr int GS = 4 * kUnroll;
+#if RBGS_UP_PINGPONG
+    // ping-pong: the loads of group g+1 are in flight during the products of group g
     T a0[kUnroll][VEC], a1[kUnroll][VEC];
-    load_group(a0, kc0, kc, 0);
+    load_group(a0, kc0, 0);
     for (int ks0 = 0; ks0 < kc; ks0 += 2 * GS) {
-      if (ks0 + GS < kc) load_group(a1, kc0, kc, ks0 + GS);
+      if (ks0 + GS < kc) load_group(a1, kc0, ks0 + GS);
       mma_group(a0, kc, ks0);
       if (ks0 + GS < kc) {
-        if (ks0 + 2 * GS < kc) load_group(a0, kc0, kc, ks0 + 2 * GS);
+        if (ks0 + 2 * GS < kc) load_group(a0, kc0, ks0 + 2 * GS);
         mma_group(a1, kc, ks0 + GS);
       }
     }
+#else
+    for (int ks0 = 0; ks0 < kc; ks0 += GS) {
+      T a0[kUnroll][VEC];
+      load_group(a0, kc0, ks0);
+      mma_group(a0, kc, ks0);
+    }
+#endif
   }
   // Epilogue: lane owns row wrow0 + lane (lanes >= WROWS idle); the product is
   // moved through LDS one 16-column slab at a time.
   C* ct = ubuf + wave * WROWS * CT_LD;
-  const int64_t row = wrow0 + lane;
-  const bool own = lane < WROWS && row < n;
   double x[NCOL];
-#pragma unroll
-  for (int c = 0; c < NCOL; ++c) x[c] = 0.0;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     __syncthreads();
@@ -185,16 +224,12 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
 #pragma unroll
       for (int e = 0; e < 4; ++e) ct[(VEC * M::row(kk, e) + v) * CT_LD + li] = acc[v][nb][e];
     __syncthreads();
-    if (own) {
+    const int lr = lane < WROWS ? lane : 0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const int cc = nb * 16 + c;
-        if (cc < bw) {
-          // step 3: Q' = W - Q R in the arithmetic C, from storage T
-          const C qp = (C)W[row + (int64_t)cc * ldw] - ct[lane * CT_LD + c];
-          x[cc] = (double)qp;
-        }
-      }
+    for (int c = 0; c < 16; ++c) {
+      // step 3: Q' = W - Q R in the arithmetic C, from storage T
+      const C qp = (C)wrow[nb * 16 + c] - ct[lr * CT_LD + c];
+      x[nb * 16 + c] = (double)qp;
     }
   }
   if (own) {
@@ -203,6 +238,26 @@ __global__ __launch_bounds__(kUpThreads) void update_kernel(
     for (int c = 0; c < NCOL; ++c)
       if (c < bw) Qout[row + (int64_t)c * ldqo] = (T)x[c];
   }
+}
+
+// Workgroups [0, nfull) take full tiles on the branch-free path; a last
+// workgroup, if n is not a multiple of the tile (or Q is not 16-byte aligned
+// along columns, then all workgroups), takes the guarded path.
+template <typename T, typename C, int NB>
+__global__ __launch_bounds__(kUpThreads) void update_kernel(
+    const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
+    const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t nfull,
+    int64_t n, int K, int bw) {
+  typedef UpdateShape<T, C, NB> Sh;
+  __shared__ __attribute__((aligned(16))) unsigned char ubuf_raw[Sh::U_BYTES];  // R chunk, then product slab
+  __shared__ double Rd[Sh::NCOL * Sh::NCOL];                                      // R_(i,i)
+  const int64_t row0 = (int64_t)blockIdx.x * Sh::TILE;
+  if ((int64_t)blockIdx.x < nfull)
+    update_tile<T, C, NB, false>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, row0, n, K, bw,
+                                 ubuf_raw, Rd);
+  else
+    update_tile<T, C, NB, true>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, row0, n, K, bw,
+                                ubuf_raw, Rd);
 }
 
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
@@ -229,21 +284,26 @@ __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t l
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+template <typename T, typename C, int NB>
+static hipError_t launch_update_nb(const void* W, int64_t ldw, const void* Q, int64_t ldq,
+                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
+                                   int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
+  constexpr int VEC = Vec16<T>::N;
+  constexpr int TILE = UpdateShape<T, C, NB>::TILE;
+  const bool vec_ok = ((ldq % VEC) == 0) && ((reinterpret_cast<uintptr_t>(Q) % 16) == 0);
+  const int64_t nfull = vec_ok ? n / TILE : 0;
+  hipLaunchKernelGGL((update_kernel<T, C, NB>), dim3((unsigned)ceil_div(n, TILE)), dim3(kUpThreads),
+                     0, st, (const T*)W, ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, nfull,
+                     n, (int)K, bw);
+  return hipGetLastError();
+}
+
 template <typename T, typename C>
 static hipError_t launch_update_t(const void* W, int64_t ldw, const void* Q, int64_t ldq,
                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
                                   int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
-  constexpr int VEC = Vec16<T>::N;
-  constexpr int WROWS = 16 * VEC;
-  const int vec_ok = ((ldq % VEC) == 0) && ((reinterpret_cast<uintptr_t>(Q) % 16) == 0);
-  dim3 grid((unsigned)ceil_div(n, 4 * WROWS));
-  if (bw <= 16)
-    hipLaunchKernelGGL((update_kernel<T, C, 1>), grid, dim3(kUpThreads), 0, st, (const T*)W, ldw,
-                       (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, n, (int)K, bw, vec_ok);
-  else
-    hipLaunchKernelGGL((update_kernel<T, C, 2>), grid, dim3(kUpThreads), 0, st, (const T*)W, ldw,
-                       (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, n, (int)K, bw, vec_ok);
-  return hipGetLastError();
+  if (bw <= 16) return launch_update_nb<T, C, 1>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+  return launch_update_nb<T, C, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
 }
 
 hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, const void* Q,
