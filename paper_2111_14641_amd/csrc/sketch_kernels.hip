@@ -2,6 +2,8 @@
 // (steps 1 and 5 of Algorithm RBGS), computed as per-row-range FP64 partial
 // sums followed by a fixed-order reduction, so results are reproducible bit
 // for bit and no floating-point atomics are needed.
+#include <type_traits>
+
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -23,9 +25,10 @@ __device__ __forceinline__ double to_f64(T x) {
 // the summation order is fixed.
 // ---------------------------------------------------------------------------
 constexpr int kSpThreads = 1024;
-constexpr int kSpTile = 256;  // rows per tile
+constexpr int kSpTile = 1024;  // rows per tile (one row per thread)
 constexpr int kSpMaxK = 2048;
-constexpr int kSpLoads = kSketchCols * kSpTile / kSpThreads;  // prefetched elements per thread
+constexpr int kSpMaxZeta = 8;
+constexpr int kSpEntVec = kSpTile * kSpMaxZeta / kSpThreads;  // plan entries per thread (8)
 
 __device__ __forceinline__ void block_exclusive_scan_2048(int* cnt, int* off, int* cur, int k) {
   // Each thread scans two consecutive counters; wave prefix sums via shuffles;
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
                                                                  uint32_t key1,
                                                                  uint16_t* __restrict__ plan_off,
                                                                  uint16_t* __restrict__ plan_ent) {
-  __shared__ uint16_t sorted[kSpTile * 8];
+  __shared__ uint16_t sorted[kSpTile * kSpMaxZeta];
   __shared__ int cnt[kSpMaxK];
   __shared__ int off[kSpMaxK];
   __shared__ int cur[kSpMaxK];
@@ -79,10 +82,14 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
   const uint32_t L = (uint32_t)(k / zeta);
   for (int t = tid; t < k; t += kSpThreads) cnt[t] = 0;
   __syncthreads();
-  uint32_t tgt[4], ent[4];
-  int nown = 0;
-  if (tid < 2 * kSpTile) {
-    const int rr = tid >> 1, half = tid & 1;
+  // task = 2 rr + half: row rr, segments 4 half .. 4 half + 3 (one Philox call)
+  constexpr int kTasks = 2 * kSpTile / kSpThreads;
+  uint32_t tgt[4 * kTasks], ent[4 * kTasks];
+  unsigned own = 0;  // bit j: slot j holds an entry
+#pragma unroll
+  for (int h = 0; h < kTasks; ++h) {
+    const int task = tid + h * kSpThreads;
+    const int rr = task >> 1, half = task & 1;
     if (rr < trows && 4 * half < zeta) {
       const uint64_t r = (uint64_t)(row0 + tile0 + rr);
       const u32x4 w = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), (uint32_t)half, kTagSparse,
@@ -92,10 +99,10 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
       for (int q = 0; q < 4; ++q) {
         const int s = 4 * half + q;
         if (s < zeta) {
-          tgt[q] = sparse_target(ws[q], (uint32_t)s, L);
-          ent[q] = ((uint32_t)rr << 1) | (ws[q] & 1u);
-          atomicAdd(&cnt[tgt[q]], 1);
-          nown = q + 1;
+          tgt[4 * h + q] = sparse_target(ws[q], (uint32_t)s, L);
+          ent[4 * h + q] = ((uint32_t)rr << 1) | (ws[q] & 1u);
+          atomicAdd(&cnt[tgt[4 * h + q]], 1);
+          own |= 1u << (4 * h + q);
         }
       }
     }
@@ -103,9 +110,12 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
   __syncthreads();
   block_exclusive_scan_2048(cnt, off, cur, k);
   __syncthreads();
-  for (int q = 0; q < nown; ++q) {
-    const int pos = atomicAdd(&cur[tgt[q]], 1);
-    sorted[pos] = (uint16_t)ent[q];
+#pragma unroll
+  for (int j = 0; j < 4 * kTasks; ++j) {
+    if (own & (1u << j)) {
+      const int pos = atomicAdd(&cur[tgt[j]], 1);
+      sorted[pos] = (uint16_t)ent[j];
+    }
   }
   __syncthreads();
   uint16_t* po = plan_off + tile * (k + 1);
@@ -131,17 +141,29 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
 
 // Sparse-sign partial sums from a plan.  A workgroup owns a range of tiles and
 // one group of up to 16 columns; thread t owns targets t (and t + 1024).  Per
-// tile the rows are staged in LDS as FP64 (row-major) and each thread sums its
-// bucket in row order with an exact sign (fma with +-1).  The next tile is
-// prefetched into registers while the current one is summed.
+// tile the rows are staged in LDS in the storage precision (exact), thread r
+// staging row r, and each thread sums its bucket in row order in FP64 with an
+// exact sign (fma with +-1).  The next tile is prefetched into registers while
+// the current one is summed; every prefetch load is unconditional (clamped
+// index, masked value).
+#ifndef RBGS_SP_STAGE64
+#define RBGS_SP_STAGE64 0
+#endif
+#ifndef RBGS_SP_UNROLL2
+#define RBGS_SP_UNROLL2 0
+#endif
 template <typename T, int TPT>
 __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
     int64_t tiles_per_wg, double* __restrict__ partial) {
-  constexpr int XC = kSketchCols + 1;           // padded row of the staged tile
-  __shared__ double xs[kSpTile * XC];           // [rr][c]
-  __shared__ uint16_t ent[kSpTile * 8];
+  // staging type in LDS: the storage type, or FP64 (converted once per row)
+  typedef typename std::conditional<RBGS_SP_STAGE64 != 0, double, T>::type ST;
+  typedef ST V4 __attribute__((ext_vector_type(4)));
+  typedef unsigned short U8 __attribute__((ext_vector_type(8)));
+  constexpr int XC = kSketchCols + (sizeof(ST) == 4 ? 4 : 0);  // padded row (16-byte aligned)
+  __shared__ __attribute__((aligned(32))) ST xs[kSpTile * XC];  // [rr][c]
+  __shared__ __attribute__((aligned(16))) uint16_t ent[kSpTile * kSpMaxZeta];
   __shared__ uint16_t off[kSpMaxK + 1];
 
   const int tid = threadIdx.x;
@@ -151,7 +173,8 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
   const int64_t ntiles = (n + kSpTile - 1) / kSpTile;
   const int64_t tbeg = (int64_t)g * tiles_per_wg;
   const int64_t tend = min(ntiles, tbeg + tiles_per_wg);
-  const int E = kSpTile * zeta;
+  const int E = kSpTile * zeta;  // plan entries per tile (a multiple of 8)
+  const int nvec = E / 8;
 
   double acc[TPT][kSketchCols];
 #pragma unroll
@@ -159,49 +182,36 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
 #pragma unroll
     for (int c = 0; c < kSketchCols; ++c) acc[j][c] = 0.0;
 
-  T px[kSpLoads];
-  uint16_t pe[8 * kSpTile / kSpThreads];
-  uint16_t po[(kSpMaxK + 1 + kSpThreads - 1) / kSpThreads];
-  // All loads are unconditional (indices clamped into range, values masked
-  // afterwards), so none of them waits on a branch.
+  T px[kSketchCols];
+  U8 pe;
+  uint16_t po[TPT + 1];
   auto fetch = [&](int64_t tile) {
     const int64_t r0 = tile * kSpTile;
     const int trows = (int)min((int64_t)kSpTile, n - r0);
+    // Rows past the end and columns past nc are loaded from clamped
+    // addresses and never masked: no plan entry names such a row, and the sums
+    // of such columns are never stored.  (A masked value would let the
+    // compiler move each load under a branch and wait for it there.)
+    const int64_t rr = r0 + (tid < trows ? tid : trows - 1);
 #pragma unroll
-    for (int i = 0; i < kSpLoads; ++i) {
-      const int e = tid + i * kSpThreads;
-      const int c = e / kSpTile, rr = e % kSpTile;
-      const bool in = rr < trows && c < nc;
-      const T v = X[(r0 + (rr < trows ? rr : trows - 1)) + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
-      px[i] = in ? v : (T)0;
-    }
-    const uint16_t* se = plan_ent + tile * (int64_t)E;
-    const int ne = trows * zeta;
-#pragma unroll
-    for (int i = 0; i < 8 * kSpTile / kSpThreads; ++i) {
-      const int e = tid + i * kSpThreads;
-      const uint16_t v = se[e < ne ? e : ne - 1];
-      pe[i] = e < ne ? v : (uint16_t)0;
-    }
+    for (int c = 0; c < kSketchCols; ++c) px[c] = X[rr + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+    pe = ((const U8*)(plan_ent + tile * (int64_t)E))[tid < nvec ? tid : nvec - 1];
     const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
 #pragma unroll
-    for (int i = 0; i < (kSpMaxK + 1 + kSpThreads - 1) / kSpThreads; ++i) {
+    for (int i = 0; i <= TPT; ++i) {
       const int t = tid + i * kSpThreads;
-      const uint16_t v = so[t <= k ? t : k];
-      po[i] = t <= k ? v : (uint16_t)0;
+      po[i] = so[t <= k ? t : k];
     }
   };
   if (tbeg < tend) fetch(tbeg);
   for (int64_t tile = tbeg; tile < tend; ++tile) {
+    V4* xw = (V4*)(xs + tid * XC);
 #pragma unroll
-    for (int i = 0; i < kSpLoads; ++i) {
-      const int e = tid + i * kSpThreads;
-      xs[(e % kSpTile) * XC + e / kSpTile] = to_f64(px[i]);
-    }
+    for (int q = 0; q < kSketchCols / 4; ++q)
+      xw[q] = (V4){(ST)px[4 * q], (ST)px[4 * q + 1], (ST)px[4 * q + 2], (ST)px[4 * q + 3]};
+    if (tid < nvec) ((U8*)ent)[tid] = pe;
 #pragma unroll
-    for (int i = 0; i < 8 * kSpTile / kSpThreads; ++i) ent[tid + i * kSpThreads] = pe[i];
-#pragma unroll
-    for (int i = 0; i < (kSpMaxK + 1 + kSpThreads - 1) / kSpThreads; ++i) {
+    for (int i = 0; i <= TPT; ++i) {
       const int t = tid + i * kSpThreads;
       if (t <= k) off[t] = po[i];
     }
@@ -211,13 +221,50 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
     for (int j = 0; j < TPT; ++j) {
       const int t = tid + j * kSpThreads;
       if (t < k) {
+        // two entries per pass (more loads in flight); an odd count leaves
+        // the second slot empty: it re-reads the first row and adds nothing
         const int b = off[t], e = off[t + 1];
-        for (int i = b; i < e; ++i) {
-          const uint32_t v = ent[i];
-          const double* xr = xs + (v >> 1) * XC;
-          const double sg = (v & 1u) ? -1.0 : 1.0;
+        if constexpr (sizeof(ST) == 8 || TPT > 1 || RBGS_SP_UNROLL2 == 0) {
+          // (register budget: one entry per pass; the next entry is read
+          // while this one is summed)
+          uint32_t vn = ent[b < e ? b : 0];
+          for (int i = b; i < e; ++i) {
+            const uint32_t v = vn;
+            vn = ent[i + 1 < e ? i + 1 : i];
+            const V4* xr = (const V4*)(xs + (v >> 1) * XC);
+            const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-          for (int c = 0; c < kSketchCols; ++c) acc[j][c] = fma(sg, xr[c], acc[j][c]);
+            for (int q = 0; q < kSketchCols / 4; ++q) {
+              const V4 x = xr[q];
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                acc[j][4 * q + u] = fma(sg, (double)x[u], acc[j][4 * q + u]);
+            }
+          }
+        } else
+        for (int i = b; i < e; i += 2) {
+          const bool two = i + 1 < e;
+          const uint32_t v0 = ent[i];
+          const uint32_t v1 = ent[two ? i + 1 : i];
+          const V4* xr0 = (const V4*)(xs + (v0 >> 1) * XC);
+          const V4* xr1 = (const V4*)(xs + (v1 >> 1) * XC);
+          const double s0 = (v0 & 1u) ? -1.0 : 1.0;
+          const double s1 = two ? ((v1 & 1u) ? -1.0 : 1.0) : 0.0;
+          V4 x0[kSketchCols / 4], x1[kSketchCols / 4];
+#pragma unroll
+          for (int q = 0; q < kSketchCols / 4; ++q) {
+            x0[q] = xr0[q];
+            x1[q] = xr1[q];
+          }
+#pragma unroll
+          for (int q = 0; q < kSketchCols / 4; ++q) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const ST y1 = two ? x1[q][u] : (ST)0;
+              acc[j][4 * q + u] = fma(s0, (double)x0[q][u], acc[j][4 * q + u]);
+              acc[j][4 * q + u] = fma(s1, (double)y1, acc[j][4 * q + u]);
+            }
+          }
         }
       }
     }
@@ -389,16 +436,21 @@ int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols) {
   return (int)std::max<int64_t>(1, G);
 }
 
+// The entries start at a 16-byte boundary (they are read 8 at a time).
+static int64_t plan_ent_offset(const SketchDesc& sk, int64_t n) {
+  return ceil_div(ceil_div(n, kSpTile) * (sk.k + 1), 8) * 8;
+}
+
 size_t sparse_plan_bytes(const SketchDesc& sk, int64_t n) {
   const int64_t ntiles = ceil_div(n, kSpTile);
-  return (size_t)ntiles * (size_t)(sk.k + 1 + kSpTile * sk.zeta) * sizeof(uint16_t);
+  return (size_t)(plan_ent_offset(sk, n) + ntiles * kSpTile * sk.zeta) * sizeof(uint16_t);
 }
 
 hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uint16_t* plan,
                               hipStream_t st) {
   const int64_t ntiles = ceil_div(n, kSpTile);
   uint16_t* off = plan;
-  uint16_t* ent = plan + ntiles * (sk.k + 1);
+  uint16_t* ent = plan + plan_ent_offset(sk, n);
   hipLaunchKernelGGL(sparse_plan_kernel, dim3((unsigned)ntiles), dim3(kSpThreads), 0, st, n, row0,
                      (int)sk.k, sk.zeta, sk.key0, sk.key1, off, ent);
   return hipGetLastError();
@@ -408,7 +460,7 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
                                   const uint16_t* plan, hipStream_t st) {
   const uint16_t* plan_off = plan;
-  const uint16_t* plan_ent = plan ? plan + ceil_div(n, kSpTile) * (sk.k + 1) : nullptr;
+  const uint16_t* plan_ent = plan ? plan + plan_ent_offset(sk, n) : nullptr;
   const int G = sketch_num_partials(sk, n, ncols);
   const int64_t groups = ceil_div(ncols, kSketchCols);
   if (sk.kind == kSparse) {

@@ -24,141 +24,198 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of a chunk held in LDS.
+// Householder QR of a row chunk held in registers.
 // ---------------------------------------------------------------------------
 constexpr int kQrThreads = 256;
-constexpr int kQrLds = 4096;  // doubles of LDS for the chunk (32 KB)
 constexpr int kQrMaxB = 32;
+constexpr int kQrRpt = 16;  // rows per thread in a chunk
 
-__device__ __forceinline__ int qr_chunk_rows(int bw) {
-  // rows per chunk: as many as fit in LDS, at least 2*bw so the tree shrinks
-  return kQrLds / bw;
+// Columns padded to a power of two (>= 4); NG = 256 / BWP threads per column.
+__host__ __device__ __forceinline__ int qr_bwp(int bw) {
+  return bw <= 4 ? 4 : (bw <= 8 ? 8 : (bw <= 16 ? 16 : 32));
+}
+// Rows per chunk, NG * kQrRpt; always >= 4 bw, so every level of the tree
+// shrinks the row count at least fourfold.
+__host__ __device__ __forceinline__ int qr_chunk_rows(int bw) {
+  return (kQrThreads / qr_bwp(bw)) * kQrRpt;
 }
 
-// In-place Householder triangularization of A (rows x bw, column-major, ld
-// rows) in LDS.  For column j: x = A[j:, j], alpha = -sign(x_0) ||x||,
-// v = x - alpha e_1, and every later column is updated as
-// a_c -= beta (v^T a_c) v with beta = 2 / (v^T v) = 1 / (||x|| (||x|| + |x_0|)).
-// All dots d_c = x^T a_c (c >= j; d_j = ||x||^2) come from one reduction pass:
-// thread (c, g) sums rows g, g + NG, g + 2 NG, ... of column c and the NG
-// threads of a column reduce by shuffles; then v^T a_c = d_c + (v_0 - x_0) a_jc.
-// On return the upper triangle holds R (a zero column gives R_jj = 0 and no
-// reflection).
-template <int BWP>
-__device__ void householder_lds(double* A, int rows, int bw, double* red /* [kQrMaxB+1] */) {
-  constexpr int NG = (kQrThreads / BWP) < 64 ? (kQrThreads / BWP) : 64;  // threads per column
-  const int tid = threadIdx.x;
-  const int c = tid / NG, g = tid % NG;
-  const bool active = tid < BWP * NG;
-  __shared__ double sc[4];  // alpha, beta, v0 - x0, flag
-  for (int j = 0; j < bw && j < rows; ++j) {
-    double d = 0.0;
-    if (active && c >= j && c < bw) {
-      const double* aj = A + j * rows;
-      const double* ac = A + c * rows;
-      for (int r = j + g; r < rows; r += NG) d = fma(aj[r], ac[r], d);
-    }
+// Lane exchange within rows of 16 lanes by DPP (no LDS round trip), on the two
+// halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
+
+// Sum over the NG consecutive lanes of a column group (NG a power of two, 8 <=
+// NG <= 64).  Every lane ends with the same bits: each step adds a partner's
+// partial sum of the same shape, and addition is commutative.
+template <int NG>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_double<kDppXor1>(v);
+  v += dpp_double<kDppXor2>(v);
+  v += dpp_double<kDppHalfMirror>(v);
+  if (NG >= 16) v += dpp_double<kDppMirror>(v);
+  if (NG >= 32) v += __shfl_xor(v, 16, 64);
+  if (NG >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// R factor of chunk b of src (rows_in x bw, ld ld_in): rows [b CH, b CH + CH).
+// Thread (c, g) = (tid / NG, tid % NG) keeps rows g + NG i (i < RPT) of column
+// c in registers.  Householder step j: x = rows j.. of column j,
+// alpha = -sign(x_0) ||x||, v = x - alpha e_j, beta = 1 / (||x|| (||x|| + |x_0|)),
+// and every later column becomes a_c - beta (v^T a_c) v.  Column j and its
+// squared norm are handed to all threads through LDS (double-buffered by the
+// parity of j); the group owning column j + 1 publishes it right after its own
+// update, so each step needs one barrier.  A zero column gives R_jj = 0 and no
+// reflection.
+//   final == 0: the bw x bw R goes to rows [b bw, b bw + bw) of dst (ld ld_out).
+//   final != 0: R with a positive diagonal goes to dst; flag[0] gets the first
+//               column col0 + j with a zero or non-finite R_jj.
+template <int BWP, int RPT>
+__device__ void qr_chunk_reg(const double* __restrict__ src, int64_t ld_in, int64_t rows_in,
+                             int bw, double* __restrict__ dst, int64_t ld_out, int final,
+                             int64_t* flag, int64_t col0, int64_t b, double* xb /* [2][NG*RPT] */,
+                             double* sg /* [2 + kQrMaxB] */) {
+  constexpr int NG = kQrThreads / BWP;
+  constexpr int CH = NG * RPT;
+  // rows g + NG i with i >= IM are >= NG IM >= bw > j: they never need a mask
+  constexpr int IM0 = (BWP * BWP + kQrThreads - 1) / kQrThreads;
+  constexpr int IM = IM0 < RPT ? IM0 : RPT;
+  const int tid = threadIdx.x, c = tid / NG, g = tid % NG;
+  const int64_t r0 = b * (int64_t)qr_chunk_rows(bw);
+  const int rows = (int)min((int64_t)CH, rows_in - r0);
+  const bool col_ok = c < bw;
+  double a[RPT];
 #pragma unroll
-    for (int o = 1; o < NG; o <<= 1) d += __shfl_xor(d, o, 64);
-    if (active && g == 0 && c < bw) red[c] = d;
-    // a_jc for this thread's column, read before any thread updates column c
-    const double ajc = (active && c > j && c < bw) ? A[j + c * rows] : 0.0;
+  for (int i = 0; i < RPT; ++i) {
+    const int r = g + NG * i;
+    const bool ok = col_ok && r < rows;
+    const double v = src[ok ? (r0 + r) + (int64_t)c * ld_in : 0];
+    a[i] = ok ? v : 0.0;
+  }
+  // publish column 0 and its squared norm
+  if (c == 0) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      xb[g + NG * i] = a[i];
+      s2 = fma(a[i], a[i], s2);
+    }
+    s2 = group_sum<NG>(s2);
+    if (g == 0) sg[0] = s2;
+  }
+  __syncthreads();
+  for (int j = 0; j < bw; ++j) {
+    const double* xj = xb + (j & 1) * CH;
+    const double sigma = sg[j & 1];
+    const double x0 = xj[j];
+    double alpha = 0.0, beta = 0.0, v0 = x0;
+    if (sigma != 0.0) {
+      const double nrm = sqrt(sigma);
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      beta = 1.0 / (nrm * (nrm + fabs(x0)));
+      v0 = x0 - alpha;
+    }
+    if (c > j && col_ok && beta != 0.0) {
+      double v[RPT];
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = g + NG * i;
+        const double x = xj[r];
+        v[i] = i >= IM ? x : (r < j ? 0.0 : (r == j ? v0 : x));
+        if (i & 1) d1 = fma(v[i], a[i], d1);
+        else d0 = fma(v[i], a[i], d0);
+      }
+      const double w = beta * group_sum<NG>(d0 + d1);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) a[i] = fma(-w, v[i], a[i]);
+    }
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < IM; ++i)
+        if (g + NG * i == j) a[i] = sigma != 0.0 ? alpha : 0.0;
+    }
+    if (c == j + 1 && col_ok) {
+      // publish the next column (rows below j + 1 are masked by the reader)
+      double* xn = xb + ((j + 1) & 1) * CH;
+      double s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = g + NG * i;
+        xn[r] = a[i];
+        if (i >= IM || r > j) s2 = fma(a[i], a[i], s2);
+      }
+      s2 = group_sum<NG>(s2);
+      if (g == 0) sg[(j + 1) & 1] = s2;
+    }
     __syncthreads();
-    if (tid == 0) {
-      const double sigma = red[j];
-      const double x0 = A[j + j * rows];
-      if (sigma == 0.0) {
-        sc[0] = 0.0;
-        sc[1] = 0.0;
-        sc[2] = 0.0;
+  }
+  // R: rows r < bw, held by g = r % NG, i = r / NG
+  double* diag = sg + 2;
+  if (final) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (col_ok && g + NG * i == c) diag[c] = a[i];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = g + NG * i;
+    if (col_ok && r < bw) {
+      if (!final) {
+        dst[(b * bw + r) + (int64_t)c * ld_out] = r <= c ? a[i] : 0.0;
       } else {
-        const double nrm = sqrt(sigma);
-        const double alpha = x0 >= 0.0 ? -nrm : nrm;
-        sc[0] = alpha;
-        sc[1] = 1.0 / (nrm * (nrm + fabs(x0)));
-        sc[2] = -alpha;  // v0 - x0
-        A[j + j * rows] = x0 - alpha;  // v_0
+        const double sgn = diag[r] < 0.0 ? -1.0 : 1.0;
+        dst[r + (int64_t)c * ld_out] = r <= c ? sgn * a[i] : 0.0;
       }
     }
-    __syncthreads();
-    const double beta = sc[1];
-    if (beta != 0.0 && active && c > j && c < bw) {
-      // w_c = v^T a_c = d_c + (v0 - x0) a_jc
-      double* ac = A + c * rows;
-      const double* v = A + j * rows;
-      const double w = beta * (red[c] + sc[2] * ajc);
-      for (int r = j + g; r < rows; r += NG) ac[r] = fma(-w, v[r], ac[r]);
+  }
+  if (final && threadIdx.x == 0 && flag != nullptr) {
+    for (int j = 0; j < bw; ++j) {
+      const double d = diag[j];
+      if (!(d != 0.0) || !isfinite(d)) {
+        atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
+                  (unsigned long long)(col0 + j));
+        break;
+      }
     }
-    __syncthreads();
-    if (tid == 0) A[j + j * rows] = sc[0];
-    // (the next iteration's reads of column j+1 start after the barrier above;
-    //  A[j][j] is not read again in this factorization)
   }
   __syncthreads();
 }
 
-// One chunk of one level of the tree: chunk b of `src` (rows_in x bw, ld ld_in)
-// -> its R factor (bw x bw) at rows [b*bw, b*bw+bw) of `dst` (ld ld_out).  With
-// final != 0 there is one chunk and R goes to the output with a positive
-// diagonal, zeros below it, and a breakdown check.  A: kQrLds doubles of LDS.
+// Dispatch on the padded width; the final level of a tree uses fewer rows per
+// thread when its input is short.
 __device__ void qr_chunk(const double* __restrict__ src, int64_t ld_in, int64_t rows_in, int bw,
                          double* __restrict__ dst, int64_t ld_out, int final, int64_t* flag,
-                         int64_t col0, int64_t b, double* A, double* red) {
-  const int CH = qr_chunk_rows(bw);
-  const int64_t r0 = b * CH;
-  const int rows = (int)min((int64_t)CH, rows_in - r0);
-  const int rows_p = max(rows, bw);  // pad short chunks with zero rows
-  // element e = r + c rows_p of the padded chunk; every load is issued before
-  // the first is used (clamped index, then select)
-  constexpr int PER = kQrLds / kQrThreads;
-  const int tot = rows_p * bw;
-  double v[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + i * kQrThreads;
-    const int r = e % rows_p, c = e / rows_p;
-    const bool ok = e < tot && r < rows;
-    const double x = src[ok ? (r0 + r) + c * ld_in : 0];
-    v[i] = ok ? x : 0.0;
-  }
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + i * kQrThreads;
-    if (e < tot) A[e] = v[i];
-  }
-  __syncthreads();
-  if (bw <= 4) householder_lds<4>(A, rows_p, bw, red);
-  else if (bw <= 8) householder_lds<8>(A, rows_p, bw, red);
-  else if (bw <= 16) householder_lds<16>(A, rows_p, bw, red);
-  else householder_lds<32>(A, rows_p, bw, red);
-  if (!final) {
-    for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
-      const int r = e % bw, c = e / bw;
-      dst[(b * bw + r) + c * ld_out] = r <= c ? A[r + c * rows_p] : 0.0;
-    }
-  } else {
-    for (int e = threadIdx.x; e < bw * bw; e += kQrThreads) {
-      const int r = e % bw, c = e / bw;
-      const double d = A[r + r * rows_p];
-      const double sgn = d < 0.0 ? -1.0 : 1.0;
-      dst[r + c * ld_out] = r <= c ? sgn * A[r + c * rows_p] : 0.0;
-    }
-    if (threadIdx.x == 0 && flag != nullptr) {
-      for (int j = 0; j < bw; ++j) {
-        const double d = A[j + j * rows_p];
-        if (!(d != 0.0) || !isfinite(d)) {
-          atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
-                    (unsigned long long)(col0 + j));
-          break;
-        }
-      }
-    }
-  }
-  __syncthreads();
+                         int64_t col0, int64_t b, double* xb, double* sg) {
+  const int bwp = qr_bwp(bw);
+  const int ng = kQrThreads / bwp;
+  const int64_t rows = rows_in - b * (int64_t)qr_chunk_rows(bw);
+  const bool short4 = rows <= 4 * ng;
+#define RBGS_QRC(BWP)                                                                            \
+  if (short4)                                                                                    \
+    qr_chunk_reg<BWP, 4>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg);    \
+  else                                                                                           \
+    qr_chunk_reg<BWP, kQrRpt>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg);
+  if (bwp == 4) { RBGS_QRC(4) }
+  else if (bwp == 8) { RBGS_QRC(8) }
+  else if (bwp == 16) { RBGS_QRC(16) }
+  else { RBGS_QRC(32) }
+#undef RBGS_QRC
 }
 
 size_t qr_stack_size(int64_t k, int bw) {
-  const int64_t CH = kQrLds / bw;
+  const int64_t CH = qr_chunk_rows(bw);
   int64_t rows = k, total = 0;
   while (rows > CH) {
     const int64_t nch = ceil_div(rows, CH);
@@ -332,16 +389,16 @@ __device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned t
 __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
     const double* __restrict__ src, int64_t k, int bw, double* __restrict__ stack,
     unsigned* counter, double* __restrict__ Rii, int64_t ldr, int64_t* flag, int64_t col0) {
-  __shared__ double A[kQrLds];
-  __shared__ double red[kQrMaxB + 1];
+  __shared__ double xb[2 * (kQrThreads / 4) * kQrRpt];
+  __shared__ double sg[2 + kQrMaxB];
   const int CH = qr_chunk_rows(bw);
   const int64_t nch = (k + CH - 1) / CH;
   if (nch == 1) {
-    qr_chunk(src, k, k, bw, Rii, ldr, 1, flag, col0, 0, A, red);
+    qr_chunk(src, k, k, bw, Rii, ldr, 1, flag, col0, 0, xb, sg);
     return;
   }
   const int64_t ld1 = nch * bw;
-  qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, blockIdx.x, A, red);
+  qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, blockIdx.x, xb, sg);
   if (!last_block_arrives(counter, (unsigned)nch)) return;
   // remaining levels in this workgroup
   const double* lsrc = stack;
@@ -351,13 +408,13 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
     const int64_t n2 = (lrows + CH - 1) / CH;
     const int64_t out_rows = n2 * bw;
     for (int64_t b2 = 0; b2 < n2; ++b2)
-      qr_chunk(lsrc, ld_in, lrows, bw, buf, out_rows, 0, nullptr, 0, b2, A, red);
+      qr_chunk(lsrc, ld_in, lrows, bw, buf, out_rows, 0, nullptr, 0, b2, xb, sg);
     lsrc = buf;
     ld_in = out_rows;
     lrows = out_rows;
     buf += out_rows * bw;
   }
-  qr_chunk(lsrc, ld_in, lrows, bw, Rii, ldr, 1, flag, col0, 0, A, red);
+  qr_chunk(lsrc, ld_in, lrows, bw, Rii, ldr, 1, flag, col0, 0, xb, sg);
   if (threadIdx.x == 0) *counter = 0u;
 }
 
@@ -391,7 +448,7 @@ hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, 
 hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
                            double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st) {
   if (bw > kQrMaxB) return hipErrorInvalidValue;
-  const int64_t CH = kQrLds / bw;
+  const int64_t CH = qr_chunk_rows(bw);
   hipLaunchKernelGGL(qr_fused_kernel, dim3((unsigned)ceil_div(k, CH)), dim3(kQrThreads), 0, st, src,
                      k, bw, stack, counter, Rii, ldr, flag, col0);
   return hipGetLastError();
