@@ -18,8 +18,10 @@ QR (N = m/p blocks, s = bytes per element; each block reads Q_(1:i-1) and W_(i)
 once and writes Q_(i) once) divided by the measured time per QR.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +31,27 @@ sys.path.insert(0, ROOT)
 METRIC = "RBGS QR time & HBM GB/s at n=1e6 m=256: FP32/BF16x3 vs FP64 at equal error"
 HBM_PEAK_GBS = 8000.0
 LS_ITERS = 4   # Richardson sweeps of the least-squares step
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernel_hbm_traffic_n1e6_m256_p16_k1024_f32.md")
+UPDATE_SRC = os.path.join(ROOT, "paper_2111_14641_amd", "csrc", "update_kernels.hip")
+
+
+def measured_traffic(n, m, p, k):
+    """HBM bytes per update launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None if it covers another workload or an older kernel source."""
+    if (n, m, p, k) != (1_000_000, 256, 16, 1024):
+        return None
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(UPDATE_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    mt = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    mh = re.search(r"source_sha256 \([^)]*\):\s*([0-9a-f]{64})", text)
+    if not mt or not mh or mh.group(1) != src:
+        return None
+    return int(mt.group(1))
 
 
 def alg_bytes(n, m, p, s):
@@ -54,36 +77,86 @@ def accuracy(W, Q, R, cert):
     return dict(rel_err=err, cond2_Q=cond, delta=cert["delta"], delta_tilde=cert["delta_tilde"])
 
 
-def time_form(W, p, kind, k, seed, variant, steps, warmup, profile=False, math="f64"):
+def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64"):
+    """Times `steps` QRs on a dedicated stream.  With profile_update, HIP events
+    bracket every update launch inside the timed region (the roofline figure)."""
     import torch
     from paper_2111_14641_amd import binding as B
     n, m = W.shape
     Q = B.colmajor(n, m, W.dtype, W.device)
     R = B.colmajor(m, m, torch.float64, W.device)
-    # accuracy run (with certificate) outside the timed region
-    _, _, _, cert = B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, want_cert=True, math=math)
-    acc = accuracy(W, Q, R, cert)
-    for _ in range(warmup):
-        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
-    torch.cuda.synchronize()
-    if profile:
-        B.profile_enable(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(steps):
-        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
-    prof = None
-    if profile:
-        prof = {name: B.profile_get(name) for name in ("update", "sketch", "reduce", "small", "trsm")}
-        B.profile_enable(False)
+    run = lambda **kw: B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math, **kw)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        # accuracy run (with certificate) outside the timed region
+        _, _, _, cert = run(want_cert=True)
+        acc = accuracy(W, Q, R, cert)
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        if profile_update:
+            B.profile_enable(True, classes=["update"])
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(steps):
+            run()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        upd = None
+        if profile_update:
+            upd = B.profile_get("update")
+            B.profile_enable(False)
     s = 4 if W.dtype == torch.float32 else 8
     gbs = alg_bytes(n, m, p, s) / (ms * 1e-3) / 1e9
-    return dict(ms=ms, alg_GBps=gbs, **acc), prof
+    return dict(ms=ms, alg_GBps=gbs, **acc), upd
+
+
+def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
+    """Per-class kernel milliseconds per QR (events around every launch; run
+    after the timed region because the events themselves cost time)."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    n, m = W.shape
+    Q = B.colmajor(n, m, W.dtype, W.device)
+    R = B.colmajor(m, m, torch.float64, W.device)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+        torch.cuda.synchronize()
+        B.profile_enable(True)
+        for _ in range(reps):
+            B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+        torch.cuda.synchronize()
+        out = {name: round(B.profile_get(name)[0] / reps, 4)
+               for name in ("update", "sketch", "reduce", "small", "trsm")}
+        B.profile_enable(False)
+    return out
+
+
+def copy_bandwidth():
+    """Measured rate of a plain streaming kernel, y = x + 1 over 1 GiB of FP32
+    (1 GiB read + 1 GiB written): a practical ceiling beside the nominal
+    8 TB/s, and the known-size dispatch that calibrates the FETCH_SIZE /
+    WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.add(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(10):
+        torch.add(a, 1.0, out=b)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 10
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(W64_host, p, k, seed, target_s=15.0):
@@ -148,9 +221,11 @@ def main():
 
     forms = {}
     print("[bench] fp32 sparse lowsync (headline)", file=sys.stderr, flush=True)
-    head, prof = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync", args.steps,
-                           args.warmup, profile=True)
+    head, upd = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync", args.steps,
+                          args.warmup, profile_update=True)
     forms["f32_sparse_lowsync"] = head
+    print("[bench] kernel breakdown", file=sys.stderr, flush=True)
+    kernel_ms = kernel_breakdown(W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync")
     if args.forms == "all":
         print("[bench] fp64 sparse lowsync", file=sys.stderr, flush=True)
         forms["f64_sparse_lowsync"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "lowsync",
@@ -170,14 +245,18 @@ def main():
                                                       "lowsync", max(2, args.steps // 10), 1)
             forms["f64_gauss_lowsync"], _ = time_form(W64, p, "gaussian", k, THETA_SEED_LARGE,
                                                       "lowsync", max(2, args.steps // 10), 1)
-    upd_ms, upd_cnt, upd_bytes = prof["update"]
+    del W64
+    copy_gbs = copy_bandwidth()
+    upd_ms, upd_cnt, upd_bytes = upd
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(n, m, p, k),
+                    traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    alg_bytes_per_launch=round(upd_bytes / max(upd_cnt, 1)),
                     kernel="update_kernel<float,double,1> (step 3 + substitution, low-sync)",
-                    avg_launch_us=round(upd_ms / max(upd_cnt, 1) * 1e3, 2),
-                    share_of_step=round(upd_ms / args.steps / head["ms"], 3))
-    kernel_ms = {name: round(v[0] / args.steps, 4) for name, v in prof.items()}
+                    launches=upd_cnt, avg_launch_us=round(upd_ms / max(upd_cnt, 1) * 1e3, 2),
+                    share_of_step=round(upd_ms / args.steps / head["ms"], 3),
+                    copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4))
     speedup = None
     if "f64_sparse_lowsync" in forms:
         speedup = forms["f64_sparse_lowsync"]["ms"] / head["ms"]

@@ -168,9 +168,10 @@ RBGS_API rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int
 RBGS_API rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
                              float* out, void* stream);
 
-/* Kernel timing for measurements.  With profiling enabled, the handle records
- * HIP events around every launch of the kernels named below on the stream it
- * enqueues them on.  rbgs_profile_get waits for the recorded events and
+/* Kernel timing for measurements.  rbgs_profile_enable takes a bit mask of
+ * kernel classes (bit c enables class c; 0 disables; -1 enables all) and
+ * clears the totals.  For every enabled class the handle records HIP events
+ * around each launch on the stream it enqueues it on.  rbgs_profile_get waits for the recorded events and
  * returns, for kernel class `which`, the summed duration in milliseconds, the
  * number of launches and the summed algorithmic bytes (the minimal HBM
  * traffic of those launches: each input element read once, each output

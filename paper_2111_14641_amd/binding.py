@@ -233,10 +233,17 @@ def theta_dense(kind, k, seed, n, row0=0, zeta=8, device="cuda"):
     return out
 
 
-def profile_enable(enable=True, device=0):
+def profile_enable(enable=True, device=0, classes=None):
+    """Record kernel timings: all classes, or only those named in `classes`."""
     lib = Library.get()
     h = lib.handle(device)
-    lib.check(lib.rbgs_profile_enable(h, enable), h)
+    if not enable:
+        mask = 0
+    elif classes is None:
+        mask = -1
+    else:
+        mask = sum(1 << PROFILE[c] for c in classes)
+    lib.check(lib.rbgs_profile_enable(h, mask), h)
 
 
 def profile_get(which, device=0):

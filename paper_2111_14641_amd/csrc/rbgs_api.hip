@@ -33,7 +33,7 @@ struct rbgs_handle_s {
   std::string last_error;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  bool profiling = false;
+  uint32_t prof_mask = 0;  // bit c: record launches of kernel class c
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   double prof_ms[kProfClasses] = {0};
@@ -92,7 +92,7 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   ProfScope(rbgs_handle h_, int which_, double bytes_, hipStream_t st_)
       : h(h_), which(which_), bytes(bytes_), st(st_) {
-    if (h->profiling) {
+    if ((h->prof_mask >> which) & 1u) {
       a = take_event(h);
       if (a) (void)hipEventRecord(a, st);
     }
@@ -499,7 +499,7 @@ rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, in
 
 rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable) {
   if (!h) return RBGS_EINVAL;
-  h->profiling = enable != 0;
+  h->prof_mask = (uint32_t)enable & ((1u << kProfClasses) - 1u);
   for (int i = 0; i < kProfClasses; ++i) {
     h->prof_ms[i] = 0;
     h->prof_cnt[i] = 0;

@@ -21,7 +21,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 #ifndef RBGS_UP_UNROLL
-#define RBGS_UP_UNROLL 8
+#define RBGS_UP_UNROLL 4
 #endif
 #ifndef RBGS_UP_PINGPONG
 #define RBGS_UP_PINGPONG 1
