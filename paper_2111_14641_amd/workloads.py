@@ -15,6 +15,11 @@ returned in FP64, column-major (Fortran order), so that column j is contiguous.
   rank-deficient, which stands in for the matrix of the paper's first numerical
   example (Section 5.1), whose exact generator differs; with n = 10^6 and
   m = 256 this is the large single-QR workload.
+* `svd_matrix_gpu(n, m, sigma, seed)`: the same construction as `svd_matrix`
+  built on the GPU with torch (U from a seeded device Gaussian by two rounds of
+  Cholesky orthonormalization, V on the host), for sizes whose FP64 factors do
+  not fit comfortably in host memory; with n = 4 10^6, m = 512 and
+  sigma = logspace(0, -10, 512) this is the mixed-precision workload.
 """
 import numpy as np
 
@@ -51,6 +56,27 @@ def oscillatory_matrix(n, m, seed, dtype=np.float64, chunk=1 << 17):
         mx = mu[None, :] * x
         W[r0:r1, :] = np.sin(10.0 * (mx + 1.0)) / (np.cos(100.0 * mx - 100.0 * mu[None, :]) + 1.1)
     return W
+
+
+def svd_matrix_gpu(n, m, sigma, seed, device="cuda"):
+    """W = U diag(sigma) V^T as an FP64 column-major CUDA tensor."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    U = torch.randn((n, m), generator=g, dtype=torch.float64, device=device)
+    for _ in range(2):
+        L = torch.linalg.cholesky(U.t() @ U)
+        U = torch.linalg.solve_triangular(L.t(), U, upper=True, left=False)  # U L^{-T}
+    V = _orthonormal(np.random.default_rng(seed), m, m)
+    M = torch.from_numpy(np.asarray(sigma, dtype=np.float64)[:, None] * V.T).to(device)
+    W = torch.empty((m, n), dtype=torch.float64, device=device).t()
+    W.copy_(U @ M)
+    return W
+
+
+def mixed_single_qr_gpu(seed=0xDA7A02, n=4_000_000, m=512, decades=10.0):
+    """The mixed-precision single-QR workload (cond(W) = 10^decades), on the GPU."""
+    return svd_matrix_gpu(n, m, np.logspace(0.0, -decades, m), seed)
 
 
 def large_single_qr(seed=0xDA7A01, n=1_000_000, m=256, dtype=np.float64):

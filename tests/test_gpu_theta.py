@@ -96,3 +96,25 @@ def test_identity_sketch_copies(gpu_lib):
     Xt = B.colmajor(50, 3, torch.float64)
     Xt.copy_(torch.from_numpy(X))
     assert np.array_equal(to_np(B.sketch_apply(Xt, "identity", 50, seed=0)), X)
+
+
+@pytest.mark.parametrize("kind,k", [("sparse", 1024), ("gaussian", 256)])
+def test_row_shards_sum_to_the_whole(gpu_lib, kind, k):
+    """Theta's columns are addressed by the global row index, so sketching G row
+    ranges with their row offsets and adding the parts in a fixed order gives
+    the sketch of the whole matrix (up to summation order): the one exchange a
+    row-sharded run needs per block."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("virtual shards", kind, k)
+    n, c = 300_001, 16
+    X = np.random.default_rng(5).standard_normal((n, c))
+    Xt = B.colmajor(n, c, torch.float64)
+    Xt.copy_(torch.from_numpy(X))
+    whole = to_np(B.sketch_apply(Xt, kind, k, seed=21))
+    bounds = [0, 70_000, 150_123, 299_999, n]
+    parts = np.zeros_like(whole)
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        parts += to_np(B.sketch_apply(Xt[a:b], kind, k, seed=21, row0=a))
+    tol = 1e-15 * (10 + np.sqrt(n)) * abs_sketch(kind, k, 21, X, 0)
+    assert np.all(np.abs(parts - whole) <= tol)
