@@ -40,6 +40,8 @@ struct rbgs_handle_s {
   int64_t prof_cnt[kProfClasses] = {0};
   double prof_bytes[kProfClasses] = {0};
   double* host_cert = nullptr;  // pinned, 4 doubles + flag
+  hipStream_t side = nullptr;   // sketches of later blocks of W run here (default priority)
+  std::vector<hipEvent_t> sync_ev;  // ordering between the caller's stream and `side`
 };
 
 namespace {
@@ -112,6 +114,30 @@ struct ProfScope {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+#ifndef RBGS_SIDE_GROUPS
+#define RBGS_SIDE_GROUPS 128
+#endif
+constexpr int kSideGroups = RBGS_SIDE_GROUPS;  // partial groups of a side-stream sketch
+
+// The side stream (created once, default priority, not blocking on the null
+// stream) and at least `nev` ordering events.
+rbgs_status ensure_side(rbgs_handle h, size_t nev) {
+  if (!h->side && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    h->side = nullptr;
+    return fail(h, RBGS_EDEVICE, "side stream creation failed");
+  }
+  while (h->sync_ev.size() < nev) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, RBGS_EDEVICE, "event creation failed");
+    }
+    h->sync_ev.push_back(e);
+  }
+  return RBGS_OK;
+}
+
 rbgs_status ensure_ws(rbgs_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return RBGS_OK;
   if (h->ws) {
@@ -167,25 +193,26 @@ double sketch_scale(const SketchDesc& d) {
   return 1.0;
 }
 
-size_t sketch_partial_doubles(const SketchDesc& d, int64_t n, int64_t ncols) {
+size_t sketch_partial_doubles(const SketchDesc& d, int64_t n, int64_t ncols, int max_groups = 0) {
   if (d.kind == kIdentity) return 0;
-  return (size_t)sketch_num_partials(d, n, ncols) * (size_t)ncols * (size_t)d.k;
+  return (size_t)sketch_num_partials(d, n, ncols, max_groups) * (size_t)ncols * (size_t)d.k;
 }
 
 // out = Theta X (k x ncols, ld ldo)
 rbgs_status do_sketch(rbgs_handle h, const SketchDesc& d, bool f32, const void* X, int64_t ldx,
                       int64_t n, int64_t ncols, int64_t row0, double* out, int64_t ldo,
-                      double* partial, const uint16_t* plan, hipStream_t st) {
+                      double* partial, const uint16_t* plan, hipStream_t st, int max_groups = 0) {
   const double s = f32 ? 4.0 : 8.0;
   if (d.kind == kIdentity) {
     ProfScope ps(h, kProfSketch, s * n * ncols + 8.0 * n * ncols, st);
     HIP_TRY(h, launch_sketch_identity(f32, X, ldx, n, ncols, out, ldo, st), "sketch_identity");
     return RBGS_OK;
   }
-  const int G = sketch_num_partials(d, n, ncols);
+  const int G = sketch_num_partials(d, n, ncols, max_groups);
   {
     ProfScope ps(h, kProfSketch, s * n * ncols, st);
-    HIP_TRY(h, launch_sketch_partials(d, f32, X, ldx, n, ncols, row0, partial, plan, st), "sketch");
+    HIP_TRY(h, launch_sketch_partials(d, f32, X, ldx, n, ncols, row0, partial, plan, st, max_groups),
+            "sketch");
   }
   {
     ProfScope ps(h, kProfReduce, 8.0 * d.k * ncols, st);
@@ -210,7 +237,7 @@ rbgs_status rbgs_create(rbgs_handle* h, int device) {
 
 rbgs_status rbgs_destroy(rbgs_handle h) {
   if (!h) return RBGS_OK;
-  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert) {
+  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side) {
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     for (auto& r : h->recs) {
@@ -218,6 +245,8 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
       (void)hipEventDestroy(r.b);
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
+    for (auto e : h->sync_ev) (void)hipEventDestroy(e);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_cert) (void)hipHostFree(h->host_cert);
   }
@@ -305,6 +334,18 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   size_t part_need = std::max(sketch_partial_doubles(d, n, m), sketch_partial_doubles(d, n, std::min<int64_t>(b, m)));
   if (m % b) part_need = std::max(part_need, sketch_partial_doubles(d, n, m % b));
   const size_t o_part = carve(part_need);
+  // The sketches of blocks 1.. of W run on a side stream while the main
+  // stream works through earlier blocks (they only read W and the plan); the
+  // small factors of a block use few compute units, so these sketches mostly
+  // fill idle ones.  Block i waits for its sketch before its least squares.
+  const int64_t nblk = (m + b - 1) / b;
+  const bool overlap = d.kind != kIdentity && nblk > 1;
+  size_t part2_need = 0;
+  if (overlap) {
+    part2_need = sketch_partial_doubles(d, n, std::min<int64_t>(b, m), kSideGroups);
+    if (m % b) part2_need = std::max(part2_need, sketch_partial_doubles(d, n, m % b, kSideGroups));
+  }
+  const size_t o_part2 = carve(part2_need);
   const size_t o_stack = carve(qr_stack_size(k, b));
   const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
@@ -321,6 +362,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   double* P = (double*)(base + o_P);
   double* E = (double*)(base + o_E);
   double* part = (double*)(base + o_part);
+  double* part2 = (double*)(base + o_part2);
   double* stack = (double*)(base + o_stack);
   uint16_t* plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
   int64_t* flag = (int64_t*)(base + o_flag);
@@ -339,10 +381,28 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
     HIP_TRY(h, launch_sparse_plan(d, n, 0, plan, st), "sketch plan");
   }
 
-  // ---- step 1 for all blocks at once: P = Theta W (W is not modified before
-  // its block is reached, so hoisting the sketches of the blocks is exact) --
-  rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, plan, st);
-  if (rs != RBGS_OK) return rs;
+  // ---- step 1 ahead of the loop: P = Theta W (W_(i) is not modified before
+  // block i, so sketching it early gives the same P_(i)) --------------------
+  if (!overlap) {
+    rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, plan, st);
+    if (rs != RBGS_OK) return rs;
+  } else {
+    rs = ensure_side(h, (size_t)nblk + 1);
+    if (rs != RBGS_OK) return rs;
+    hipEvent_t ev_start = h->sync_ev[nblk];
+    HIP_TRY(h, hipEventRecord(ev_start, st), "event record");
+    HIP_TRY(h, hipStreamWaitEvent(h->side, ev_start, 0), "stream wait");
+    rs = do_sketch(h, d, f32, W, ldw, n, std::min<int64_t>(b, m), 0, P, k, part, plan, st);
+    if (rs != RBGS_OK) return rs;
+    for (int64_t blk = 1; blk < nblk; ++blk) {
+      const int64_t c0 = blk * b;
+      const int64_t bwb = std::min<int64_t>(b, m - c0);
+      rs = do_sketch(h, d, f32, (const char*)W + es * (size_t)(c0 * ldw), ldw, n, bwb, 0,
+                     P + c0 * k, k, part2, plan, h->side, kSideGroups);
+      if (rs != RBGS_OK) return rs;
+      HIP_TRY(h, hipEventRecord(h->sync_ev[blk], h->side), "event record");
+    }
+  }
 
   const char* Wb = (const char*)W;
   char* Qb = (char*)Q;
@@ -356,6 +416,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
     const void* Wi = Wb + es * (size_t)(c0 * ldw);
     void* Qi = Qb + es * (size_t)(c0 * ldq);
 
+    if (overlap && K > 0) HIP_TRY(h, hipStreamWaitEvent(st, h->sync_ev[c0 / b], 0), "stream wait");
     // ---- step 2: sketched least squares by l Richardson sweeps ----------
     // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
     // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.

@@ -143,8 +143,10 @@ struct SketchDesc {
   uint32_t key0, key1;
 };
 
-// Number of partial blocks (row ranges) the sketch kernels use for n rows.
-int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols);
+// Number of partial blocks (row ranges) the sketch kernels use for n rows;
+// max_groups > 0 caps it (a sketch that runs beside other work occupies fewer
+// compute units for longer).
+int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups = 0);
 // Columns handled per partial block pass.
 constexpr int kSketchCols = 16;
 
@@ -153,11 +155,12 @@ constexpr int kSketchCols = 16;
 size_t sparse_plan_bytes(const SketchDesc& sk, int64_t n);
 hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uint16_t* plan,
                               hipStream_t st);
-// partial[g][c][t] (g < G, c < ncols, t < k), G = sketch_num_partials(sk, n, ncols).
+// partial[g][c][t] (g < G, c < ncols, t < k),
+// G = sketch_num_partials(sk, n, ncols, max_groups).
 // `plan` (sparse sign only) must have been built for the same rows.
 hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
-                                  const uint16_t* plan, hipStream_t st);
+                                  const uint16_t* plan, hipStream_t st, int max_groups = 0);
 // out[t + c*ldo] = scale * sum_g partial[g][c][t]
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
                                 double scale, double* out, int64_t ldo, hipStream_t st);

@@ -419,7 +419,7 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
 // ---------------------------------------------------------------------------
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols) {
+int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups) {
   // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
   // over the column groups.  Gaussian: about 512 workgroups of 256 threads.
   // Each row range is at least one tile long.
@@ -433,6 +433,7 @@ int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols) {
     tile = kSpTile;
   }
   G = std::min<int64_t>(G, ceil_div(n, tile));
+  if (max_groups > 0) G = std::min<int64_t>(G, max_groups);
   return (int)std::max<int64_t>(1, G);
 }
 
@@ -458,10 +459,10 @@ hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uin
 
 hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
-                                  const uint16_t* plan, hipStream_t st) {
+                                  const uint16_t* plan, hipStream_t st, int max_groups) {
   const uint16_t* plan_off = plan;
   const uint16_t* plan_ent = plan ? plan + plan_ent_offset(sk, n) : nullptr;
-  const int G = sketch_num_partials(sk, n, ncols);
+  const int G = sketch_num_partials(sk, n, ncols, max_groups);
   const int64_t groups = ceil_div(ncols, kSketchCols);
   if (sk.kind == kSparse) {
     if (plan_off == nullptr || plan_ent == nullptr) return hipErrorInvalidValue;

@@ -28,7 +28,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 constexpr int kQrThreads = 256;
 constexpr int kQrMaxB = 32;
-constexpr int kQrRpt = 16;  // rows per thread in a chunk
+#ifndef RBGS_QR_RPT
+#define RBGS_QR_RPT 16
+#endif
+constexpr int kQrRpt = RBGS_QR_RPT;  // rows per thread in a chunk
 
 // Columns padded to a power of two (>= 4); NG = 256 / BWP threads per column.
 __host__ __device__ __forceinline__ int qr_bwp(int bw) {
@@ -271,7 +274,7 @@ hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
 // ---------------------------------------------------------------------------
 
 // out0[j][c] = sum_t S[t][j] X0[t][c] (c < n0), out1[j][c] = sum_t S[t][j] X1[t][c]
-// (c < n1), j < K.  16 lanes per output (t strided by 16), shuffle reduction.
+// (c < n1), j < K.  One wave per output (t strided by 64), fixed reduction tree.
 __global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict__ S, int64_t k,
                                                        int64_t K, const double* __restrict__ X0,
                                                        int n0, const double* __restrict__ X1,
@@ -279,8 +282,8 @@ __global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict_
                                                        int64_t ldo0, double* __restrict__ out1,
                                                        int64_t ldo1, double* __restrict__ out1t,
                                                        int64_t ldo1t) {
-  const int q = threadIdx.x & 15;
-  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;  // output index
+  const int lane = threadIdx.x & 63;
+  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // output index
   const int ncol = n0 + n1;
   const bool ok = o < K * ncol;
   const int64_t j = ok ? o % K : 0;
@@ -288,18 +291,16 @@ __global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict_
   const double* x = col < n0 ? X0 + (int64_t)col * k : X1 + (int64_t)(col - n0) * k;
   const double* sj = S + j * k;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int64_t t = q;
-  for (; t + 48 < k; t += 64) {
+  int64_t t = lane;
+  for (; t + 192 < k; t += 256) {
     a0 = fma(sj[t], x[t], a0);
-    a1 = fma(sj[t + 16], x[t + 16], a1);
-    a2 = fma(sj[t + 32], x[t + 32], a2);
-    a3 = fma(sj[t + 48], x[t + 48], a3);
+    a1 = fma(sj[t + 64], x[t + 64], a1);
+    a2 = fma(sj[t + 128], x[t + 128], a2);
+    a3 = fma(sj[t + 192], x[t + 192], a3);
   }
-  for (; t < k; t += 16) a0 = fma(sj[t], x[t], a0);
-  double v = (a0 + a1) + (a2 + a3);
-#pragma unroll
-  for (int d = 1; d < 16; d <<= 1) v += __shfl_xor(v, d, 64);
-  if (ok && q == 0) {
+  for (; t < k; t += 64) a0 = fma(sj[t], x[t], a0);
+  const double v = group_sum<64>((a0 + a1) + (a2 + a3));
+  if (ok && lane == 0) {
     if (col < n0) {
       out0[j + (int64_t)col * ldo0] = v;
     } else {
@@ -310,66 +311,52 @@ __global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict_
   }
 }
 
-// Ynew[j][c] = Y[j][c] + C[j][c] - sum_l G[j][l] Y[l][c].  4 lanes per output
-// split l in quarters; lanes (jl, q) = (lane % 16, lane / 16) in each wave.
+// Ynew[j][c] = Y[j][c] + C[j][c] - sum_l G[j][l] Y[l][c], reading row j of the
+// symmetric G as its column j (both halves are stored), so both operands of
+// the dot are contiguous.  16 lanes per output (l strided by 16).
 __global__ __launch_bounds__(256) void gram_sweep_kernel(const double* __restrict__ G, int64_t ldg,
                                                          int64_t K, const double* __restrict__ C,
                                                          const double* __restrict__ Y,
                                                          int64_t ldy, double* __restrict__ Ynew,
                                                          int64_t ldyn, int bw) {
-  const int lane = threadIdx.x & 63;
-  const int jl = lane & 15, q = lane >> 4;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // wave index
-  const int64_t jblocks = (K + 15) / 16;
-  const bool okw = w < jblocks * bw;
-  const int64_t jb = okw ? w % jblocks : 0;
-  const int c = okw ? (int)(w / jblocks) : 0;
-  const int64_t j = jb * 16 + jl;
-  const bool ok = okw && j < K;
-  const int64_t jc = ok ? j : 0;
-  const int64_t l0 = (K * q) / 4, l1 = (K * (q + 1)) / 4;
+  const int q = threadIdx.x & 15;
+  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const bool ok = o < K * bw;
+  const int64_t j = ok ? o % K : 0;
+  const int c = ok ? (int)(o / K) : 0;
+  const double* gj = G + j * ldg;
   const double* yc = Y + (int64_t)c * ldy;
   double a0 = 0.0, a1 = 0.0;
-  int64_t l = l0;
-  for (; l + 1 < l1; l += 2) {
-    a0 = fma(G[jc + l * ldg], yc[l], a0);
-    a1 = fma(G[jc + (l + 1) * ldg], yc[l + 1], a1);
+  int64_t l = q;
+  for (; l + 16 < K; l += 32) {
+    a0 = fma(gj[l], yc[l], a0);
+    a1 = fma(gj[l + 16], yc[l + 16], a1);
   }
-  if (l < l1) a0 = fma(G[jc + l * ldg], yc[l], a0);
-  double v = a0 + a1;
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+  for (; l < K; l += 16) a0 = fma(gj[l], yc[l], a0);
+  const double v = group_sum<16>(a0 + a1);
   if (ok && q == 0) Ynew[j + (int64_t)c * ldyn] = yc[j] + (C[j + (int64_t)c * K] - v);
 }
 
-// E[t][c] = P[t][c] - sum_j S[t][j] Y[j][c].  4 lanes per output split j in
-// quarters; lanes (tl, q) = (lane % 16, lane / 16).
+// E[t][c] = P[t][c] - sum_j S[t][j] Y[j][c].  16 lanes per output split j
+// (strided by 16); lane = q + 16 tl covers rows t = 4 tb + tl.
 __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P,
                                                     const double* __restrict__ S, int64_t k,
                                                     int64_t K, const double* __restrict__ Y,
                                                     int64_t ldy, double* __restrict__ E, int bw) {
-  const int lane = threadIdx.x & 63;
-  const int tl = lane & 15, q = lane >> 4;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t tblocks = (k + 15) / 16;
-  const bool okw = w < tblocks * bw;
-  const int64_t tb = okw ? w % tblocks : 0;
-  const int c = okw ? (int)(w / tblocks) : 0;
-  const int64_t t = tb * 16 + tl;
-  const bool ok = okw && t < k;
-  const int64_t tc = ok ? t : 0;
-  const int64_t j0 = (K * q) / 4, j1 = (K * (q + 1)) / 4;
+  const int q = threadIdx.x & 15;
+  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;  // output index
+  const bool ok = o < k * bw;
+  const int64_t t = ok ? o % k : 0;
+  const int c = ok ? (int)(o / k) : 0;
   const double* yc = Y + (int64_t)c * ldy;
   double a0 = 0.0, a1 = 0.0;
-  int64_t j = j0;
-  for (; j + 1 < j1; j += 2) {
-    a0 = fma(S[tc + j * k], yc[j], a0);
-    a1 = fma(S[tc + (j + 1) * k], yc[j + 1], a1);
+  int64_t j = q;
+  for (; j + 16 < K; j += 32) {
+    a0 = fma(S[t + j * k], yc[j], a0);
+    a1 = fma(S[t + (j + 16) * k], yc[j + 16], a1);
   }
-  if (j < j1) a0 = fma(S[tc + j * k], yc[j], a0);
-  double v = a0 + a1;
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+  for (; j < K; j += 16) a0 = fma(S[t + j * k], yc[j], a0);
+  const double v = group_sum<16>(a0 + a1);
   if (ok && q == 0) E[t + (int64_t)c * k] = P[t + (int64_t)c * k] - v;
 }
 
@@ -418,10 +405,122 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// ---------------------------------------------------------------------------
+// R_(i,i) of a k x bw sketch with k <= 1024 and bw <= 16 in one workgroup of
+// 16 waves: wave c keeps column c in registers (lane l holds rows l + 64 i),
+// so every reduction is within one wave (DPP inside rows of 16 lanes, then
+// the four row sums read as scalars and added in a fixed order: every lane
+// gets the same bits).  Householder steps as in qr_chunk_reg: column j and
+// its squared norm are published through LDS (double-buffered), one barrier
+// per column.
+// ---------------------------------------------------------------------------
+constexpr int kQwThreads = 1024;
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+  v = group_sum<16>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kQwThreads) void qr_wave_kernel(const double* __restrict__ src,
+                                                             int64_t k, int bw,
+                                                             double* __restrict__ Rii, int64_t ldr,
+                                                             int64_t* flag, int64_t col0) {
+  constexpr int CH = 64 * RPT;
+  __shared__ double xb[2 * CH];
+  __shared__ double sg[2];
+  __shared__ double diag[16];
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  const bool col_ok = c < bw;
+  double a[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = lane + 64 * i;
+    const bool ok = col_ok && r < k;
+    const double v = src[ok ? r + (int64_t)c * k : 0];
+    a[i] = ok ? v : 0.0;
+  }
+  if (c == 0) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      xb[lane + 64 * i] = a[i];
+      s2 = fma(a[i], a[i], s2);
+    }
+    s2 = wave_total(s2);
+    if (lane == 0) sg[0] = s2;
+  }
+  __syncthreads();
+  for (int j = 0; j < bw; ++j) {
+    const double* xj = xb + (j & 1) * CH;
+    const double sigma = sg[j & 1];
+    const double x0 = xj[j];
+    double alpha = 0.0, beta = 0.0, v0 = x0;
+    if (sigma != 0.0) {
+      const double nrm = sqrt(sigma);
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      beta = 1.0 / (nrm * (nrm + fabs(x0)));
+      v0 = x0 - alpha;
+    }
+    if (c > j && col_ok && beta != 0.0) {
+      // rows lane + 64 i with i >= 1 are >= 64 > j: only i = 0 needs the mask
+      double v[RPT];
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const double x = xj[lane + 64 * i];
+        v[i] = i > 0 ? x : (lane < j ? 0.0 : (lane == j ? v0 : x));
+        if (i & 1) d1 = fma(v[i], a[i], d1);
+        else d0 = fma(v[i], a[i], d0);
+      }
+      const double w = beta * wave_total(d0 + d1);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) a[i] = fma(-w, v[i], a[i]);
+    }
+    if (c == j && lane == j) a[0] = sigma != 0.0 ? alpha : 0.0;
+    if (c == j + 1 && col_ok) {
+      double* xn = xb + ((j + 1) & 1) * CH;
+      double s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        xn[lane + 64 * i] = a[i];
+        if (i > 0 || lane > j) s2 = fma(a[i], a[i], s2);
+      }
+      s2 = wave_total(s2);
+      if (lane == 0) sg[(j + 1) & 1] = s2;
+    }
+    __syncthreads();
+  }
+  // R_(r,c), r <= c < bw, sits in lane r of wave c (i = 0)
+  if (col_ok && lane == c) diag[c] = a[0];
+  __syncthreads();
+  if (col_ok && lane < bw) {
+    const double sgn = diag[lane] < 0.0 ? -1.0 : 1.0;
+    Rii[lane + (int64_t)c * ldr] = lane <= c ? sgn * a[0] : 0.0;
+  }
+  if (threadIdx.x == 0 && flag != nullptr) {
+    for (int j = 0; j < bw; ++j) {
+      const double d = diag[j];
+      if (!(d != 0.0) || !isfinite(d)) {
+        atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
+                  (unsigned long long)(col0 + j));
+        break;
+      }
+    }
+  }
+}
+
 hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* X0, int n0,
                            const double* X1, int n1, double* out0, int64_t ldo0, double* out1,
                            int64_t ldo1, double* out1t, int64_t ldo1t, hipStream_t st) {
-  const int64_t threads = K * (n0 + n1) * 16;
+  const int64_t threads = K * (n0 + n1) * 64;
   if (threads == 0) return hipSuccess;
   hipLaunchKernelGGL(gram_sty_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st, S,
                      k, K, X0, n0, X1, n1, out0, ldo0, out1, ldo1, out1t, ldo1t);
@@ -431,16 +530,17 @@ hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* 
 hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const double* C,
                              const double* Y, int64_t ldy, double* Ynew, int64_t ldyn, int bw,
                              hipStream_t st) {
-  const int64_t waves = ceil_div(K, 16) * bw;
-  hipLaunchKernelGGL(gram_sweep_kernel, dim3((unsigned)ceil_div(waves * 64, 256)), dim3(256), 0, st,
+  const int64_t threads = K * bw * 16;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(gram_sweep_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st,
                      G, ldg, K, C, Y, ldy, Ynew, ldyn, bw);
   return hipGetLastError();
 }
 
 hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
                         int64_t ldy, double* E, int bw, hipStream_t st) {
-  const int64_t waves = ceil_div(k, 16) * bw;
-  hipLaunchKernelGGL(resid_kernel, dim3((unsigned)ceil_div(waves * 64, 256)), dim3(256), 0, st, P,
+  const int64_t threads = k * bw * 16;
+  hipLaunchKernelGGL(resid_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st, P,
                      S, k, K, Y, ldy, E, bw);
   return hipGetLastError();
 }
@@ -448,6 +548,16 @@ hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, 
 hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
                            double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st) {
   if (bw > kQrMaxB) return hipErrorInvalidValue;
+  if (bw <= 16 && k <= 1024) {
+#define RBGS_QW(R)                                                                              \
+  hipLaunchKernelGGL(qr_wave_kernel<R>, dim3(1), dim3(kQwThreads), 0, st, src, k, bw, Rii, ldr, \
+                     flag, col0)
+    if (k <= 256) RBGS_QW(4);
+    else if (k <= 512) RBGS_QW(8);
+    else RBGS_QW(16);
+#undef RBGS_QW
+    return hipGetLastError();
+  }
   const int64_t CH = qr_chunk_rows(bw);
   hipLaunchKernelGGL(qr_fused_kernel, dim3((unsigned)ceil_div(k, CH)), dim3(kQrThreads), 0, st, src,
                      k, bw, stack, counter, Rii, ldr, flag, col0);

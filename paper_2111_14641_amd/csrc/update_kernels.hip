@@ -26,6 +26,15 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 #ifndef RBGS_UP_PINGPONG
 #define RBGS_UP_PINGPONG 1
 #endif
+#ifndef RBGS_UP_SLAB
+#define RBGS_UP_SLAB 16   // columns of the product per pass through LDS in the epilogue
+#endif
+#ifndef RBGS_UP_WLATE
+#define RBGS_UP_WLATE 0   // 1: load the W_(i) row in the epilogue instead of before the product
+#endif
+#ifndef RBGS_UP_MINW
+#define RBGS_UP_MINW 0    // > 0: ask the compiler for this many waves per SIMD
+#endif
 constexpr int kUpThreads = 256;
 constexpr int kKC = 128;                  // rows of R per LDS chunk
 constexpr int kUnroll = RBGS_UP_UNROLL;   // K-steps whose loads are issued together
@@ -97,7 +106,8 @@ struct UpdateShape {
   static constexpr int WROWS = 16 * VEC;  // rows per wave
   static constexpr int TILE = 4 * WROWS;  // rows per workgroup
   static constexpr int NCOL = 16 * NB;
-  static constexpr int CT_LD = 17;        // one 16-column slab of the product per pass
+  static constexpr int SLAB = RBGS_UP_SLAB;
+  static constexpr int CT_LD = SLAB + 1;  // one slab of the product per pass
   static constexpr int RS_BYTES = kKC * NCOL * sizeof(C);
   static constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(C);
   static constexpr int U_BYTES = RS_BYTES > CT_BYTES ? RS_BYTES : CT_BYTES;
@@ -124,13 +134,15 @@ __device__ __forceinline__ void update_tile(
   const bool own = lane < WROWS && (!TAIL || row < n);
   const int bwc = bw - 1;
 
-  // W_(i) row of this lane, loaded first so its latency overlaps the product
+  // W_(i) row of this lane (loaded first so its latency overlaps the product,
+  // or in the epilogue to free registers during the product)
   T wrow[NCOL];
-  {
+  auto load_w = [&]() {
     const int64_t rr = TAIL ? (row < n ? row : n - 1) : (lane < WROWS ? row : wrow0);
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) wrow[c] = W[rr + (int64_t)(c < bw ? c : bwc) * ldw];
-  }
+  };
+  if (!RBGS_UP_WLATE) load_w();
   if (Rii != nullptr) {
     for (int e = threadIdx.x; e < NCOL * NCOL; e += kUpThreads) {
       const int r = e % NCOL, c = e / NCOL;
@@ -213,23 +225,32 @@ __device__ __forceinline__ void update_tile(
 #endif
   }
   // Epilogue: lane owns row wrow0 + lane (lanes >= WROWS idle); the product is
-  // moved through LDS one 16-column slab at a time.
+  // moved through LDS one slab of SLAB columns at a time.
+  if (RBGS_UP_WLATE) load_w();
+  constexpr int SLAB = Sh::SLAB;
   C* ct = ubuf + wave * WROWS * CT_LD;
   double x[NCOL];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
-    __syncthreads();
 #pragma unroll
-    for (int v = 0; v < VEC; ++v)
+    for (int h = 0; h < 16 / SLAB; ++h) {
+      __syncthreads();
+      if (li / SLAB == h) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ct[(VEC * M::row(kk, e) + v) * CT_LD + li] = acc[v][nb][e];
-    __syncthreads();
-    const int lr = lane < WROWS ? lane : 0;
+        for (int v = 0; v < VEC; ++v)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      // step 3: Q' = W - Q R in the arithmetic C, from storage T
-      const C qp = (C)wrow[nb * 16 + c] - ct[lr * CT_LD + c];
-      x[nb * 16 + c] = (double)qp;
+          for (int e = 0; e < 4; ++e)
+            ct[(VEC * M::row(kk, e) + v) * CT_LD + (li - h * SLAB)] = acc[v][nb][e];
+      }
+      __syncthreads();
+      const int lr = lane < WROWS ? lane : 0;
+#pragma unroll
+      for (int c = 0; c < SLAB; ++c) {
+        // step 3: Q' = W - Q R in the arithmetic C, from storage T
+        const int cc = nb * 16 + h * SLAB + c;
+        const C qp = (C)wrow[cc] - ct[lr * CT_LD + c];
+        x[cc] = (double)qp;
+      }
     }
   }
   if (own) {
@@ -244,7 +265,7 @@ __device__ __forceinline__ void update_tile(
 // workgroup, if n is not a multiple of the tile (or Q is not 16-byte aligned
 // along columns, then all workgroups), takes the guarded path.
 template <typename T, typename C, int NB>
-__global__ __launch_bounds__(kUpThreads) void update_kernel(
+__global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_kernel(
     const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
     const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t nfull,
     int64_t n, int K, int bw) {

@@ -97,6 +97,10 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (64, 16, 4, 64, "identity", "plain"),           # Theta = I
     (300, 20, 6, 300, "identity", "lowsync"),
     (9000, 40, 16, 2048, "sparse", "lowsync"),      # largest sparse k
+    (5000, 96, 32, 256, "gaussian", "lowsync"),     # widest blocks after the first (2 x 16 columns)
+    (5000, 96, 32, 256, "sparse", "plain"),
+    (3000, 70, 32, 512, "sparse", "lowsync"),       # 32-wide tree over 4 chunks, ragged last block
+    (4000, 72, 24, 256, "gaussian", "plain"),       # width 24 padded to 32 in the tree
 ])
 def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
     W = svd_matrix(n, m, np.logspace(0, -2, m), seed=n + m + b)
