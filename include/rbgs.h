@@ -149,6 +149,53 @@ RBGS_API rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t 
                     const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
                     double* R, int64_t ldr, double* S_out, rbgs_cert* cert);
 
+/* One problem of a batch.  W, Q, R as for rbgs_qr (device); the struct itself
+ * is host memory. */
+typedef struct {
+  const void* W;
+  int64_t ldw;
+  int64_t n, m;
+  void* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+  int64_t p;        /* block width; 0 = chosen by rbgs_autotune (set on return) */
+  int64_t k;        /* sketch rows; 0 = chosen by rbgs_autotune (set on return) */
+  int32_t status;   /* out: rbgs_status of this problem                        */
+  int32_t reserved;
+} rbgs_problem;
+
+/* Independent RBGS QR factorizations (Algorithm RBGS of Section 2) of a batch
+ * of problems with their own n, m, p and k.
+ *   probs host, `count` problems.  Problem i uses the sketch (sk->kind,
+ *         sk->zeta, seed sk->seed + i, its own k); sk->k is ignored.
+ *   opts  host; store, math, variant and ls_iters apply to every problem; the
+ *         batch is enqueued on opts->stream.
+ *   graph 1: the first call with a given batch (same pointers, sizes, options)
+ *         runs it and records the whole enqueue sequence as a HIP graph; a later
+ *         call with the identical batch launches that graph, one launch for the
+ *         batch.  The graph reads W at run time, so W may change between calls.
+ *         0: no graph.
+ * The problems are spread over four internal streams (largest first, each to
+ * the least loaded stream), joined back to opts->stream.  Problems with p or
+ * k equal to 0 are tuned first (rbgs_autotune, which waits for the device).
+ * Every problem is validated before anything is enqueued: on an invalid
+ * problem the call returns RBGS_EINVAL (or RBGS_EUNSUPPORTED) with that
+ * problem's status set and enqueues nothing.  No certificate is computed. */
+RBGS_API rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
+                                     const rbgs_sketch* sk, const rbgs_opts* opts, int32_t graph);
+
+/* Autotuner for batched problems: measures RBGS QR on the device for an n x m
+ * problem of synthetic data with every candidate (p, k), p in {16, 32} (not
+ * above m) and k in {2m, 3m, 4m} (rounded up to a multiple of 8, at most n),
+ * and returns the fastest.  Every candidate keeps k >= 2m, so the expected
+ * cond2(Q) = cond2(Theta U) stays below about 6 (Section 3).  Results are
+ * cached in the handle per (m, ceil(log2 n), store, math, kind, variant).
+ * Waits for the device; uses the handle's workspace and a temporary
+ * allocation of 2 n m elements freed before returning. */
+RBGS_API rbgs_status rbgs_autotune(rbgs_handle h, int64_t n, int64_t m, const rbgs_sketch* sk,
+                                   const rbgs_opts* opts, int64_t* p, int64_t* k);
+
 /* Sketch of a block of rows: out = Theta[:, row0:row0+n] X (Section 1.3), the
  * operation of steps 1 and 5 of Algorithm RBGS.
  *   X   device, n x c (ld ldx >= n), element type `store` (rbgs_store).

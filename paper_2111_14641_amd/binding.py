@@ -38,6 +38,13 @@ class rbgs_cert(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class rbgs_problem(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_void_p), ("ldw", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("m", ctypes.c_int64), ("Q", ctypes.c_void_p), ("ldq", ctypes.c_int64),
+                ("R", ctypes.c_void_p), ("ldr", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class RbgsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -53,6 +60,10 @@ _SIGNATURES = {
     "rbgs_qr": ([_P, _P, _I64, _I64, _I64, _I64, ctypes.POINTER(rbgs_sketch),
                  ctypes.POINTER(rbgs_opts), _P, _I64, _P, _I64, _P, ctypes.POINTER(rbgs_cert)],
                 ctypes.c_int),
+    "rbgs_qr_batched": ([_P, _I64, ctypes.POINTER(rbgs_problem), ctypes.POINTER(rbgs_sketch),
+                         ctypes.POINTER(rbgs_opts), _I32], ctypes.c_int),
+    "rbgs_autotune": ([_P, _I64, _I64, ctypes.POINTER(rbgs_sketch), ctypes.POINTER(rbgs_opts),
+                       ctypes.POINTER(_I64), ctypes.POINTER(_I64)], ctypes.c_int),
     "rbgs_sketch_apply": ([_P, ctypes.POINTER(rbgs_sketch), _I32, _P, _I64, _I64, _I64, _I64, _P,
                            _I64, _P], ctypes.c_int),
     "rbgs_theta_dense": ([_P, ctypes.POINTER(rbgs_sketch), _I64, _I64, _P, _P], ctypes.c_int),
@@ -107,6 +118,15 @@ class Library:
     def rbgs_qr(self, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, cert):
         return self.lib.rbgs_qr(h, W, ldw, n, m, p, ctypes.byref(sk), ctypes.byref(opts), Q, ldq,
                                 R, ldr, S_out, ctypes.byref(cert) if cert is not None else None)
+
+    def rbgs_qr_batched(self, h, count, probs, sk, opts, graph):
+        return self.lib.rbgs_qr_batched(h, count, probs, ctypes.byref(sk), ctypes.byref(opts), graph)
+
+    def rbgs_autotune(self, h, n, m, sk, opts):
+        p, k = _I64(), _I64()
+        st = self.lib.rbgs_autotune(h, n, m, ctypes.byref(sk), ctypes.byref(opts), ctypes.byref(p),
+                                    ctypes.byref(k))
+        return st, p.value, k.value
 
     def rbgs_sketch_apply(self, h, sk, store, X, ldx, n, c, row0, out, ldo, stream):
         return self.lib.rbgs_sketch_apply(h, ctypes.byref(sk), store, X, ldx, n, c, row0, out,
@@ -201,6 +221,56 @@ def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync", ls_i
         cd = dict(delta=cert.delta, delta_tilde=cert.delta_tilde,
                   breakdown_col=cert.breakdown_col, nonfinite=cert.nonfinite, status=st)
     return Q, R, S, cd
+
+
+def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=8, variant="lowsync",
+                    ls_iters=4, Qs=None, Rs=None, math="f64", graph=False):
+    """Independent RBGS QRs of column-major CUDA tensors Ws (same dtype and
+    device) in one call; problem i uses sketch seed `seed + i`.  ps / ks: block
+    widths and sketch sizes per problem (None or 0 = autotuned).
+
+    Returns (Qs, Rs, ps, ks) with the block widths and sketch sizes used."""
+    torch = _torch()
+    lib = Library.get()
+    count = len(Ws)
+    if count == 0:
+        raise ValueError("empty batch")
+    dt = Ws[0].dtype
+    store = {torch.float64: "f64", torch.float32: "f32"}.get(dt)
+    if store is None or any(W.dtype != dt for W in Ws):
+        raise TypeError("all W must be float32 or all float64")
+    dev = Ws[0].device
+    h = lib.handle(dev.index or 0)
+    Qs = list(Qs) if Qs is not None else [colmajor(W.shape[0], W.shape[1], dt, dev) for W in Ws]
+    Rs = list(Rs) if Rs is not None else [colmajor(W.shape[1], W.shape[1], torch.float64, dev)
+                                          for W in Ws]
+    arr = (rbgs_problem * count)()
+    for i, (W, Q, R) in enumerate(zip(Ws, Qs, Rs)):
+        wp, ldw = as_colmajor(W)
+        qp, ldq = as_colmajor(Q)
+        rp, ldr = as_colmajor(R)
+        p = int(ps[i]) if ps is not None and ps[i] else 0
+        k = int(ks[i]) if ks is not None and ks[i] else 0
+        arr[i] = rbgs_problem(wp, ldw, W.shape[0], W.shape[1], qp, ldq, rp, ldr, p, k, 0, 0)
+    sk = make_sketch(kind, 0, seed, zeta)
+    opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters), _stream_ptr(Ws[0]))
+    st = lib.rbgs_qr_batched(h, count, arr, sk, opts, 1 if graph else 0)
+    lib.check(st, h)
+    return Qs, Rs, [arr[i].p for i in range(count)], [arr[i].k for i in range(count)]
+
+
+def autotune(n, m, kind="sparse", store="f32", math="f64", variant="lowsync", ls_iters=4, zeta=8,
+             device=0):
+    """(p, k) the library's autotuner picks for an n x m problem."""
+    lib = Library.get()
+    h = lib.handle(device)
+    sk = make_sketch(kind, 0, 0, zeta)
+    import torch
+    opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters),
+                     torch.cuda.current_stream(device).cuda_stream)
+    st, p, k = lib.rbgs_autotune(h, n, m, sk, opts)
+    lib.check(st, h)
+    return p, k
 
 
 def sketch_apply(X, kind, k, seed, zeta=8, row0=0, out=None):

@@ -42,6 +42,17 @@ struct rbgs_handle_s {
   double* host_cert = nullptr;  // pinned, 4 doubles + flag
   hipStream_t side = nullptr;   // sketches of later blocks of W run here (default priority)
   std::vector<hipEvent_t> sync_ev;  // ordering between the caller's stream and `side`
+  bool no_overlap = false;      // set on the lanes of a batch: everything on one stream
+  // batched calls: lanes (child handles with their own stream and workspace)
+  std::vector<rbgs_handle> lanes;
+  std::vector<hipStream_t> lane_streams;
+  std::vector<hipEvent_t> lane_ev;
+  // graph of the last batch enqueued with graph capture, and its key
+  std::vector<int64_t> graph_key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  // autotuner: (m, ceil log2 n, store, math, kind, variant) -> (p, k)
+  std::vector<std::pair<std::vector<int64_t>, std::pair<int64_t, int64_t>>> tuned;
 };
 
 namespace {
@@ -224,6 +235,49 @@ rbgs_status do_sketch(rbgs_handle h, const SketchDesc& d, bool f32, const void* 
 
 }  // namespace
 
+static rbgs_status validate_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m,
+                               int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q,
+                               int64_t ldq, double* R, int64_t ldr) {
+  // ---- host-side validation (nothing is enqueued on failure) -------------
+  if (!W || !Q || !R) return fail(h, RBGS_EINVAL, "W, Q and R must be non-NULL");
+  if (!opts) return fail(h, RBGS_EINVAL, "options are NULL");
+  if (n < 1 || m < 1) return fail(h, RBGS_EINVAL, "n and m must be >= 1");
+  if (m > n) return fail(h, RBGS_EINVAL, "m must not exceed n");
+  if (p < 1) return fail(h, RBGS_EINVAL, "block width p must be >= 1");
+  if (ldw < n || ldq < n) return fail(h, RBGS_EINVAL, "leading dimensions of W and Q must be >= n");
+  if (ldr < m) return fail(h, RBGS_EINVAL, "leading dimension of R must be >= m");
+  std::string why;
+  if (!valid_sketch(sk, n, why)) return fail(h, RBGS_EINVAL, why);
+  if (sk->k < m) return fail(h, RBGS_EINVAL, "sketch dimension k must be >= m");
+  if (sk->k > n) return fail(h, RBGS_EINVAL, "sketch dimension k must be <= n");
+  if (opts->store != RBGS_STORE_F64 && opts->store != RBGS_STORE_F32)
+    return fail(h, RBGS_EINVAL, "unknown storage type");
+  if (opts->math != RBGS_MATH_F64 && opts->math != RBGS_MATH_F32)
+    return fail(h, RBGS_EINVAL, "unknown arithmetic");
+  if (opts->store == RBGS_STORE_F64 && opts->math != RBGS_MATH_F64)
+    return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
+  if (opts->variant != RBGS_VARIANT_PLAIN && opts->variant != RBGS_VARIANT_LOWSYNC)
+    return fail(h, RBGS_EINVAL, "unknown variant");
+  if (opts->ls_iters < 1 || opts->ls_iters > 16)
+    return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
+  if (p > 32) return fail(h, RBGS_EUNSUPPORTED, "block width p > 32 is not implemented");
+  const size_t es = opts->store == RBGS_STORE_F32 ? 4 : 8;
+  {
+    // Q == W (same ld) is the in-place factorization; any other overlap is invalid.
+    const char* w0 = (const char*)W;
+    const char* w1 = w0 + es * (size_t)(ldw * (m - 1) + n);
+    const char* q0 = (const char*)Q;
+    const char* q1 = q0 + es * (size_t)(ldq * (m - 1) + n);
+    const bool same = (w0 == q0) && (ldw == ldq);
+    if (!same && q0 < w1 && w0 < q1) return fail(h, RBGS_EINVAL, "Q overlaps W (only Q == W is allowed)");
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + 8 * (size_t)(ldr * (m - 1) + m);
+    if ((r0 < w1 && w0 < r1) || (r0 < q1 && q0 < r1)) return fail(h, RBGS_EINVAL, "R overlaps W or Q");
+  }
+
+  return RBGS_OK;
+}
+
 extern "C" {
 
 rbgs_status rbgs_create(rbgs_handle* h, int device) {
@@ -237,7 +291,9 @@ rbgs_status rbgs_create(rbgs_handle* h, int device) {
 
 rbgs_status rbgs_destroy(rbgs_handle h) {
   if (!h) return RBGS_OK;
-  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side) {
+  for (auto c : h->lanes) rbgs_destroy(c);
+  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side ||
+      !h->lane_streams.empty() || h->graph) {
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     for (auto& r : h->recs) {
@@ -247,6 +303,10 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
     for (auto e : h->pool) (void)hipEventDestroy(e);
     for (auto e : h->sync_ev) (void)hipEventDestroy(e);
     if (h->side) (void)hipStreamDestroy(h->side);
+    for (auto e : h->lane_ev) (void)hipEventDestroy(e);
+    for (auto q : h->lane_streams) (void)hipStreamDestroy(q);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_cert) (void)hipHostFree(h->host_cert);
   }
@@ -272,46 +332,15 @@ const char* rbgs_last_error(rbgs_handle h) { return h ? h->last_error.c_str() : 
 rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
                     const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
                     double* R, int64_t ldr, double* S_out, rbgs_cert* cert) {
-  // ---- host-side validation (nothing is enqueued on failure) -------------
   if (!h) return RBGS_EINVAL;
   h->last_error.clear();
-  if (!W || !Q || !R) return fail(h, RBGS_EINVAL, "W, Q and R must be non-NULL");
-  if (!opts) return fail(h, RBGS_EINVAL, "options are NULL");
-  if (n < 1 || m < 1) return fail(h, RBGS_EINVAL, "n and m must be >= 1");
-  if (m > n) return fail(h, RBGS_EINVAL, "m must not exceed n");
-  if (p < 1) return fail(h, RBGS_EINVAL, "block width p must be >= 1");
-  if (ldw < n || ldq < n) return fail(h, RBGS_EINVAL, "leading dimensions of W and Q must be >= n");
-  if (ldr < m) return fail(h, RBGS_EINVAL, "leading dimension of R must be >= m");
-  std::string why;
-  if (!valid_sketch(sk, n, why)) return fail(h, RBGS_EINVAL, why);
-  if (sk->k < m) return fail(h, RBGS_EINVAL, "sketch dimension k must be >= m");
-  if (sk->k > n) return fail(h, RBGS_EINVAL, "sketch dimension k must be <= n");
-  if (opts->store != RBGS_STORE_F64 && opts->store != RBGS_STORE_F32)
-    return fail(h, RBGS_EINVAL, "unknown storage type");
-  if (opts->math != RBGS_MATH_F64 && opts->math != RBGS_MATH_F32)
-    return fail(h, RBGS_EINVAL, "unknown arithmetic");
-  if (opts->store == RBGS_STORE_F64 && opts->math != RBGS_MATH_F64)
-    return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
-  if (opts->variant != RBGS_VARIANT_PLAIN && opts->variant != RBGS_VARIANT_LOWSYNC)
-    return fail(h, RBGS_EINVAL, "unknown variant");
-  if (opts->ls_iters < 1 || opts->ls_iters > 16)
-    return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
-  if (p > 32) return fail(h, RBGS_EUNSUPPORTED, "block width p > 32 is not implemented");
+  {
+    const rbgs_status vs = validate_qr(h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr);
+    if (vs != RBGS_OK) return vs;
+  }
   const bool f32 = opts->store == RBGS_STORE_F32;
   const bool f32_math = opts->math == RBGS_MATH_F32;
   const size_t es = f32 ? 4 : 8;
-  {
-    // Q == W (same ld) is the in-place factorization; any other overlap is invalid.
-    const char* w0 = (const char*)W;
-    const char* w1 = w0 + es * (size_t)(ldw * (m - 1) + n);
-    const char* q0 = (const char*)Q;
-    const char* q1 = q0 + es * (size_t)(ldq * (m - 1) + n);
-    const bool same = (w0 == q0) && (ldw == ldq);
-    if (!same && q0 < w1 && w0 < q1) return fail(h, RBGS_EINVAL, "Q overlaps W (only Q == W is allowed)");
-    const char* r0 = (const char*)R;
-    const char* r1 = r0 + 8 * (size_t)(ldr * (m - 1) + m);
-    if ((r0 < w1 && w0 < r1) || (r0 < q1 && q0 < r1)) return fail(h, RBGS_EINVAL, "R overlaps W or Q");
-  }
 
   DeviceGuard guard(h->device);
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
@@ -339,7 +368,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   // small factors of a block use few compute units, so these sketches mostly
   // fill idle ones.  Block i waits for its sketch before its least squares.
   const int64_t nblk = (m + b - 1) / b;
-  const bool overlap = d.kind != kIdentity && nblk > 1;
+  const bool overlap = !h->no_overlap && d.kind != kIdentity && nblk > 1;
   size_t part2_need = 0;
   if (overlap) {
     part2_need = sketch_partial_doubles(d, n, std::min<int64_t>(b, m), kSideGroups);
@@ -511,6 +540,288 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
     snprintf(buf, sizeof buf, "R(%lld,%lld) is zero or not finite", (long long)bcol, (long long)bcol);
     return fail(h, RBGS_EBREAKDOWN, buf);
   }
+  return RBGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched factorizations and the autotuner.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr int kBatchLanes = 4;  // internal streams of a batch
+
+rbgs_status ensure_lanes(rbgs_handle h, int L) {
+  while ((int)h->lanes.size() < L) {
+    rbgs_handle c = nullptr;
+    if (rbgs_create(&c, h->device) != RBGS_OK) return fail(h, RBGS_ENOMEM, "lane handle");
+    c->no_overlap = true;
+    h->lanes.push_back(c);
+  }
+  while ((int)h->lane_streams.size() < L) {
+    hipStream_t q;
+    HIP_TRY(h, hipStreamCreateWithFlags(&q, hipStreamNonBlocking), "lane stream");
+    h->lane_streams.push_back(q);
+  }
+  while ((int)h->lane_ev.size() < L + 1) {
+    hipEvent_t e;
+    HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming), "lane event");
+    h->lane_ev.push_back(e);
+  }
+  return RBGS_OK;
+}
+
+int64_t ceil_log2(int64_t n) {
+  int64_t b = 0;
+  while (((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+double batch_bytes(const rbgs_problem& pr, size_t es) {
+  double tot = 0.0;
+  for (int64_t c0 = 0; c0 < pr.m; c0 += pr.p) {
+    const int64_t bw = std::min<int64_t>(pr.p, pr.m - c0);
+    tot += (double)(c0 + 2 * bw) * (double)pr.n * (double)es;
+  }
+  return tot;
+}
+
+// Enqueue every problem on its lane; lanes fork from and join back to st.
+rbgs_status enqueue_batch(rbgs_handle h, int64_t count, rbgs_problem* probs,
+                          const rbgs_sketch* sk, const rbgs_opts* opts,
+                          const std::vector<std::vector<int64_t>>& lane_items) {
+  hipStream_t st = (hipStream_t)opts->stream;
+  const int L = (int)lane_items.size();
+  HIP_TRY(h, hipEventRecord(h->lane_ev[L], st), "event record");
+  for (int l = 0; l < L; ++l)
+    HIP_TRY(h, hipStreamWaitEvent(h->lane_streams[l], h->lane_ev[L], 0), "stream wait");
+  for (int l = 0; l < L; ++l) {
+    for (int64_t i : lane_items[l]) {
+      rbgs_problem& pr = probs[i];
+      rbgs_sketch ski = *sk;
+      ski.k = pr.k;
+      ski.seed = sk->seed + (uint64_t)i;
+      rbgs_opts oi = *opts;
+      oi.stream = h->lane_streams[l];
+      pr.status = rbgs_qr(h->lanes[l], pr.W, pr.ldw, pr.n, pr.m, pr.p, &ski, &oi, pr.Q, pr.ldq,
+                          pr.R, pr.ldr, nullptr, nullptr);
+      if (pr.status != RBGS_OK)
+        return fail(h, (rbgs_status)pr.status,
+                    "problem " + std::to_string(i) + ": " + h->lanes[l]->last_error);
+    }
+  }
+  for (int l = 0; l < L; ++l) {
+    HIP_TRY(h, hipEventRecord(h->lane_ev[l], h->lane_streams[l]), "event record");
+    HIP_TRY(h, hipStreamWaitEvent(st, h->lane_ev[l], 0), "stream wait");
+  }
+  return RBGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbgs_status rbgs_autotune(rbgs_handle h, int64_t n, int64_t m, const rbgs_sketch* sk,
+                          const rbgs_opts* opts, int64_t* p_out, int64_t* k_out) {
+  if (!h) return RBGS_EINVAL;
+  if (!sk || !opts || !p_out || !k_out) return fail(h, RBGS_EINVAL, "NULL argument");
+  if (n < 1 || m < 1 || m > n) return fail(h, RBGS_EINVAL, "need 1 <= m <= n");
+  const std::vector<int64_t> key = {m, ceil_log2(n), opts->store, opts->math, sk->kind, sk->zeta,
+                                    opts->variant};
+  for (auto& e : h->tuned)
+    if (e.first == key) {
+      *p_out = e.second.first;
+      *k_out = e.second.second;
+      return RBGS_OK;
+    }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  rbgs_status rs = ensure_lanes(h, 1);
+  if (rs != RBGS_OK) return rs;
+  rbgs_handle lane = h->lanes[0];
+  const bool f32 = opts->store == RBGS_STORE_F32;
+  const size_t es = f32 ? 4 : 8;
+  const int64_t step = sk->kind == RBGS_SKETCH_SPARSE_SIGN ? std::max<int64_t>(4, sk->zeta) * 4 : 4;
+  std::vector<int64_t> ps, ks;
+  for (int64_t pc : {16, 32}) {
+    const int64_t pp = std::min<int64_t>(pc, m);
+    if (std::find(ps.begin(), ps.end(), pp) == ps.end()) ps.push_back(pp);
+  }
+  for (int64_t mult : {2, 3, 4}) {
+    int64_t kc = ((mult * m + step - 1) / step) * step;
+    if (sk->kind == RBGS_SKETCH_SPARSE_SIGN) kc = ((kc + sk->zeta - 1) / sk->zeta) * sk->zeta;
+    kc = std::min<int64_t>(kc, n);
+    if (kc >= m && std::find(ks.begin(), ks.end(), kc) == ks.end()) ks.push_back(kc);
+  }
+  if (ks.empty()) return fail(h, RBGS_EINVAL, "no admissible sketch size for this n, m");
+  void* W = nullptr;
+  void* Q = nullptr;
+  double* R = nullptr;
+  auto cleanup = [&]() {
+    (void)hipDeviceSynchronize();
+    if (W) (void)hipFree(W);
+    if (Q) (void)hipFree(Q);
+    if (R) (void)hipFree(R);
+  };
+  if (hipMalloc(&W, es * (size_t)(n * m)) != hipSuccess || hipMalloc(&Q, es * (size_t)(n * m)) != hipSuccess ||
+      hipMalloc((void**)&R, 8 * (size_t)(m * m)) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(h, RBGS_ENOMEM, "autotuner buffers");
+  }
+  hipStream_t st = h->lane_streams[0];
+  hipEvent_t e0 = h->lane_ev[0], e1 = h->lane_ev[1];
+  hipEvent_t t0, t1;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+    cleanup();
+    return fail(h, RBGS_EDEVICE, "event creation failed");
+  }
+  (void)e0;
+  (void)e1;
+  double best = 1e300;
+  int64_t bp = ps[0], bk = ks[0];
+  rbgs_status out = RBGS_OK;
+  if (launch_fill_test(W, f32, n, m, n, st) != hipSuccess) out = fail(h, RBGS_EDEVICE, "fill");
+  for (int64_t pp : ps) {
+    for (int64_t kc : ks) {
+      if (out != RBGS_OK) break;
+      rbgs_sketch ski = *sk;
+      ski.k = kc;
+      rbgs_opts oi = *opts;
+      oi.stream = st;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3 && out == RBGS_OK; ++rep) {
+        if (rep == 1) (void)hipEventRecord(t0, st);
+        out = rbgs_qr(lane, W, n, n, m, pp, &ski, &oi, Q, n, R, m, nullptr, nullptr);
+        if (out != RBGS_OK) h->last_error = lane->last_error;
+      }
+      if (out != RBGS_OK) break;
+      (void)hipEventRecord(t1, st);
+      if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+        out = fail(h, RBGS_EDEVICE, "autotuner timing");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bp = pp;
+        bk = kc;
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  cleanup();
+  if (out != RBGS_OK) return out;
+  h->tuned.push_back({key, {bp, bk}});
+  *p_out = bp;
+  *k_out = bk;
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
+                            const rbgs_sketch* sk, const rbgs_opts* opts, int32_t graph) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  if (count < 1 || !probs || !sk || !opts) return fail(h, RBGS_EINVAL, "empty batch or NULL argument");
+  if (graph != 0 && graph != 1) return fail(h, RBGS_EINVAL, "graph must be 0 or 1");
+  // tune the problems that ask for it, then validate every problem
+  for (int64_t i = 0; i < count; ++i) {
+    rbgs_problem& pr = probs[i];
+    if (pr.p < 0 || pr.k < 0) {
+      pr.status = RBGS_EINVAL;
+      return fail(h, RBGS_EINVAL, "problem " + std::to_string(i) + ": negative p or k");
+    }
+    if (pr.p == 0 || pr.k == 0) {
+      if (pr.n < 1 || pr.m < 1 || pr.m > pr.n) {
+        pr.status = RBGS_EINVAL;
+        return fail(h, RBGS_EINVAL, "problem " + std::to_string(i) + ": need 1 <= m <= n");
+      }
+      int64_t tp = 0, tk = 0;
+      const rbgs_status ts = rbgs_autotune(h, pr.n, pr.m, sk, opts, &tp, &tk);
+      if (ts != RBGS_OK) {
+        pr.status = ts;
+        return ts;
+      }
+      if (pr.p == 0) pr.p = tp;
+      if (pr.k == 0) pr.k = tk;
+    }
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    rbgs_problem& pr = probs[i];
+    rbgs_sketch ski = *sk;
+    ski.k = pr.k;
+    ski.seed = sk->seed + (uint64_t)i;
+    pr.status = validate_qr(h, pr.W, pr.ldw, pr.n, pr.m, pr.p, &ski, opts, pr.Q, pr.ldq, pr.R, pr.ldr);
+    if (pr.status != RBGS_OK) {
+      h->last_error = "problem " + std::to_string(i) + ": " + h->last_error;
+      return (rbgs_status)pr.status;
+    }
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)opts->stream;
+  const bool use_graph = graph == 1 && st != nullptr;
+  std::vector<int64_t> key = {count, opts->store, opts->math, opts->variant, opts->ls_iters,
+                              (int64_t)(intptr_t)st, sk->kind, sk->zeta, (int64_t)sk->seed};
+  for (int64_t i = 0; i < count; ++i) {
+    const rbgs_problem& pr = probs[i];
+    for (int64_t v : {(int64_t)(intptr_t)pr.W, pr.ldw, pr.n, pr.m, (int64_t)(intptr_t)pr.Q, pr.ldq,
+                      (int64_t)(intptr_t)pr.R, pr.ldr, pr.p, pr.k})
+      key.push_back(v);
+  }
+  if (use_graph && h->graph_exec && key == h->graph_key) {
+    HIP_TRY(h, hipGraphLaunch(h->graph_exec, st), "hipGraphLaunch");
+    for (int64_t i = 0; i < count; ++i) probs[i].status = RBGS_OK;
+    return RBGS_OK;
+  }
+  // largest problem first, each to the least loaded lane
+  const int L = (int)std::min<int64_t>(kBatchLanes, count);
+  rbgs_status rs = ensure_lanes(h, L);
+  if (rs != RBGS_OK) return rs;
+  const size_t es = opts->store == RBGS_STORE_F32 ? 4 : 8;
+  std::vector<int64_t> order(count);
+  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return batch_bytes(probs[a], es) > batch_bytes(probs[b], es);
+  });
+  std::vector<std::vector<int64_t>> lane_items(L);
+  std::vector<double> load(L, 0.0);
+  for (int64_t i : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lane_items[l].push_back(i);
+    load[l] += batch_bytes(probs[i], es);
+  }
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items);
+  if (rs != RBGS_OK || !use_graph) return rs;
+  // record the same enqueue sequence as a graph for later identical calls
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->graph_key.clear();
+  HIP_TRY(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(st, &g);
+  if (rs != RBGS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rs;
+  }
+  if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(h, ie, "hipGraphInstantiate");
+  }
+  h->graph = g;
+  h->graph_exec = ex;
+  h->graph_key = key;
   return RBGS_OK;
 }
 

@@ -185,6 +185,8 @@ hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_
 
 // Small FP64 factors (Sections 2.1 and 2.2).  Workspace for the QR tree of a k x bw matrix.
 size_t qr_stack_size(int64_t k, int bw);
+// Synthetic full-rank test matrix (n x m, ld >= n) for the autotuner.
+hipError_t launch_fill_test(void* X, bool f32, int64_t n, int64_t m, int64_t ld, hipStream_t st);
 // out0 (K x n0, ld ldo0) = S^T X0, out1 (K x n1, ld ldo1) = S^T X1 and, if
 // out1t is not null, out1t (n1 x K, ld ldo1t) = (S^T X1)^T.  S: k x K (ld k);
 // X0, X1: k x n0, k x n1 (ld k).

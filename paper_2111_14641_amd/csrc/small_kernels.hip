@@ -517,6 +517,27 @@ __global__ __launch_bounds__(kQwThreads) void qr_wave_kernel(const double* __res
   }
 }
 
+// Deterministic test matrix for the autotuner: x[r][c] = a hash of (r, c)
+// mapped to [-1, 1) (full rank with overwhelming probability).
+__global__ void fill_test_kernel(void* X, int f32, int64_t n, int64_t m, int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * m) return;
+  const int64_t r = idx % n, c = idx / n;
+  uint32_t h = (uint32_t)r * 0x9E3779B1u ^ ((uint32_t)c * 0x85EBCA77u + 0x165667B1u);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  const double v = (double)(h >> 8) * (1.0 / 8388608.0) - 1.0;
+  if (f32) ((float*)X)[r + c * ld] = (float)v;
+  else ((double*)X)[r + c * ld] = v;
+}
+
+hipError_t launch_fill_test(void* X, bool f32, int64_t n, int64_t m, int64_t ld, hipStream_t st) {
+  hipLaunchKernelGGL(fill_test_kernel, dim3((unsigned)ceil_div(n * m, 256)), dim3(256), 0, st, X,
+                     f32 ? 1 : 0, n, m, ld);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* X0, int n0,
                            const double* X1, int n1, double* out0, int64_t ldo0, double* out1,
                            int64_t ldo1, double* out1t, int64_t ldo1t, hipStream_t st) {

@@ -96,3 +96,24 @@ def test_profile_interface_without_gpu(lib_and_handle):
     assert lib.rbgs_profile_get(h, 0, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)) == B.RBGS_OK
     assert cnt.value == 0
     assert lib.rbgs_profile_get(h, 9, None, None, None) == B.RBGS_EINVAL
+
+
+def test_batched_validation_on_host(lib_and_handle):
+    lib, h = lib_and_handle
+    sk = B.rbgs_sketch(1, 8, 0, 1)
+    op = B.rbgs_opts(1, 0, 1, 4, None)
+    arr = (B.rbgs_problem * 2)()
+    arr[0] = B.rbgs_problem(0x1000, 100, 100, 8, 0x100000, 100, 0x200000, 8, 4, 32, 0, 0)
+    arr[1] = B.rbgs_problem(0x300000, 50, 50, 80, 0x400000, 50, 0x500000, 80, 4, 96, 0, 0)  # m > n
+    assert lib.rbgs_qr_batched(h, 2, arr, ctypes.byref(sk), ctypes.byref(op), 0) == B.RBGS_EINVAL
+    assert arr[1].status == B.RBGS_EINVAL
+    assert "problem 1" in lib.rbgs_last_error(h).decode()
+    assert lib.rbgs_qr_batched(h, 0, arr, ctypes.byref(sk), ctypes.byref(op), 0) == B.RBGS_EINVAL
+    assert lib.rbgs_qr_batched(h, 1, arr, ctypes.byref(sk), ctypes.byref(op), 2) == B.RBGS_EINVAL
+    arr[0].p = 33
+    assert lib.rbgs_qr_batched(h, 1, arr, ctypes.byref(sk), ctypes.byref(op), 0) == B.RBGS_EUNSUPPORTED
+    p, k = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.rbgs_autotune(h, 10, 20, ctypes.byref(sk), ctypes.byref(op), ctypes.byref(p),
+                             ctypes.byref(k)) == B.RBGS_EINVAL
+    assert lib.rbgs_autotune(h, 100, 20, None, ctypes.byref(op), ctypes.byref(p),
+                             ctypes.byref(k)) == B.RBGS_EINVAL
