@@ -136,6 +136,57 @@ def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
     return out
 
 
+def batched_form(count=512, reps=3):
+    """The batched workload: `count` FP32 problems of uneven n and m, tuned p
+    and k, one graph launch per batch, against the same QRs launched one by
+    one.  Aggregate algorithmic GB/s over all problems."""
+    import numpy as np
+    import torch
+    from paper_2111_14641_amd import binding as B
+    from paper_2111_14641_amd.workloads import batched_problems
+    probs = batched_problems(count)
+    Ws = [w for w, _, _, _ in probs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t = time.perf_counter()
+        Qs, Rs, ps, ks = B.rbgs_qr_batched(Ws, seed=0x2111146414, graph=True)  # tune, run, record
+        torch.cuda.synchronize()
+        first_s = time.perf_counter() - t
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            B.rbgs_qr_batched(Ws, ps, ks, seed=0x2111146414, Qs=Qs, Rs=Rs, graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / reps
+        # the same factorizations, one rbgs_qr call after another
+        Q1 = [B.colmajor(W.shape[0], W.shape[1], torch.float32) for W in Ws]
+        R1 = [B.colmajor(W.shape[1], W.shape[1], torch.float64) for W in Ws]
+        e0.record(stream)
+        for i, W in enumerate(Ws):
+            B.rbgs_qr(W, ps[i], "sparse", ks[i], 0x2111146414 + i, 8, "lowsync", LS_ITERS,
+                      Q=Q1[i], R=R1[i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_single = e0.elapsed_time(e1)
+    tot = sum(alg_bytes(W.shape[0], W.shape[1], ps[i], 4) for i, W in enumerate(Ws))
+    errs, conds = [], []
+    for W, Q, R in zip(Ws, Qs, Rs):
+        Wd, Qd = W.double(), Q.double()
+        errs.append((torch.linalg.norm(Wd - Qd @ R) / torch.linalg.norm(Wd)).item())
+        ev = np.linalg.eigvalsh((Qd.t() @ Qd).cpu().numpy())
+        conds.append(float(np.sqrt(ev[-1] / ev[0])))
+    del Q1, R1
+    return dict(problems=count, alg_GB=round(tot / 1e9, 3), ms_graph=round(ms_graph, 3),
+                GBps_graph=round(tot / (ms_graph * 1e-3) / 1e9, 1), ms_one_by_one=round(ms_single, 3),
+                GBps_one_by_one=round(tot / (ms_single * 1e-3) / 1e9, 1),
+                speedup=round(ms_single / ms_graph, 3), first_call_s=round(first_s, 3),
+                max_rel_err=float(f"{max(errs):.3g}"), max_cond2_Q=float(f"{max(conds):.4g}"),
+                p_used=sorted(set(ps)), k_over_m=sorted(set(round(k / W.shape[1], 2)
+                                                          for k, W in zip(ks, Ws))))
+
+
 def copy_bandwidth():
     """Measured rate of a plain streaming kernel, y = x + 1 over 1 GiB of FP32
     (1 GiB read + 1 GiB written): a practical ceiling beside the nominal
@@ -198,6 +249,7 @@ def main():
     ap.add_argument("--k", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gaussian", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--forms", default="all", help="'headline' to time only the headline form")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -246,6 +298,9 @@ def main():
             forms["f64_gauss_lowsync"], _ = time_form(W64, p, "gaussian", k, THETA_SEED_LARGE,
                                                       "lowsync", max(2, args.steps // 10), 1)
     del W64
+    if args.forms == "all" and not args.no_batched:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        forms["batched_512_f32"] = batched_form()
     copy_gbs = copy_bandwidth()
     upd_ms, upd_cnt, upd_bytes = upd
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0

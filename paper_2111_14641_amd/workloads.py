@@ -20,6 +20,12 @@ returned in FP64, column-major (Fortran order), so that column j is contiguous.
   Cholesky orthonormalization, V on the host), for sizes whose FP64 factors do
   not fit comfortably in host memory; with n = 4 10^6, m = 512 and
   sigma = logspace(0, -10, 512) this is the mixed-precision workload.
+* `batched_problems(count, seed)`: the batched workload, `count` FP32
+  matrices on the GPU with n = round(2^u), u ~ U[14, 18], m drawn from
+  {32, 64, 128, 256} and W = G diag(sigma) V^T, G a seeded Gaussian n x m
+  (cond(G) <= (1 + sqrt(m/n)) / (1 - sqrt(m/n)) < 1.3), sigma =
+  logspace(0, -c, m), c ~ U[2, 10], V a seeded orthogonal m x m matrix: so
+  cond(W) is 10^c up to that factor.
 """
 import numpy as np
 
@@ -77,6 +83,27 @@ def svd_matrix_gpu(n, m, sigma, seed, device="cuda"):
 def mixed_single_qr_gpu(seed=0xDA7A02, n=4_000_000, m=512, decades=10.0):
     """The mixed-precision single-QR workload (cond(W) = 10^decades), on the GPU."""
     return svd_matrix_gpu(n, m, np.logspace(0.0, -decades, m), seed)
+
+
+def batched_problems(count=512, seed=0xDA7A04, device="cuda"):
+    """List of (W (FP32, column-major, on `device`), n, m, c)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    out = []
+    for _ in range(count):
+        n = int(round(2.0 ** rng.uniform(14.0, 18.0)))
+        m = int(rng.choice([32, 64, 128, 256]))
+        c = float(rng.uniform(2.0, 10.0))
+        V = _orthonormal(rng, m, m)
+        M = torch.from_numpy(np.logspace(0.0, -c, m)[:, None] * V.T).to(device)
+        G = torch.randn((n, m), generator=g, dtype=torch.float64, device=device)
+        W = torch.empty((m, n), dtype=torch.float32, device=device).t()
+        W.copy_(G @ M)
+        del G
+        out.append((W, n, m, c))
+    return out
 
 
 def large_single_qr(seed=0xDA7A01, n=1_000_000, m=256, dtype=np.float64):

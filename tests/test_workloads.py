@@ -34,3 +34,14 @@ def test_oscillatory_matrix_formula_and_chunking():
         # (another rounding order of the arguments: the denominator can be 0.1)
         assert np.allclose(W[:, j], ref, rtol=1e-11, atol=1e-12)
     assert np.all(np.abs(W) <= 10 / 0.1 + 1e-9)
+
+
+def test_batched_problems_on_the_cpu_device():
+    probs = wl.batched_problems(count=4, seed=3, device="cpu")
+    for W, n, m, c in probs:
+        assert 2 ** 14 - 1 <= n <= 2 ** 18 + 1 and m in (32, 64, 128, 256)
+        assert W.dtype.is_floating_point and W.element_size() == 4 and W.stride() == (1, n)
+        s = np.linalg.svd(W.double().numpy(), compute_uv=False)
+        ratio = s[0] / s[-1]
+        # FP32 rounding (about 6e-8 relative) hides singular values below it
+        assert min(10 ** c / 1.5, 1e6) <= ratio <= 10 ** c * 1.5
