@@ -196,6 +196,56 @@ RBGS_API rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem*
 RBGS_API rbgs_status rbgs_autotune(rbgs_handle h, int64_t n, int64_t m, const rbgs_sketch* sk,
                                    const rbgs_opts* opts, int64_t* p, int64_t* k);
 
+/* Sparse matrix in compressed sparse row form (device arrays). */
+typedef struct {
+  int64_t n;                /* rows = columns                                */
+  int64_t nnz;
+  const int64_t* row_ptr;   /* n + 1 offsets                                 */
+  const int32_t* col_idx;   /* nnz column indices, each in [0, n)            */
+  const double* val;        /* nnz FP64 values                               */
+} rbgs_csr;
+
+/* Y = alpha A X + beta Y0 for a block of bs <= 32 vectors (the product of
+ * step 2 of Algorithm RBGS-Arnoldi, Section 4.1).  X: n x bs (ld ldx),
+ * element type xstore; Y: n x bs (ld ldy), element type ystore; Y0: n x bs
+ * FP64 (ld ldy0) or NULL (then beta is ignored); Y must not overlap X.
+ * FP64 arithmetic.  Enqueued on `stream`. */
+RBGS_API rbgs_status rbgs_spmm(rbgs_handle h, const rbgs_csr* A, int32_t xstore, const void* X,
+                               int64_t ldx, int64_t bs, double alpha, double beta, const double* Y0,
+                               int64_t ldy0, int32_t ystore, void* Y, int64_t ldy, void* stream);
+
+/* RBGS block Arnoldi (Algorithm RBGS-Arnoldi, Section 4.1): W_(1) = B and
+ * W_(i) = A Q_(i-1) for i = 2..nblocks, each followed by iteration i of
+ * RBGS.  On return Q (n x m, m = nblocks bs, element type opts->store) is
+ * orthonormal with respect to the sketched product and R (m x m FP64, ld
+ * ldr) holds the RBGS R factor: the Arnoldi identity reads
+ * A Q_(1:p-1) = Q R_(1:p,2:p), so H = R[:, bs:m] and R_(1:p,1) = B's
+ * coordinates.  B: n x bs (ld ldb), element type opts->store.  sk: as for
+ * rbgs_qr with m <= sk->k <= n.  cert: as for rbgs_qr. */
+RBGS_API rbgs_status rbgs_block_arnoldi(rbgs_handle h, const rbgs_csr* A, const void* B,
+                                        int64_t ldb, int64_t bs, int64_t nblocks,
+                                        const rbgs_sketch* sk, const rbgs_opts* opts, void* Q,
+                                        int64_t ldq, double* R, int64_t ldr, rbgs_cert* cert);
+
+/* Restarted randomized block GMRES (Section 4.2) for A X = B: each cycle
+ * forms the residual R0 = B - A X (FP64), runs RBGS-Arnoldi on it with
+ * blocks_per_cycle + 1 blocks (basis stored as opts->store), solves the
+ * block Hessenberg least-squares problem min_Z ||H Z - R_(1:p,1)||_F in FP64
+ * on the device, and updates X <- X + Q_(1:p-1) Z.  Stops when
+ * ||B - A X||_F / ||B||_F <= tol (checked at the start of each cycle and at
+ * the end) or after max_cycles.
+ *   B, X   device, n x bs FP64 (ld n); X is the initial guess on entry.
+ *   iters  host out: block iterations done (cycles x blocks_per_cycle).
+ *   relres host out: final ||B - A X||_F / ||B||_F.
+ *   history host or NULL, max_cycles + 1 doubles: relative residual at the
+ *          start of every cycle and at the end (unused entries are -1).
+ * Waits for the device once per cycle.  Returns RBGS_ENOTCONV (with X, iters
+ * and relres valid) if tol is not reached. */
+RBGS_API rbgs_status rbgs_block_gmres(rbgs_handle h, const rbgs_csr* A, const double* B, double* X,
+                                      int64_t bs, int64_t blocks_per_cycle, int64_t max_cycles,
+                                      double tol, const rbgs_sketch* sk, const rbgs_opts* opts,
+                                      int64_t* iters, double* relres, double* history);
+
 /* Sketch of a block of rows: out = Theta[:, row0:row0+n] X (Section 1.3), the
  * operation of steps 1 and 5 of Algorithm RBGS.
  *   X   device, n x c (ld ldx >= n), element type `store` (rbgs_store).

@@ -45,6 +45,11 @@ class rbgs_problem(ctypes.Structure):
                 ("k", ctypes.c_int64), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class rbgs_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class RbgsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -64,6 +69,15 @@ _SIGNATURES = {
                          ctypes.POINTER(rbgs_opts), _I32], ctypes.c_int),
     "rbgs_autotune": ([_P, _I64, _I64, ctypes.POINTER(rbgs_sketch), ctypes.POINTER(rbgs_opts),
                        ctypes.POINTER(_I64), ctypes.POINTER(_I64)], ctypes.c_int),
+    "rbgs_spmm": ([_P, ctypes.POINTER(rbgs_csr), _I32, _P, _I64, _I64, ctypes.c_double,
+                   ctypes.c_double, _P, _I64, _I32, _P, _I64, _P], ctypes.c_int),
+    "rbgs_block_arnoldi": ([_P, ctypes.POINTER(rbgs_csr), _P, _I64, _I64, _I64,
+                            ctypes.POINTER(rbgs_sketch), ctypes.POINTER(rbgs_opts), _P, _I64, _P,
+                            _I64, ctypes.POINTER(rbgs_cert)], ctypes.c_int),
+    "rbgs_block_gmres": ([_P, ctypes.POINTER(rbgs_csr), _P, _P, _I64, _I64, _I64, ctypes.c_double,
+                          ctypes.POINTER(rbgs_sketch), ctypes.POINTER(rbgs_opts),
+                          ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "rbgs_sketch_apply": ([_P, ctypes.POINTER(rbgs_sketch), _I32, _P, _I64, _I64, _I64, _I64, _P,
                            _I64, _P], ctypes.c_int),
     "rbgs_theta_dense": ([_P, ctypes.POINTER(rbgs_sketch), _I64, _I64, _P, _P], ctypes.c_int),
@@ -271,6 +285,106 @@ def autotune(n, m, kind="sparse", store="f32", math="f64", variant="lowsync", ls
     st, p, k = lib.rbgs_autotune(h, n, m, sk, opts)
     lib.check(st, h)
     return p, k
+
+
+class CSR:
+    """A square CSR matrix on the device (int64 row pointers, int32 columns,
+    FP64 values), kept alive with its C descriptor."""
+
+    def __init__(self, indptr, indices, data, device="cuda"):
+        torch = _torch()
+        self.row_ptr = torch.as_tensor(indptr, dtype=torch.int64).to(device)
+        self.col_idx = torch.as_tensor(indices, dtype=torch.int32).to(device)
+        self.val = torch.as_tensor(data, dtype=torch.float64).to(device)
+        self.n = int(self.row_ptr.numel() - 1)
+        self.device = self.val.device
+
+    def struct(self):
+        return rbgs_csr(self.n, int(self.val.numel()), self.row_ptr.data_ptr(),
+                        self.col_idx.data_ptr(), self.val.data_ptr())
+
+
+def spmm(A, X, alpha=1.0, beta=0.0, Y0=None, out_dtype=None):
+    """alpha A X + beta Y0 for a column-major block X (n x bs) on the device."""
+    torch = _torch()
+    lib = Library.get()
+    h = lib.handle(A.device.index or 0)
+    n, bs = X.shape
+    dt = out_dtype or X.dtype
+    Y = colmajor(n, bs, dt, X.device)
+    xp, ldx = as_colmajor(X)
+    yp, ldy = as_colmajor(Y)
+    y0p, ldy0 = as_colmajor(Y0) if Y0 is not None else (None, n)
+    st = lib.lib.rbgs_spmm(h, ctypes.byref(A.struct()), STORE[_store_of(X.dtype)], xp, ldx, bs,
+                           float(alpha), float(beta), y0p, ldy0, STORE[_store_of(dt)], yp, ldy,
+                           _stream_ptr(X))
+    lib.check(st, h)
+    return Y
+
+
+def _store_of(dtype):
+    torch = _torch()
+    if dtype == torch.float64:
+        return "f64"
+    if dtype == torch.float32:
+        return "f32"
+    raise TypeError("expected float32 or float64")
+
+
+def block_arnoldi(A, B, nblocks, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync",
+                  ls_iters=4, math="f64", want_cert=False):
+    """RBGS-Arnoldi from the block B (n x bs, column-major, FP32 or FP64).
+    Returns (Q, R, cert): H = R[:, bs:] is the block Hessenberg matrix."""
+    torch = _torch()
+    lib = Library.get()
+    h = lib.handle(A.device.index or 0)
+    n, bs = B.shape
+    m = nblocks * bs
+    Q = colmajor(n, m, B.dtype, B.device)
+    R = colmajor(m, m, torch.float64, B.device)
+    bp, ldb = as_colmajor(B)
+    opts = rbgs_opts(STORE[_store_of(B.dtype)], MATH[math], VARIANT[variant], int(ls_iters),
+                     _stream_ptr(B))
+    cert = rbgs_cert() if want_cert else None
+    st = lib.lib.rbgs_block_arnoldi(h, ctypes.byref(A.struct()), bp, ldb, bs, nblocks,
+                                    ctypes.byref(make_sketch(kind, k, seed, zeta)),
+                                    ctypes.byref(opts), Q.data_ptr(), n, R.data_ptr(), m,
+                                    ctypes.byref(cert) if cert is not None else None)
+    lib.check(st, h)
+    cd = None
+    if cert is not None:
+        cd = dict(delta=cert.delta, delta_tilde=cert.delta_tilde,
+                  breakdown_col=cert.breakdown_col, nonfinite=cert.nonfinite)
+    return Q, R, cd
+
+
+def block_gmres(A, B, X0=None, blocks_per_cycle=40, max_cycles=10, tol=1e-8, kind="sparse",
+                k=None, seed=0, zeta=8, store="f32", variant="lowsync", ls_iters=4, math="f64"):
+    """Restarted randomized block GMRES for A X = B (B: n x bs FP64 on the
+    device).  Returns (X, block iterations, final relative residual, history,
+    converged)."""
+    torch = _torch()
+    lib = Library.get()
+    h = lib.handle(A.device.index or 0)
+    n, bs = B.shape
+    Bc = colmajor(n, bs, torch.float64, B.device)
+    Bc.copy_(B)
+    X = colmajor(n, bs, torch.float64, B.device)
+    if X0 is None:
+        X.zero_()
+    else:
+        X.copy_(X0)
+    opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters), _stream_ptr(B))
+    iters, rel = _I64(), ctypes.c_double()
+    hist = (ctypes.c_double * (max_cycles + 1))()
+    st = lib.lib.rbgs_block_gmres(h, ctypes.byref(A.struct()), Bc.data_ptr(), X.data_ptr(), bs,
+                                  blocks_per_cycle, max_cycles, float(tol),
+                                  ctypes.byref(make_sketch(kind, k, seed, zeta)), ctypes.byref(opts),
+                                  ctypes.byref(iters), ctypes.byref(rel), hist)
+    if st not in (RBGS_OK, RBGS_ENOTCONV):
+        lib.check(st, h)
+    history = [v for v in hist if v >= 0.0]
+    return X, iters.value, rel.value, history, st == RBGS_OK
 
 
 def sketch_apply(X, kind, k, seed, zeta=8, row0=0, out=None):

@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librbgs.so")
 ARCH = "gfx950"
 
-SOURCES = ["rbgs_api.hip", "sketch_kernels.hip", "update_kernels.hip", "small_kernels.hip"]
+SOURCES = ["rbgs_api.hip", "sketch_kernels.hip", "update_kernels.hip", "small_kernels.hip",
+           "krylov_kernels.hip"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form
 # v_pk_* FP32 operations from scalar code.

@@ -51,6 +51,9 @@ struct rbgs_handle_s {
   std::vector<int64_t> graph_key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // block GMRES: basis, R, residual and least-squares buffers (grown on demand)
+  void* kry = nullptr;
+  size_t kry_bytes = 0;
   // autotuner: (m, ceil log2 n, store, math, kind, variant) -> (p, k)
   std::vector<std::pair<std::vector<int64_t>, std::pair<int64_t, int64_t>>> tuned;
 };
@@ -293,7 +296,7 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
   if (!h) return RBGS_OK;
   for (auto c : h->lanes) rbgs_destroy(c);
   if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side ||
-      !h->lane_streams.empty() || h->graph) {
+      !h->lane_streams.empty() || h->graph || h->kry) {
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     for (auto& r : h->recs) {
@@ -307,6 +310,7 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
     for (auto q : h->lane_streams) (void)hipStreamDestroy(q);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->kry) (void)hipFree(h->kry);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_cert) (void)hipHostFree(h->host_cert);
   }
@@ -329,27 +333,62 @@ const char* rbgs_status_string(rbgs_status s) {
 
 const char* rbgs_last_error(rbgs_handle h) { return h ? h->last_error.c_str() : ""; }
 
-rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
-                    const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
-                    double* R, int64_t ldr, double* S_out, rbgs_cert* cert) {
-  if (!h) return RBGS_EINVAL;
-  h->last_error.clear();
-  {
-    const rbgs_status vs = validate_qr(h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr);
-    if (vs != RBGS_OK) return vs;
-  }
-  const bool f32 = opts->store == RBGS_STORE_F32;
-  const bool f32_math = opts->math == RBGS_MATH_F32;
-  const size_t es = f32 ? 4 : 8;
+}  // extern "C"
 
-  DeviceGuard guard(h->device);
-  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)opts->stream;
-  const SketchDesc d = make_desc(sk);
-  const int64_t k = d.k;
-  const int b = (int)p;
+namespace {
 
-  // ---- workspace ---------------------------------------------------------
+// State of one RBGS factorization in progress: the blocks are processed one
+// at a time, so a caller can form W_(i) from Q_(i-1) between blocks (block
+// Arnoldi) or hand all of W at once (rbgs_qr).
+struct QrRun {
+  rbgs_handle h;
+  SketchDesc d;
+  bool f32, f32_math;
+  size_t es;
+  hipStream_t st;
+  int64_t n, m, k;
+  int b, l, variant;
+  const char* Wb;
+  int64_t ldw;
+  char* Qb;
+  void* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+  double *S, *P, *E, *part, *part2, *stack, *G, *Cb, *Yb, *cscratch, *cout;
+  uint16_t* plan;
+  int64_t* flag;
+  unsigned* counters;
+  bool overlap;  // sketches of blocks 1.. of W on the side stream (rbgs_qr only)
+};
+
+// Workspace, zeroed R, breakdown flag, sketch plan.  `hoist` says whether all
+// of W is available now (its sketch may be taken ahead of the loop).
+rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m,
+                     int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
+                     double* R, int64_t ldr, double* S_out, bool hoist) {
+  r.h = h;
+  r.d = make_desc(sk);
+  r.f32 = opts->store == RBGS_STORE_F32;
+  r.f32_math = opts->math == RBGS_MATH_F32;
+  r.es = r.f32 ? 4 : 8;
+  r.st = (hipStream_t)opts->stream;
+  r.n = n;
+  r.m = m;
+  r.k = r.d.k;
+  r.b = (int)p;
+  r.l = opts->ls_iters;
+  r.variant = opts->variant;
+  r.Wb = (const char*)W;
+  r.ldw = ldw;
+  r.Qb = (char*)Q;
+  r.Q = Q;
+  r.ldq = ldq;
+  r.R = R;
+  r.ldr = ldr;
+  const SketchDesc& d = r.d;
+  const int64_t k = r.k;
+  const int b = r.b;
   size_t off = 0;
   auto carve = [&](size_t doubles) {
     size_t o = off;
@@ -360,7 +399,8 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   const size_t o_P = carve((size_t)k * m);
   const size_t o_E = carve((size_t)k * b);
   // partial sums for every sketch width used: all of W, a full block, the last block
-  size_t part_need = std::max(sketch_partial_doubles(d, n, m), sketch_partial_doubles(d, n, std::min<int64_t>(b, m)));
+  size_t part_need = std::max(hoist ? sketch_partial_doubles(d, n, m) : 0,
+                              sketch_partial_doubles(d, n, std::min<int64_t>(b, m)));
   if (m % b) part_need = std::max(part_need, sketch_partial_doubles(d, n, m % b));
   const size_t o_part = carve(part_need);
   // The sketches of blocks 1.. of W run on a side stream while the main
@@ -368,9 +408,9 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   // small factors of a block use few compute units, so these sketches mostly
   // fill idle ones.  Block i waits for its sketch before its least squares.
   const int64_t nblk = (m + b - 1) / b;
-  const bool overlap = !h->no_overlap && d.kind != kIdentity && nblk > 1;
+  r.overlap = hoist && !h->no_overlap && d.kind != kIdentity && nblk > 1;
   size_t part2_need = 0;
-  if (overlap) {
+  if (r.overlap) {
     part2_need = sketch_partial_doubles(d, n, std::min<int64_t>(b, m), kSideGroups);
     if (m % b) part2_need = std::max(part2_need, sketch_partial_doubles(d, n, m % b, kSideGroups));
   }
@@ -387,143 +427,153 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   rbgs_status rs = ensure_ws(h, off);
   if (rs != RBGS_OK) return rs;
   char* base = (char*)h->ws;
-  double* S = S_out ? S_out : (double*)(base + o_S);
-  double* P = (double*)(base + o_P);
-  double* E = (double*)(base + o_E);
-  double* part = (double*)(base + o_part);
-  double* part2 = (double*)(base + o_part2);
-  double* stack = (double*)(base + o_stack);
-  uint16_t* plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
-  int64_t* flag = (int64_t*)(base + o_flag);
-  unsigned* counters = (unsigned*)(base + o_cnt);  // [1]: QR tree arrivals
-  double* G = (double*)(base + o_G);
-  double* Cb = (double*)(base + o_C);
-  double* Yb = (double*)(base + o_Y);
-  double* cscratch = (double*)(base + o_cs);
-  double* cout = (double*)(base + o_cout);
-
+  r.S = S_out ? S_out : (double*)(base + o_S);
+  r.P = (double*)(base + o_P);
+  r.E = (double*)(base + o_E);
+  r.part = (double*)(base + o_part);
+  r.part2 = (double*)(base + o_part2);
+  r.stack = (double*)(base + o_stack);
+  r.plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
+  r.flag = (int64_t*)(base + o_flag);
+  r.counters = (unsigned*)(base + o_cnt);  // [1]: QR tree arrivals
+  r.G = (double*)(base + o_G);
+  r.Cb = (double*)(base + o_C);
+  r.Yb = (double*)(base + o_Y);
+  r.cscratch = (double*)(base + o_cs);
+  r.cout = (double*)(base + o_cout);
+  hipStream_t st = r.st;
   HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
-  HIP_TRY(h, launch_set_i64(flag, -1, st), "flag");
-  HIP_TRY(h, launch_set_u32(counters, 2, 0u, st), "counters");
-  if (plan) {
+  HIP_TRY(h, launch_set_i64(r.flag, -1, st), "flag");
+  HIP_TRY(h, launch_set_u32(r.counters, 2, 0u, st), "counters");
+  if (r.plan) {
     ProfScope ps(h, kProfSketch, 0.0, st);
-    HIP_TRY(h, launch_sparse_plan(d, n, 0, plan, st), "sketch plan");
+    HIP_TRY(h, launch_sparse_plan(d, n, 0, r.plan, st), "sketch plan");
   }
-
+  if (!hoist) return RBGS_OK;
   // ---- step 1 ahead of the loop: P = Theta W (W_(i) is not modified before
   // block i, so sketching it early gives the same P_(i)) --------------------
-  if (!overlap) {
-    rs = do_sketch(h, d, f32, W, ldw, n, m, 0, P, k, part, plan, st);
+  if (!r.overlap) return do_sketch(h, d, r.f32, W, ldw, n, m, 0, r.P, k, r.part, r.plan, st);
+  rs = ensure_side(h, (size_t)nblk + 1);
+  if (rs != RBGS_OK) return rs;
+  hipEvent_t ev_start = h->sync_ev[nblk];
+  HIP_TRY(h, hipEventRecord(ev_start, st), "event record");
+  HIP_TRY(h, hipStreamWaitEvent(h->side, ev_start, 0), "stream wait");
+  rs = do_sketch(h, d, r.f32, W, ldw, n, std::min<int64_t>(b, m), 0, r.P, k, r.part, r.plan, st);
+  if (rs != RBGS_OK) return rs;
+  for (int64_t blk = 1; blk < nblk; ++blk) {
+    const int64_t c0 = blk * b;
+    const int64_t bwb = std::min<int64_t>(b, m - c0);
+    rs = do_sketch(h, d, r.f32, r.Wb + r.es * (size_t)(c0 * ldw), ldw, n, bwb, 0, r.P + c0 * k, k,
+                   r.part2, r.plan, h->side, kSideGroups);
     if (rs != RBGS_OK) return rs;
-  } else {
-    rs = ensure_side(h, (size_t)nblk + 1);
+    HIP_TRY(h, hipEventRecord(h->sync_ev[blk], h->side), "event record");
+  }
+  return RBGS_OK;
+}
+
+// Steps 1 (unless hoisted) to 5 of block i = c0 / b, reading W_(i) at Wi (ld
+// ldwi) and writing Q_(i); the column block of R is filled.
+rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sketch_w) {
+  rbgs_handle h = r.h;
+  const SketchDesc& d = r.d;
+  hipStream_t st = r.st;
+  const int64_t k = r.k, n = r.n, m = r.m;
+  const int b = r.b, l = r.l;
+  const int bw = (int)std::min<int64_t>(b, m - c0);
+  const int64_t K = c0;
+  double* Pi = r.P + c0 * k;
+  double* Rk = r.R + c0 * r.ldr;          // R_(1:i-1,i): rows [0, K), columns [c0, c0+bw)
+  double* Rii = r.R + c0 + c0 * r.ldr;    // R_(i,i)
+  const int64_t ldr = r.ldr;
+  void* Qi = r.Qb + r.es * (size_t)(c0 * r.ldq);
+  rbgs_status rs;
+  if (sketch_w) {
+    rs = do_sketch(h, d, r.f32, Wi, ldwi, n, bw, 0, Pi, k, r.part, r.plan, st);
     if (rs != RBGS_OK) return rs;
-    hipEvent_t ev_start = h->sync_ev[nblk];
-    HIP_TRY(h, hipEventRecord(ev_start, st), "event record");
-    HIP_TRY(h, hipStreamWaitEvent(h->side, ev_start, 0), "stream wait");
-    rs = do_sketch(h, d, f32, W, ldw, n, std::min<int64_t>(b, m), 0, P, k, part, plan, st);
-    if (rs != RBGS_OK) return rs;
-    for (int64_t blk = 1; blk < nblk; ++blk) {
-      const int64_t c0 = blk * b;
-      const int64_t bwb = std::min<int64_t>(b, m - c0);
-      rs = do_sketch(h, d, f32, (const char*)W + es * (size_t)(c0 * ldw), ldw, n, bwb, 0,
-                     P + c0 * k, k, part2, plan, h->side, kSideGroups);
-      if (rs != RBGS_OK) return rs;
-      HIP_TRY(h, hipEventRecord(h->sync_ev[blk], h->side), "event record");
+  }
+  if (r.overlap && K > 0) HIP_TRY(h, hipStreamWaitEvent(st, h->sync_ev[c0 / b], 0), "stream wait");
+  // ---- step 2: sketched least squares by l Richardson sweeps ----------
+  // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
+  // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.
+  if (K > 0) {
+    ProfScope ps(h, kProfSmall, 0.0, st);
+    const int bprev = b;  // width of block i-1 (only the last block can be narrower)
+    const double* Sprev = r.S + (K - bprev) * k;
+    double* Ccol = (l > 1) ? r.Cb : Rk;
+    const int64_t ldc = (l > 1) ? K : ldr;
+    HIP_TRY(h, launch_gram_sty(r.S, k, K, Pi, bw, Sprev, bprev, Ccol, ldc, r.G + (K - bprev) * m,
+                               m, r.G + (K - bprev), m, st),
+            "least squares: sketch products");
+    // sweeps: Y_1 = c, Y_{s+1} = Y_s + c - G Y_s.  Targets alternate between
+    // R_(1:i-1,i) and Yb so that the last sweep lands in R and no sweep
+    // writes its own input.
+    const double* Ycur = r.Cb;
+    int64_t ldycur = K;
+    for (int it = 1; it < l; ++it) {
+      const bool toR = ((l - 1 - it) & 1) == 0;
+      double* Ynext = toR ? Rk : r.Yb;
+      const int64_t ldn = toR ? ldr : K;
+      HIP_TRY(h, launch_gram_sweep(r.G, m, K, r.Cb, Ycur, ldycur, Ynext, ldn, bw, st),
+              "least squares: sweep");
+      Ycur = Ynext;
+      ldycur = ldn;
     }
   }
-
-  const char* Wb = (const char*)W;
-  char* Qb = (char*)Q;
-  const int l = opts->ls_iters;
-  for (int64_t c0 = 0; c0 < m; c0 += b) {
-    const int bw = (int)std::min<int64_t>(b, m - c0);
-    const int64_t K = c0;
-    const double* Pi = P + c0 * k;
-    double* Rk = R + c0 * ldr;            // R_(1:i-1,i): rows [0, K), columns [c0, c0+bw)
-    double* Rii = R + c0 + c0 * ldr;      // R_(i,i)
-    const void* Wi = Wb + es * (size_t)(c0 * ldw);
-    void* Qi = Qb + es * (size_t)(c0 * ldq);
-
-    if (overlap && K > 0) HIP_TRY(h, hipStreamWaitEvent(st, h->sync_ev[c0 / b], 0), "stream wait");
-    // ---- step 2: sketched least squares by l Richardson sweeps ----------
-    // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
-    // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.
-    if (K > 0) {
+  const double ub = (double)r.es * (double)n * (double)(K + 2 * bw);
+  if (r.variant == RBGS_VARIANT_LOWSYNC) {
+    // ---- steps 4-5 with postponed sketching: S'_(i) = P_(i) - S R_(1:i-1,i)
+    {
       ProfScope ps(h, kProfSmall, 0.0, st);
-      const int bprev = b;  // width of block i-1 (only the last block can be narrower)
-      const double* Sprev = S + (K - bprev) * k;
-      double* Ccol = (l > 1) ? Cb : Rk;
-      const int64_t ldc = (l > 1) ? K : ldr;
-      HIP_TRY(h, launch_gram_sty(S, k, K, Pi, bw, Sprev, bprev, Ccol, ldc, G + (K - bprev) * m, m,
-                                 G + (K - bprev), m, st),
-              "least squares: sketch products");
-      // sweeps: Y_1 = c, Y_{s+1} = Y_s + c - G Y_s.  Targets alternate between
-      // R_(1:i-1,i) and Yb so that the last sweep lands in R and no sweep
-      // writes its own input.
-      const double* Ycur = Cb;
-      int64_t ldycur = K;
-      for (int it = 1; it < l; ++it) {
-        const bool toR = ((l - 1 - it) & 1) == 0;
-        double* Ynext = toR ? Rk : Yb;
-        const int64_t ldn = toR ? ldr : K;
-        HIP_TRY(h, launch_gram_sweep(G, m, K, Cb, Ycur, ldycur, Ynext, ldn, bw, st),
-                "least squares: sweep");
-        Ycur = Ynext;
-        ldycur = ldn;
+      const double* Sp = Pi;
+      if (K > 0) {
+        HIP_TRY(h, launch_resid(Pi, r.S, k, K, Rk, ldr, r.E, bw, st), "S'");
+        Sp = r.E;
       }
+      HIP_TRY(h, launch_qr_fused(Sp, k, bw, r.stack, r.counters + 1, Rii, ldr, r.flag, c0, st),
+              "qr of sketch");
     }
-    const double ub = (double)es * (double)n * (double)(K + 2 * bw);
-    if (opts->variant == RBGS_VARIANT_LOWSYNC) {
-      // ---- steps 4-5 with postponed sketching: S'_(i) = P_(i) - S R_(1:i-1,i)
-      {
-        ProfScope ps(h, kProfSmall, 0.0, st);
-        const double* Sp = Pi;
-        if (K > 0) {
-          HIP_TRY(h, launch_resid(Pi, S, k, K, Rk, ldr, E, bw, st), "S'");
-          Sp = E;
-        }
-        HIP_TRY(h, launch_qr_fused(Sp, k, bw, stack, counters + 1, Rii, ldr, flag, c0, st),
-                "qr of sketch");
-      }
-      // ---- step 3 + substitution in one pass --------------------------
-      {
-        ProfScope ps(h, kProfUpdate, ub, st);
-        HIP_TRY(h, launch_update(f32, f32_math, Wi, ldw, Q, ldq, Qi, ldq, Rk, Rii, ldr, n, K, bw, st),
-                "update");
-      }
-    } else {
-      // ---- step 3: Q'_(i), stored in Q_(i) ------------------------------
-      {
-        ProfScope ps(h, kProfUpdate, ub, st);
-        HIP_TRY(h, launch_update(f32, f32_math, Wi, ldw, Q, ldq, Qi, ldq, Rk, nullptr, ldr, n, K, bw, st),
-                "update");
-      }
-      // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution -----------
-      rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, E, k, part, plan, st);
-      if (rs != RBGS_OK) return rs;
-      {
-        ProfScope ps(h, kProfSmall, 0.0, st);
-        HIP_TRY(h, launch_qr_fused(E, k, bw, stack, counters + 1, Rii, ldr, flag, c0, st),
-                "qr of sketch");
-      }
-      {
-        ProfScope ps(h, kProfTrsm, 2.0 * es * n * bw, st);
-        HIP_TRY(h, launch_trsm(f32, Qi, ldq, Rii, ldr, n, bw, st), "substitution");
-      }
+    // ---- step 3 + substitution in one pass --------------------------
+    {
+      ProfScope ps(h, kProfUpdate, ub, st);
+      HIP_TRY(h, launch_update(r.f32, r.f32_math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, Rii, ldr, n,
+                               K, bw, st),
+              "update");
     }
-    // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------
-    rs = do_sketch(h, d, f32, Qi, ldq, n, bw, 0, S + c0 * k, k, part, plan, st);
+  } else {
+    // ---- step 3: Q'_(i), stored in Q_(i) ------------------------------
+    {
+      ProfScope ps(h, kProfUpdate, ub, st);
+      HIP_TRY(h, launch_update(r.f32, r.f32_math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, nullptr, ldr,
+                               n, K, bw, st),
+              "update");
+    }
+    // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution -----------
+    rs = do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.E, k, r.part, r.plan, st);
     if (rs != RBGS_OK) return rs;
+    {
+      ProfScope ps(h, kProfSmall, 0.0, st);
+      HIP_TRY(h, launch_qr_fused(r.E, k, bw, r.stack, r.counters + 1, Rii, ldr, r.flag, c0, st),
+              "qr of sketch");
+    }
+    {
+      ProfScope ps(h, kProfTrsm, 2.0 * r.es * n * bw, st);
+      HIP_TRY(h, launch_trsm(r.f32, Qi, r.ldq, Rii, ldr, n, bw, st), "substitution");
+    }
   }
+  // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------
+  return do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.S + c0 * k, k, r.part, r.plan, st);
+}
 
-  if (!cert) return RBGS_OK;
-  // ---- step 6: certificates (host waits) ---------------------------------
-  HIP_TRY(h, launch_certificates(S, P, R, ldr, k, m, cscratch, cout, st), "certificates");
+// Step 6: certificates; the host waits for the stream.
+rbgs_status qr_certify(QrRun& r, rbgs_cert* cert) {
+  rbgs_handle h = r.h;
+  hipStream_t st = r.st;
+  HIP_TRY(h, launch_certificates(r.S, r.P, r.R, r.ldr, r.k, r.m, r.cscratch, r.cout, st),
+          "certificates");
   if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
-  HIP_TRY(h, hipMemcpyAsync(h->host_cert, cout, 4 * sizeof(double), hipMemcpyDeviceToHost, st),
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert, r.cout, 4 * sizeof(double), hipMemcpyDeviceToHost, st),
           "copy certificate");
-  HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, r.flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
           "copy flag");
   HIP_TRY(h, hipStreamSynchronize(st), "stream synchronize");
   const double* hc = h->host_cert;
@@ -541,6 +591,32 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
     return fail(h, RBGS_EBREAKDOWN, buf);
   }
   return RBGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m, int64_t p,
+                    const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
+                    double* R, int64_t ldr, double* S_out, rbgs_cert* cert) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  {
+    const rbgs_status vs = validate_qr(h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr);
+    if (vs != RBGS_OK) return vs;
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  QrRun r;
+  rbgs_status rs = qr_begin(r, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, true);
+  if (rs != RBGS_OK) return rs;
+  for (int64_t c0 = 0; c0 < m; c0 += p) {
+    rs = qr_block(r, c0, r.Wb + r.es * (size_t)(c0 * ldw), ldw, false);
+    if (rs != RBGS_OK) return rs;
+  }
+  if (!cert) return RBGS_OK;
+  return qr_certify(r, cert);
 }
 
 // ---------------------------------------------------------------------------
@@ -822,6 +898,246 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   h->graph = g;
   h->graph_exec = ex;
   h->graph_key = key;
+  return RBGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Block Krylov solvers (Section 4).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+rbgs_status validate_csr(rbgs_handle h, const rbgs_csr* A) {
+  if (!A) return fail(h, RBGS_EINVAL, "A is NULL");
+  if (A->n < 1 || A->nnz < 0) return fail(h, RBGS_EINVAL, "A needs n >= 1 and nnz >= 0");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(h, RBGS_EINVAL, "A has NULL arrays");
+  if (A->n > INT32_MAX) return fail(h, RBGS_EUNSUPPORTED, "n above 2^31 - 1");
+  return RBGS_OK;
+}
+
+int store_bytes(int32_t store) { return store == RBGS_STORE_F32 ? 4 : 8; }
+
+rbgs_status ensure_kry(rbgs_handle h, size_t bytes) {
+  if (bytes <= h->kry_bytes) return RBGS_OK;
+  if (h->kry) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->kry);
+    h->kry = nullptr;
+    h->kry_bytes = 0;
+  }
+  if (hipMalloc(&h->kry, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, RBGS_ENOMEM, "Krylov buffers of " + std::to_string(bytes) + " bytes");
+  }
+  h->kry_bytes = bytes;
+  return RBGS_OK;
+}
+
+// RBGS-Arnoldi on a caller-validated configuration: W_(1) at B (ld ldb),
+// W_(i) = A Q_(i-1) formed in place in Q.
+rbgs_status arnoldi_run(rbgs_handle h, const rbgs_csr* A, const void* B, int64_t ldb, int64_t bs,
+                        int64_t nblocks, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q,
+                        int64_t ldq, double* R, int64_t ldr, rbgs_cert* cert) {
+  const int64_t n = A->n, m = nblocks * bs;
+  const int es = store_bytes(opts->store);
+  QrRun r;
+  rbgs_status rs = qr_begin(r, h, Q, ldq, n, m, bs, sk, opts, Q, ldq, R, ldr, nullptr, false);
+  if (rs != RBGS_OK) return rs;
+  rs = qr_block(r, 0, B, ldb, true);
+  if (rs != RBGS_OK) return rs;
+  char* Qb = (char*)Q;
+  for (int64_t i = 1; i < nblocks; ++i) {
+    void* Qi = Qb + (size_t)es * (size_t)(i * bs * ldq);
+    const void* Qp = Qb + (size_t)es * (size_t)((i - 1) * bs * ldq);
+    HIP_TRY(h, launch_spmm(n, A->row_ptr, A->col_idx, A->val, es, Qp, ldq, (int)bs, 1.0, 0.0,
+                           nullptr, 0, es, Qi, ldq, r.st),
+            "A Q_(i-1)");
+    rs = qr_block(r, i * bs, Qi, ldq, true);
+    if (rs != RBGS_OK) return rs;
+  }
+  return cert ? qr_certify(r, cert) : RBGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbgs_status rbgs_spmm(rbgs_handle h, const rbgs_csr* A, int32_t xstore, const void* X, int64_t ldx,
+                      int64_t bs, double alpha, double beta, const double* Y0, int64_t ldy0,
+                      int32_t ystore, void* Y, int64_t ldy, void* stream) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  rbgs_status vs = validate_csr(h, A);
+  if (vs != RBGS_OK) return vs;
+  if (!X || !Y) return fail(h, RBGS_EINVAL, "X and Y must be non-NULL");
+  if (bs < 1 || bs > 32) return fail(h, bs < 1 ? RBGS_EINVAL : RBGS_EUNSUPPORTED, "need 1 <= bs <= 32");
+  if ((xstore != RBGS_STORE_F32 && xstore != RBGS_STORE_F64) ||
+      (ystore != RBGS_STORE_F32 && ystore != RBGS_STORE_F64))
+    return fail(h, RBGS_EINVAL, "unknown storage type");
+  const int64_t n = A->n;
+  if (ldx < n || ldy < n || (Y0 && ldy0 < n)) return fail(h, RBGS_EINVAL, "leading dimensions must be >= n");
+  {
+    const char* x0 = (const char*)X;
+    const char* x1 = x0 + (size_t)store_bytes(xstore) * (size_t)(ldx * (bs - 1) + n);
+    const char* y0 = (const char*)Y;
+    const char* y1 = y0 + (size_t)store_bytes(ystore) * (size_t)(ldy * (bs - 1) + n);
+    if (y0 < x1 && x0 < y1) return fail(h, RBGS_EINVAL, "Y overlaps X");
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  HIP_TRY(h, launch_spmm(n, A->row_ptr, A->col_idx, A->val, store_bytes(xstore), X, ldx, (int)bs,
+                         alpha, beta, Y0, ldy0, store_bytes(ystore), Y, ldy, (hipStream_t)stream),
+          "spmm");
+  return RBGS_OK;
+}
+
+rbgs_status rbgs_block_arnoldi(rbgs_handle h, const rbgs_csr* A, const void* B, int64_t ldb,
+                               int64_t bs, int64_t nblocks, const rbgs_sketch* sk,
+                               const rbgs_opts* opts, void* Q, int64_t ldq, double* R, int64_t ldr,
+                               rbgs_cert* cert) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  rbgs_status vs = validate_csr(h, A);
+  if (vs != RBGS_OK) return vs;
+  if (!B) return fail(h, RBGS_EINVAL, "B is NULL");
+  if (bs < 1 || nblocks < 1) return fail(h, RBGS_EINVAL, "need bs >= 1 and nblocks >= 1");
+  const int64_t n = A->n, m = nblocks * bs;
+  if (ldb < n) return fail(h, RBGS_EINVAL, "ldb must be >= n");
+  // Q plays W (formed block by block in place): the checks of rbgs_qr apply
+  vs = validate_qr(h, Q, ldq, n, m, bs, sk, opts, Q, ldq, R, ldr);
+  if (vs != RBGS_OK) return vs;
+  {
+    const size_t es = (size_t)store_bytes(opts->store);
+    const char* b0 = (const char*)B;
+    const char* b1 = b0 + es * (size_t)(ldb * (bs - 1) + n);
+    const char* q0 = (const char*)Q;
+    const char* q1 = q0 + es * (size_t)(ldq * (m - 1) + n);
+    if (b0 < q1 && q0 < b1) return fail(h, RBGS_EINVAL, "B overlaps Q");
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  return arnoldi_run(h, A, B, ldb, bs, nblocks, sk, opts, Q, ldq, R, ldr, cert);
+}
+
+rbgs_status rbgs_block_gmres(rbgs_handle h, const rbgs_csr* A, const double* B, double* X,
+                             int64_t bs, int64_t blocks_per_cycle, int64_t max_cycles, double tol,
+                             const rbgs_sketch* sk, const rbgs_opts* opts, int64_t* iters,
+                             double* relres, double* history) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  rbgs_status vs = validate_csr(h, A);
+  if (vs != RBGS_OK) return vs;
+  if (!B || !X || !iters || !relres) return fail(h, RBGS_EINVAL, "NULL argument");
+  if (bs < 1 || bs > 32) return fail(h, bs < 1 ? RBGS_EINVAL : RBGS_EUNSUPPORTED, "need 1 <= bs <= 32");
+  if (blocks_per_cycle < 1 || max_cycles < 1 || !(tol >= 0.0))
+    return fail(h, RBGS_EINVAL, "need blocks_per_cycle >= 1, max_cycles >= 1, tol >= 0");
+  const int64_t n = A->n, nb = blocks_per_cycle + 1, m = nb * bs;
+  if (m > n) return fail(h, RBGS_EINVAL, "(blocks_per_cycle + 1) bs must not exceed n");
+  if ((const void*)B == (const void*)X) return fail(h, RBGS_EINVAL, "B and X must differ");
+  const size_t es = (size_t)store_bytes(opts ? opts->store : RBGS_STORE_F64);
+  // buffers: basis | R | T (residual) | LS matrix | Z | resid | sumsq scratch | norms
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    size_t o = off;
+    off += ((bytes + 255) / 256) * 256;
+    return o;
+  };
+  const size_t o_Q = carve(es * (size_t)(n * m));
+  const size_t o_R = carve(8 * (size_t)(m * m));
+  const size_t o_T = carve(8 * (size_t)(n * bs));
+  const size_t o_A = carve(8 * (size_t)(m * m));
+  const size_t o_Z = carve(8 * (size_t)(m * bs));
+  const size_t o_res = carve(8 * (size_t)bs);
+  const size_t o_ss = carve(8 * sumsq_scratch());
+  const size_t o_nrm = carve(8 * 2);
+  // validate the Arnoldi configuration with the basis location as a stand-in
+  // (device pointers are not dereferenced by validation)
+  {
+    const char* fake = (const char*)(uintptr_t)0x1000;
+    vs = validate_qr(h, fake, n, n, m, bs, sk, opts, (void*)fake, n, (double*)(fake + es * (size_t)(n * m) + 4096), m);
+    if (vs != RBGS_OK) return vs;
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  rbgs_status rs = ensure_kry(h, off);
+  if (rs != RBGS_OK) return rs;
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  char* base = (char*)h->kry;
+  void* Qb = base + o_Q;
+  double* Rm = (double*)(base + o_R);
+  double* T = (double*)(base + o_T);
+  double* Als = (double*)(base + o_A);
+  double* Z = (double*)(base + o_Z);
+  double* res = (double*)(base + o_res);
+  double* ss = (double*)(base + o_ss);
+  double* nrm = (double*)(base + o_nrm);
+  hipStream_t st = (hipStream_t)opts->stream;
+  const bool f32 = opts->store == RBGS_STORE_F32;
+  auto norm2_to_host = [&](const double* Y, double* out) -> rbgs_status {
+    HIP_TRY(h, launch_sumsq(Y, n, n, (int)bs, ss, nrm, st), "norm");
+    HIP_TRY(h, hipMemcpyAsync(h->host_cert, nrm, sizeof(double), hipMemcpyDeviceToHost, st), "copy norm");
+    HIP_TRY(h, hipStreamSynchronize(st), "stream synchronize");
+    *out = h->host_cert[0];
+    return RBGS_OK;
+  };
+  auto residual = [&](double* out_rel) -> rbgs_status {
+    HIP_TRY(h, launch_spmm(n, A->row_ptr, A->col_idx, A->val, 8, X, n, (int)bs, -1.0, 1.0, B, n, 8,
+                           T, n, st),
+            "residual");
+    double rr = 0.0;
+    rbgs_status r2 = norm2_to_host(T, &rr);
+    if (r2 != RBGS_OK) return r2;
+    *out_rel = rr;
+    return RBGS_OK;
+  };
+  double bb = 0.0;
+  rs = norm2_to_host(B, &bb);
+  if (rs != RBGS_OK) return rs;
+  if (history)
+    for (int64_t c = 0; c <= max_cycles; ++c) history[c] = -1.0;
+  const double bnorm = sqrt(bb);
+  int64_t done = 0;
+  double rel = 0.0;
+  bool converged = false;
+  int64_t c = 0;
+  for (; c < max_cycles; ++c) {
+    double rr = 0.0;
+    rs = residual(&rr);
+    if (rs != RBGS_OK) return rs;
+    rel = bnorm > 0 ? sqrt(rr) / bnorm : sqrt(rr);
+    if (history) history[c] = rel;
+    if (rel <= tol) {
+      converged = true;
+      break;
+    }
+    // W_(1) = R0 in the basis precision, then RBGS-Arnoldi in place
+    HIP_TRY(h, launch_convert(T, n, n, (int)bs, f32, Qb, n, st), "residual to basis");
+    rs = arnoldi_run(h, A, Qb, n, bs, nb, sk, opts, Qb, n, Rm, m, nullptr);
+    if (rs != RBGS_OK) return rs;
+    // min_Z ||H Z - R_(1:p,1)||, H = R[:, bs:m] (block upper Hessenberg)
+    const int64_t nc = m - bs;
+    HIP_TRY(h, hipMemcpyAsync(Als, Rm + bs * m, 8 * (size_t)(m * nc), hipMemcpyDeviceToDevice, st),
+            "copy H");
+    HIP_TRY(h, hipMemcpyAsync(Als + nc * m, Rm, 8 * (size_t)(m * bs), hipMemcpyDeviceToDevice, st),
+            "copy R_(1:p,1)");
+    HIP_TRY(h, launch_hess_ls(Als, m, (int)m, (int)nc, (int)bs, (int)bs, Z, nc, res, st),
+            "Hessenberg least squares");
+    HIP_TRY(h, launch_gemm_update(f32, n, (int)nc, (int)bs, Qb, n, Z, nc, X, n, st), "X += Q Z");
+    done += blocks_per_cycle;
+  }
+  if (!converged) {
+    double rr = 0.0;
+    rs = residual(&rr);
+    if (rs != RBGS_OK) return rs;
+    rel = bnorm > 0 ? sqrt(rr) / bnorm : sqrt(rr);
+    if (history) history[c] = rel;
+    converged = rel <= tol;
+  }
+  *iters = done;
+  *relres = rel;
+  if (!converged) return fail(h, RBGS_ENOTCONV, "relative residual " + std::to_string(rel) + " above tol");
   return RBGS_OK;
 }
 

@@ -185,6 +185,30 @@ hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_
 
 // Small FP64 factors (Sections 2.1 and 2.2).  Workspace for the QR tree of a k x bw matrix.
 size_t qr_stack_size(int64_t k, int bw);
+// ---- block Krylov solvers --------------------------------------------------
+// Y (n x bs, ld ldy, element size ty: 4 or 8) = alpha A X + beta Y0, A in CSR
+// (row pointers rp[n+1] int64, column indices ci int32, values av FP64), X of
+// element size tx, Y0 FP64 or NULL.  FP64 arithmetic.  bs <= 32.
+hipError_t launch_spmm(int64_t n, const int64_t* rp, const int32_t* ci, const double* av, int tx,
+                       const void* X, int64_t ldx, int bs, double alpha, double beta,
+                       const double* Y0, int64_t ldy0, int ty, void* Y, int64_t ldy,
+                       hipStream_t st);
+// min_Z ||A[:, :nc] Z - A[:, nc:nc+nrhs]||_F for a matrix zero below `band`
+// subdiagonals (A overwritten); Z nc x nrhs; resid[c] = squared residual norm.
+hipError_t launch_hess_ls(double* A, int64_t lda, int nr, int nc, int nrhs, int band, double* Z,
+                          int64_t ldz, double* resid, hipStream_t st);
+// X (n x bs FP64) += Q (n x N, FP32 or FP64) Z (N x bs FP64).
+hipError_t launch_gemm_update(bool f32, int64_t n, int N, int bs, const void* Q, int64_t ldq,
+                              const double* Z, int64_t ldz, double* X, int64_t ldx,
+                              hipStream_t st);
+// out = ||X||_F^2 (n x bs FP64), scratch of sumsq_scratch() doubles; fixed order.
+size_t sumsq_scratch();
+hipError_t launch_sumsq(const double* X, int64_t ldx, int64_t n, int bs, double* scratch,
+                        double* out, hipStream_t st);
+// Y (FP32 or FP64) = X (FP64), n x bs.
+hipError_t launch_convert(const double* X, int64_t ldx, int64_t n, int bs, bool f32, void* Y,
+                          int64_t ldy, hipStream_t st);
+
 // Synthetic full-rank test matrix (n x m, ld >= n) for the autotuner.
 hipError_t launch_fill_test(void* X, bool f32, int64_t n, int64_t m, int64_t ld, hipStream_t st);
 // out0 (K x n0, ld ldo0) = S^T X0, out1 (K x n1, ld ldo1) = S^T X1 and, if

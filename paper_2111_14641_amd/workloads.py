@@ -26,6 +26,17 @@ returned in FP64, column-major (Fortran order), so that column j is contiguous.
   (cond(G) <= (1 + sqrt(m/n)) / (1 - sqrt(m/n)) < 1.3), sigma =
   logspace(0, -c, m), c ~ U[2, 10], V a seeded orthogonal m x m matrix: so
   cond(W) is 10^c up to that factor.
+* `convection_diffusion_csr(N, beta)`: the block GMRES operator, the 2-D
+  convection-diffusion operator -Laplace(u) + beta (1, 1) . grad(u) on the
+  unit square with homogeneous Dirichlet conditions, discretized on the N x N
+  interior grid (h = 1 / (N + 1)) by the 5-point stencil with first-order
+  upwind convection and scaled by h^2: diagonal 4 + 2 beta h, west and south
+  -1 - beta h, east and north -1.  Unknown (i, j) (1-based) is row
+  (i - 1) + N (j - 1).  Returns CSR arrays (indptr int64, indices int32,
+  data float64), columns sorted within each row.  N = 1024 gives n = 1048576
+  with 5 n - 4 N nonzeros.
+* `gmres_rhs(n, bs, seed)`: the block of right-hand sides, seeded standard
+  Gaussian n x bs (FP64, column-major).
 """
 import numpy as np
 
@@ -104,6 +115,36 @@ def batched_problems(count=512, seed=0xDA7A04, device="cuda"):
         del G
         out.append((W, n, m, c))
     return out
+
+
+def convection_diffusion_csr(N, beta=50.0):
+    h = 1.0 / (N + 1)
+    n = N * N
+    r = np.arange(n, dtype=np.int64)
+    i = r % N
+    j = r // N
+    cols, vals, valid = [], [], []
+    # neighbours in increasing column order: south, west, centre, east, north
+    for dc, ok, v in ((-N, j > 0, -1.0 - beta * h), (-1, i > 0, -1.0 - beta * h),
+                      (0, np.ones(n, bool), 4.0 + 2.0 * beta * h), (1, i < N - 1, -1.0),
+                      (N, j < N - 1, -1.0)):
+        cols.append(r + dc)
+        vals.append(np.full(n, v))
+        valid.append(ok)
+    C = np.stack(cols, axis=1)
+    V = np.stack(vals, axis=1)
+    M = np.stack(valid, axis=1)
+    counts = M.sum(axis=1)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    indices = C[M].astype(np.int32)
+    data = V[M].astype(np.float64)
+    return indptr, indices, data
+
+
+def gmres_rhs(n, bs, seed=0xDA7A03):
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((n, bs)))
 
 
 def large_single_qr(seed=0xDA7A01, n=1_000_000, m=256, dtype=np.float64):

@@ -1,0 +1,138 @@
+"""Block Krylov solvers on the GPU against the FP64 oracle: CSR SpMM,
+RBGS-Arnoldi (elementwise and through the Arnoldi identity), randomized block
+GMRES (exact solution when the Krylov space is everything; convergence and
+solution on a larger grid), and a few cycles on the 1024 x 1024 grid."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import krylov
+from oracle.theta import Sketch
+from paper_2111_14641_amd.workloads import convection_diffusion_csr, gmres_rhs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def host_csr(N):
+    indptr, indices, data = convection_diffusion_csr(N)
+    return (indptr, indices, data), sp.csr_matrix((data, indices, indptr), shape=(N * N, N * N))
+
+
+def dev(X, dtype):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    Xt = B.colmajor(X.shape[0], X.shape[1], dtype)
+    Xt.copy_(torch.from_numpy(np.asarray(X, dtype=np.float64)))
+    return Xt
+
+
+def to_np(t):
+    return np.ascontiguousarray(t.double().cpu().numpy())
+
+
+@pytest.mark.parametrize("bs", [1, 8, 13])
+@pytest.mark.parametrize("xdt,ydt", [("f64", "f64"), ("f32", "f32"), ("f64", "f32")])
+def test_spmm_matches_library_product(gpu_lib, bs, xdt, ydt):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("spmm", bs, xdt, ydt)
+    arrs, A = host_csr(37)
+    n = A.shape[0]
+    rng = np.random.default_rng(bs)
+    X = rng.standard_normal((n, bs))
+    Y0 = rng.standard_normal((n, bs))
+    tx = torch.float64 if xdt == "f64" else torch.float32
+    ty = torch.float64 if ydt == "f64" else torch.float32
+    if xdt == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    Ad = B.CSR(*arrs)
+    Y = to_np(B.spmm(Ad, dev(X, tx), alpha=-1.5, beta=0.5, Y0=dev(Y0, torch.float64), out_dtype=ty))
+    ref = -1.5 * (A @ X) + 0.5 * Y0
+    scale = 1.5 * (abs(A) @ np.abs(X)) + 0.5 * np.abs(Y0)
+    tol = (4e-16 if ydt == "f64" else 2 ** -24) * 8 * scale
+    assert np.all(np.abs(Y - ref) <= tol + 1e-300)
+
+
+@pytest.mark.parametrize("kind", ["sparse", "gaussian"])
+def test_arnoldi_matches_oracle(gpu_lib, kind):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("arnoldi", kind)
+    N, bs, nb, k = 64, 4, 10, 160
+    arrs, A = host_csr(N)
+    n = N * N
+    Bh = gmres_rhs(n, bs, seed=11)
+    Q, R, cert = B.block_arnoldi(B.CSR(*arrs), dev(Bh, torch.float64), nb, kind, k, seed=21,
+                                 ls_iters=2, want_cert=True)
+    Qg, Rg = to_np(Q), to_np(R)
+    th = Sketch(kind, k, seed=21).materialize(n)
+    Qo, Ro, So = krylov.rbgs_arnoldi(A, Bh, nb, th, "lowsync", "richardson", 2)
+    m = nb * bs
+    assert np.linalg.norm(Rg - Ro) <= 1e-11 * np.linalg.norm(Ro)
+    assert np.linalg.norm(Qg - Qo) <= 1e-10 * np.linalg.norm(Qo)
+    An = np.linalg.norm(A.toarray(), 2)
+    assert np.linalg.norm(A @ Qg[:, :m - bs] - Qg @ Rg[:, bs:]) <= 1e-12 * An * np.linalg.norm(Qg)
+    assert cert["delta"] < 1e-10 and cert["breakdown_col"] == -1
+
+
+def test_gmres_exact_solution_small(gpu_lib):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("gmres exact")
+    N, bs = 8, 2
+    arrs, A = host_csr(N)
+    n = N * N
+    Bh = gmres_rhs(n, bs, seed=4)
+    X, iters, rel, hist, ok = B.block_gmres(B.CSR(*arrs), dev(Bh, torch.float64), None,
+                                           n // bs - 1, 2, 1e-10, kind="identity", k=n,
+                                           store="f64", variant="plain")
+    Xd = spla.spsolve(A.tocsc(), Bh)
+    assert ok and rel <= 1e-10
+    assert np.linalg.norm(to_np(X) - Xd) <= 1e-9 * np.linalg.norm(Xd)
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_gmres_converges_like_the_oracle(gpu_lib, store):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("gmres", store)
+    N, bs, p, k = 32, 4, 20, 512
+    arrs, A = host_csr(N)
+    n = N * N
+    Bh = gmres_rhs(n, bs, seed=5)
+    X, iters, rel, hist, ok = B.block_gmres(B.CSR(*arrs), dev(Bh, torch.float64), None, p, 30, 1e-8,
+                                           kind="sparse", k=k, seed=6, store=store)
+    Xo, ho = krylov.block_gmres(A, Bh, np.zeros((n, bs)), p, 30, 1e-8,
+                                Sketch("sparse", k, seed=6).materialize(n))
+    assert ok and rel <= 1e-8 and ho[-1] <= 1e-8
+    # same number of cycles give or take one; same solution
+    assert abs(len(hist) - len(ho)) <= 1
+    Xd = spla.spsolve(A.tocsc(), Bh)
+    assert np.linalg.norm(to_np(X) - Xd) <= 1e-5 * np.linalg.norm(Xd)
+    if store == "f64":
+        np.testing.assert_allclose(hist[:3], ho[:3], rtol=1e-6)
+
+
+def test_gmres_full_grid_first_cycles(gpu_lib):
+    """The 1024 x 1024 operator, 8 right-hand sides, 40 blocks per cycle,
+    k = 1280, FP32 basis: three cycles reduce the residual."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("gmres 1024^2")
+    N, bs = 1024, 8
+    arrs, _ = host_csr(N)
+    n = N * N
+    Bh = gmres_rhs(n, bs)
+    X, iters, rel, hist, ok = B.block_gmres(B.CSR(*arrs), dev(Bh, torch.float64), None, 40, 3, 1e-8,
+                                           kind="sparse", k=1280, seed=7, store="f32")
+    say("history", hist)
+    assert iters == 120 and len(hist) == 4
+    assert all(b < a for a, b in zip(hist, hist[1:]))
+    assert np.isfinite(to_np(X)).all()
