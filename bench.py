@@ -187,6 +187,48 @@ def batched_form(count=512, reps=3):
                                                           for k, W in zip(ks, Ws))))
 
 
+def gmres_form(N=1024, bs=8, blocks=40, k=1280, max_cycles=60, tol=1e-8):
+    """Restarted randomized block GMRES on the N x N convection-diffusion
+    operator (n = N^2, FP64 CSR), bs Gaussian right-hand sides, `blocks` blocks
+    per cycle (basis m = blocks bs), sparse-sign sketch with k rows, FP32 basis,
+    FP64 Hessenberg least squares; plus the CSR SpMM rate."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    from paper_2111_14641_amd.workloads import convection_diffusion_csr, gmres_rhs
+    indptr, indices, data = convection_diffusion_csr(N)
+    A = B.CSR(indptr, indices, data)
+    n = N * N
+    Bh = gmres_rhs(n, bs)
+    Bt = B.colmajor(n, bs, torch.float64)
+    Bt.copy_(torch.from_numpy(Bh))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        X32 = B.colmajor(n, bs, torch.float32)
+        X32.copy_(Bt)
+        B.spmm(A, X32)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            B.spmm(A, X32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        spmm_us = e0.elapsed_time(e1) / 20 * 1e3
+        spmm_bytes = 8 * (n + 1) + 12 * len(data) + 2 * 4 * n * bs  # CSR + X once + Y
+        t = time.perf_counter()
+        X, iters, rel, hist, ok = B.block_gmres(A, Bt, None, blocks, max_cycles, tol, kind="sparse",
+                                                k=k, seed=0x2111146413, store="f32")
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t
+    return dict(n=n, nnz=len(data), bs=bs, blocks_per_cycle=blocks, k=k, converged=bool(ok),
+                cycles=len(hist) - (0 if ok else 1), block_iters=iters, relres=float(f"{rel:.3g}"),
+                seconds=round(secs, 3), ms_per_block_iter=round(secs * 1e3 / max(iters, 1), 4),
+                history_head=[float(f"{v:.3g}") for v in hist[:4]],
+                history_tail=[float(f"{v:.3g}") for v in hist[-3:]],
+                spmm_us=round(spmm_us, 2), spmm_GBps=round(spmm_bytes / (spmm_us * 1e-6) / 1e9, 1))
+
+
 def copy_bandwidth():
     """Measured rate of a plain streaming kernel, y = x + 1 over 1 GiB of FP32
     (1 GiB read + 1 GiB written): a practical ceiling beside the nominal
@@ -250,6 +292,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gaussian", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--forms", default="all", help="'headline' to time only the headline form")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -301,6 +344,9 @@ def main():
     if args.forms == "all" and not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         forms["batched_512_f32"] = batched_form()
+    if args.forms == "all" and not args.no_gmres:
+        print("[bench] block GMRES", file=sys.stderr, flush=True)
+        forms["gmres_convdiff_1024_f32basis"] = gmres_form()
     copy_gbs = copy_bandwidth()
     upd_ms, upd_cnt, upd_bytes = upd
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0
