@@ -28,12 +28,28 @@ __global__ __launch_bounds__(256) void spmm_csr_kernel(int64_t n, const int64_t*
 #pragma unroll
   for (int j = 0; j < MB; ++j) acc[j] = 0.0;
   const int64_t e0 = rp[row], e1 = rp[row + 1];
-  for (int64_t e = e0; e < e1; ++e) {
-    const int64_t c = ci[e];
-    const double a = av[e];
+  // entries in chunks of 8: all loads of a chunk are issued before the first
+  // is used (indices clamped into the row, values of padding entries zero)
+  constexpr int EC = 8;
+  for (int64_t eb = e0; eb < e1; eb += EC) {
+    int64_t c[EC];
+    double a[EC];
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
-      if (j < bs) acc[j] = fma(a, (double)X[c + j * ldx], acc[j]);
+    for (int q = 0; q < EC; ++q) {
+      const bool in = eb + q < e1;
+      const int64_t e = in ? eb + q : e1 - 1;
+      c[q] = ci[e];
+      const double v = av[e];
+      a[q] = in ? v : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < EC; ++q) {
+      // every column slot is accumulated (slots j >= bs read column 0 and are
+      // never stored), so no load sits under a branch
+#pragma unroll
+      for (int j = 0; j < MB; ++j)
+        acc[j] = fma(a[q], (double)X[c[q] + (int64_t)(j < bs ? j : 0) * ldx], acc[j]);
+    }
   }
 #pragma unroll
   for (int j = 0; j < MB; ++j) {
@@ -186,20 +202,33 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int64_t n, int N, int 
     __syncthreads();
     for (int e = threadIdx.x; e < CH * 32; e += blockDim.x) {
       const int j = e % CH, c = e / CH;
-      zs[e] = (j < jc && c < bs) ? Z[(j0 + j) + (int64_t)c * ldz] : 0.0;
+      const bool in = j < jc && c < bs;
+      const double z = Z[in ? (j0 + j) + (int64_t)c * ldz : 0];
+      zs[e] = in ? z : 0.0;
     }
     __syncthreads();
-    for (int j = 0; j < jc; ++j) {
-      const double q = (double)Q[rr + (int64_t)(j0 + j) * ldq];
+    // eight columns of Q per pass, loads issued together (rows of zs past jc
+    // are zero, so the clamped extra loads add nothing)
+    for (int j = 0; j < jc; j += 8) {
+      double q[8];
 #pragma unroll
-      for (int c = 0; c < 32; ++c)
-        if (c < bs) acc[c] = fma(q, zs[j + c * CH], acc[c]);
+      for (int u = 0; u < 8; ++u) q[u] = (double)Q[rr + (int64_t)(j0 + min(j + u, jc - 1)) * ldq];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jj = min(j + u, CH - 1);
+        const double qu = j + u < jc ? q[u] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] = fma(qu, zs[jj + c * CH], acc[c]);
+      }
     }
   }
+  double x[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) x[c] = X[rr + (int64_t)(c < bs ? c : 0) * ldx];
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 32; ++c)
-      if (c < bs) X[row + (int64_t)c * ldx] += acc[c];
+      if (c < bs) X[row + (int64_t)c * ldx] = x[c] + acc[c];
   }
 }
 

@@ -315,10 +315,19 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
 
   for (int64_t tile0 = rbeg; tile0 < rend; tile0 += kGaTile) {
     const int trows = (int)min((int64_t)kGaTile, rend - tile0);
-    for (int e = tid; e < kGaTile * kSketchCols; e += kGaThreads) {
+    // unconditional loads from clamped addresses, then masked
+    T v[kGaTile * kSketchCols / kGaThreads];
+#pragma unroll
+    for (int i = 0; i < kGaTile * kSketchCols / kGaThreads; ++i) {
+      const int e = tid + i * kGaThreads;
       const int c = e / kGaTile, rr = e % kGaTile;
-      xs[rr * kSketchCols + c] =
-          (rr < trows && c < nc) ? to_f64(X[(tile0 + rr) + (int64_t)(col0 + c) * ldx]) : 0.0;
+      v[i] = X[(tile0 + (rr < trows ? rr : trows - 1)) + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+    }
+#pragma unroll
+    for (int i = 0; i < kGaTile * kSketchCols / kGaThreads; ++i) {
+      const int e = tid + i * kGaThreads;
+      const int c = e / kGaTile, rr = e % kGaTile;
+      xs[rr * kSketchCols + c] = (rr < trows && c < nc) ? to_f64(v[i]) : 0.0;
     }
     __syncthreads();
     for (int rr = 0; rr < trows; rr += 4) {

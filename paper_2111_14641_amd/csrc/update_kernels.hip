@@ -35,6 +35,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 #ifndef RBGS_UP_MINW
 #define RBGS_UP_MINW 0    // > 0: ask the compiler for this many waves per SIMD
 #endif
+
 constexpr int kUpThreads = 256;
 constexpr int kKC = 128;                  // rows of R per LDS chunk
 constexpr int kUnroll = RBGS_UP_UNROLL;   // K-steps whose loads are issued together
@@ -296,7 +297,10 @@ __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t l
   if (row >= n) return;
   double x[kMaxB];
 #pragma unroll
-  for (int c = 0; c < kMaxB; ++c) x[c] = c < bw ? (double)Qb[row + (int64_t)c * ldq] : 0.0;
+  for (int c = 0; c < kMaxB; ++c) {
+    const double v = (double)Qb[row + (int64_t)(c < bw ? c : bw - 1) * ldq];  // unconditional load
+    x[c] = c < bw ? v : 0.0;
+  }
   row_substitute<kMaxB>(x, Rd, bw);
 #pragma unroll
   for (int c = 0; c < kMaxB; ++c)
