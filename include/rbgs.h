@@ -78,11 +78,16 @@ typedef enum { RBGS_MATH_F64 = 0, RBGS_MATH_F32 = 1 } rbgs_math;
  *              (r_lo, r_hi, c, 0x53504152), c = 0, 1; 1 <= zeta <= 8,
  *              k % zeta == 0, k <= 2048.
  *  IDENTITY    Theta = I, k == n (testing: RBGS then reduces to block
- *              Gram-Schmidt with exact projections). */
+ *              Gram-Schmidt with exact projections).
+ *  RADEMACHER  Theta = B / sqrt(k), B[t][r] = +-1 (the other dense
+ *              oblivious embedding of Section 1.3): bit t % 32 of word
+ *              (t % 128) / 32 of the output of counter (r_lo, r_hi, t / 128,
+ *              0x52414445), a set bit meaning -1; k % 4 == 0. */
 typedef enum {
   RBGS_SKETCH_GAUSSIAN = 0,
   RBGS_SKETCH_SPARSE_SIGN = 1,
-  RBGS_SKETCH_IDENTITY = 2
+  RBGS_SKETCH_IDENTITY = 2,
+  RBGS_SKETCH_RADEMACHER = 3
 } rbgs_sketch_kind;
 
 /* Inter-block QR in steps 4-5 (Section 2.2):

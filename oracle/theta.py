@@ -29,6 +29,12 @@ Sparse sign (block CountSketch), Theta = c_z * B with c_z = fl64(1/sqrt(zeta)):
         s*L + (((w_s >> 1) * L) >> 31),   sign_s = -1 if w_s & 1 else +1,
   so every column has exactly zeta nonzeros, one per segment of L rows.
 
+Rademacher, Theta = c_k * B with c_k = fl64(1 / sqrt(k)) (Section 1.3: i.i.d.
+  entries +-1/sqrt(k) with probability 1/2 each): the counter
+  (r mod 2^32, r >> 32, q, 0x52414445) gives 128 bits x0 | x1 << 32 |
+  x2 << 64 | x3 << 96; entry B[t, r] for t = 128 q + b is -1 if bit b is set,
+  +1 otherwise.  Requires k % 4 == 0.
+
 Identity: Theta = I (requires k == n).  RBGS with Theta = I is block
 Gram-Schmidt with exact least-squares projections (Section 2), which the tests
 use to pin the oracle against Householder QR.
@@ -38,7 +44,9 @@ Sketches are always formed as c * (Z @ X) (or c * (B @ X)) in FP64.
 Parity: pinned (tests/test_oracle_theta.py): the fp32 logarithm and sine /
 cosine polynomials against numpy's FP64 functions to a few fp32 ulps, the
 Gaussian samples against the normal distribution (moments, Kolmogorov-Smirnov),
-the sparse-sign columns against their defining invariants (exactly zeta
+the Rademacher entries against their distribution (values +-1, sign balance,
+pairwise independence of targets and of columns), the sparse-sign columns
+against their defining invariants (exactly zeta
 distinct rows, one per segment, unit column norm, uniform row distribution),
 and the blocked application against explicit dense products.
 """
@@ -49,6 +57,7 @@ from .philox import philox4x32_10, split_seed
 
 TAG_GAUSS = 0x47415553
 TAG_SPARSE = 0x53504152
+TAG_RADEMACHER = 0x52414445
 
 F32 = np.float32
 
@@ -154,6 +163,25 @@ def gaussian_z(rows, k, seed):
     return z
 
 
+def rademacher_b(rows, k, seed):
+    """Unscaled Rademacher entries B[:, rows] as an int8 array of shape
+    (len(rows), k) with values +-1: out[i, t] = B[t, rows[i]]."""
+    if k % 4:
+        raise ValueError("Rademacher sketch needs k % 4 == 0")
+    rows = np.asarray(rows, dtype=np.uint64)
+    k0, k1 = split_seed(seed)
+    nq = (k + 127) // 128
+    q = np.arange(nq, dtype=np.uint32)
+    r_lo = (rows & np.uint64(0xFFFFFFFF)).astype(np.uint32)[:, None]
+    r_hi = (rows >> np.uint64(32)).astype(np.uint32)[:, None]
+    words = philox4x32_10(r_lo, r_hi, q[None, :], np.uint32(TAG_RADEMACHER), k0, k1)
+    # bits[i, q, w, b] = bit b of word w of call q; target t = 128 q + 32 w + b
+    W = np.stack(words, axis=2)                                       # (len, nq, 4)
+    bits = (W[..., None] >> np.arange(32, dtype=np.uint32)) & np.uint32(1)
+    bits = bits.reshape(rows.shape[0], nq * 128)[:, :k]
+    return np.where(bits == 1, -1, 1).astype(np.int8)
+
+
 def sparse_sign_entries(rows, k, zeta, seed):
     """Row indices (uint32, shape (len(rows), zeta)) and signs (+1/-1 int8) of
     the nonzeros of the unscaled sparse-sign columns B[:, rows]."""
@@ -176,13 +204,13 @@ def sparse_sign_entries(rows, k, zeta, seed):
 class Sketch:
     """A sketching operator Theta in R^{k x n} defined by (kind, k, seed, zeta).
 
-    kind: "gaussian", "sparse" or "identity".
+    kind: "gaussian", "sparse", "rademacher" or "identity".
     """
 
     def __init__(self, kind, k, seed=0, zeta=8, chunk_rows=8192):
         self.kind, self.k, self.seed, self.zeta = kind, int(k), int(seed), int(zeta)
         self.chunk_rows = chunk_rows
-        if kind == "gaussian":
+        if kind in ("gaussian", "rademacher"):
             self.scale = 1.0 / np.sqrt(float(self.k))
         elif kind == "sparse":
             self.scale = 1.0 / np.sqrt(float(self.zeta))
@@ -217,6 +245,8 @@ class Sketch:
             return np.eye(n)
         if self.kind == "gaussian":
             return self.scale * gaussian_z(np.arange(n), self.k, self.seed).T.astype(np.float64)
+        if self.kind == "rademacher":
+            return self.scale * rademacher_b(np.arange(n), self.k, self.seed).T.astype(np.float64)
         idx, sign = sparse_sign_entries(np.arange(n), self.k, self.zeta, self.seed)
         T = np.zeros((self.k, n))
         cols = np.repeat(np.arange(n), self.zeta)
@@ -252,7 +282,11 @@ class Sketch:
         out = np.zeros((self.k, c))
         for r0 in range(0, n_loc, self.chunk_rows):
             r1 = min(n_loc, r0 + self.chunk_rows)
-            Z = gaussian_z(np.arange(row0 + r0, row0 + r1), self.k, self.seed)
+            rows = np.arange(row0 + r0, row0 + r1)
+            if self.kind == "rademacher":
+                Z = rademacher_b(rows, self.k, self.seed)
+            else:
+                Z = gaussian_z(rows, self.k, self.seed)
             out += Z.T.astype(np.float64) @ X[r0:r1]
         return self.scale * out
 

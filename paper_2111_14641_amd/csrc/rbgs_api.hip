@@ -174,7 +174,8 @@ bool valid_sketch(const rbgs_sketch* sk, int64_t n, std::string& why) {
   if (sk->k < 1) { why = "sketch dimension k must be >= 1"; return false; }
   switch (sk->kind) {
     case RBGS_SKETCH_GAUSSIAN:
-      if (sk->k % 4) { why = "Gaussian sketch needs k % 4 == 0"; return false; }
+    case RBGS_SKETCH_RADEMACHER:
+      if (sk->k % 4) { why = "dense sketches need k % 4 == 0"; return false; }
       if (sk->k > (int64_t)1 << 20) { why = "k too large"; return false; }
       return true;
     case RBGS_SKETCH_SPARSE_SIGN:
@@ -202,7 +203,7 @@ SketchDesc make_desc(const rbgs_sketch* sk) {
 }
 
 double sketch_scale(const SketchDesc& d) {
-  if (d.kind == kGaussian) return 1.0 / sqrt((double)d.k);
+  if (d.kind == kGaussian || d.kind == kRademacher) return 1.0 / sqrt((double)d.k);
   if (d.kind == kSparse) return 1.0 / sqrt((double)d.zeta);
   return 1.0;
 }

@@ -40,6 +40,7 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 
 constexpr uint32_t kTagGauss = 0x47415553u;
 constexpr uint32_t kTagSparse = 0x53504152u;
+constexpr uint32_t kTagRademacher = 0x52414445u;
 
 // fp32 constants by bit pattern (correctly rounded values of the named reals).
 __device__ __forceinline__ float f32c(uint32_t b) { return __uint_as_float(b); }
@@ -117,6 +118,18 @@ __device__ __forceinline__ void gauss4(uint64_t r, uint32_t j, uint32_t k0, uint
   gauss_pair(x.z, x.w, z[2], z[3]);
 }
 
+// Unscaled Rademacher entries B[4j .. 4j+3][r] = +-1: target t takes bit
+// t % 32 of word (t % 128) / 32 of the Philox call (r, t / 128); bit 1 = -1.
+__device__ __forceinline__ void rademacher4(uint64_t r, uint32_t j, uint32_t k0, uint32_t k1,
+                                            float z[4]) {
+  const u32x4 x = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), j >> 5, kTagRademacher, k0, k1);
+  const uint32_t q = (j >> 3) & 3u;
+  const uint32_t w = q == 0 ? x.x : (q == 1 ? x.y : (q == 2 ? x.z : x.w));
+  const uint32_t bits = w >> (4u * (j & 7u));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) z[i] = ((bits >> i) & 1u) ? -1.0f : 1.0f;
+}
+
 // Row (target) of the nonzero of segment s of the sparse-sign column r:
 // s*L + (((w_s >> 1) * L) >> 31), sign bit = w_s & 1 (1 = negative).
 __device__ __forceinline__ uint32_t sparse_target(uint32_t w, uint32_t s, uint32_t L) {
@@ -134,7 +147,7 @@ __device__ __forceinline__ void sparse_words(uint64_t r, uint32_t k0, uint32_t k
 // ---------------------------------------------------------------------------
 // Host launchers (all enqueue on `st`, return hipError_t of the launch).
 // ---------------------------------------------------------------------------
-enum SketchKind { kGaussian = 0, kSparse = 1, kIdentity = 2 };
+enum SketchKind { kGaussian = 0, kSparse = 1, kIdentity = 2, kRademacher = 3 };
 
 struct SketchDesc {
   int kind;

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
 constexpr int kGaThreads = 256;
 constexpr int kGaTile = 128;
 
-template <typename T>
+template <typename T, int KIND>
 __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int64_t row0, int k,
     uint32_t key0, uint32_t key1, int64_t rows_per_wg, double* __restrict__ partial) {
@@ -332,7 +332,10 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
     __syncthreads();
     for (int rr = 0; rr < trows; rr += 4) {
       float z[4] = {0.f, 0.f, 0.f, 0.f};
-      if (jvalid && rr + kk < trows) gauss4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
+      if (jvalid && rr + kk < trows) {
+        if constexpr (KIND == kRademacher) rademacher4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
+        else gauss4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
+      }
       const double b = xs[(rr + kk) * kSketchCols + (lane & 15)];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -408,6 +411,14 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
     gauss4((uint64_t)(row0 + rl), (uint32_t)jj, key0, key1, z);
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[4 * jj + q + k * rl] = z[q];
+  } else if (kind == kRademacher) {
+    const int64_t groups = k / 4;
+    if (idx >= groups * n) return;
+    const int64_t jj = idx % groups, rl = idx / groups;
+    float z[4];
+    rademacher4((uint64_t)(row0 + rl), (uint32_t)jj, key0, key1, z);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[4 * jj + q + k * rl] = z[q];
   } else if (kind == kSparse) {
     if (idx >= n) return;
     float* col = out + k * idx;
@@ -430,11 +441,11 @@ static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups) {
   // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
-  // over the column groups.  Gaussian: about 512 workgroups of 256 threads.
-  // Each row range is at least one tile long.
+  // over the column groups.  Dense (Gaussian, Rademacher): about 512
+  // workgroups of 256 threads.  Each row range is at least one tile long.
   const int64_t groups = ceil_div(ncols, kSketchCols);
   int64_t G, tile;
-  if (sk.kind == kGaussian) {
+  if (sk.kind == kGaussian || sk.kind == kRademacher) {
     G = ceil_div(512, groups * ceil_div(sk.k, 256));
     tile = kGaTile;
   } else {
@@ -491,14 +502,15 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
   } else {
     const int64_t rpw = ceil_div(ceil_div(n, G), kGaTile) * kGaTile;
     dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)groups);
-    if (f32)
-      hipLaunchKernelGGL(sketch_gauss_kernel<float>, grid, dim3(kGaThreads), 0, st,
-                         (const float*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1,
-                         rpw, partial);
-    else
-      hipLaunchKernelGGL(sketch_gauss_kernel<double>, grid, dim3(kGaThreads), 0, st,
-                         (const double*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1,
-                         rpw, partial);
+#define RBGS_GA(T, KIND)                                                                         \
+  hipLaunchKernelGGL((sketch_gauss_kernel<T, KIND>), grid, dim3(kGaThreads), 0, st, (const T*)X, \
+                     ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1, rpw, partial)
+    if (sk.kind == kRademacher) {
+      if (f32) RBGS_GA(float, kRademacher); else RBGS_GA(double, kRademacher);
+    } else {
+      if (f32) RBGS_GA(float, kGaussian); else RBGS_GA(double, kGaussian);
+    }
+#undef RBGS_GA
   }
   return hipGetLastError();
 }
@@ -525,7 +537,8 @@ hipError_t launch_sketch_identity(bool f32, const void* X, int64_t ldx, int64_t 
 
 hipError_t launch_theta_dense(const SketchDesc& sk, int64_t n, int64_t row0, float* out,
                               hipStream_t st) {
-  int64_t total = sk.kind == kGaussian ? (sk.k / 4) * n : (sk.kind == kSparse ? n : sk.k * n);
+  int64_t total = (sk.kind == kGaussian || sk.kind == kRademacher) ? (sk.k / 4) * n
+                                                                     : (sk.kind == kSparse ? n : sk.k * n);
   hipLaunchKernelGGL(theta_dense_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
                      sk.kind, sk.k, sk.zeta, sk.key0, sk.key1, n, row0, out);
   return hipGetLastError();

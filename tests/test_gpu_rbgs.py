@@ -75,7 +75,7 @@ def test_small_workload_fp64_matches_oracle(gpu_lib, small, variant):
 
 
 @pytest.mark.parametrize("variant", ["plain", "lowsync"])
-@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256)])
+@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256), ("rademacher", 256)])
 def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     W = svd_matrix(10_000, 64, np.logspace(0, -2, 64), seed=5)
     say("well-conditioned", variant, kind)
@@ -101,6 +101,8 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (5000, 96, 32, 256, "sparse", "plain"),
     (3000, 70, 32, 512, "sparse", "lowsync"),       # 32-wide tree over 4 chunks, ragged last block
     (4000, 72, 24, 256, "gaussian", "plain"),       # width 24 padded to 32 in the tree
+    (4097, 30, 8, 132, "rademacher", "lowsync"),    # Rademacher, partial last Philox call
+    (3000, 40, 16, 256, "rademacher", "plain"),
 ])
 def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
     W = svd_matrix(n, m, np.logspace(0, -2, m), seed=n + m + b)

@@ -47,6 +47,19 @@ def test_sparse_theta_bit_exact(gpu_lib, k, zeta, n, row0, seed):
     assert S.scale == 1 / np.sqrt(zeta)
 
 
+@pytest.mark.parametrize("k,n,row0,seed", [
+    (256, 1000, 0, 0x2111146412),
+    (100, 333, 12345, 7),               # k not a multiple of 128: a partial last Philox call
+    (260, 300, 2**32 - 100, 99),        # crosses the 32-bit boundary of the row counter
+])
+def test_rademacher_theta_bit_exact(gpu_lib, k, n, row0, seed):
+    from paper_2111_14641_amd import binding as B
+    say("theta rademacher", k, n, row0, seed)
+    Bg = to_np(B.theta_dense("rademacher", k, seed, n, row0))
+    Bo = th.rademacher_b(np.arange(row0, row0 + n, dtype=np.uint64), k, seed).T.astype(np.float32)
+    assert np.array_equal(Bg, Bo)
+
+
 def abs_sketch(kind, k, seed, X, row0, zeta=8):
     """|Theta| |X| (the scale of the rounding-error bound of a sketch)."""
     import scipy.sparse as sp
@@ -58,6 +71,8 @@ def abs_sketch(kind, k, seed, X, row0, zeta=8):
             Z = th.gaussian_z(rows[r0:r0 + 8192], k, seed).astype(np.float64)
             out += np.abs(Z).T @ np.abs(X[r0:r0 + 8192])
         return out / np.sqrt(k)
+    if kind == "rademacher":
+        return np.broadcast_to(np.abs(X).sum(axis=0) / np.sqrt(k), (k, X.shape[1]))
     idx, _ = th.sparse_sign_entries(rows, k, zeta, seed)
     Bm = sp.csr_matrix((np.ones(idx.size), (idx.ravel().astype(np.int64), np.repeat(np.arange(n), zeta))),
                        shape=(k, n))
@@ -65,7 +80,8 @@ def abs_sketch(kind, k, seed, X, row0, zeta=8):
 
 
 @pytest.mark.parametrize("kind,k", [("gaussian", 256), ("gaussian", 100), ("sparse", 1024),
-                                    ("sparse", 2048), ("sparse", 64)])
+                                    ("sparse", 2048), ("sparse", 64), ("rademacher", 256),
+                                    ("rademacher", 100)])
 @pytest.mark.parametrize("n,c,row0", [(4097, 16, 0), (1000, 5, 31), (70000, 33, 1 << 20), (3, 1, 0)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_sketch_apply_matches_oracle(gpu_lib, kind, k, n, c, row0, dtype):
@@ -98,7 +114,7 @@ def test_identity_sketch_copies(gpu_lib):
     assert np.array_equal(to_np(B.sketch_apply(Xt, "identity", 50, seed=0)), X)
 
 
-@pytest.mark.parametrize("kind,k", [("sparse", 1024), ("gaussian", 256)])
+@pytest.mark.parametrize("kind,k", [("sparse", 1024), ("gaussian", 256), ("rademacher", 256)])
 def test_row_shards_sum_to_the_whole(gpu_lib, kind, k):
     """Theta's columns are addressed by the global row index, so sketching G row
     ranges with their row offsets and adding the parts in a fixed order gives

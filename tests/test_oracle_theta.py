@@ -58,6 +58,47 @@ def test_gaussian_depends_on_seed_row_and_target():
     assert not np.any(big[0] == big[1])        # the high word of the row index counts
 
 
+def test_rademacher_bits_by_pure_python():
+    """Entry t of column r is bit t % 128 of the 128-bit output of Philox call
+    (r, t // 128): checked bit by bit with integer arithmetic in plain Python."""
+    from oracle.philox import philox4x32_10, split_seed
+    seed, k = 0x0123456789ABCDEF, 260
+    rows = [0, 7, 2**32 + 3]
+    B = th.rademacher_b(np.array(rows, dtype=np.uint64), k, seed)
+    k0, k1 = split_seed(seed)
+    for i, r in enumerate(rows):
+        for q in range((k + 127) // 128):
+            w = philox4x32_10(np.uint32(r & 0xFFFFFFFF), np.uint32(r >> 32), np.uint32(q),
+                              np.uint32(th.TAG_RADEMACHER), k0, k1)
+            big = sum(int(x) << (32 * e) for e, x in enumerate(w))
+            for b in range(128):
+                t = 128 * q + b
+                if t < k:
+                    assert B[i, t] == (-1 if (big >> b) & 1 else 1)
+
+
+def test_rademacher_entries_distribution():
+    """Section 1.3: i.i.d. +-1/sqrt(k), each sign with probability 1/2."""
+    B = th.rademacher_b(np.arange(4096), 256, seed=0x5EED).astype(np.float64)
+    assert set(np.unique(B)) == {-1.0, 1.0}
+    n = B.size
+    assert abs(B.mean()) < 5 / np.sqrt(n)
+    # neighbouring bits, bits of different words and calls, neighbouring columns
+    for a, b in [(B[:, :-1], B[:, 1:]), (B[:, :224], B[:, 32:]), (B[:, :128], B[:, 128:]),
+                 (B[:-1], B[1:])]:
+        assert abs(np.mean(a * b)) < 5 / np.sqrt(a.size)
+    # every target row is balanced over the columns
+    col = B.mean(axis=0)
+    assert np.max(np.abs(col)) < 5 / np.sqrt(B.shape[0])
+    a = th.rademacher_b(np.arange(8), 128, seed=1)
+    b = th.rademacher_b(np.arange(8), 128, seed=2)
+    c = th.rademacher_b(np.arange(1, 9), 128, seed=1)
+    assert np.mean(a == b) < 0.6
+    assert np.array_equal(a[1:], c[:-1])
+    T = th.Sketch("rademacher", 64, seed=3).dense(100)
+    assert np.allclose(np.abs(T), 1 / 8.0, rtol=0, atol=0)
+
+
 def test_sparse_sign_structure():
     n, k, zeta = 20000, 1024, 8
     idx, sgn = th.sparse_sign_entries(np.arange(n), k, zeta, seed=99)
@@ -77,7 +118,7 @@ def test_sparse_sign_structure():
     assert np.all((T != 0).sum(axis=0) == 8)
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher"])
 def test_apply_matches_dense(kind):
     n, k, c = 3000, 64, 5
     rng = np.random.default_rng(4)
@@ -92,17 +133,19 @@ def test_apply_matches_dense(kind):
 
 
 def test_frobenius_norm_of_theta():
-    """Corollary on ||Theta||_F: E||Theta||_F^2 = n for both operators (exact for
-    the sparse sign)."""
+    """Corollary on ||Theta||_F: E||Theta||_F^2 = n for every operator (exact for
+    the sparse sign and the Rademacher matrix)."""
     n = 4000
     Tg = th.Sketch("gaussian", 128, seed=5).dense(n)
     fro2 = (Tg**2).sum()
     assert abs(fro2 - n) < 5 * np.sqrt(2 * n)      # chi-square(kn)/k
     Ts = th.Sketch("sparse", 128, seed=5).dense(n)
     assert abs((Ts**2).sum() - n) < 1e-9
+    Tr = th.Sketch("rademacher", 128, seed=5).dense(n)
+    assert abs((Tr**2).sum() - n) < 1e-9
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher"])
 def test_subspace_embedding_distortion(kind):
     """For a fixed d-dimensional subspace and k = 8d the singular values of
     Theta U (U orthonormal) lie in a band of width about sqrt(d/k) around 1, as
