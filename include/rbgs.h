@@ -95,8 +95,20 @@ typedef enum {
  *  LOWSYNC  RCholeskyQR with postponed sketching:
  *           S'_(i) = P_(i) - S_(1:i-1) R_(1:i-1,i); the update and the
  *           substitution are then one pass over the rows and each block needs
- *           a single device-wide reduction (the sketch of Q_(i)). */
-typedef enum { RBGS_VARIANT_PLAIN = 0, RBGS_VARIANT_LOWSYNC = 1 } rbgs_variant;
+ *           a single device-wide reduction (the sketch of Q_(i)).
+ *  TWICE    RCholeskyQR run twice (Section 2.2.4): after PLAIN gives
+ *           Q'_(i) = Q*_(i) R1, RCholeskyQR of Q*_(i) gives Q*_(i) = Q_(i) R2
+ *           and R_(i,i) = R2 R1 (one more sketch, QR and substitution).
+ *  L2QR     l2-QR + RCholeskyQR (Section 2.2.4, the form the paper's
+ *           experiments use): R' of the l2 QR of Q'_(i) by a Householder
+ *           TSQR tree, Q*_(i) = Q'_(i) R'^-1 by substitution, RCholeskyQR of
+ *           Q*_(i) = Q_(i) R'' and R_(i,i) = R'' R'. */
+typedef enum {
+  RBGS_VARIANT_PLAIN = 0,
+  RBGS_VARIANT_LOWSYNC = 1,
+  RBGS_VARIANT_TWICE = 2,
+  RBGS_VARIANT_L2QR = 3
+} rbgs_variant;
 
 typedef struct {
   int32_t kind;      /* rbgs_sketch_kind                                  */
@@ -266,7 +278,8 @@ RBGS_API rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int
  * definition above: out[t + k*(r - row0)] = Z[t][r] (Gaussian), B[t][r]
  * (sparse sign, +-1 or 0) or I[t][r] (identity) for t < k, row0 <= r < row0+n.
  *   out device, k x n float (ld k), overwritten.  Theta = scale * out with
- *   scale = 1/sqrt(k) (Gaussian), 1/sqrt(zeta) (sparse sign), 1 (identity). */
+ *   scale = 1/sqrt(k) (Gaussian, Rademacher), 1/sqrt(zeta) (sparse sign),
+ *   1 (identity). */
 RBGS_API rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
                              float* out, void* stream);
 
@@ -279,8 +292,8 @@ RBGS_API rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int6
  * traffic of those launches: each input element read once, each output
  * element written once).
  *   which: 0 = update (steps 3 [+5 fused]), 1 = sketch partial products,
- *          2 = sketch reduction, 3 = small FP64 factors, 4 = substitution
- *          (plain variant). */
+ *          2 = sketch reduction, 3 = small FP64 factors, 4 = substitutions
+ *          and l2 QR passes over the block (all variants but LOWSYNC). */
 RBGS_API rbgs_status rbgs_profile_enable(rbgs_handle h, int32_t enable);
 RBGS_API rbgs_status rbgs_profile_get(rbgs_handle h, int32_t which, double* ms, int64_t* launches,
                              double* bytes);

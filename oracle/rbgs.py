@@ -17,6 +17,10 @@ diagonal.
        or by RCholeskyQR with postponed sketching ("lowsync", Section 2.2.3:
        S'_(i) = P_(i) - S_(1:i-1) R_(1:i-1,i)); in both, R_(i,i) is the R factor
        of the l2-QR of S'_(i) and Q_(i) = Q'_(i) R_(i,i)^{-1} by substitution.
+       Two more stable forms of Section 2.2.4: "twice" runs RCholeskyQR on
+       the Q-factor of the first RCholeskyQR (Q'_(i) = Q* R1, Q* = Q_(i) R2,
+       R_(i,i) = R2 R1), and "l2qr" first takes the l2 (Householder) QR
+       Q'_(i) = Q* R', then RCholeskyQR Q* = Q_(i) R'' and R_(i,i) = R'' R'.
   6. Delta = ||I - S^T S||_F and Delta~ = ||P - S R||_F / ||P||_F.
 
 Least-squares solvers for step 2:
@@ -77,8 +81,9 @@ def rbgs(W, b, theta, variant="plain", ls="householder", ls_iters=2):
     """RBGS QR of W (n x m, FP64) with block width b and sketch `theta`
     (a callable X -> Theta X, e.g. oracle.theta.Sketch).
 
-    variant: "plain" (RCholeskyQR in steps 4-5) or "lowsync" (RCholeskyQR with
-             postponed sketching).
+    variant: "plain" (RCholeskyQR in steps 4-5), "lowsync" (RCholeskyQR with
+             postponed sketching), "twice" (RCholeskyQR twice) or "l2qr"
+             (l2-QR + RCholeskyQR).
     ls:      "householder" or "richardson" (with `ls_iters` sweeps).
     Returns a dict with Q, R, S (= Theta Q), P (= Theta W), delta, delta_tilde.
     """
@@ -110,22 +115,43 @@ def rbgs(W, b, theta, variant="plain", ls="householder", ls_iters=2):
         # 3. projection
         Qp = Wi - Q[:, :c0] @ Rij
         # 4. sketch of Q'_(i) and R_(i,i)
-        if variant == "plain":
-            Sp = theta(Qp)
+        if variant in ("plain", "twice"):
+            Qi, Rii = rcholeskyqr(Qp, theta(Qp))
+            if variant == "twice":
+                Qi, R2 = rcholeskyqr(Qi, theta(Qi))
+                Rii = R2 @ Rii
         elif variant == "lowsync":
-            Sp = Pi - S[:, :c0] @ Rij
+            Qi, Rii = rcholeskyqr(Qp, Pi - S[:, :c0] @ Rij)
+        elif variant == "l2qr":
+            Qs, Rp = l2_qr_posdiag(Qp)
+            Qi, R2 = rcholeskyqr(Qs, theta(Qs))
+            Rii = R2 @ Rp
         else:
             raise ValueError(variant)
-        Rii = qr_r_posdiag(Sp)
         R[c0:c1, c0:c1] = Rii
-        # Q_(i) = Q'_(i) R_(i,i)^{-1} by substitution: solve Q_(i) R_(i,i) = Q'_(i),
-        # i.e. R_(i,i)^T Q_(i)^T = Q'_(i)^T (lower triangular, forward substitution).
-        Qi = sla.solve_triangular(Rii.T, Qp.T, lower=True).T
         Q[:, c0:c1] = Qi
         # 5. sketch of Q_(i)
         S[:, c0:c1] = theta(Qi)
     delta, delta_tilde = certificates(S, P, R)
     return dict(Q=Q, R=R, S=S, P=P, delta=delta, delta_tilde=delta_tilde)
+
+
+def rcholeskyqr(Qp, Sp):
+    """Steps 4-5 core of RCholeskyQR (Section 2.2.2): R = R factor of the l2-QR
+    of the sketch Sp = Theta Qp (positive diagonal) and Q = Qp R^{-1} by
+    substitution -- solve Q R = Qp, i.e. R^T Q^T = Qp^T (lower triangular,
+    forward substitution)."""
+    Rf = qr_r_posdiag(Sp)
+    return sla.solve_triangular(Rf.T, Qp.T, lower=True).T, Rf
+
+
+def l2_qr_posdiag(A):
+    """Householder (LAPACK) QR A = Q R of a tall matrix with R's diagonal made
+    positive (the columns of Q flipped with the rows of R)."""
+    Qh, Rh = np.linalg.qr(A, mode="reduced")
+    d = np.sign(np.diag(Rh))
+    d[d == 0] = 1.0
+    return Qh * d[None, :], d[:, None] * Rh
 
 
 def certificates(S, P, R):

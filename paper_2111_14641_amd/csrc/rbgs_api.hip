@@ -1,5 +1,5 @@
 // C ABI of the RBGS library: argument validation, workspace, and the block
-// loop of Algorithm RBGS (Section 2) for both inter-block variants of
+// loop of Algorithm RBGS (Section 2) for the inter-block variants of
 // Section 2.2.  Every step is enqueued on the caller's stream; nothing waits
 // on the host unless a certificate is requested.
 #include <math.h>
@@ -260,7 +260,7 @@ static rbgs_status validate_qr(rbgs_handle h, const void* W, int64_t ldw, int64_
     return fail(h, RBGS_EINVAL, "unknown arithmetic");
   if (opts->store == RBGS_STORE_F64 && opts->math != RBGS_MATH_F64)
     return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
-  if (opts->variant != RBGS_VARIANT_PLAIN && opts->variant != RBGS_VARIANT_LOWSYNC)
+  if (opts->variant < RBGS_VARIANT_PLAIN || opts->variant > RBGS_VARIANT_L2QR)
     return fail(h, RBGS_EINVAL, "unknown variant");
   if (opts->ls_iters < 1 || opts->ls_iters > 16)
     return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
@@ -356,7 +356,7 @@ struct QrRun {
   int64_t ldq;
   double* R;
   int64_t ldr;
-  double *S, *P, *E, *part, *part2, *stack, *G, *Cb, *Yb, *cscratch, *cout;
+  double *S, *P, *E, *part, *part2, *stack, *G, *Cb, *Yb, *cscratch, *cout, *Rt, *tall;
   uint16_t* plan;
   int64_t* flag;
   unsigned* counters;
@@ -425,6 +425,14 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   const size_t o_Y = carve((size_t)m * b);   // Richardson iterate
   const size_t o_cs = carve(cert_scratch_size(k, m));
   const size_t o_cout = carve(4);
+  const bool twice = r.variant == RBGS_VARIANT_TWICE || r.variant == RBGS_VARIANT_L2QR;
+  const size_t o_Rt = twice ? carve((size_t)b * b) : 0;   // second R factor of a block
+  size_t tall_need = 0;                                   // TSQR tree of Q'_(i)
+  if (r.variant == RBGS_VARIANT_L2QR) {
+    tall_need = qr_stack_size(n, (int)std::min<int64_t>(b, m));
+    if (m % b) tall_need = std::max(tall_need, qr_stack_size(n, (int)(m % b)));
+  }
+  const size_t o_tall = tall_need ? carve(tall_need) : 0;
   rbgs_status rs = ensure_ws(h, off);
   if (rs != RBGS_OK) return rs;
   char* base = (char*)h->ws;
@@ -442,6 +450,8 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.Yb = (double*)(base + o_Y);
   r.cscratch = (double*)(base + o_cs);
   r.cout = (double*)(base + o_cout);
+  r.Rt = twice ? (double*)(base + o_Rt) : nullptr;
+  r.tall = tall_need ? (double*)(base + o_tall) : nullptr;
   hipStream_t st = r.st;
   HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
   HIP_TRY(h, launch_set_i64(r.flag, -1, st), "flag");
@@ -548,17 +558,48 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
                                n, K, bw, st),
               "update");
     }
-    // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution -----------
-    rs = do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.E, k, r.part, r.plan, st);
-    if (rs != RBGS_OK) return rs;
-    {
-      ProfScope ps(h, kProfSmall, 0.0, st);
-      HIP_TRY(h, launch_qr_fused(r.E, k, bw, r.stack, r.counters + 1, Rii, ldr, r.flag, c0, st),
-              "qr of sketch");
+    if (r.variant == RBGS_VARIANT_L2QR) {
+      // ---- step 4, l2 part: Q'_(i) = Q* R' (R' by TSQR), Q* = Q'_(i) R'^-1
+      {
+        ProfScope ps(h, kProfTrsm, r.es * n * bw, st);
+        HIP_TRY(h, launch_qr_tall(r.f32, Qi, r.ldq, n, bw, r.tall, Rii, ldr, r.flag, c0, st),
+                "l2 qr of the block");
+      }
+      {
+        ProfScope ps(h, kProfTrsm, 2.0 * r.es * n * bw, st);
+        HIP_TRY(h, launch_trsm(r.f32, Qi, r.ldq, Rii, ldr, n, bw, st), "substitution");
+      }
+    } else {
+      // ---- step 4: S'_(i) = Theta Q'_(i), R_(i,i), substitution ---------
+      rs = do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.E, k, r.part, r.plan, st);
+      if (rs != RBGS_OK) return rs;
+      {
+        ProfScope ps(h, kProfSmall, 0.0, st);
+        HIP_TRY(h, launch_qr_fused(r.E, k, bw, r.stack, r.counters + 1, Rii, ldr, r.flag, c0, st),
+                "qr of sketch");
+      }
+      {
+        ProfScope ps(h, kProfTrsm, 2.0 * r.es * n * bw, st);
+        HIP_TRY(h, launch_trsm(r.f32, Qi, r.ldq, Rii, ldr, n, bw, st), "substitution");
+      }
     }
-    {
-      ProfScope ps(h, kProfTrsm, 2.0 * r.es * n * bw, st);
-      HIP_TRY(h, launch_trsm(r.f32, Qi, r.ldq, Rii, ldr, n, bw, st), "substitution");
+    if (r.Rt) {
+      // ---- RCholeskyQR of the current Q_(i) = Q_(i) R2; R_(i,i) <- R2 R_(i,i)
+      rs = do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.E, k, r.part, r.plan, st);
+      if (rs != RBGS_OK) return rs;
+      {
+        ProfScope ps(h, kProfSmall, 0.0, st);
+        HIP_TRY(h, launch_qr_fused(r.E, k, bw, r.stack, r.counters + 1, r.Rt, b, r.flag, c0, st),
+                "qr of sketch");
+      }
+      {
+        ProfScope ps(h, kProfTrsm, 2.0 * r.es * n * bw, st);
+        HIP_TRY(h, launch_trsm(r.f32, Qi, r.ldq, r.Rt, b, n, bw, st), "substitution");
+      }
+      {
+        ProfScope ps(h, kProfSmall, 0.0, st);
+        HIP_TRY(h, launch_trmm_upper(r.Rt, b, Rii, ldr, bw, st), "R2 R1");
+      }
     }
   }
   // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------

@@ -244,6 +244,15 @@ hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, 
 // diagonal entry is zero or not finite, if it is still -1).
 hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
                            double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st);
+// R factor (positive diagonal) of the l2 QR of a tall rows x bw matrix (FP32 or
+// FP64, ld ld) by a Householder TSQR tree, one launch per level; stack:
+// qr_stack_size(rows, bw) doubles; flag as for launch_qr_fused.
+hipError_t launch_qr_tall(bool f32, const void* src, int64_t ld, int64_t rows, int bw,
+                          double* stack, double* R, int64_t ldr, int64_t* flag, int64_t col0,
+                          hipStream_t st);
+// R <- A R for upper triangular bw x bw A and R (upper triangles only).
+hipError_t launch_trmm_upper(const double* A, int64_t lda, double* R, int64_t ldr, int bw,
+                             hipStream_t st);
 hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 // Fill an m x m column-major matrix (ld) with zeros.
 hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);

@@ -83,8 +83,8 @@ __device__ __forceinline__ double group_sum(double v) {
 //   final == 0: the bw x bw R goes to rows [b bw, b bw + bw) of dst (ld ld_out).
 //   final != 0: R with a positive diagonal goes to dst; flag[0] gets the first
 //               column col0 + j with a zero or non-finite R_jj.
-template <int BWP, int RPT>
-__device__ void qr_chunk_reg(const double* __restrict__ src, int64_t ld_in, int64_t rows_in,
+template <typename T, int BWP, int RPT>
+__device__ void qr_chunk_reg(const T* __restrict__ src, int64_t ld_in, int64_t rows_in,
                              int bw, double* __restrict__ dst, int64_t ld_out, int final,
                              int64_t* flag, int64_t col0, int64_t b, double* xb /* [2][NG*RPT] */,
                              double* sg /* [2 + kQrMaxB] */) {
@@ -102,7 +102,7 @@ __device__ void qr_chunk_reg(const double* __restrict__ src, int64_t ld_in, int6
   for (int i = 0; i < RPT; ++i) {
     const int r = g + NG * i;
     const bool ok = col_ok && r < rows;
-    const double v = src[ok ? (r0 + r) + (int64_t)c * ld_in : 0];
+    const double v = (double)src[ok ? (r0 + r) + (int64_t)c * ld_in : 0];
     a[i] = ok ? v : 0.0;
   }
   // publish column 0 and its squared norm
@@ -198,7 +198,8 @@ __device__ void qr_chunk_reg(const double* __restrict__ src, int64_t ld_in, int6
 
 // Dispatch on the padded width; the final level of a tree uses fewer rows per
 // thread when its input is short.
-__device__ void qr_chunk(const double* __restrict__ src, int64_t ld_in, int64_t rows_in, int bw,
+template <typename T>
+__device__ void qr_chunk(const T* __restrict__ src, int64_t ld_in, int64_t rows_in, int bw,
                          double* __restrict__ dst, int64_t ld_out, int final, int64_t* flag,
                          int64_t col0, int64_t b, double* xb, double* sg) {
   const int bwp = qr_bwp(bw);
@@ -207,9 +208,9 @@ __device__ void qr_chunk(const double* __restrict__ src, int64_t ld_in, int64_t 
   const bool short4 = rows <= 4 * ng;
 #define RBGS_QRC(BWP)                                                                            \
   if (short4)                                                                                    \
-    qr_chunk_reg<BWP, 4>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg);    \
+    qr_chunk_reg<T, BWP, 4>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg); \
   else                                                                                           \
-    qr_chunk_reg<BWP, kQrRpt>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg);
+    qr_chunk_reg<T, BWP, kQrRpt>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, b, xb, sg);
   if (bwp == 4) { RBGS_QRC(4) }
   else if (bwp == 8) { RBGS_QRC(8) }
   else if (bwp == 16) { RBGS_QRC(16) }
@@ -405,6 +406,34 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// One level of a Householder TSQR tree over a tall rows_in x bw matrix:
+// workgroup b factors chunk b.  Non-final levels stack the chunk R factors
+// (rows [b bw, b bw + bw) of dst, ld ld_out); the final level (one chunk)
+// writes R with a positive diagonal and raises the breakdown flag.
+template <typename T>
+__global__ __launch_bounds__(kQrThreads) void qr_level_kernel(
+    const T* __restrict__ src, int64_t ld_in, int64_t rows_in, int bw, double* __restrict__ dst,
+    int64_t ld_out, int final, int64_t* flag, int64_t col0) {
+  __shared__ double xb[2 * (kQrThreads / 4) * kQrRpt];
+  __shared__ double sg[2 + kQrMaxB];
+  qr_chunk<T>(src, ld_in, rows_in, bw, dst, ld_out, final, flag, col0, blockIdx.x, xb, sg);
+}
+
+// R <- A R for upper triangular bw x bw A (ld lda) and R (ld ldr); only the
+// upper triangles are read and written.  Entry (i, j) sums A_il R_lj for
+// l = i..j in increasing l.
+__global__ __launch_bounds__(1024) void trmm_upper_kernel(const double* __restrict__ A, int64_t lda,
+                                                          double* __restrict__ R, int64_t ldr,
+                                                          int bw) {
+  const int i = threadIdx.x % kQrMaxB, j = threadIdx.x / kQrMaxB;
+  const bool on = i < bw && j < bw && i <= j;
+  double v = 0.0;
+  if (on)
+    for (int l = i; l <= j; ++l) v = fma(A[i + l * lda], R[l + j * ldr], v);
+  __syncthreads();
+  if (on) R[i + j * ldr] = v;
+}
+
 // ---------------------------------------------------------------------------
 // R_(i,i) of a k x bw sketch with k <= 1024 and bw <= 16 in one workgroup of
 // 16 waves: wave c keeps column c in registers (lane l holds rows l + 64 i),
@@ -582,6 +611,53 @@ hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, 
   const int64_t CH = qr_chunk_rows(bw);
   hipLaunchKernelGGL(qr_fused_kernel, dim3((unsigned)ceil_div(k, CH)), dim3(kQrThreads), 0, st, src,
                      k, bw, stack, counter, Rii, ldr, flag, col0);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_tall(bool f32, const void* src, int64_t ld, int64_t rows, int bw,
+                          double* stack, double* R, int64_t ldr, int64_t* flag, int64_t col0,
+                          hipStream_t st) {
+  if (bw > kQrMaxB || bw < 1 || rows < bw) return hipErrorInvalidValue;
+  const int64_t CH = qr_chunk_rows(bw);
+  const int64_t nch = ceil_div(rows, CH);
+  if (nch == 1) {
+    if (f32)
+      hipLaunchKernelGGL(qr_level_kernel<float>, dim3(1), dim3(kQrThreads), 0, st,
+                         (const float*)src, ld, rows, bw, R, ldr, 1, flag, col0);
+    else
+      hipLaunchKernelGGL(qr_level_kernel<double>, dim3(1), dim3(kQrThreads), 0, st,
+                         (const double*)src, ld, rows, bw, R, ldr, 1, flag, col0);
+    return hipGetLastError();
+  }
+  int64_t out_rows = nch * bw;
+  if (f32)
+    hipLaunchKernelGGL(qr_level_kernel<float>, dim3((unsigned)nch), dim3(kQrThreads), 0, st,
+                       (const float*)src, ld, rows, bw, stack, out_rows, 0, nullptr, 0);
+  else
+    hipLaunchKernelGGL(qr_level_kernel<double>, dim3((unsigned)nch), dim3(kQrThreads), 0, st,
+                       (const double*)src, ld, rows, bw, stack, out_rows, 0, nullptr, 0);
+  // the levels occupy consecutive parts of the stack (qr_stack_size(rows, bw))
+  const double* lsrc = stack;
+  int64_t lrows = out_rows;
+  double* buf = stack + out_rows * bw;
+  while (lrows > CH) {
+    const int64_t n2 = ceil_div(lrows, CH);
+    out_rows = n2 * bw;
+    hipLaunchKernelGGL(qr_level_kernel<double>, dim3((unsigned)n2), dim3(kQrThreads), 0, st, lsrc,
+                       lrows, lrows, bw, buf, out_rows, 0, nullptr, 0);
+    lsrc = buf;
+    lrows = out_rows;
+    buf += out_rows * bw;
+  }
+  hipLaunchKernelGGL(qr_level_kernel<double>, dim3(1), dim3(kQrThreads), 0, st, lsrc, lrows, lrows,
+                     bw, R, ldr, 1, flag, col0);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_upper(const double* A, int64_t lda, double* R, int64_t ldr, int bw,
+                             hipStream_t st) {
+  if (bw > kQrMaxB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(trmm_upper_kernel, dim3(1), dim3(1024), 0, st, A, lda, R, ldr, bw);
   return hipGetLastError();
 }
 

@@ -103,6 +103,12 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (4000, 72, 24, 256, "gaussian", "plain"),       # width 24 padded to 32 in the tree
     (4097, 30, 8, 132, "rademacher", "lowsync"),    # Rademacher, partial last Philox call
     (3000, 40, 16, 256, "rademacher", "plain"),
+    (4097, 30, 8, 128, "sparse", "twice"),          # two-pass forms: ragged rows and last block
+    (5000, 17, 1, 64, "gaussian", "l2qr"),          # TSQR of single columns
+    (3000, 70, 32, 512, "sparse", "l2qr"),          # 32-wide TSQR over four tree levels
+    (4000, 72, 24, 256, "rademacher", "twice"),
+    (64, 16, 4, 64, "identity", "l2qr"),
+    (300, 20, 6, 300, "identity", "twice"),
 ])
 def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
     W = svd_matrix(n, m, np.logspace(0, -2, m), seed=n + m + b)
@@ -118,7 +124,7 @@ def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
         assert rel(R, d[:, None] * Rh) < 1e-13
 
 
-@pytest.mark.parametrize("variant", ["plain", "lowsync"])
+@pytest.mark.parametrize("variant", ["plain", "lowsync", "twice", "l2qr"])
 @pytest.mark.parametrize("decades", [2, 8])
 def test_fp32_storage_fp64_arithmetic(gpu_lib, variant, decades):
     """FP32 storage, FP64 products: Q'_(i) is accurate to u32 relative to itself,
@@ -154,6 +160,38 @@ def test_fp32_arithmetic(gpu_lib, variant):
     assert factorization_error(W8, Q, R) <= 1e-6
     assert cert["delta"] > 0.1                 # certificate: not stable
     assert cond2(Q) > 10
+
+
+@pytest.mark.parametrize("variant", ["twice", "l2qr"])
+@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256)])
+def test_two_pass_forms_fp64_elementwise(gpu_lib, variant, kind, k):
+    W = svd_matrix(10_000, 64, np.logspace(0, -2, 64), seed=5)
+    say("two-pass", variant, kind)
+    Q, R, S, cert = gpu_qr(W, 8, kind, k, 17, variant)
+    o = oracle_qr(W, 8, kind, k, 17, variant)
+    assert rel(R, o["R"]) < 1e-12
+    assert rel(Q, o["Q"]) < 1e-12
+    assert rel(S, o["S"]) < 1e-12
+    assert cert["delta"] < 1e-12
+
+
+@pytest.mark.parametrize("decades", [8, 12])
+def test_second_pass_restores_sketched_orthogonality(gpu_lib, decades):
+    """One block with cond(W) = 10^decades: the certificate Delta of RCholeskyQR
+    grows like u cond(W), that of the two-pass forms stays at a few u m
+    (Section 2.2.4), on the GPU as in the oracle; R agrees with the oracle's
+    to ~u cond of the block's sketch."""
+    W = svd_matrix(4000, 16, np.logspace(0, -decades, 16), seed=3)
+    say("second pass", decades)
+    _, Rp, _, cp = gpu_qr(W, 16, "gaussian", 128, 4, "plain")
+    assert cp["delta"] > 1e-3 * 2.0**-53 * 10.0**decades
+    for variant in ("twice", "l2qr"):
+        Q, R, S, cert = gpu_qr(W, 16, "gaussian", 128, 4, variant)
+        o = oracle_qr(W, 16, "gaussian", 128, 4, variant)
+        assert cert["delta"] < 100 * 2.0**-53 * 16
+        assert cert["delta_tilde"] < 100 * 2.0**-53 * 16
+        assert factorization_error(W, Q, R) < 100 * 2.0**-53 * 16
+        assert rel(R, o["R"]) < 1e-13 * 10.0**(decades / 2)
 
 
 def test_determinism_and_in_place(gpu_lib, small):

@@ -29,7 +29,7 @@ def small_case():
 
 
 # -- Theta = I: RBGS is block Gram-Schmidt with exact projections -------------
-@pytest.mark.parametrize("variant", ["plain", "lowsync"])
+@pytest.mark.parametrize("variant", ["plain", "lowsync", "twice", "l2qr"])
 @pytest.mark.parametrize("ls,iters", [("householder", 0), ("richardson", 2)])
 @pytest.mark.parametrize("n,m,b", [(48, 12, 4), (64, 16, 5), (30, 7, 3), (20, 20, 20), (33, 9, 1)])
 def test_identity_sketch_equals_householder_qr(variant, ls, iters, n, m, b):
@@ -47,7 +47,7 @@ def test_closed_form_well_conditioned(kind):
     W = svd_matrix(10_000, 64, np.logspace(0, -2, 64), seed=5)
     th = Sketch(kind, 256, seed=17).materialize(W.shape[0])
     Qc, Rc = orb.rbgs_closed_form(W, th)
-    for variant in ("plain", "lowsync"):
+    for variant in ("plain", "lowsync", "twice", "l2qr"):
         out = orb.rbgs(W, 8, th, variant)
         assert rel(out["R"], Rc) < 1e-12
         assert rel(out["Q"], Qc) < 1e-12
@@ -63,7 +63,7 @@ def test_closed_form_ill_conditioned(small_case):
 
 
 # -- invariants and certificates ----------------------------------------------
-@pytest.mark.parametrize("variant", ["plain", "lowsync"])
+@pytest.mark.parametrize("variant", ["plain", "lowsync", "twice", "l2qr"])
 def test_invariants_and_certificates(small_case, variant):
     W, th = small_case
     out = orb.rbgs(W, 8, th, variant)
@@ -133,6 +133,29 @@ def test_plain_and_lowsync_agree(small_case):
     b = orb.rbgs(W, 8, th, "lowsync")
     assert rel(a["R"], b["R"]) < 1e-12
     assert rel(a["Q"], b["Q"]) < 1e-6
+
+
+@pytest.mark.parametrize("decades", [8, 12])
+def test_second_pass_restores_sketched_orthogonality(decades):
+    """Section 2.2.4: running RCholeskyQR twice, or after an l2-QR, makes the
+    block's sketched orthogonality independent of its conditioning.  One
+    block (b = m) with cond(W) = 10^decades: RCholeskyQR leaves
+    Delta ~ u cond(W), the two-pass forms Delta ~ u m; R2 of the second pass
+    is I up to ~u cond(W)."""
+    W = svd_matrix(4000, 16, np.logspace(0, -decades, 16), seed=3)
+    th = Sketch("gaussian", 128, seed=4).materialize(4000)
+    plain = orb.rbgs(W, 16, th, "plain")
+    assert plain["delta"] > 1e-3 * U64 * 10.0**decades
+    for variant in ("twice", "l2qr"):
+        out = orb.rbgs(W, 16, th, variant)
+        assert out["delta"] < 100 * U64 * 16
+        assert out["delta_tilde"] < 100 * U64 * 16
+        assert factorization_error(W, out["Q"], out["R"]) < 100 * U64 * 16
+        assert np.all(np.diag(out["R"]) > 0) and np.all(np.tril(out["R"], -1) == 0)
+    # the first pass of "twice" is the plain result: R2 = R_twice R_plain^{-1} ~ I
+    tw = orb.rbgs(W, 16, th, "twice")
+    R2 = sla.solve_triangular(plain["R"].T, tw["R"].T, lower=True).T
+    assert np.linalg.norm(R2 - np.eye(16)) < 100 * U64 * 10.0**decades
 
 
 def test_ragged_last_block():
