@@ -334,12 +334,20 @@ def main():
                                                  max(3, args.steps // 4), 1)
         forms["f64_sparse_plain"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "plain",
                                                  max(3, args.steps // 4), 1)
+        print("[bench] two-pass inter-block forms", file=sys.stderr, flush=True)
+        forms["f32_sparse_twice"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "twice",
+                                                 max(3, args.steps // 4), 1)
+        forms["f32_sparse_l2qr"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "l2qr",
+                                                max(3, args.steps // 4), 1)
         if not args.no_gaussian:
             print("[bench] gaussian forms", file=sys.stderr, flush=True)
             forms["f32_gauss_lowsync"], _ = time_form(W32, p, "gaussian", k, THETA_SEED_LARGE,
                                                       "lowsync", max(2, args.steps // 10), 1)
             forms["f64_gauss_lowsync"], _ = time_form(W64, p, "gaussian", k, THETA_SEED_LARGE,
                                                       "lowsync", max(2, args.steps // 10), 1)
+            forms["f32_rademacher_lowsync"], _ = time_form(W32, p, "rademacher", k,
+                                                           THETA_SEED_LARGE, "lowsync",
+                                                           max(2, args.steps // 10), 1)
     del W64
     if args.forms == "all" and not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
