@@ -85,7 +85,7 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
     n, m = W.shape
     Q = B.colmajor(n, m, W.dtype, W.device)
     R = B.colmajor(m, m, torch.float64, W.device)
-    run = lambda **kw: B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math, **kw)
+    run = lambda **kw: B.rbgs_qr(W, p, kind, k, seed, None, variant, LS_ITERS, Q=Q, R=R, math=math, **kw)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         # accuracy run (with certificate) outside the timed region
@@ -124,11 +124,11 @@ def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
     R = B.colmajor(m, m, torch.float64, W.device)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+        B.rbgs_qr(W, p, kind, k, seed, None, variant, LS_ITERS, Q=Q, R=R, math=math)
         torch.cuda.synchronize()
         B.profile_enable(True)
         for _ in range(reps):
-            B.rbgs_qr(W, p, kind, k, seed, 8, variant, LS_ITERS, Q=Q, R=R, math=math)
+            B.rbgs_qr(W, p, kind, k, seed, None, variant, LS_ITERS, Q=Q, R=R, math=math)
         torch.cuda.synchronize()
         out = {name: round(B.profile_get(name)[0] / reps, 4)
                for name in ("update", "sketch", "reduce", "small", "trsm")}

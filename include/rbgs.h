@@ -82,12 +82,23 @@ typedef enum { RBGS_MATH_F64 = 0, RBGS_MATH_F32 = 1 } rbgs_math;
  *  RADEMACHER  Theta = B / sqrt(k), B[t][r] = +-1 (the other dense
  *              oblivious embedding of Section 1.3): bit t % 32 of word
  *              (t % 128) / 32 of the output of counter (r_lo, r_hi, t / 128,
- *              0x52414445), a set bit meaning -1; k % 4 == 0. */
+ *              0x52414445), a set bit meaning -1; k % 4 == 0.
+ *  SRHT        Theta = P H D / sqrt(k) (subsampled randomized Hadamard
+ *              transform, Section 1.3, zero padding to N = 2^L rows): D =
+ *              diag(d_r), d_r = -1 if bit r % 128 of the output of counter
+ *              (r / 128 lo, hi, 0, 0x53524854) is set; H[s][r] =
+ *              (-1)^popcount(s & r) (Sylvester order); row j of P selects
+ *              s_j = the top L bits of word j % 4 of counter (j / 4, 0, 1,
+ *              0x53524854) (uniform, with replacement).  L = zeta if zeta > 0,
+ *              else the smallest L with 2^L >= the rows of the call (row0 + n
+ *              for the sketch calls; give zeta explicitly when sketching row
+ *              ranges separately); k <= 2048. */
 typedef enum {
   RBGS_SKETCH_GAUSSIAN = 0,
   RBGS_SKETCH_SPARSE_SIGN = 1,
   RBGS_SKETCH_IDENTITY = 2,
-  RBGS_SKETCH_RADEMACHER = 3
+  RBGS_SKETCH_RADEMACHER = 3,
+  RBGS_SKETCH_SRHT = 4
 } rbgs_sketch_kind;
 
 /* Inter-block QR in steps 4-5 (Section 2.2):
@@ -112,7 +123,8 @@ typedef enum {
 
 typedef struct {
   int32_t kind;      /* rbgs_sketch_kind                                  */
-  int32_t zeta;      /* nonzeros per column of the sparse sign (1..8)     */
+  int32_t zeta;      /* sparse sign: nonzeros per column (1..8); SRHT:
+                        log2 of the transform size (0: derived)           */
   int64_t k;         /* sketch dimension (rows of Theta), m <= k <= n     */
   uint64_t seed;     /* Philox key                                        */
 } rbgs_sketch;
@@ -276,10 +288,11 @@ RBGS_API rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int
 
 /* Explicit unscaled sketching matrix, for brute-force checks of the
  * definition above: out[t + k*(r - row0)] = Z[t][r] (Gaussian), B[t][r]
- * (sparse sign, +-1 or 0) or I[t][r] (identity) for t < k, row0 <= r < row0+n.
+ * (sparse sign, +-1 or 0), B[t][r] (Rademacher), (H D)[s_t][r] (SRHT) or
+ * I[t][r] (identity) for t < k, row0 <= r < row0+n.
  *   out device, k x n float (ld k), overwritten.  Theta = scale * out with
- *   scale = 1/sqrt(k) (Gaussian, Rademacher), 1/sqrt(zeta) (sparse sign),
- *   1 (identity). */
+ *   scale = 1/sqrt(k) (Gaussian, Rademacher, SRHT), 1/sqrt(zeta) (sparse
+ *   sign), 1 (identity). */
 RBGS_API rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, int64_t row0,
                              float* out, void* stream);
 

@@ -35,6 +35,18 @@ Rademacher, Theta = c_k * B with c_k = fl64(1 / sqrt(k)) (Section 1.3: i.i.d.
   x2 << 64 | x3 << 96; entry B[t, r] for t = 128 q + b is -1 if bit b is set,
   +1 otherwise.  Requires k % 4 == 0.
 
+SRHT (Section 1.3: random signs, Walsh-Hadamard matrix, uniform row sampling,
+  scale 1/sqrt(k), zero padding to a power of two), Theta = c_k * P H D with
+  c_k = fl64(1 / sqrt(k)), for a transform size N = 2^L >= n:
+    D = diag(d_r): d_r = -1 if bit (r mod 128) of the 128-bit output of the
+        counter (q mod 2^32, q >> 32, 0, 0x53524854), q = r >> 7, is set
+        (bits numbered as for the Rademacher operator);
+    H[s, r] = (-1)^popcount(s & r) (Sylvester's construction);
+    P selects rows s_0 .. s_{k-1}: s_j = word (j mod 4) of the counter
+        (j >> 2, 0, 1, 0x53524854), shifted right by 32 - L (its top L bits),
+        i.e. uniform on [0, N) and drawn with replacement.
+  L is given (`zeta`) or, if 0, the smallest L with 2^L >= the row count.
+
 Identity: Theta = I (requires k == n).  RBGS with Theta = I is block
 Gram-Schmidt with exact least-squares projections (Section 2), which the tests
 use to pin the oracle against Householder QR.
@@ -58,6 +70,7 @@ from .philox import philox4x32_10, split_seed
 TAG_GAUSS = 0x47415553
 TAG_SPARSE = 0x53504152
 TAG_RADEMACHER = 0x52414445
+TAG_SRHT = 0x53524854
 
 F32 = np.float32
 
@@ -182,6 +195,66 @@ def rademacher_b(rows, k, seed):
     return np.where(bits == 1, -1, 1).astype(np.int8)
 
 
+def _bits128(q, tag, c2, seed):
+    """Bits of the 128-bit Philox outputs for counters (q lo, q hi, c2, tag):
+    array (len(q), 128) of 0/1, bit b of word w at position 32 w + b."""
+    q = np.asarray(q, dtype=np.uint64)
+    k0, k1 = split_seed(seed)
+    words = philox4x32_10((q & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                          (q >> np.uint64(32)).astype(np.uint32),
+                          np.uint32(c2), np.uint32(tag), k0, k1)
+    W = np.stack(words, axis=-1)                                      # (len, 4)
+    return ((W[..., None] >> np.arange(32, dtype=np.uint32)) & np.uint32(1)).reshape(q.shape[0], 128)
+
+
+def srht_signs(rows, seed):
+    """d_r for the global rows `rows` (+1 / -1 as float64)."""
+    rows = np.asarray(rows, dtype=np.uint64)
+    if rows.size == 0:
+        return np.zeros(0)
+    q = rows >> np.uint64(7)
+    uq, inv = np.unique(q, return_inverse=True)
+    bits = _bits128(uq, TAG_SRHT, 0, seed)[inv, (rows & np.uint64(127)).astype(np.int64)]
+    return np.where(bits == 1, -1.0, 1.0)
+
+
+def srht_samples(k, L, seed):
+    """Sampled rows s_0 .. s_{k-1} of the 2^L-point transform (uint64)."""
+    k0, k1 = split_seed(seed)
+    j = np.arange(k, dtype=np.uint64)
+    words = philox4x32_10((j >> np.uint64(2)).astype(np.uint32), np.uint32(0), np.uint32(1),
+                          np.uint32(TAG_SRHT), k0, k1)
+    w = np.stack(words, axis=-1)[np.arange(k), (j & np.uint64(3)).astype(np.int64)].astype(np.uint64)
+    return (w >> np.uint64(32 - L)) if L > 0 else np.zeros(k, dtype=np.uint64)
+
+
+def fwht(A):
+    """Unnormalized Walsh-Hadamard transform H A along axis 0 (length a power
+    of two), H[s, r] = (-1)^popcount(s & r): log2(N) butterfly stages, stage h
+    combining rows i and i + h of every block of 2h rows into their sum and
+    difference."""
+    A = np.array(A, dtype=np.float64, copy=True)
+    N = A.shape[0]
+    if N & (N - 1):
+        raise ValueError("length must be a power of two")
+    h = 1
+    while h < N:
+        B = A.reshape(N // (2 * h), 2, h, *A.shape[1:])
+        top = B[:, 0] + B[:, 1]
+        bot = B[:, 0] - B[:, 1]
+        B[:, 0], B[:, 1] = top, bot
+        A = B.reshape(A.shape)
+        h *= 2
+    return A
+
+
+def ceil_log2(n):
+    L = 0
+    while (1 << L) < n:
+        L += 1
+    return L
+
+
 def sparse_sign_entries(rows, k, zeta, seed):
     """Row indices (uint32, shape (len(rows), zeta)) and signs (+1/-1 int8) of
     the nonzeros of the unscaled sparse-sign columns B[:, rows]."""
@@ -204,13 +277,17 @@ def sparse_sign_entries(rows, k, zeta, seed):
 class Sketch:
     """A sketching operator Theta in R^{k x n} defined by (kind, k, seed, zeta).
 
-    kind: "gaussian", "sparse", "rademacher" or "identity".
+    kind: "gaussian", "sparse", "rademacher", "srht" or "identity".  For
+    "srht", `zeta` is log2 of the transform size (0: the smallest power of two
+    covering the rows of the call).
     """
 
-    def __init__(self, kind, k, seed=0, zeta=8, chunk_rows=8192):
+    def __init__(self, kind, k, seed=0, zeta=None, chunk_rows=8192):
+        if zeta is None:
+            zeta = 0 if kind == "srht" else 8
         self.kind, self.k, self.seed, self.zeta = kind, int(k), int(seed), int(zeta)
         self.chunk_rows = chunk_rows
-        if kind in ("gaussian", "rademacher"):
+        if kind in ("gaussian", "rademacher", "srht"):
             self.scale = 1.0 / np.sqrt(float(self.k))
         elif kind == "sparse":
             self.scale = 1.0 / np.sqrt(float(self.zeta))
@@ -222,10 +299,27 @@ class Sketch:
         self._csr = None
         self._csr_n = 0
 
+    def srht_L(self, rows):
+        return self.zeta if self.zeta > 0 else ceil_log2(rows)
+
+    def _srht_apply(self, X, row0):
+        """c_k (H D X_pad)[s, :], X_pad holding X at rows row0 .. of N = 2^L."""
+        n_loc, c = X.shape
+        L = self.srht_L(row0 + n_loc)
+        N = 1 << L
+        if row0 + n_loc > N:
+            raise ValueError("rows beyond the SRHT transform size")
+        Xp = np.zeros((N, c))
+        Xp[row0:row0 + n_loc] = srht_signs(np.arange(row0, row0 + n_loc), self.seed)[:, None] * X
+        Y = fwht(Xp)
+        return self.scale * Y[srht_samples(self.k, L, self.seed).astype(np.int64)]
+
     def materialize(self, n):
         """Form Theta explicitly once and apply it by a product from then on:
         a dense k x n FP64 matrix, or for the sparse sign a compressed sparse
         row matrix of the unscaled +-1 entries (so large n stays cheap)."""
+        if self.kind == "srht":
+            return self       # applied by the fast transform every time
         if self.kind == "sparse":
             idx, sign = sparse_sign_entries(np.arange(n), self.k, self.zeta, self.seed)
             cols = np.repeat(np.arange(n), self.zeta)
@@ -247,6 +341,12 @@ class Sketch:
             return self.scale * gaussian_z(np.arange(n), self.k, self.seed).T.astype(np.float64)
         if self.kind == "rademacher":
             return self.scale * rademacher_b(np.arange(n), self.k, self.seed).T.astype(np.float64)
+        if self.kind == "srht":
+            # columns of Theta are the transforms of the unit vectors
+            L = self.srht_L(n)
+            H = fwht(np.eye(1 << L)[:, :n])
+            return self.scale * H[srht_samples(self.k, L, self.seed).astype(np.int64)] * \
+                srht_signs(np.arange(n), self.seed)[None, :]
         idx, sign = sparse_sign_entries(np.arange(n), self.k, self.zeta, self.seed)
         T = np.zeros((self.k, n))
         cols = np.repeat(np.arange(n), self.zeta)
@@ -272,6 +372,8 @@ class Sketch:
             if row0 != 0 or n_loc != self.k:
                 raise ValueError("identity sketch needs k == n")
             return X.copy()
+        if self.kind == "srht":
+            return self._srht_apply(X, row0)
         if self.kind == "sparse":
             idx, sign = sparse_sign_entries(np.arange(row0, row0 + n_loc), self.k,
                                             self.zeta, self.seed)

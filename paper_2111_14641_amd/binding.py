@@ -17,7 +17,7 @@ RBGS_OK, RBGS_EINVAL, RBGS_ENOMEM, RBGS_EDEVICE, RBGS_EBREAKDOWN, RBGS_ENOTCONV,
 # rbgs_store / rbgs_math / rbgs_sketch_kind / rbgs_variant
 STORE = {"f64": 0, "f32": 1}
 MATH = {"f64": 0, "f32": 1}
-SKETCH = {"gaussian": 0, "sparse": 1, "identity": 2, "rademacher": 3}
+SKETCH = {"gaussian": 0, "sparse": 1, "identity": 2, "rademacher": 3, "srht": 4}
 VARIANT = {"plain": 0, "lowsync": 1, "twice": 2, "l2qr": 3}
 PROFILE = {"update": 0, "sketch": 1, "reduce": 2, "small": 3, "trsm": 4}
 
@@ -184,11 +184,15 @@ def _stream_ptr(X):
     return torch.cuda.current_stream(X.device).cuda_stream
 
 
-def make_sketch(kind, k, seed, zeta=8):
+def make_sketch(kind, k, seed, zeta=None):
+    """zeta: nonzeros per column (sparse sign, default 8) or log2 of the SRHT
+    transform size (default 0: derived from the row count)."""
+    if zeta is None:
+        zeta = 0 if kind == "srht" else 8
     return rbgs_sketch(SKETCH[kind], int(zeta), int(k), int(seed) & 0xFFFFFFFFFFFFFFFF)
 
 
-def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync", ls_iters=4,
+def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=None, variant="lowsync", ls_iters=4,
             Q=None, R=None, want_S=False, want_cert=False, math="f64"):
     """RBGS QR of a column-major CUDA tensor W (n x m, float32 or float64).
 
@@ -237,7 +241,7 @@ def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync", ls_i
     return Q, R, S, cd
 
 
-def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=8, variant="lowsync",
+def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=None, variant="lowsync",
                     ls_iters=4, Qs=None, Rs=None, math="f64", graph=False):
     """Independent RBGS QRs of column-major CUDA tensors Ws (same dtype and
     device) in one call; problem i uses sketch seed `seed + i`.  ps / ks: block
@@ -273,7 +277,7 @@ def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=8, variant
     return Qs, Rs, [arr[i].p for i in range(count)], [arr[i].k for i in range(count)]
 
 
-def autotune(n, m, kind="sparse", store="f32", math="f64", variant="lowsync", ls_iters=4, zeta=8,
+def autotune(n, m, kind="sparse", store="f32", math="f64", variant="lowsync", ls_iters=4, zeta=None,
              device=0):
     """(p, k) the library's autotuner picks for an n x m problem."""
     lib = Library.get()
@@ -331,7 +335,7 @@ def _store_of(dtype):
     raise TypeError("expected float32 or float64")
 
 
-def block_arnoldi(A, B, nblocks, kind="sparse", k=None, seed=0, zeta=8, variant="lowsync",
+def block_arnoldi(A, B, nblocks, kind="sparse", k=None, seed=0, zeta=None, variant="lowsync",
                   ls_iters=4, math="f64", want_cert=False):
     """RBGS-Arnoldi from the block B (n x bs, column-major, FP32 or FP64).
     Returns (Q, R, cert): H = R[:, bs:] is the block Hessenberg matrix."""
@@ -359,7 +363,7 @@ def block_arnoldi(A, B, nblocks, kind="sparse", k=None, seed=0, zeta=8, variant=
 
 
 def block_gmres(A, B, X0=None, blocks_per_cycle=40, max_cycles=10, tol=1e-8, kind="sparse",
-                k=None, seed=0, zeta=8, store="f32", variant="lowsync", ls_iters=4, math="f64"):
+                k=None, seed=0, zeta=None, store="f32", variant="lowsync", ls_iters=4, math="f64"):
     """Restarted randomized block GMRES for A X = B (B: n x bs FP64 on the
     device).  Returns (X, block iterations, final relative residual, history,
     converged)."""
@@ -387,7 +391,7 @@ def block_gmres(A, B, X0=None, blocks_per_cycle=40, max_cycles=10, tol=1e-8, kin
     return X, iters.value, rel.value, history, st == RBGS_OK
 
 
-def sketch_apply(X, kind, k, seed, zeta=8, row0=0, out=None):
+def sketch_apply(X, kind, k, seed, zeta=None, row0=0, out=None):
     """Theta[:, row0:row0+n] X for a column-major CUDA tensor X (n x c)."""
     torch = _torch()
     lib = Library.get()
@@ -404,7 +408,7 @@ def sketch_apply(X, kind, k, seed, zeta=8, row0=0, out=None):
     return out
 
 
-def theta_dense(kind, k, seed, n, row0=0, zeta=8, device="cuda"):
+def theta_dense(kind, k, seed, n, row0=0, zeta=None, device="cuda"):
     """Explicit unscaled Theta[:, row0:row0+n] (k x n float32, column-major)."""
     torch = _torch()
     lib = Library.get()

@@ -186,16 +186,32 @@ bool valid_sketch(const rbgs_sketch* sk, int64_t n, std::string& why) {
     case RBGS_SKETCH_IDENTITY:
       if (sk->k != n) { why = "identity sketch needs k == n"; return false; }
       return true;
+    case RBGS_SKETCH_SRHT:
+      if (sk->k > 2048) { why = "SRHT supports k <= 2048"; return false; }
+      if (sk->zeta < 0 || sk->zeta > 32) { why = "SRHT needs 0 <= log2 of the transform size <= 32"; return false; }
+      if (sk->zeta > 0 && n > ((int64_t)1 << sk->zeta)) {
+        why = "SRHT transform size 2^zeta is smaller than the number of rows";
+        return false;
+      }
+      if (sk->zeta == 0 && n > ((int64_t)1 << 32)) { why = "SRHT supports at most 2^32 rows"; return false; }
+      return true;
     default:
       why = "unknown sketch kind";
       return false;
   }
 }
 
-SketchDesc make_desc(const rbgs_sketch* sk) {
+// rows_total: the global row count the sketch must cover (the SRHT transform
+// size defaults to the smallest power of two >= rows_total).
+SketchDesc make_desc(const rbgs_sketch* sk, int64_t rows_total) {
   SketchDesc d;
   d.kind = sk->kind;
   d.zeta = sk->zeta;
+  if (sk->kind == RBGS_SKETCH_SRHT && sk->zeta == 0) {
+    int l = 0;
+    while (((int64_t)1 << l) < rows_total) ++l;
+    d.zeta = l;
+  }
   d.k = sk->k;
   d.key0 = (uint32_t)(sk->seed & 0xFFFFFFFFull);
   d.key1 = (uint32_t)(sk->seed >> 32);
@@ -203,7 +219,7 @@ SketchDesc make_desc(const rbgs_sketch* sk) {
 }
 
 double sketch_scale(const SketchDesc& d) {
-  if (d.kind == kGaussian || d.kind == kRademacher) return 1.0 / sqrt((double)d.k);
+  if (d.kind == kGaussian || d.kind == kRademacher || d.kind == kSrht) return 1.0 / sqrt((double)d.k);
   if (d.kind == kSparse) return 1.0 / sqrt((double)d.zeta);
   return 1.0;
 }
@@ -369,7 +385,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
                      int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
                      double* R, int64_t ldr, double* S_out, bool hoist) {
   r.h = h;
-  r.d = make_desc(sk);
+  r.d = make_desc(sk, n);
   r.f32 = opts->store == RBGS_STORE_F32;
   r.f32_math = opts->math == RBGS_MATH_F32;
   r.es = r.f32 ? 4 : 8;
@@ -1198,9 +1214,11 @@ rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t stor
     return fail(h, RBGS_EINVAL, why);
   }
   if (ldo < sk->k) return fail(h, RBGS_EINVAL, "ldo must be >= k");
+  if (sk->kind == RBGS_SKETCH_SRHT && sk->zeta > 0 && row0 + n > ((int64_t)1 << sk->zeta))
+    return fail(h, RBGS_EINVAL, "rows beyond the SRHT transform size 2^zeta");
   DeviceGuard guard(h->device);
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
-  const SketchDesc d = make_desc(sk);
+  const SketchDesc d = make_desc(sk, row0 + n);
   const size_t part_bytes = ((sketch_partial_doubles(d, n, c) * 8 + 255) / 256) * 256;
   const size_t plan_bytes = d.kind == kSparse ? sparse_plan_bytes(d, n) : 0;
   rbgs_status rs = ensure_ws(h, part_bytes + plan_bytes + 256);
@@ -1221,9 +1239,12 @@ rbgs_status rbgs_theta_dense(rbgs_handle h, const rbgs_sketch* sk, int64_t n, in
   if (!sk) return fail(h, RBGS_EINVAL, "sketch descriptor is NULL");
   if (sk->kind != RBGS_SKETCH_IDENTITY && !valid_sketch(sk, n, why)) return fail(h, RBGS_EINVAL, why);
   if (sk->kind == RBGS_SKETCH_IDENTITY && sk->k < 1) return fail(h, RBGS_EINVAL, "k must be >= 1");
+  if (sk->kind == RBGS_SKETCH_SRHT && sk->zeta > 0 && row0 + n > ((int64_t)1 << sk->zeta))
+    return fail(h, RBGS_EINVAL, "rows beyond the SRHT transform size 2^zeta");
   DeviceGuard guard(h->device);
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
-  HIP_TRY(h, launch_theta_dense(make_desc(sk), n, row0, out, (hipStream_t)stream), "theta_dense");
+  HIP_TRY(h, launch_theta_dense(make_desc(sk, row0 + n), n, row0, out, (hipStream_t)stream),
+          "theta_dense");
   return RBGS_OK;
 }
 

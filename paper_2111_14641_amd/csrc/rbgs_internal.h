@@ -41,6 +41,7 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 constexpr uint32_t kTagGauss = 0x47415553u;
 constexpr uint32_t kTagSparse = 0x53504152u;
 constexpr uint32_t kTagRademacher = 0x52414445u;
+constexpr uint32_t kTagSrht = 0x53524854u;
 
 // fp32 constants by bit pattern (correctly rounded values of the named reals).
 __device__ __forceinline__ float f32c(uint32_t b) { return __uint_as_float(b); }
@@ -130,6 +131,24 @@ __device__ __forceinline__ void rademacher4(uint64_t r, uint32_t j, uint32_t k0,
   for (int i = 0; i < 4; ++i) z[i] = ((bits >> i) & 1u) ? -1.0f : 1.0f;
 }
 
+// SRHT random sign of global row r: bit r % 128 of the output of the Philox
+// call (r / 128, 0, 0x53524854); a set bit means -1.
+__device__ __forceinline__ double srht_sign(uint64_t r, uint32_t k0, uint32_t k1) {
+  const uint64_t q = r >> 7;
+  const u32x4 x = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), 0u, kTagSrht, k0, k1);
+  const uint32_t wsel = (uint32_t)(r >> 5) & 3u;
+  const uint32_t w = wsel == 0 ? x.x : (wsel == 1 ? x.y : (wsel == 2 ? x.z : x.w));
+  return ((w >> (r & 31u)) & 1u) ? -1.0 : 1.0;
+}
+// SRHT sampled row s_j of the 2^logn-point transform: the top logn bits of
+// word j % 4 of the Philox call (j / 4, 0, 1, 0x53524854) (0 if logn == 0).
+__device__ __forceinline__ uint64_t srht_sample(uint32_t j, int logn, uint32_t k0, uint32_t k1) {
+  const u32x4 x = philox4x32_10(j >> 2, 0u, 1u, kTagSrht, k0, k1);
+  const uint32_t q = j & 3u;
+  const uint32_t w = q == 0 ? x.x : (q == 1 ? x.y : (q == 2 ? x.z : x.w));
+  return logn == 0 ? 0ull : (uint64_t)(w >> (32 - logn));
+}
+
 // Row (target) of the nonzero of segment s of the sparse-sign column r:
 // s*L + (((w_s >> 1) * L) >> 31), sign bit = w_s & 1 (1 = negative).
 __device__ __forceinline__ uint32_t sparse_target(uint32_t w, uint32_t s, uint32_t L) {
@@ -147,11 +166,11 @@ __device__ __forceinline__ void sparse_words(uint64_t r, uint32_t k0, uint32_t k
 // ---------------------------------------------------------------------------
 // Host launchers (all enqueue on `st`, return hipError_t of the launch).
 // ---------------------------------------------------------------------------
-enum SketchKind { kGaussian = 0, kSparse = 1, kIdentity = 2, kRademacher = 3 };
+enum SketchKind { kGaussian = 0, kSparse = 1, kIdentity = 2, kRademacher = 3, kSrht = 4 };
 
 struct SketchDesc {
   int kind;
-  int zeta;
+  int zeta;   // sparse sign: nonzeros per column; SRHT: log2 of the transform size
   int64_t k;
   uint32_t key0, key1;
 };

@@ -400,6 +400,131 @@ __global__ void sketch_identity_kernel(const T* __restrict__ X, int64_t ldx, int
 // ---------------------------------------------------------------------------
 // Explicit unscaled Theta (k x n, float) for brute-force checks.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// SRHT (Section 1.3): Theta = P H D / sqrt(k) with H the Sylvester-ordered
+// Walsh-Hadamard matrix of size 2^logn >= the global row count.  With the row
+// index split as r = 1024 h + t, H = H_hi (x) H_1024, so
+//     (H D x)[s] = sum_h (-1)^popcount(s_hi & h) (H_1024 D x_h)[s_lo],
+// x_h being chunk h (1024 rows, zero outside [row0, row0 + n)).  A workgroup
+// takes a range of chunks; for each it transforms the chunk in LDS (FP64,
+// butterflies on 4 + 4 + 2 index bits, each group in registers between LDS
+// transposes) and thread j adds row s_lo of the result, with the sign above,
+// to its k-row sums.  Sums are FP64 in a fixed order; partials per workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kHrThreads = 1024;
+constexpr int kHrChunk = 1024;
+constexpr int kHrLd = kSketchCols + 1;   // LDS row stride in doubles
+
+template <int N>
+__device__ __forceinline__ void fwht_reg(double (&a)[N]) {
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if ((i & h) == 0) {
+        const double u = a[i], v = a[i + h];
+        a[i] = u + v;
+        a[i + h] = u - v;
+      }
+}
+
+template <typename T, int TPT>
+__global__ __launch_bounds__(kHrThreads) void sketch_srht_kernel(
+    const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int64_t row0, int k, int logn,
+    uint32_t key0, uint32_t key1, int64_t chunks_per_wg, double* __restrict__ partial) {
+  __shared__ double ys[kHrChunk * kHrLd];
+  const int tid = threadIdx.x;
+  const int g = blockIdx.x;
+  const int col0 = blockIdx.y * kSketchCols;
+  const int nc = min(kSketchCols, ncols - col0);
+  const int64_t h0 = row0 / kHrChunk;
+  const int64_t h1 = (row0 + n - 1) / kHrChunk + 1;
+  const int64_t hb = h0 + (int64_t)g * chunks_per_wg;
+  const int64_t he = min(h1, hb + chunks_per_wg);
+
+  uint32_t slo[TPT];
+  uint64_t shi[TPT];
+#pragma unroll
+  for (int j = 0; j < TPT; ++j) {
+    const int t = tid + j * kHrThreads;
+    const uint64_t sj = srht_sample((uint32_t)(t < k ? t : 0), logn, key0, key1);
+    slo[j] = (uint32_t)(sj & (kHrChunk - 1));
+    shi[j] = sj >> 10;
+  }
+  double acc[TPT][kSketchCols];
+#pragma unroll
+  for (int j = 0; j < TPT; ++j)
+#pragma unroll
+    for (int c = 0; c < kSketchCols; ++c) acc[j][c] = 0.0;
+
+  for (int64_t h = hb; h < he; ++h) {
+    // row tid of the chunk times its sign (clamped loads; rows outside the
+    // call's range count as zero)
+    {
+      const int64_t gr = h * kHrChunk + tid;
+      const int64_t r = gr - row0;
+      const int64_t rc = r < 0 ? 0 : (r >= n ? n - 1 : r);
+      T v[kSketchCols];
+#pragma unroll
+      for (int c = 0; c < kSketchCols; ++c) v[c] = X[rc + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+      const double sg = (r >= 0 && r < n) ? srht_sign((uint64_t)gr, key0, key1) : 0.0;
+#pragma unroll
+      for (int c = 0; c < kSketchCols; ++c) ys[tid * kHrLd + c] = sg * (double)v[c];
+    }
+    __syncthreads();
+    {  // index bits 0-3: thread holds rows 16 b + i of column c
+      const int c = tid & 15, b = tid >> 4;
+      double a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = ys[(16 * b + i) * kHrLd + c];
+      fwht_reg<16>(a);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) ys[(16 * b + i) * kHrLd + c] = a[i];
+    }
+    __syncthreads();
+    {  // bits 4-7: rows lo4 + 16 i + 256 hi2
+      const int c = tid & 15, lo4 = (tid >> 4) & 15, hi2 = tid >> 8;
+      double a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = ys[(lo4 + 16 * i + 256 * hi2) * kHrLd + c];
+      fwht_reg<16>(a);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) ys[(lo4 + 16 * i + 256 * hi2) * kHrLd + c] = a[i];
+    }
+    __syncthreads();
+    {  // bits 8-9: rows low8 + 256 i of columns 4 cg .. 4 cg + 3
+      const int cg = tid & 3, low8 = tid >> 2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = ys[(low8 + 256 * i) * kHrLd + 4 * cg + q];
+        fwht_reg<4>(a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ys[(low8 + 256 * i) * kHrLd + 4 * cg + q] = a[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TPT; ++j) {
+      const double sgn = (__popcll(shi[j] & (uint64_t)h) & 1) ? -1.0 : 1.0;
+      const double* yr = ys + slo[j] * kHrLd;
+#pragma unroll
+      for (int c = 0; c < kSketchCols; ++c) acc[j][c] = fma(sgn, yr[c], acc[j][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < TPT; ++j) {
+    const int t = tid + j * kHrThreads;
+    if (t < k) {
+#pragma unroll
+      for (int c = 0; c < kSketchCols; ++c)
+        if (c < nc) partial[((int64_t)g * ncols + col0 + c) * k + t] = acc[j][c];
+    }
+  }
+}
+
 __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0, uint32_t key1,
                                    int64_t n, int64_t row0, float* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -419,6 +544,13 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
     rademacher4((uint64_t)(row0 + rl), (uint32_t)jj, key0, key1, z);
 #pragma unroll
     for (int q = 0; q < 4; ++q) out[4 * jj + q + k * rl] = z[q];
+  } else if (kind == kSrht) {
+    if (idx >= k * n) return;
+    const int64_t t = idx % k, rl = idx / k;
+    const uint64_t r = (uint64_t)(row0 + rl);
+    const uint64_t s = srht_sample((uint32_t)t, zeta, key0, key1);
+    const double v = srht_sign(r, key0, key1) * ((__popcll(s & r) & 1) ? -1.0 : 1.0);
+    out[t + k * rl] = (float)v;
   } else if (kind == kSparse) {
     if (idx >= n) return;
     float* col = out + k * idx;
@@ -448,6 +580,12 @@ int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_
   if (sk.kind == kGaussian || sk.kind == kRademacher) {
     G = ceil_div(512, groups * ceil_div(sk.k, 256));
     tile = kGaTile;
+  } else if (sk.kind == kSrht) {
+    // one 1024-thread workgroup per CU; a range may start mid-chunk, so it
+    // can touch one chunk more than n / 1024
+    G = std::min<int64_t>(ceil_div(256, groups), ceil_div(n, kHrChunk) + 1);
+    if (max_groups > 0) G = std::min<int64_t>(G, max_groups);
+    return (int)std::max<int64_t>(1, G);
   } else {
     G = ceil_div(256, groups);
     tile = kSpTile;
@@ -499,6 +637,29 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
       if (two) RBGS_SP(double, 2); else RBGS_SP(double, 1);
     }
 #undef RBGS_SP
+  } else if (sk.kind == kSrht) {
+    const int64_t nchunks = (row0 + n - 1) / kHrChunk + 1 - row0 / kHrChunk;
+    const int64_t cpw = ceil_div(nchunks, G);
+    dim3 grid(G, (unsigned)groups);
+    if (f32) {
+      if (sk.k > kHrThreads)
+        hipLaunchKernelGGL((sketch_srht_kernel<float, 2>), grid, dim3(kHrThreads), 0, st,
+                           (const float*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
+                           sk.key1, cpw, partial);
+      else
+        hipLaunchKernelGGL((sketch_srht_kernel<float, 1>), grid, dim3(kHrThreads), 0, st,
+                           (const float*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
+                           sk.key1, cpw, partial);
+    } else {
+      if (sk.k > kHrThreads)
+        hipLaunchKernelGGL((sketch_srht_kernel<double, 2>), grid, dim3(kHrThreads), 0, st,
+                           (const double*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
+                           sk.key1, cpw, partial);
+      else
+        hipLaunchKernelGGL((sketch_srht_kernel<double, 1>), grid, dim3(kHrThreads), 0, st,
+                           (const double*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.zeta, sk.key0,
+                           sk.key1, cpw, partial);
+    }
   } else {
     const int64_t rpw = ceil_div(ceil_div(n, G), kGaTile) * kGaTile;
     dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)groups);
@@ -539,6 +700,7 @@ hipError_t launch_theta_dense(const SketchDesc& sk, int64_t n, int64_t row0, flo
                               hipStream_t st) {
   int64_t total = (sk.kind == kGaussian || sk.kind == kRademacher) ? (sk.k / 4) * n
                                                                      : (sk.kind == kSparse ? n : sk.k * n);
+  if (sk.kind == kSrht && row0 + n > ((int64_t)1 << sk.zeta)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(theta_dense_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
                      sk.kind, sk.k, sk.zeta, sk.key0, sk.key1, n, row0, out);
   return hipGetLastError();

@@ -32,7 +32,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def gpu_qr(W, b, kind, k, seed, variant, store="f64", ls_iters=2, zeta=8, inplace=False, math="f64"):
+def gpu_qr(W, b, kind, k, seed, variant, store="f64", ls_iters=2, zeta=None, inplace=False, math="f64"):
     import torch
     from paper_2111_14641_amd import binding as B
     n, m = W.shape
@@ -46,7 +46,7 @@ def gpu_qr(W, b, kind, k, seed, variant, store="f64", ls_iters=2, zeta=8, inplac
     return to(Q), to(R), to(S), cert
 
 
-def oracle_qr(W, b, kind, k, seed, variant, ls_iters=2, zeta=8):
+def oracle_qr(W, b, kind, k, seed, variant, ls_iters=2, zeta=None):
     th = Sketch(kind, k, seed=seed, zeta=zeta).materialize(W.shape[0])
     return orb.rbgs(W, b, th, variant, "richardson", ls_iters)
 
@@ -75,7 +75,8 @@ def test_small_workload_fp64_matches_oracle(gpu_lib, small, variant):
 
 
 @pytest.mark.parametrize("variant", ["plain", "lowsync"])
-@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256), ("rademacher", 256)])
+@pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256), ("rademacher", 256),
+                                    ("srht", 256)])
 def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     W = svd_matrix(10_000, 64, np.logspace(0, -2, 64), seed=5)
     say("well-conditioned", variant, kind)
@@ -109,6 +110,8 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (4000, 72, 24, 256, "rademacher", "twice"),
     (64, 16, 4, 64, "identity", "l2qr"),
     (300, 20, 6, 300, "identity", "twice"),
+    (4097, 30, 8, 128, "srht", "lowsync"),          # SRHT: ragged chunk, transform of 2^13
+    (3000, 40, 16, 2048, "srht", "plain"),          # SRHT with two outputs per thread
 ])
 def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
     W = svd_matrix(n, m, np.logspace(0, -2, m), seed=n + m + b)

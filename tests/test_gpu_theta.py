@@ -60,6 +60,36 @@ def test_rademacher_theta_bit_exact(gpu_lib, k, n, row0, seed):
     assert np.array_equal(Bg, Bo)
 
 
+def srht_entries(k, seed, rows, L):
+    """Unscaled SRHT entries d_r (-1)^popcount(s_t & r) for the given global
+    rows (the closed form of H, pinned against scipy's Hadamard matrix)."""
+    s = th.srht_samples(k, L, seed)
+    d = th.srht_signs(rows, seed)
+    par = np.zeros((k, len(rows)), dtype=np.int64)
+    x = s[:, None] & np.asarray(rows, dtype=np.uint64)[None, :]
+    while np.any(x):
+        par ^= (x & np.uint64(1)).astype(np.int64)
+        x = x >> np.uint64(1)
+    return (np.where(par == 1, -1.0, 1.0) * d[None, :]).astype(np.float32)
+
+
+@pytest.mark.parametrize("k,n,row0,L,seed", [
+    (256, 1000, 0, 10, 0x2111146413),
+    (100, 333, 12345, 15, 7),
+    (2048, 300, 2**31 + 5, 32, 99),     # widest transform, row index above 2^31
+    (64, 50, 0, 6, 3),                  # transform smaller than one 1024-row chunk
+])
+def test_srht_theta_bit_exact(gpu_lib, k, n, row0, L, seed):
+    from paper_2111_14641_amd import binding as B
+    say("theta srht", k, n, row0, L, seed)
+    Tg = to_np(B.theta_dense("srht", k, seed, n, row0, zeta=L))
+    To = srht_entries(k, seed, np.arange(row0, row0 + n, dtype=np.uint64), L)
+    assert np.array_equal(Tg, To)
+    if row0 == 0:
+        Td = th.Sketch("srht", k, seed=seed, zeta=L).dense(n) * np.sqrt(k)
+        assert np.array_equal(To.astype(np.float64), np.round(Td))
+
+
 def abs_sketch(kind, k, seed, X, row0, zeta=8):
     """|Theta| |X| (the scale of the rounding-error bound of a sketch)."""
     import scipy.sparse as sp
@@ -71,7 +101,7 @@ def abs_sketch(kind, k, seed, X, row0, zeta=8):
             Z = th.gaussian_z(rows[r0:r0 + 8192], k, seed).astype(np.float64)
             out += np.abs(Z).T @ np.abs(X[r0:r0 + 8192])
         return out / np.sqrt(k)
-    if kind == "rademacher":
+    if kind in ("rademacher", "srht"):
         return np.broadcast_to(np.abs(X).sum(axis=0) / np.sqrt(k), (k, X.shape[1]))
     idx, _ = th.sparse_sign_entries(rows, k, zeta, seed)
     Bm = sp.csr_matrix((np.ones(idx.size), (idx.ravel().astype(np.int64), np.repeat(np.arange(n), zeta))),
@@ -81,7 +111,8 @@ def abs_sketch(kind, k, seed, X, row0, zeta=8):
 
 @pytest.mark.parametrize("kind,k", [("gaussian", 256), ("gaussian", 100), ("sparse", 1024),
                                     ("sparse", 2048), ("sparse", 64), ("rademacher", 256),
-                                    ("rademacher", 100)])
+                                    ("rademacher", 100), ("srht", 256), ("srht", 2048),
+                                    ("srht", 30)])
 @pytest.mark.parametrize("n,c,row0", [(4097, 16, 0), (1000, 5, 31), (70000, 33, 1 << 20), (3, 1, 0)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_sketch_apply_matches_oracle(gpu_lib, kind, k, n, c, row0, dtype):
@@ -100,7 +131,9 @@ def test_sketch_apply_matches_oracle(gpu_lib, kind, k, n, c, row0, dtype):
     Xt.copy_(torch.from_numpy(X))
     got = to_np(B.sketch_apply(Xt, kind, k, seed=11, row0=row0))
     ref = th.Sketch(kind, k, seed=11).apply(X, row0=row0)
-    tol = 1e-15 * (10 + np.sqrt(n)) * abs_sketch(kind, k, 11, X, row0)
+    # the transform of the SRHT adds log2 N levels of pairwise sums
+    depth = np.sqrt(n) if kind != "srht" else np.sqrt(n) + th.ceil_log2(row0 + n)
+    tol = 1e-15 * (10 + depth) * abs_sketch(kind, k, 11, X, row0)
     assert np.all(np.abs(got - ref) <= tol)
 
 
@@ -114,7 +147,8 @@ def test_identity_sketch_copies(gpu_lib):
     assert np.array_equal(to_np(B.sketch_apply(Xt, "identity", 50, seed=0)), X)
 
 
-@pytest.mark.parametrize("kind,k", [("sparse", 1024), ("gaussian", 256), ("rademacher", 256)])
+@pytest.mark.parametrize("kind,k", [("sparse", 1024), ("gaussian", 256), ("rademacher", 256),
+                                    ("srht", 1024)])
 def test_row_shards_sum_to_the_whole(gpu_lib, kind, k):
     """Theta's columns are addressed by the global row index, so sketching G row
     ranges with their row offsets and adding the parts in a fixed order gives
@@ -127,10 +161,11 @@ def test_row_shards_sum_to_the_whole(gpu_lib, kind, k):
     X = np.random.default_rng(5).standard_normal((n, c))
     Xt = B.colmajor(n, c, torch.float64)
     Xt.copy_(torch.from_numpy(X))
-    whole = to_np(B.sketch_apply(Xt, kind, k, seed=21))
+    z = th.ceil_log2(n) if kind == "srht" else None   # one SRHT size for every range
+    whole = to_np(B.sketch_apply(Xt, kind, k, seed=21, zeta=z))
     bounds = [0, 70_000, 150_123, 299_999, n]
     parts = np.zeros_like(whole)
     for a, b in zip(bounds[:-1], bounds[1:]):
-        parts += to_np(B.sketch_apply(Xt[a:b], kind, k, seed=21, row0=a))
+        parts += to_np(B.sketch_apply(Xt[a:b], kind, k, seed=21, row0=a, zeta=z))
     tol = 1e-15 * (10 + np.sqrt(n)) * abs_sketch(kind, k, 21, X, 0)
     assert np.all(np.abs(parts - whole) <= tol)

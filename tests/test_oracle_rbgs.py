@@ -42,7 +42,7 @@ def test_identity_sketch_equals_householder_qr(variant, ls, iters, n, m, b):
 
 
 # -- the exact-arithmetic closed form -----------------------------------------
-@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher", "srht"])
 def test_closed_form_well_conditioned(kind):
     W = svd_matrix(10_000, 64, np.logspace(0, -2, 64), seed=5)
     th = Sketch(kind, 256, seed=17).materialize(W.shape[0])

@@ -99,6 +99,72 @@ def test_rademacher_entries_distribution():
     assert np.allclose(np.abs(T), 1 / 8.0, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("N", [1, 2, 16, 1024])
+def test_fwht_equals_scipy_hadamard(N):
+    """The butterfly transform against scipy's Sylvester-construction
+    Hadamard matrix (an independent implementation of H)."""
+    import scipy.linalg as sla
+    X = np.random.default_rng(N).integers(-50, 50, size=(N, 3)).astype(np.float64)
+    assert np.array_equal(th.fwht(X), sla.hadamard(N) @ X)
+
+
+def test_srht_signs_and_samples_by_pure_python():
+    """d_r is bit r % 128 of the call (r // 128, 0, 0) and s_j the top L bits of
+    word j % 4 of the call (j // 4, 0, 1): checked with plain integer code."""
+    from oracle.philox import philox4x32_10, split_seed
+    seed = 0xFEEDFACE12345
+    k0, k1 = split_seed(seed)
+    tag = np.uint32(th.TAG_SRHT)
+    rows = [0, 1, 127, 128, 5000, 2**32 + 77, 2**35 + 3]
+    d = th.srht_signs(np.array(rows, dtype=np.uint64), seed)
+    for r, dr in zip(rows, d):
+        q = r >> 7
+        w = philox4x32_10(np.uint32(q & 0xFFFFFFFF), np.uint32(q >> 32), np.uint32(0), tag, k0, k1)
+        big = sum(int(x) << (32 * e) for e, x in enumerate(w))
+        assert dr == (-1.0 if (big >> (r & 127)) & 1 else 1.0)
+    for L in (1, 10, 20, 32):
+        s = th.srht_samples(9, L, seed)
+        for j in range(9):
+            w = philox4x32_10(np.uint32(j >> 2), np.uint32(0), np.uint32(1), tag, k0, k1)
+            assert int(s[j]) == int(w[j & 3]) >> (32 - L)
+
+
+def test_srht_distribution_and_unbiasedness():
+    """Signs balanced, samples uniform on [0, 2^L); E[Theta^T Theta] = I
+    (Monte Carlo over seeds; exact expectation of the definition)."""
+    d = th.srht_signs(np.arange(200_000), seed=3)
+    assert abs(d.mean()) < 5 / np.sqrt(d.size)
+    s = th.srht_samples(100_000, 6, seed=4)
+    counts = np.bincount(s.astype(np.int64), minlength=64)
+    chi = ((counts - counts.mean())**2 / counts.mean()).sum()
+    assert st.chi2.sf(chi, 63) > 1e-4
+    n, k, reps = 6, 4, 3000
+    acc = np.zeros((n, n))
+    for rep in range(reps):
+        T = th.Sketch("srht", k, seed=1000 + rep).dense(n)
+        acc += T.T @ T
+    acc /= reps
+    # each entry of Theta^T Theta is a mean of k products of +-1/k; its
+    # standard deviation over seeds is <= 1/sqrt(k)
+    assert np.max(np.abs(acc - np.eye(n))) < 5 / np.sqrt(k * reps)
+    T = th.Sketch("srht", 64, seed=3).dense(100)
+    assert np.allclose(np.abs(T), 1 / 8.0, rtol=0, atol=0)
+
+
+def test_srht_zero_padding_and_explicit_size():
+    """Zero padding: the sketch of n rows with transform size 2^L equals the
+    same rows embedded in any larger power of two only if L is the same; a
+    given L (zeta) fixes Theta for every row range."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((3000, 4))
+    S = th.Sketch("srht", 64, seed=9, zeta=13)
+    whole = S.apply(X)
+    parts = S.apply(X[:1234], row0=0) + S.apply(X[1234:], row0=1234)
+    assert np.allclose(parts, whole, rtol=0, atol=1e-12 * np.abs(X).sum())
+    T = S.dense(3000)
+    assert np.allclose(T @ X, whole, rtol=0, atol=1e-12 * np.abs(X).sum())
+
+
 def test_sparse_sign_structure():
     n, k, zeta = 20000, 1024, 8
     idx, sgn = th.sparse_sign_entries(np.arange(n), k, zeta, seed=99)
@@ -118,12 +184,13 @@ def test_sparse_sign_structure():
     assert np.all((T != 0).sum(axis=0) == 8)
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher", "srht"])
 def test_apply_matches_dense(kind):
     n, k, c = 3000, 64, 5
     rng = np.random.default_rng(4)
     X = rng.standard_normal((n, c))
-    S = th.Sketch(kind, k, seed=11, chunk_rows=700)
+    # (the SRHT transform size is fixed explicitly so row ranges share Theta)
+    S = th.Sketch(kind, k, seed=11, chunk_rows=700, zeta=12 if kind == "srht" else None)
     T = S.dense(n)
     got = S.apply(X)
     assert np.allclose(got, T @ X, rtol=0, atol=1e-12 * np.abs(T) .sum(axis=1).max() * np.abs(X).max())
@@ -134,7 +201,7 @@ def test_apply_matches_dense(kind):
 
 def test_frobenius_norm_of_theta():
     """Corollary on ||Theta||_F: E||Theta||_F^2 = n for every operator (exact for
-    the sparse sign and the Rademacher matrix)."""
+    the sparse sign, the Rademacher matrix and the SRHT)."""
     n = 4000
     Tg = th.Sketch("gaussian", 128, seed=5).dense(n)
     fro2 = (Tg**2).sum()
@@ -143,9 +210,11 @@ def test_frobenius_norm_of_theta():
     assert abs((Ts**2).sum() - n) < 1e-9
     Tr = th.Sketch("rademacher", 128, seed=5).dense(n)
     assert abs((Tr**2).sum() - n) < 1e-9
+    Th = th.Sketch("srht", 128, seed=5).dense(n)
+    assert abs((Th**2).sum() - n) < 1e-9
 
 
-@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse", "rademacher", "srht"])
 def test_subspace_embedding_distortion(kind):
     """For a fixed d-dimensional subspace and k = 8d the singular values of
     Theta U (U orthonormal) lie in a band of width about sqrt(d/k) around 1, as
