@@ -114,6 +114,43 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
     return dict(ms=ms, alg_GBps=gbs, **acc), upd
 
 
+def post_form(W, p, kind, k, seed, reps=3):
+    """Cholesky-QR post-processing of the headline factorization: ms per call
+    (HIP events on the call's stream) and the l2 orthogonality of Q before
+    and after."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    n, m = W.shape
+    Q0 = B.colmajor(n, m, W.dtype, W.device)
+    R0 = B.colmajor(m, m, torch.float64, W.device)
+    B.rbgs_qr(W, p, kind, k, seed, None, "lowsync", LS_ITERS, Q=Q0, R=R0)
+    Q = B.colmajor(n, m, W.dtype, W.device)
+    R = B.colmajor(m, m, torch.float64, W.device)
+    torch.cuda.synchronize()
+
+    def orth(X):
+        Xd = X.double()
+        return float(torch.linalg.matrix_norm(torch.eye(m, dtype=torch.float64, device=X.device)
+                                              - Xd.t() @ Xd))
+    before = orth(Q0)
+    stream = torch.cuda.Stream()
+    times = []
+    with torch.cuda.stream(stream):
+        for _ in range(reps + 1):
+            Q.copy_(Q0)
+            R.copy_(R0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            B.cholqr_post(Q, R, check=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+    after = orth(Q)
+    err = float(torch.linalg.matrix_norm(W.double() - Q.double() @ R) / torch.linalg.matrix_norm(W.double()))
+    return dict(ms=sorted(times[1:])[len(times[1:]) // 2], orth_before=before, orth_after=after,
+                rel_err_after=err)
+
+
 def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
     """Per-class kernel milliseconds per QR (events around every launch; run
     after the timed region because the events themselves cost time)."""
@@ -333,6 +370,13 @@ def main():
         forms["f32_sparse_plain"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "plain",
                                                  max(3, args.steps // 4), 1)
         forms["f64_sparse_plain"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "plain",
+                                                 max(3, args.steps // 4), 1)
+        print("[bench] Cholesky-QR post-processing", file=sys.stderr, flush=True)
+        forms["post_cholqr_f32"] = post_form(W32, p, "sparse", k, THETA_SEED_LARGE)
+        print("[bench] SRHT sketch", file=sys.stderr, flush=True)
+        forms["f32_srht_lowsync"], _ = time_form(W32, p, "srht", k, THETA_SEED_LARGE, "lowsync",
+                                                 max(3, args.steps // 4), 1)
+        forms["f64_srht_lowsync"], _ = time_form(W64, p, "srht", k, THETA_SEED_LARGE, "lowsync",
                                                  max(3, args.steps // 4), 1)
         print("[bench] two-pass inter-block forms", file=sys.stderr, flush=True)
         forms["f32_sparse_twice"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "twice",

@@ -275,6 +275,23 @@ RBGS_API rbgs_status rbgs_block_gmres(rbgs_handle h, const rbgs_csr* A, const do
                                       double tol, const rbgs_sketch* sk, const rbgs_opts* opts,
                                       int64_t* iters, double* relres, double* history);
 
+/* Cholesky-QR post-processing of a factorization W = Q R (the remark on
+ * post-processing in Section 2.2): R' = upper Cholesky factor of Q^T Q (FP64,
+ * Gram matrix on FP64 matrix cores), then Q <- Q R'^{-1} (block substitution,
+ * FP64 arithmetic) and R <- R' R.  For the well-conditioned Q that RBGS
+ * returns, the new Q is orthonormal in the l2 sense to about u cond(Q)^2 (plus
+ * the rounding of the storage type) and W = Q R still holds.
+ *   store  rbgs_store of Q.
+ *   Q      device, n x m (ld ldq >= n), overwritten.
+ *   R      device, m x m FP64 upper triangular (ld ldr >= m), overwritten.
+ *   breakdown_col  host or NULL: if given, the call waits for the stream and
+ *          stores the first pivot j at which Q^T Q was not positive definite
+ *          (-1 if none; then RBGS_EBREAKDOWN is returned).
+ * 1 <= m <= min(n, 8192).  Enqueued on `stream`. */
+RBGS_API rbgs_status rbgs_cholqr_post(rbgs_handle h, int32_t store, void* Q, int64_t ldq, int64_t n,
+                                      int64_t m, double* R, int64_t ldr, int64_t* breakdown_col,
+                                      void* stream);
+
 /* Sketch of a block of rows: out = Theta[:, row0:row0+n] X (Section 1.3), the
  * operation of steps 1 and 5 of Algorithm RBGS.
  *   X   device, n x c (ld ldx >= n), element type `store` (rbgs_store).

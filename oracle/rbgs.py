@@ -163,6 +163,15 @@ def certificates(S, P, R):
     return float(delta), float(delta_tilde)
 
 
+def cholqr_post(Q, R):
+    """Cholesky-QR post-processing (remark on post-processing, Section 2.2):
+    R' = upper Cholesky factor of Q^T Q, Q <- Q R'^{-1} (substitution),
+    R <- R' R."""
+    Rp = np.linalg.cholesky(Q.T @ Q).T
+    Qn = sla.solve_triangular(Rp.T, Q.T, lower=True).T
+    return Qn, Rp @ R
+
+
 def rbgs_closed_form(W, theta):
     """Exact-arithmetic result of RBGS for full-rank W: Theta W = (Theta Q) R with
     Theta Q orthonormal, so R is the positive-diagonal R factor of Theta W and

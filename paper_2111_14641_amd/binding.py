@@ -81,6 +81,7 @@ _SIGNATURES = {
     "rbgs_sketch_apply": ([_P, ctypes.POINTER(rbgs_sketch), _I32, _P, _I64, _I64, _I64, _I64, _P,
                            _I64, _P], ctypes.c_int),
     "rbgs_theta_dense": ([_P, ctypes.POINTER(rbgs_sketch), _I64, _I64, _P, _P], ctypes.c_int),
+    "rbgs_cholqr_post": ([_P, _I32, _P, _I64, _I64, _I64, _P, _I64, _P, _P], ctypes.c_int),
     "rbgs_profile_enable": ([_P, _I32], ctypes.c_int),
     "rbgs_profile_get": ([_P, _I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -148,6 +149,9 @@ class Library:
 
     def rbgs_theta_dense(self, h, sk, n, row0, out, stream):
         return self.lib.rbgs_theta_dense(h, ctypes.byref(sk), n, row0, out, stream)
+
+    def rbgs_cholqr_post(self, h, store, Q, ldq, n, m, R, ldr, breakdown, stream):
+        return self.lib.rbgs_cholqr_post(h, store, Q, ldq, n, m, R, ldr, breakdown, stream)
 
     def rbgs_profile_enable(self, h, enable):
         return self.lib.rbgs_profile_enable(h, int(enable))
@@ -389,6 +393,23 @@ def block_gmres(A, B, X0=None, blocks_per_cycle=40, max_cycles=10, tol=1e-8, kin
         lib.check(st, h)
     history = [v for v in hist if v >= 0.0]
     return X, iters.value, rel.value, history, st == RBGS_OK
+
+
+def cholqr_post(Q, R, check=True):
+    """Cholesky-QR post-processing in place: Q <- Q R'^{-1}, R <- R' R with
+    R'^T R' = Q^T Q.  With check=True waits and raises on a breakdown."""
+    torch = _torch()
+    lib = Library.get()
+    n, m = Q.shape
+    store = "f64" if Q.dtype == torch.float64 else "f32"
+    h = lib.handle(Q.device.index or 0)
+    qp, ldq = as_colmajor(Q)
+    rp, ldr = as_colmajor(R)
+    bc = ctypes.c_int64(-1)
+    st = lib.rbgs_cholqr_post(h, STORE[store], qp, ldq, n, m, rp, ldr,
+                              ctypes.byref(bc) if check else None, _stream_ptr(Q))
+    lib.check(st, h)
+    return Q, R
 
 
 def sketch_apply(X, kind, k, seed, zeta=None, row0=0, out=None):

@@ -1199,6 +1199,60 @@ rbgs_status rbgs_block_gmres(rbgs_handle h, const rbgs_csr* A, const double* B, 
   return RBGS_OK;
 }
 
+rbgs_status rbgs_cholqr_post(rbgs_handle h, int32_t store, void* Q, int64_t ldq, int64_t n,
+                             int64_t m, double* R, int64_t ldr, int64_t* breakdown_col,
+                             void* stream) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  if (!Q || !R) return fail(h, RBGS_EINVAL, "Q and R must be non-NULL");
+  if (n < 1 || m < 1 || m > n) return fail(h, RBGS_EINVAL, "need 1 <= m <= n");
+  if (m > 8192) return fail(h, RBGS_EUNSUPPORTED, "m > 8192 is not implemented");
+  if (ldq < n || ldr < m) return fail(h, RBGS_EINVAL, "bad leading dimension");
+  if (store != RBGS_STORE_F64 && store != RBGS_STORE_F32) return fail(h, RBGS_EINVAL, "unknown storage type");
+  const bool f32 = store == RBGS_STORE_F32;
+  const size_t es = f32 ? 4 : 8;
+  {
+    const char* q0 = (const char*)Q;
+    const char* q1 = q0 + es * (size_t)(ldq * (m - 1) + n);
+    const char* r0 = (const char*)R;
+    const char* r1 = r0 + 8 * (size_t)(ldr * (m - 1) + m);
+    if (r0 < q1 && q0 < r1) return fail(h, RBGS_EINVAL, "R overlaps Q");
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  const size_t mm = (size_t)m * m;
+  const size_t part = (size_t)gram_splits(n, m) * mm;
+  auto r256 = [](size_t doubles) { return ((doubles * 8 + 255) / 256) * 256; };
+  rbgs_status rs = ensure_ws(h, r256(part) + 2 * r256(mm) + 256);
+  if (rs != RBGS_OK) return rs;
+  char* base = (char*)h->ws;
+  double* partial = (double*)base;
+  double* G = (double*)(base + r256(part));
+  double* T = (double*)(base + r256(part) + r256(mm));
+  int64_t* flag = (int64_t*)(base + r256(part) + 2 * r256(mm));
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(h, launch_set_i64(flag, -1, st), "flag");
+  HIP_TRY(h, launch_gram(f32, Q, ldq, n, m, partial, G, st), "gram");
+  HIP_TRY(h, launch_cholesky(G, m, flag, st), "cholesky");
+  // Q <- Q R'^{-1} block column by block column: X_b = (Q_b - X_(1:b-1) R'_(1:b-1,b)) R'_bb^{-1}
+  for (int64_t b0 = 0; b0 < m; b0 += 16) {
+    const int bw = (int)std::min<int64_t>(16, m - b0);
+    char* Qb = (char*)Q + es * (size_t)(b0 * ldq);
+    HIP_TRY(h, launch_update(f32, false, Qb, ldq, Q, ldq, Qb, ldq, G + b0 * m, G + b0 + b0 * m, m, n,
+                             b0, bw, st),
+            "substitution");
+  }
+  HIP_TRY(h, launch_trmm_full(G, m, R, ldr, m, T, st), "R' R");
+  if (!breakdown_col) return RBGS_OK;
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+          "copy flag");
+  HIP_TRY(h, hipStreamSynchronize(st), "stream synchronize");
+  memcpy(breakdown_col, h->host_cert + 4, sizeof(int64_t));
+  if (*breakdown_col >= 0) return fail(h, RBGS_EBREAKDOWN, "Q^T Q is not positive definite in FP64");
+  return RBGS_OK;
+}
+
 rbgs_status rbgs_sketch_apply(rbgs_handle h, const rbgs_sketch* sk, int32_t store, const void* X,
                               int64_t ldx, int64_t n, int64_t c, int64_t row0, double* out,
                               int64_t ldo, void* stream) {

@@ -272,6 +272,17 @@ hipError_t launch_qr_tall(bool f32, const void* src, int64_t ld, int64_t rows, i
 // R <- A R for upper triangular bw x bw A and R (upper triangles only).
 hipError_t launch_trmm_upper(const double* A, int64_t lda, double* R, int64_t ldr, int bw,
                              hipStream_t st);
+// Cholesky-QR post-processing pieces.
+// Row splits of the Gram kernel (partial buffer: gram_splits(n, m) * m * m doubles).
+int gram_splits(int64_t n, int64_t m);
+// G = Q^T Q (m x m FP64, ld m, symmetric) of the n x m matrix Q (FP32 or FP64).
+hipError_t launch_gram(bool f32, const void* Q, int64_t ldq, int64_t n, int64_t m, double* partial,
+                       double* G, hipStream_t st);
+// In place: A (m x m, ld m, SPD) <- its upper Cholesky factor; flag as above.
+hipError_t launch_cholesky(double* A, int64_t m, int64_t* flag, hipStream_t st);
+// R <- A R for upper triangular m x m A and R; T: m x m scratch.
+hipError_t launch_trmm_full(const double* A, int64_t lda, double* R, int64_t ldr, int64_t m,
+                            double* T, hipStream_t st);
 hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 // Fill an m x m column-major matrix (ld) with zeros.
 hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);

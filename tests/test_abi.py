@@ -117,3 +117,14 @@ def test_batched_validation_on_host(lib_and_handle):
                              ctypes.byref(k)) == B.RBGS_EINVAL
     assert lib.rbgs_autotune(h, 100, 20, None, ctypes.byref(op), ctypes.byref(p),
                              ctypes.byref(k)) == B.RBGS_EINVAL
+
+
+def test_cholqr_post_validation_on_host(lib_and_handle):
+    lib, h = lib_and_handle
+    assert lib.rbgs_cholqr_post(h, 0, None, 10, 10, 4, 0x200000, 4, None, None) == B.RBGS_EINVAL
+    assert lib.rbgs_cholqr_post(h, 0, 0x1000, 10, 10, 11, 0x200000, 11, None, None) == B.RBGS_EINVAL
+    assert lib.rbgs_cholqr_post(h, 0, 0x1000, 5, 10, 4, 0x200000, 4, None, None) == B.RBGS_EINVAL
+    assert lib.rbgs_cholqr_post(h, 3, 0x1000, 10, 10, 4, 0x200000, 4, None, None) == B.RBGS_EINVAL
+    assert lib.rbgs_cholqr_post(h, 0, 0x1000, 10, 10, 4, 0x1000 + 8, 4, None, None) == B.RBGS_EINVAL
+    assert lib.rbgs_cholqr_post(h, 0, 0x1000, 20000, 20000, 9000, 0x9000000000, 9000, None,
+                                None) == B.RBGS_EUNSUPPORTED

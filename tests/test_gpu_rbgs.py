@@ -197,6 +197,54 @@ def test_second_pass_restores_sketched_orthogonality(gpu_lib, decades):
         assert rel(R, o["R"]) < 1e-13 * 10.0**(decades / 2)
 
 
+@pytest.mark.parametrize("n,m,b,store", [(10_000, 64, 8, "f64"), (7777, 70, 16, "f64"),
+                                         (10_000, 64, 8, "f32"), (3000, 200, 16, "f64")])
+def test_cholqr_post_processing(gpu_lib, n, m, b, store):
+    """Post-processing on the GPU against the oracle's on the same RBGS output
+    (FP64: elementwise; the Gram matrix and the Cholesky factor differ only in
+    summation order) and against LAPACK's QR of W."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    W = svd_matrix(n, m, np.logspace(0, -3, m), seed=n + m)
+    if store == "f32":
+        W = W.astype(np.float32).astype(np.float64)
+    say("cholqr post", n, m, b, store)
+    dt = torch.float64 if store == "f64" else torch.float32
+    Wt = B.colmajor(n, m, dt)
+    Wt.copy_(torch.from_numpy(W))
+    Q, R, _, _ = B.rbgs_qr(Wt, b, "sparse", 4 * m, 5, None, "lowsync", 4, want_cert=True)
+    torch.cuda.synchronize()
+    Q0 = np.ascontiguousarray(Q.cpu().numpy()).astype(np.float64)
+    R0 = R.cpu().numpy().astype(np.float64)
+    B.cholqr_post(Q, R)
+    torch.cuda.synchronize()
+    Qg = np.ascontiguousarray(Q.cpu().numpy()).astype(np.float64)
+    Rg = R.cpu().numpy().astype(np.float64)
+    Qo, Ro = orb.cholqr_post(Q0, R0)
+    u = 2.0**-53 if store == "f64" else 2.0**-24
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0)
+    assert np.linalg.norm(np.eye(m) - Qg.T @ Qg) < 100 * u * m
+    assert factorization_error(W, Qg, Rg) < 100 * u * m
+    tol = 1e-12 if store == "f64" else 64 * u
+    assert rel(Rg, Ro) < tol
+    assert rel(Qg, Qo) < tol
+    Qh, Rh = np.linalg.qr(W)
+    d = np.sign(np.diag(Rh))
+    assert rel(Rg, d[:, None] * Rh) < (1e-12 if store == "f64" else 1e-5)
+
+
+def test_cholqr_post_breakdown(gpu_lib):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("cholqr post breakdown")
+    Q = B.colmajor(500, 6, torch.float64)
+    Q.copy_(torch.from_numpy(np.random.default_rng(0).standard_normal((500, 6))))
+    Q[:, 3] = 0.0
+    R = torch.eye(6, dtype=torch.float64, device="cuda").t().contiguous().t()
+    with pytest.raises(RuntimeError, match="positive definite"):
+        B.cholqr_post(Q, R)
+
+
 def test_determinism_and_in_place(gpu_lib, small):
     say("determinism")
     a = gpu_qr(small, 8, "sparse", 256, 5, "lowsync")

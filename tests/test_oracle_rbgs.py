@@ -158,6 +158,23 @@ def test_second_pass_restores_sketched_orthogonality(decades):
     assert np.linalg.norm(R2 - np.eye(16)) < 100 * U64 * 10.0**decades
 
 
+def test_cholqr_post_processing_gives_householder_qr():
+    """Post-processing (remark in Section 2.2): after RBGS, Cholesky QR of the
+    well-conditioned Q gives an l2-orthonormal Q, keeps W = Q R, and -- QR
+    with positive diagonal being unique -- reproduces LAPACK's Householder
+    QR of W."""
+    W = svd_matrix(6000, 40, np.logspace(0, -3, 40), seed=12)
+    th = Sketch("gaussian", 160, seed=13).materialize(6000)
+    out = orb.rbgs(W, 8, th, "lowsync")
+    Qn, Rn = orb.cholqr_post(out["Q"], out["R"])
+    Qh, Rh = lapack_qr_posdiag(W)
+    assert np.linalg.norm(np.eye(40) - Qn.T @ Qn) < 50 * U64 * 40
+    assert factorization_error(W, Qn, Rn) < 10 * U64 * 40
+    assert rel(Rn, Rh) < 1e-13
+    assert rel(Qn, Qh) < 1e-12
+    assert np.all(np.tril(Rn, -1) == 0) and np.all(np.diag(Rn) > 0)
+
+
 def test_ragged_last_block():
     W = svd_matrix(5000, 30, np.logspace(0, -3, 30), seed=9)
     th = Sketch("sparse", 128, seed=2).materialize(5000)
