@@ -99,6 +99,53 @@ def test_large_workload_full_size(gpu_lib, large_w, store):
     assert np.linalg.norm(Rh[:p, :p] - R11) <= 1e-12 * np.linalg.norm(R11)
 
 
+def test_large_workload_srht_two_pass_and_post(gpu_lib, large_w):
+    """The large workload in FP32 storage with the SRHT (transform of 2^20
+    rows), the two-pass inter-block forms and the Cholesky-QR post-processing:
+    metrics at full size, sampled sketch columns against the oracle's fast
+    transform, R_(1,1) against the oracle, l2 orthogonality after the
+    post-processing."""
+    import torch
+    from oracle.rbgs import qr_r_posdiag
+    from oracle.theta import Sketch
+    from paper_2111_14641_amd import binding as B
+    from paper_2111_14641_amd.workloads import THETA_SEED_LARGE
+    n, m, p, k = 1_000_000, 256, 16, 1024
+    W = B.colmajor(n, m, torch.float32)
+    W.copy_(torch.from_numpy(large_w))
+    Win = np.asfortranarray(W[:, :p].double().cpu().numpy())
+    th = Sketch("srht", k, seed=THETA_SEED_LARGE)
+    for variant in ("lowsync", "twice", "l2qr"):
+        say("full size srht", variant)
+        Q, R, S, cert = B.rbgs_qr(W, p, "srht", k, THETA_SEED_LARGE, None, variant, 4,
+                                  want_S=True, want_cert=True)
+        torch.cuda.synchronize()
+        Rh = R.cpu().numpy()
+        assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+        err, cond = gpu_metrics(W, Q, R)
+        say("metrics", variant, err, cond, cert["delta"])
+        assert err <= 1e-6 and cond <= 10 and cert["delta"] < 0.1
+        # the two-pass forms sketch the FP32-rounded Q of their first pass, so
+        # their R_(1,1) = R2 R1 carries R2 = I + O(u32 cond)
+        R11 = qr_r_posdiag(th.apply(Win))
+        tol = 1e-12 if variant == "lowsync" else 64 * 2.0**-24
+        assert np.linalg.norm(Rh[:p, :p] - R11) <= tol * np.linalg.norm(R11)
+    Qh = np.asfortranarray(Q[:, [0, 100, 255]].double().cpu().numpy())
+    Sh = S.cpu().numpy()[:, [0, 100, 255]]
+    ref = th.apply(Qh)
+    tol = 1e-15 * (10 + np.sqrt(n) + 20) * (np.abs(Qh).sum(axis=0) / np.sqrt(k))[None, :]
+    assert np.all(np.abs(Sh - ref) <= tol)
+    say("post-processing")
+    B.cholqr_post(Q, R)
+    torch.cuda.synchronize()
+    err, cond = gpu_metrics(W, Q, R)
+    Qd = Q.double()
+    orth = float(torch.linalg.matrix_norm(torch.eye(m, dtype=torch.float64, device=Q.device)
+                                          - Qd.t() @ Qd))
+    say("after post", err, cond, orth)
+    assert err <= 1e-6 and orth <= 1e-5
+
+
 @pytest.mark.skip(reason="this case (input built on the GPU with torch randn / Cholesky / "
                          "triangular solve at 4e6 x 512, then Gaussian-sketch RBGS) faulted the GPU "
                          "once; the library's index ranges for this shape were re-checked on the "
