@@ -56,6 +56,9 @@ struct rbgs_handle_s {
   size_t kry_bytes = 0;
   // autotuner: (m, ceil log2 n, store, math, kind, variant) -> (p, k)
   std::vector<std::pair<std::vector<int64_t>, std::pair<int64_t, int64_t>>> tuned;
+  // lock-step batches: workspace of every problem and the device descriptors
+  void* bws = nullptr;
+  size_t bws_bytes = 0;
 };
 
 namespace {
@@ -313,7 +316,7 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
   if (!h) return RBGS_OK;
   for (auto c : h->lanes) rbgs_destroy(c);
   if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side ||
-      !h->lane_streams.empty() || h->graph || h->kry) {
+      !h->lane_streams.empty() || h->graph || h->kry || h->bws) {
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
     for (auto& r : h->recs) {
@@ -328,6 +331,7 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->kry) (void)hipFree(h->kry);
+    if (h->bws) (void)hipFree(h->bws);
     if (h->ws) (void)hipFree(h->ws);
     if (h->host_cert) (void)hipHostFree(h->host_cert);
   }
@@ -722,12 +726,206 @@ double batch_bytes(const rbgs_problem& pr, size_t es) {
 }
 
 // Enqueue every problem on its lane; lanes fork from and join back to st.
+// ---------------------------------------------------------------------------
+// Lock-step groups: problems with the same m, p and k (low-sync form, sparse
+// sign, p <= 16, k <= 1024) advance block by block together, each kernel of
+// a block step launched once for the whole group over a device array of
+// per-problem descriptors (pointers, n, seed, prefix sums of the flattened
+// grids).  The descriptors and every problem's workspace live in the
+// handle's batch arena, laid out and uploaded before anything is enqueued.
+// ---------------------------------------------------------------------------
+struct LockGroup {
+  std::vector<int64_t> idx;   // problem indices
+  int64_t m = 0, p = 0, k = 0;
+  BatchItem* items = nullptr; // device array in the arena
+  int64_t plan_tiles = 0, up_tiles = 0, sk_wgs = 0;
+};
+
+bool lockstep_ok(const rbgs_problem& pr, const rbgs_sketch* sk, const rbgs_opts* opts) {
+  return opts->variant == RBGS_VARIANT_LOWSYNC && sk->kind == RBGS_SKETCH_SPARSE_SIGN &&
+         pr.p <= 16 && pr.k <= 1024;
+}
+
+// Groups, arena layout and descriptor upload (waits for the copy).
+rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* probs,
+                           const rbgs_sketch* sk, const rbgs_opts* opts,
+                           std::vector<LockGroup>& groups, std::vector<int64_t>& rest) {
+  groups.clear();
+  rest.clear();
+  for (int64_t i = 0; i < count; ++i) {
+    const rbgs_problem& pr = probs[i];
+    if (!lockstep_ok(pr, sk, opts)) {
+      rest.push_back(i);
+      continue;
+    }
+    LockGroup* g = nullptr;
+    for (auto& gg : groups)
+      if (gg.m == pr.m && gg.p == pr.p && gg.k == pr.k) g = &gg;
+    if (!g) {
+      groups.emplace_back();
+      g = &groups.back();
+      g->m = pr.m;
+      g->p = pr.p;
+      g->k = pr.k;
+    }
+    g->idx.push_back(i);
+  }
+  // groups of one problem gain nothing: run them on the lanes
+  for (size_t gi = 0; gi < groups.size();) {
+    if (groups[gi].idx.size() < 2) {
+      rest.push_back(groups[gi].idx[0]);
+      groups.erase(groups.begin() + gi);
+    } else {
+      ++gi;
+    }
+  }
+  if (groups.empty()) return RBGS_OK;
+  // an earlier batch may still run out of the arena: wait before it is rewritten
+  if (h->bws) HIP_TRY(h, hipDeviceSynchronize(), "synchronize before batch setup");
+  const bool f32 = opts->store == RBGS_STORE_F32;
+  const int64_t tile_rows = update_tile_rows(f32);
+  auto r256 = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
+  size_t off = 0;
+  std::vector<std::vector<BatchItem>> host(groups.size());
+  std::vector<size_t> items_off(groups.size());
+  std::vector<std::vector<size_t>> offs(groups.size());  // per problem: 11 buffer offsets
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    LockGroup& g = groups[gi];
+    const int64_t np = (int64_t)g.idx.size();
+    items_off[gi] = off;
+    off += r256(sizeof(BatchItem) * (size_t)np);
+    host[gi].resize(np);
+    const int64_t target_g = std::max<int64_t>(4, (1024 + np - 1) / np);
+    for (int64_t q = 0; q < np; ++q) {
+      const int64_t i = g.idx[q];
+      const rbgs_problem& pr = probs[i];
+      BatchItem& it = host[gi][q];
+      memset(&it, 0, sizeof it);
+      rbgs_sketch ski = *sk;
+      ski.k = pr.k;
+      ski.seed = sk->seed + (uint64_t)i;
+      const SketchDesc d = make_desc(&ski, pr.n);
+      const int64_t tiles = sparse_plan_tiles(pr.n);
+      const int64_t G = std::min<int64_t>(tiles, target_g);
+      const int64_t tpw = (tiles + G - 1) / G;
+      it.W = pr.W;
+      it.Q = pr.Q;
+      it.n = pr.n;
+      it.ldw = pr.ldw;
+      it.ldq = pr.ldq;
+      it.ldr = pr.ldr;
+      it.R = pr.R;
+      it.key0 = d.key0;
+      it.key1 = d.key1;
+      it.plan_tile0 = g.plan_tiles;
+      g.plan_tiles += tiles;
+      it.up_tile0 = g.up_tiles;
+      const int64_t ut = (pr.n + tile_rows - 1) / tile_rows;
+      it.up_nfull = update_vec_ok(f32, pr.Q, pr.ldq) ? pr.n / tile_rows : 0;
+      g.up_tiles += ut;
+      it.sk_wg0 = g.sk_wgs;
+      it.sk_G = (int32_t)G;
+      it.sk_tpw = tpw;
+      g.sk_wgs += G;
+      const int64_t m = g.m, k = g.k, b = g.p;
+      std::vector<size_t> o;
+      for (size_t doubles : {(size_t)(k * m), (size_t)(k * m), (size_t)(k * b), (size_t)(m * m),
+                             (size_t)(m * b), (size_t)(m * b), (size_t)(G * k * m), (size_t)1}) {
+        o.push_back(off);
+        off += r256(doubles * 8);
+      }
+      o.push_back(off);  // plan
+      off += r256(sparse_plan_bytes(d, pr.n));
+      o.push_back((size_t)plan_offsets_len(d, pr.n));  // entry offset (elements)
+      offs[gi].insert(offs[gi].end(), o.begin(), o.end());
+    }
+  }
+  if (off > h->bws_bytes) {
+    if (h->bws) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(h->bws);
+      h->bws = nullptr;
+      h->bws_bytes = 0;
+    }
+    if (hipMalloc(&h->bws, off) != hipSuccess) {
+      (void)hipGetLastError();
+      h->bws = nullptr;
+      return fail(h, RBGS_ENOMEM, "batch workspace of " + std::to_string(off) + " bytes");
+    }
+    h->bws_bytes = off;
+  }
+  char* base = (char*)h->bws;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    LockGroup& g = groups[gi];
+    const size_t np = g.idx.size();
+    for (size_t q = 0; q < np; ++q) {
+      BatchItem& it = host[gi][q];
+      const size_t* o = &offs[gi][q * 10];
+      it.S = (double*)(base + o[0]);
+      it.P = (double*)(base + o[1]);
+      it.E = (double*)(base + o[2]);
+      it.G = (double*)(base + o[3]);
+      it.Cb = (double*)(base + o[4]);
+      it.Yb = (double*)(base + o[5]);
+      it.part = (double*)(base + o[6]);
+      it.flag = (int64_t*)(base + o[7]);
+      uint16_t* plan = (uint16_t*)(base + o[8]);
+      it.plan_off_w = plan;
+      it.plan_ent_w = plan + o[9];
+      it.plan_off = plan;
+      it.plan_ent = plan + o[9];
+    }
+    g.items = (BatchItem*)(base + items_off[gi]);
+    HIP_TRY(h, hipMemcpy(g.items, host[gi].data(), sizeof(BatchItem) * np, hipMemcpyHostToDevice),
+            "upload batch descriptors");
+  }
+  return RBGS_OK;
+}
+
+// Enqueue one lock-step group on st.
+rbgs_status enqueue_group(rbgs_handle h, const LockGroup& g, const rbgs_sketch* sk,
+                          const rbgs_opts* opts, hipStream_t st) {
+  const bool f32 = opts->store == RBGS_STORE_F32;
+  const bool f32_math = opts->math == RBGS_MATH_F32;
+  const int np = (int)g.idx.size();
+  const int64_t m = g.m, p = g.p, k = g.k;
+  const int l = opts->ls_iters;
+  const int zeta = sk->zeta;
+  const double scale = 1.0 / sqrt((double)zeta);
+  HIP_TRY(h, launch_init_batched(g.items, np, m, st), "batch init");
+  HIP_TRY(h, launch_plan_batched(g.items, np, g.plan_tiles, (int)k, zeta, st), "batch plan");
+  HIP_TRY(h, launch_sketch_batched(f32, g.items, np, g.sk_wgs, 0, 0, m, (int)k, zeta, scale, st),
+          "batch sketch of W");
+  for (int64_t c0 = 0; c0 < m; c0 += p) {
+    const int bw = (int)std::min<int64_t>(p, m - c0);
+    const int64_t K = c0;
+    if (K > 0) {
+      HIP_TRY(h, launch_gram_sty_batched(g.items, np, k, K, bw, (int)p, m, l > 1, st),
+              "batch least squares: sketch products");
+      int cur = 0;
+      for (int it = 1; it < l; ++it) {
+        const int dst = ((l - 1 - it) & 1) == 0 ? 2 : 1;
+        HIP_TRY(h, launch_sweep_batched(g.items, np, m, K, bw, cur, dst, st), "batch sweep");
+        cur = dst;
+      }
+      HIP_TRY(h, launch_resid_batched(g.items, np, k, K, bw, st), "batch S'");
+    }
+    HIP_TRY(h, launch_qr_batched(g.items, np, k, bw, c0, st), "batch qr of sketch");
+    HIP_TRY(h, launch_update_batched(f32, f32_math, g.items, np, g.up_tiles, K, bw, st),
+            "batch update");
+    HIP_TRY(h, launch_sketch_batched(f32, g.items, np, g.sk_wgs, 1, c0, bw, (int)k, zeta, scale, st),
+            "batch sketch of Q");
+  }
+  return RBGS_OK;
+}
+
 rbgs_status enqueue_batch(rbgs_handle h, int64_t count, rbgs_problem* probs,
                           const rbgs_sketch* sk, const rbgs_opts* opts,
-                          const std::vector<std::vector<int64_t>>& lane_items) {
+                          const std::vector<std::vector<int64_t>>& lane_items,
+                          const std::vector<LockGroup>& groups) {
   hipStream_t st = (hipStream_t)opts->stream;
   const int L = (int)lane_items.size();
-  HIP_TRY(h, hipEventRecord(h->lane_ev[L], st), "event record");
+  if (L > 0) HIP_TRY(h, hipEventRecord(h->lane_ev[L], st), "event record");
   for (int l = 0; l < L; ++l)
     HIP_TRY(h, hipStreamWaitEvent(h->lane_streams[l], h->lane_ev[L], 0), "stream wait");
   for (int l = 0; l < L; ++l) {
@@ -744,6 +942,11 @@ rbgs_status enqueue_batch(rbgs_handle h, int64_t count, rbgs_problem* probs,
         return fail(h, (rbgs_status)pr.status,
                     "problem " + std::to_string(i) + ": " + h->lanes[l]->last_error);
     }
+  }
+  for (const LockGroup& g : groups) {
+    const rbgs_status rs = enqueue_group(h, g, sk, opts, st);
+    if (rs != RBGS_OK) return rs;
+    for (int64_t i : g.idx) probs[i].status = RBGS_OK;
   }
   for (int l = 0; l < L; ++l) {
     HIP_TRY(h, hipEventRecord(h->lane_ev[l], h->lane_streams[l]), "event record");
@@ -909,13 +1112,27 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
     for (int64_t i = 0; i < count; ++i) probs[i].status = RBGS_OK;
     return RBGS_OK;
   }
+  // a recorded graph refers to the batch arena, which the setup below lays out anew
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->graph_key.clear();
+  // lock-step groups on the caller's stream; the other problems on the lanes
+  std::vector<LockGroup> groups;
+  std::vector<int64_t> rest;
+  rbgs_status rs = lockstep_setup(h, count, probs, sk, opts, groups, rest);
+  if (rs != RBGS_OK) return rs;
   // largest problem first, each to the least loaded lane
-  const int L = (int)std::min<int64_t>(kBatchLanes, count);
-  rbgs_status rs = ensure_lanes(h, L);
+  const int L = (int)std::min<int64_t>(kBatchLanes, (int64_t)rest.size());
+  rs = ensure_lanes(h, std::max(L, 1));
   if (rs != RBGS_OK) return rs;
   const size_t es = opts->store == RBGS_STORE_F32 ? 4 : 8;
-  std::vector<int64_t> order(count);
-  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  std::vector<int64_t> order = rest;
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return batch_bytes(probs[a], es) > batch_bytes(probs[b], es);
   });
@@ -926,7 +1143,7 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
     lane_items[l].push_back(i);
     load[l] += batch_bytes(probs[i], es);
   }
-  rs = enqueue_batch(h, count, probs, sk, opts, lane_items);
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups);
   if (rs != RBGS_OK || !use_graph) return rs;
   // record the same enqueue sequence as a graph for later identical calls
   if (h->graph_exec) {
@@ -939,7 +1156,7 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   }
   h->graph_key.clear();
   HIP_TRY(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-  rs = enqueue_batch(h, count, probs, sk, opts, lane_items);
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(st, &g);
   if (rs != RBGS_OK) {

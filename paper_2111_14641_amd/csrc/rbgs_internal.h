@@ -175,6 +175,67 @@ struct SketchDesc {
   uint32_t key0, key1;
 };
 
+// One problem of a lock-step batch (device copy; see launch_*_batched).  The
+// problems of a batch share m, p, k, the sketch kind and the options; they
+// differ in n, the leading dimensions, the pointers and the seed.
+struct BatchItem {
+  const void* W;
+  void* Q;
+  double *R, *S, *P, *E, *G, *Cb, *Yb, *part;
+  const uint16_t* plan_off;
+  const uint16_t* plan_ent;
+  uint16_t* plan_off_w;     // the same plan, writable, for the plan kernel
+  uint16_t* plan_ent_w;
+  int64_t* flag;
+  int64_t n, ldw, ldq, ldr;
+  uint32_t key0, key1;
+  int64_t plan_tile0;       // first flattened plan tile (prefix over problems)
+  int64_t up_tile0;         // first flattened update tile
+  int64_t up_nfull;         // update tiles on the unguarded vector path
+  int64_t sk_wg0;           // first flattened sketch workgroup
+  int64_t sk_tpw;           // sketch tiles per workgroup
+  int32_t sk_G;             // sketch row groups (partial sums) of this problem
+  int32_t pad;
+};
+
+// Workgroup -> problem for flattened grids: the last problem whose prefix
+// `first(p)` is <= bx (prefixes nondecreasing, first(0) = 0).
+template <typename F>
+__device__ __forceinline__ int batch_find(int nprob, int64_t bx, F first) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(mid) <= bx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Lock-step batch launchers (all problems of `items`, nprob of them, device array).
+hipError_t launch_plan_batched(const BatchItem* items, int nprob, int64_t total_tiles, int k,
+                               int zeta, hipStream_t st);
+// which = 0: all m columns of W into P; which = 1: Q_(i) (columns c0 .. c0 + ncols) into S.
+hipError_t launch_sketch_batched(bool f32, const BatchItem* items, int nprob, int64_t total_wgs,
+                                 int which, int64_t c0, int64_t ncols, int k, int zeta,
+                                 double scale, hipStream_t st);
+hipError_t launch_gram_sty_batched(const BatchItem* items, int nprob, int64_t k, int64_t K, int bw,
+                                   int bprev, int64_t m, bool to_cb, hipStream_t st);
+// src/dst: 0 = Cb (ld K), 1 = Yb (ld K), 2 = R_(1:i-1,i) (ld ldr)
+hipError_t launch_sweep_batched(const BatchItem* items, int nprob, int64_t m, int64_t K, int bw,
+                                int src, int dst, hipStream_t st);
+hipError_t launch_resid_batched(const BatchItem* items, int nprob, int64_t k, int64_t K, int bw,
+                                hipStream_t st);
+hipError_t launch_qr_batched(const BatchItem* items, int nprob, int64_t k, int bw, int64_t c0,
+                             hipStream_t st);
+hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items, int nprob,
+                                 int64_t total_tiles, int64_t K, int bw, hipStream_t st);
+hipError_t launch_init_batched(const BatchItem* items, int nprob, int64_t m, hipStream_t st);
+// rows per update tile (for the flattened prefix) and the unguarded tile count
+int64_t update_tile_rows(bool f32);
+bool update_vec_ok(bool f32, const void* Q, int64_t ldq);
+int64_t sparse_plan_tiles(int64_t n);
+int64_t plan_offsets_len(const SketchDesc& sk, int64_t n);
+
 // Number of partial blocks (row ranges) the sketch kernels use for n rows;
 // max_groups > 0 caps it (a sketch that runs beside other work occupies fewer
 // compute units for longer).

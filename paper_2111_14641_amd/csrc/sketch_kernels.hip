@@ -66,17 +66,15 @@ __device__ __forceinline__ void block_exclusive_scan_2048(int* cnt, int* off, in
 // holds, sorted by target and, within a target, by row, the entries
 // (row-in-tile << 1) | sign_bit, and the offsets of every target's bucket.
 //   off: [ntiles][k + 1] uint16     ent: [ntiles][kSpTile * zeta] uint16
-__global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int64_t row0, int k,
-                                                                 int zeta, uint32_t key0,
-                                                                 uint32_t key1,
-                                                                 uint16_t* __restrict__ plan_off,
-                                                                 uint16_t* __restrict__ plan_ent) {
+__device__ __forceinline__ void sparse_plan_tile(int64_t n, int64_t row0, int k, int zeta,
+                                                 uint32_t key0, uint32_t key1,
+                                                 uint16_t* __restrict__ plan_off,
+                                                 uint16_t* __restrict__ plan_ent, int64_t tile) {
   __shared__ uint16_t sorted[kSpTile * kSpMaxZeta];
   __shared__ int cnt[kSpMaxK];
   __shared__ int off[kSpMaxK];
   __shared__ int cur[kSpMaxK];
   const int tid = threadIdx.x;
-  const int64_t tile = blockIdx.x;
   const int64_t tile0 = tile * kSpTile;
   const int trows = (int)min((int64_t)kSpTile, n - tile0);
   const uint32_t L = (uint32_t)(k / zeta);
@@ -139,6 +137,24 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
   for (int i = tid; i < trows * zeta; i += kSpThreads) pe[i] = sorted[i];
 }
 
+__global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int64_t row0, int k,
+                                                                 int zeta, uint32_t key0,
+                                                                 uint32_t key1,
+                                                                 uint16_t* __restrict__ plan_off,
+                                                                 uint16_t* __restrict__ plan_ent) {
+  sparse_plan_tile(n, row0, k, zeta, key0, key1, plan_off, plan_ent, blockIdx.x);
+}
+
+// Lock-step batch: flattened tiles of all problems.
+__global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const BatchItem* items,
+                                                                         int nprob, int k,
+                                                                         int zeta) {
+  const int p = batch_find(nprob, blockIdx.x, [&](int q) { return items[q].plan_tile0; });
+  const BatchItem& it = items[p];
+  sparse_plan_tile(it.n, 0, k, zeta, it.key0, it.key1, it.plan_off_w, it.plan_ent_w,
+                   (int64_t)blockIdx.x - it.plan_tile0);
+}
+
 // Sparse-sign partial sums from a plan.  A workgroup owns a range of tiles and
 // one group of up to 16 columns; thread t owns targets t (and t + 1024).  Per
 // tile the rows are staged in LDS in the storage precision (exact), thread r
@@ -153,10 +169,10 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_kernel(int64_t n, int6
 #define RBGS_SP_UNROLL2 0
 #endif
 template <typename T, int TPT>
-__global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
+__device__ __forceinline__ void sketch_sparse_body(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
-    int64_t tiles_per_wg, double* __restrict__ partial) {
+    int64_t tiles_per_wg, double* __restrict__ partial, int g, int cg) {
   // staging type in LDS: the storage type, or FP64 (converted once per row)
   typedef typename std::conditional<RBGS_SP_STAGE64 != 0, double, T>::type ST;
   typedef ST V4 __attribute__((ext_vector_type(4)));
@@ -167,8 +183,7 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
   __shared__ uint16_t off[kSpMaxK + 1];
 
   const int tid = threadIdx.x;
-  const int g = blockIdx.x;
-  const int col0 = blockIdx.y * kSketchCols;
+  const int col0 = cg * kSketchCols;
   const int nc = min(kSketchCols, ncols - col0);
   const int64_t ntiles = (n + kSpTile - 1) / kSpTile;
   const int64_t tbeg = (int64_t)g * tiles_per_wg;
@@ -281,6 +296,28 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
   }
 }
 
+template <typename T, int TPT>
+__global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
+    const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
+    const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
+    int64_t tiles_per_wg, double* __restrict__ partial) {
+  sketch_sparse_body<T, TPT>(X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg, partial,
+                             blockIdx.x, blockIdx.y);
+}
+
+// Lock-step batch: workgroup -> (problem, row group) over the flattened
+// groups; which = 0 sketches W (columns 0 ..), which = 1 Q (columns c0 ..).
+template <typename T, int TPT>
+__global__ __launch_bounds__(kSpThreads) void sketch_sparse_batched_kernel(
+    const BatchItem* items, int nprob, int which, int64_t c0, int ncols, int k, int zeta) {
+  const int p = batch_find(nprob, blockIdx.x, [&](int q) { return items[q].sk_wg0; });
+  const BatchItem& it = items[p];
+  const T* X = which == 0 ? (const T*)it.W : (const T*)it.Q + c0 * it.ldq;
+  const int64_t ldx = which == 0 ? it.ldw : it.ldq;
+  sketch_sparse_body<T, TPT>(X, ldx, it.n, ncols, k, zeta, it.plan_off, it.plan_ent, it.sk_tpw,
+                             it.part, (int)((int64_t)blockIdx.x - it.sk_wg0), blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Gaussian: out = Z X on FP64 matrix cores (v_mfma_f64_16x16x4f64) with Z
 // regenerated from Philox for every 4-row step.  A wave owns 64 targets: lane
@@ -362,11 +399,10 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
 // 8 lanes per output: lane q sums g = q, q+8, ... in order, then the eight
 // partial sums are combined by a fixed butterfly.
 constexpr int kRedLanes = 8;
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __restrict__ partial,
-                                                            int G, int64_t k, int64_t ncols,
-                                                            double scale, double* __restrict__ out,
-                                                            int64_t ldo) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sketch_reduce_body(const double* __restrict__ partial, int G,
+                                                   int64_t k, int64_t ncols, double scale,
+                                                   double* __restrict__ out, int64_t ldo,
+                                                   int64_t gid) {
   const int q = (int)(gid % kRedLanes);
   const int64_t idx = gid / kRedLanes;
   const bool ok = idx < k * ncols;
@@ -386,6 +422,25 @@ __global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __rest
 #pragma unroll
   for (int d = 1; d < kRedLanes; d <<= 1) s += __shfl_xor(s, d, 64);
   if (ok && q == 0) out[t + c * ldo] = scale * s;
+}
+
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __restrict__ partial,
+                                                            int G, int64_t k, int64_t ncols,
+                                                            double scale, double* __restrict__ out,
+                                                            int64_t ldo) {
+  sketch_reduce_body(partial, G, k, ncols, scale, out, ldo,
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Lock-step batch: blockIdx.y = problem; which = 0: into P, 1: into S (columns c0 ..).
+__global__ __launch_bounds__(256) void sketch_reduce_batched_kernel(const BatchItem* items,
+                                                                    int which, int64_t c0,
+                                                                    int64_t k, int64_t ncols,
+                                                                    double scale) {
+  const BatchItem& it = items[blockIdx.y];
+  double* out = which == 0 ? it.P : it.S + c0 * k;
+  sketch_reduce_body(it.part, it.sk_G, k, ncols, scale, out, k,
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <typename T>
@@ -681,6 +736,38 @@ hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t
   const int64_t total = k * ncols * kRedLanes;
   hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
                      partial, G, k, ncols, scale, out, ldo);
+  return hipGetLastError();
+}
+
+int64_t sparse_plan_tiles(int64_t n) { return ceil_div(n, kSpTile); }
+int64_t plan_offsets_len(const SketchDesc& sk, int64_t n) { return plan_ent_offset(sk, n); }
+
+hipError_t launch_plan_batched(const BatchItem* items, int nprob, int64_t total_tiles, int k,
+                               int zeta, hipStream_t st) {
+  if (k > kSpMaxK || zeta > kSpMaxZeta) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sparse_plan_batched_kernel, dim3((unsigned)total_tiles), dim3(kSpThreads), 0,
+                     st, items, nprob, k, zeta);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_batched(bool f32, const BatchItem* items, int nprob, int64_t total_wgs,
+                                 int which, int64_t c0, int64_t ncols, int k, int zeta,
+                                 double scale, hipStream_t st) {
+  if (k > kSpMaxK) return hipErrorInvalidValue;
+  dim3 grid((unsigned)total_wgs, (unsigned)ceil_div(ncols, kSketchCols));
+  const bool two = k > kSpThreads;
+#define RBGS_SPB(T, TPT)                                                                    \
+  hipLaunchKernelGGL((sketch_sparse_batched_kernel<T, TPT>), grid, dim3(kSpThreads), 0, st, \
+                     items, nprob, which, c0, (int)ncols, k, zeta)
+  if (f32) {
+    if (two) RBGS_SPB(float, 2); else RBGS_SPB(float, 1);
+  } else {
+    if (two) RBGS_SPB(double, 2); else RBGS_SPB(double, 1);
+  }
+#undef RBGS_SPB
+  const int64_t total = (int64_t)k * ncols * kRedLanes;
+  hipLaunchKernelGGL(sketch_reduce_batched_kernel, dim3((unsigned)ceil_div(total, 256), (unsigned)nprob),
+                     dim3(256), 0, st, items, which, c0, (int64_t)k, ncols, scale);
   return hipGetLastError();
 }
 

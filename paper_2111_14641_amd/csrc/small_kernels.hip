@@ -276,15 +276,15 @@ hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st) {
 
 // out0[j][c] = sum_t S[t][j] X0[t][c] (c < n0), out1[j][c] = sum_t S[t][j] X1[t][c]
 // (c < n1), j < K.  One wave per output (t strided by 64), fixed reduction tree.
-__global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict__ S, int64_t k,
-                                                       int64_t K, const double* __restrict__ X0,
-                                                       int n0, const double* __restrict__ X1,
-                                                       int n1, double* __restrict__ out0,
-                                                       int64_t ldo0, double* __restrict__ out1,
-                                                       int64_t ldo1, double* __restrict__ out1t,
-                                                       int64_t ldo1t) {
+__device__ __forceinline__ void gram_sty_body(const double* __restrict__ S, int64_t k, int64_t K,
+                                              const double* __restrict__ X0, int n0,
+                                              const double* __restrict__ X1, int n1,
+                                              double* __restrict__ out0, int64_t ldo0,
+                                              double* __restrict__ out1, int64_t ldo1,
+                                              double* __restrict__ out1t, int64_t ldo1t,
+                                              int64_t bx) {
   const int lane = threadIdx.x & 63;
-  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // output index
+  const int64_t o = (bx * blockDim.x + threadIdx.x) >> 6;  // output index
   const int ncol = n0 + n1;
   const bool ok = o < K * ncol;
   const int64_t j = ok ? o % K : 0;
@@ -312,16 +312,38 @@ __global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict_
   }
 }
 
+__global__ __launch_bounds__(256) void gram_sty_kernel(const double* __restrict__ S, int64_t k,
+                                                       int64_t K, const double* __restrict__ X0,
+                                                       int n0, const double* __restrict__ X1,
+                                                       int n1, double* __restrict__ out0,
+                                                       int64_t ldo0, double* __restrict__ out1,
+                                                       int64_t ldo1, double* __restrict__ out1t,
+                                                       int64_t ldo1t) {
+  gram_sty_body(S, k, K, X0, n0, X1, n1, out0, ldo0, out1, ldo1, out1t, ldo1t, blockIdx.x);
+}
+
+// Lock-step batch (blockIdx.y = problem): c = S^T P_(i) into Cb (ld K) or
+// R_(1:i-1,i), and the new Gram block from S_(i-1) (columns K - bprev ..).
+__global__ __launch_bounds__(256) void gram_sty_batched_kernel(const BatchItem* items, int64_t k,
+                                                               int64_t K, int bw, int bprev,
+                                                               int64_t m, int to_cb) {
+  const BatchItem& it = items[blockIdx.y];
+  double* out0 = to_cb ? it.Cb : it.R + K * it.ldr;
+  const int64_t ldo0 = to_cb ? K : it.ldr;
+  gram_sty_body(it.S, k, K, it.P + K * k, bw, it.S + (K - bprev) * k, bprev, out0, ldo0,
+                it.G + (K - bprev) * m, m, it.G + (K - bprev), m, blockIdx.x);
+}
+
 // Ynew[j][c] = Y[j][c] + C[j][c] - sum_l G[j][l] Y[l][c], reading row j of the
 // symmetric G as its column j (both halves are stored), so both operands of
 // the dot are contiguous.  16 lanes per output (l strided by 16).
-__global__ __launch_bounds__(256) void gram_sweep_kernel(const double* __restrict__ G, int64_t ldg,
-                                                         int64_t K, const double* __restrict__ C,
-                                                         const double* __restrict__ Y,
-                                                         int64_t ldy, double* __restrict__ Ynew,
-                                                         int64_t ldyn, int bw) {
+__device__ __forceinline__ void gram_sweep_body(const double* __restrict__ G, int64_t ldg,
+                                                int64_t K, const double* __restrict__ C,
+                                                const double* __restrict__ Y, int64_t ldy,
+                                                double* __restrict__ Ynew, int64_t ldyn, int bw,
+                                                int64_t bx) {
   const int q = threadIdx.x & 15;
-  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int64_t o = (bx * blockDim.x + threadIdx.x) >> 4;
   const bool ok = o < K * bw;
   const int64_t j = ok ? o % K : 0;
   const int c = ok ? (int)(o / K) : 0;
@@ -338,14 +360,34 @@ __global__ __launch_bounds__(256) void gram_sweep_kernel(const double* __restric
   if (ok && q == 0) Ynew[j + (int64_t)c * ldyn] = yc[j] + (C[j + (int64_t)c * K] - v);
 }
 
+__global__ __launch_bounds__(256) void gram_sweep_kernel(const double* __restrict__ G, int64_t ldg,
+                                                         int64_t K, const double* __restrict__ C,
+                                                         const double* __restrict__ Y,
+                                                         int64_t ldy, double* __restrict__ Ynew,
+                                                         int64_t ldyn, int bw) {
+  gram_sweep_body(G, ldg, K, C, Y, ldy, Ynew, ldyn, bw, blockIdx.x);
+}
+
+// Lock-step batch: buffers by role, 0 = Cb (ld K), 1 = Yb (ld K), 2 = R_(1:i-1,i).
+__global__ __launch_bounds__(256) void gram_sweep_batched_kernel(const BatchItem* items, int64_t m,
+                                                                 int64_t K, int bw, int src,
+                                                                 int dst) {
+  const BatchItem& it = items[blockIdx.y];
+  const double* Y = src == 0 ? it.Cb : (src == 1 ? it.Yb : it.R + K * it.ldr);
+  const int64_t ldy = src == 2 ? it.ldr : K;
+  double* Yn = dst == 0 ? it.Cb : (dst == 1 ? it.Yb : it.R + K * it.ldr);
+  const int64_t ldyn = dst == 2 ? it.ldr : K;
+  gram_sweep_body(it.G, m, K, it.Cb, Y, ldy, Yn, ldyn, bw, blockIdx.x);
+}
+
 // E[t][c] = P[t][c] - sum_j S[t][j] Y[j][c].  16 lanes per output split j
 // (strided by 16); lane = q + 16 tl covers rows t = 4 tb + tl.
-__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P,
-                                                    const double* __restrict__ S, int64_t k,
-                                                    int64_t K, const double* __restrict__ Y,
-                                                    int64_t ldy, double* __restrict__ E, int bw) {
+__device__ __forceinline__ void resid_body(const double* __restrict__ P,
+                                           const double* __restrict__ S, int64_t k, int64_t K,
+                                           const double* __restrict__ Y, int64_t ldy,
+                                           double* __restrict__ E, int bw, int64_t bx) {
   const int q = threadIdx.x & 15;
-  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;  // output index
+  const int64_t o = (bx * blockDim.x + threadIdx.x) >> 4;  // output index
   const bool ok = o < k * bw;
   const int64_t t = ok ? o % k : 0;
   const int c = ok ? (int)(o / k) : 0;
@@ -359,6 +401,19 @@ __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P
   for (; j < K; j += 16) a0 = fma(S[t + j * k], yc[j], a0);
   const double v = group_sum<16>(a0 + a1);
   if (ok && q == 0) E[t + (int64_t)c * k] = P[t + (int64_t)c * k] - v;
+}
+
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P,
+                                                    const double* __restrict__ S, int64_t k,
+                                                    int64_t K, const double* __restrict__ Y,
+                                                    int64_t ldy, double* __restrict__ E, int bw) {
+  resid_body(P, S, k, K, Y, ldy, E, bw, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void resid_batched_kernel(const BatchItem* items, int64_t k,
+                                                            int64_t K, int bw) {
+  const BatchItem& it = items[blockIdx.y];
+  resid_body(it.P + K * k, it.S, k, K, it.R + K * it.ldr, it.ldr, it.E, bw, blockIdx.x);
 }
 
 __device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned total) {
@@ -458,10 +513,9 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 template <int RPT>
-__global__ __launch_bounds__(kQwThreads) void qr_wave_kernel(const double* __restrict__ src,
-                                                             int64_t k, int bw,
-                                                             double* __restrict__ Rii, int64_t ldr,
-                                                             int64_t* flag, int64_t col0) {
+__device__ __forceinline__ void qr_wave_body(const double* __restrict__ src, int64_t k, int bw,
+                                             double* __restrict__ Rii, int64_t ldr, int64_t* flag,
+                                             int64_t col0) {
   constexpr int CH = 64 * RPT;
   __shared__ double xb[2 * CH];
   __shared__ double sg[2];
@@ -546,6 +600,32 @@ __global__ __launch_bounds__(kQwThreads) void qr_wave_kernel(const double* __res
   }
 }
 
+template <int RPT>
+__global__ __launch_bounds__(kQwThreads) void qr_wave_kernel(const double* __restrict__ src,
+                                                             int64_t k, int bw,
+                                                             double* __restrict__ Rii, int64_t ldr,
+                                                             int64_t* flag, int64_t col0) {
+  qr_wave_body<RPT>(src, k, bw, Rii, ldr, flag, col0);
+}
+
+// Lock-step batch (blockIdx.x = problem): R_(i,i) of S'_(i) (E, or P_(1) for
+// the first block).
+template <int RPT>
+__global__ __launch_bounds__(kQwThreads) void qr_wave_batched_kernel(const BatchItem* items,
+                                                                     int64_t k, int bw,
+                                                                     int64_t c0) {
+  const BatchItem& it = items[blockIdx.x];
+  qr_wave_body<RPT>(c0 == 0 ? it.P : it.E, k, bw, it.R + c0 + c0 * it.ldr, it.ldr, it.flag, c0);
+}
+
+// Lock-step batch initialisation: R = 0 (m x m) and the breakdown flag.
+__global__ void init_batched_kernel(const BatchItem* items, int64_t m) {
+  const BatchItem& it = items[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < m * m) it.R[(idx % m) + it.ldr * (idx / m)] = 0.0;
+  if (idx == 0) *it.flag = -1;
+}
+
 // Deterministic test matrix for the autotuner: x[r][c] = a hash of (r, c)
 // mapped to [-1, 1) (full rank with overwhelming probability).
 __global__ void fill_test_kernel(void* X, int f32, int64_t n, int64_t m, int64_t ld) {
@@ -592,6 +672,49 @@ hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, 
   const int64_t threads = k * bw * 16;
   hipLaunchKernelGGL(resid_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st, P,
                      S, k, K, Y, ldy, E, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_sty_batched(const BatchItem* items, int nprob, int64_t k, int64_t K, int bw,
+                                   int bprev, int64_t m, bool to_cb, hipStream_t st) {
+  const int64_t threads = K * (bw + bprev) * 64;
+  hipLaunchKernelGGL(gram_sty_batched_kernel, dim3((unsigned)ceil_div(threads, 256), (unsigned)nprob),
+                     dim3(256), 0, st, items, k, K, bw, bprev, m, to_cb ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_batched(const BatchItem* items, int nprob, int64_t m, int64_t K, int bw,
+                                int src, int dst, hipStream_t st) {
+  const int64_t threads = K * bw * 16;
+  hipLaunchKernelGGL(gram_sweep_batched_kernel, dim3((unsigned)ceil_div(threads, 256), (unsigned)nprob),
+                     dim3(256), 0, st, items, m, K, bw, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_batched(const BatchItem* items, int nprob, int64_t k, int64_t K, int bw,
+                                hipStream_t st) {
+  const int64_t threads = k * bw * 16;
+  hipLaunchKernelGGL(resid_batched_kernel, dim3((unsigned)ceil_div(threads, 256), (unsigned)nprob),
+                     dim3(256), 0, st, items, k, K, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_batched(const BatchItem* items, int nprob, int64_t k, int bw, int64_t c0,
+                             hipStream_t st) {
+  if (bw > 16 || k > 1024) return hipErrorInvalidValue;
+#define RBGS_QWB(R)                                                                            \
+  hipLaunchKernelGGL(qr_wave_batched_kernel<R>, dim3((unsigned)nprob), dim3(kQwThreads), 0, st, \
+                     items, k, bw, c0)
+  if (k <= 256) RBGS_QWB(4);
+  else if (k <= 512) RBGS_QWB(8);
+  else RBGS_QWB(16);
+#undef RBGS_QWB
+  return hipGetLastError();
+}
+
+hipError_t launch_init_batched(const BatchItem* items, int nprob, int64_t m, hipStream_t st) {
+  hipLaunchKernelGGL(init_batched_kernel, dim3((unsigned)ceil_div(m * m, 256), (unsigned)nprob),
+                     dim3(256), 0, st, items, m);
   return hipGetLastError();
 }
 

@@ -282,6 +282,30 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_kernel(
                                 ubuf_raw, Rd);
 }
 
+// Lock-step batch (low-sync form): workgroup -> (problem, tile) over the
+// flattened tiles; block columns c0 = K .. K + bw of each problem.
+template <typename T, typename C, int NB>
+__global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kernel(
+    const BatchItem* items, int nprob, int K, int bw) {
+  typedef UpdateShape<T, C, NB> Sh;
+  __shared__ __attribute__((aligned(16))) unsigned char ubuf_raw[Sh::U_BYTES];
+  __shared__ double Rd[Sh::NCOL * Sh::NCOL];
+  const int p = batch_find(nprob, blockIdx.x, [&](int q) { return items[q].up_tile0; });
+  const BatchItem& it = items[p];
+  const int64_t tile = (int64_t)blockIdx.x - it.up_tile0;
+  const T* Wi = (const T*)it.W + (int64_t)K * it.ldw;
+  const T* Q = (const T*)it.Q;
+  T* Qi = (T*)it.Q + (int64_t)K * it.ldq;
+  const double* Rk = it.R + (int64_t)K * it.ldr;
+  const double* Rii = it.R + K + (int64_t)K * it.ldr;
+  if (tile < it.up_nfull)
+    update_tile<T, C, NB, false>(Wi, it.ldw, Q, it.ldq, Qi, it.ldq, Rk, Rii, it.ldr,
+                                 tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
+  else
+    update_tile<T, C, NB, true>(Wi, it.ldw, Q, it.ldq, Qi, it.ldq, Rk, Rii, it.ldr,
+                                tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
+}
+
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t ldq,
@@ -340,6 +364,31 @@ hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, co
   if (f32)
     return launch_update_t<float, double>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   return launch_update_t<double, double>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+}
+
+int64_t update_tile_rows(bool f32) {
+  return f32 ? UpdateShape<float, double, 1>::TILE : UpdateShape<double, double, 1>::TILE;
+}
+
+bool update_vec_ok(bool f32, const void* Q, int64_t ldq) {
+  const int VEC = f32 ? Vec16<float>::N : Vec16<double>::N;
+  return ((ldq % VEC) == 0) && ((reinterpret_cast<uintptr_t>(Q) % 16) == 0);
+}
+
+hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items, int nprob,
+                                 int64_t total_tiles, int64_t K, int bw, hipStream_t st) {
+  if (bw > 16) return hipErrorInvalidValue;
+  dim3 grid((unsigned)total_tiles);
+  if (f32 && f32_math)
+    hipLaunchKernelGGL((update_batched_kernel<float, float, 1>), grid, dim3(kUpThreads), 0, st,
+                       items, nprob, (int)K, bw);
+  else if (f32)
+    hipLaunchKernelGGL((update_batched_kernel<float, double, 1>), grid, dim3(kUpThreads), 0, st,
+                       items, nprob, (int)K, bw);
+  else
+    hipLaunchKernelGGL((update_batched_kernel<double, double, 1>), grid, dim3(kUpThreads), 0, st,
+                       items, nprob, (int)K, bw);
+  return hipGetLastError();
 }
 
 hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_t ldr, int64_t n,

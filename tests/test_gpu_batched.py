@@ -118,3 +118,84 @@ def test_autotuned_batch_fp32_metrics(gpu_lib):
         assert cond2(Qg) <= 10
     # cached: the same classes give the same answers
     assert B.autotune(Wh[2].shape[0], Wh[2].shape[1]) == (ps[2], ks[2])
+
+
+LOCK = [  # n, m, p, k: two lock-step groups (same m, p, k) and two problems on the streams
+    (3000, 48, 16, 128), (20001, 48, 16, 128), (1025, 48, 16, 128), (70000, 48, 16, 128),
+    (4096, 40, 8, 96), (9999, 40, 8, 96), (2500, 40, 8, 96),
+    (6000, 48, 32, 128), (5000, 40, 16, 96),
+]
+
+
+def make_lock_batch(store, decades, seed0):
+    import torch
+    from paper_2111_14641_amd import binding as B
+    dt = torch.float64 if store == "f64" else torch.float32
+    Wh, Ws = [], []
+    for i, (n, m, p, k) in enumerate(LOCK):
+        W = svd_matrix(n, m, np.logspace(0, -decades, m), seed=seed0 + i)
+        if store == "f32":
+            W = W.astype(np.float32).astype(np.float64)
+        Wt = B.colmajor(n, m, dt)
+        Wt.copy_(torch.from_numpy(W))
+        Wh.append(W)
+        Ws.append(Wt)
+    return Wh, Ws
+
+
+@pytest.mark.parametrize("store,ls", [("f64", 2), ("f64", 4), ("f64", 1), ("f32", 4)])
+def test_lockstep_groups_match_oracle(gpu_lib, store, ls):
+    """Problems that share m, p and k run block by block together (one launch
+    per kernel and step for the group); each must equal the oracle's RBGS of
+    its own W with its own sketch, as the problems run on the streams do.
+    Ragged row counts (1025, 20001, 9999) cover partial plan and update tiles."""
+    from paper_2111_14641_amd import binding as B
+    say("lock-step batch", store, ls)
+    decades = 2.0
+    Wh, Ws = make_lock_batch(store, decades, 700)
+    ps = [s[2] for s in LOCK]
+    ks = [s[3] for s in LOCK]
+    Qs, Rs, _, _ = B.rbgs_qr_batched(Ws, ps, ks, kind="sparse", seed=41, variant="lowsync",
+                                     ls_iters=ls)
+    for i, (W, Q, R) in enumerate(zip(Wh, Qs, Rs)):
+        n, m, p, k = LOCK[i]
+        th = Sketch("sparse", k, seed=41 + i).materialize(n)
+        o = orb.rbgs(W, p, th, "lowsync", "richardson", ls)
+        Rg, Qg = to_np(R), to_np(Q)
+        assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) > 0), i
+        if store == "f64":
+            assert np.linalg.norm(Rg - o["R"]) <= 1e-12 * np.linalg.norm(o["R"]), i
+            assert np.linalg.norm(Qg - o["Q"]) <= 1e-11 * np.linalg.norm(o["Q"]), i
+            assert factorization_error(W, Qg, Rg) < 1e-14, i
+        else:
+            assert np.linalg.norm(Rg - o["R"]) <= 64 * 2.0**-24 * 10**decades * np.linalg.norm(o["R"]), i
+            assert factorization_error(W, Qg, Rg) <= 1e-6, i
+            assert cond2(Qg) <= 10, i
+
+
+def test_lockstep_in_place_and_graph_replay(gpu_lib):
+    """Lock-step groups in place (Q = W) and under graph record/replay: the
+    replays give the eager result bit for bit."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("lock-step in place and graph")
+    Wh, Ws = make_lock_batch("f32", 4.0, 800)
+    ps = [s[2] for s in LOCK]
+    ks = [s[3] for s in LOCK]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        Qe, Re, _, _ = B.rbgs_qr_batched(Ws, ps, ks, seed=3)
+        Qg, Rg, _, _ = B.rbgs_qr_batched(Ws, ps, ks, seed=3, graph=True)
+        for rep in range(2):
+            for Q in Qg:
+                Q.zero_()
+            B.rbgs_qr_batched(Ws, ps, ks, seed=3, Qs=Qg, Rs=Rg, graph=True)
+            torch.cuda.synchronize()
+            for Q, R, Q1, R1 in zip(Qg, Rg, Qe, Re):
+                assert np.array_equal(to_np(Q), to_np(Q1)) and np.array_equal(to_np(R), to_np(R1)), rep
+        Wc = [W.clone() for W in Ws]
+        Ri = [torch.zeros_like(R) for R in Re]
+        B.rbgs_qr_batched(Wc, ps, ks, seed=3, Qs=Wc, Rs=Ri)
+        torch.cuda.synchronize()
+    for Q, R, Q1, R1 in zip(Wc, Ri, Qe, Re):
+        assert np.array_equal(to_np(Q), to_np(Q1)) and np.array_equal(to_np(R), to_np(R1))
