@@ -205,9 +205,16 @@ typedef struct {
  *         call with the identical batch launches that graph, one launch for the
  *         batch.  The graph reads W at run time, so W may change between calls.
  *         0: no graph.
- * The problems are spread over four internal streams (largest first, each to
- * the least loaded stream), joined back to opts->stream.  Problems with p or
- * k equal to 0 are tuned first (rbgs_autotune, which waits for the device).
+ * Problems that share m, p and k (low-sync form, sparse sign, p <= 32,
+ * k <= 2048; two or more of them) run in lock step on opts->stream: block by
+ * block, one launch per kernel and block step for the whole group, from a
+ * device array of per-problem descriptors and workspaces in the handle's
+ * batch arena (laid out, uploaded and -- if an earlier batch may still use
+ * it -- waited for on the host before anything is enqueued).  The other
+ * problems are spread over four internal streams (largest first, each to the
+ * least loaded stream), joined back to opts->stream.  A call that lays the
+ * arena out again drops the recorded graph.  Problems with p or k equal to 0
+ * are tuned first (rbgs_autotune, which waits for the device).
  * Every problem is validated before anything is enqueued: on an invalid
  * problem the call returns RBGS_EINVAL (or RBGS_EUNSUPPORTED) with that
  * problem's status set and enqueues nothing.  No certificate is computed. */

@@ -728,7 +728,7 @@ double batch_bytes(const rbgs_problem& pr, size_t es) {
 // Enqueue every problem on its lane; lanes fork from and join back to st.
 // ---------------------------------------------------------------------------
 // Lock-step groups: problems with the same m, p and k (low-sync form, sparse
-// sign, p <= 16, k <= 1024) advance block by block together, each kernel of
+// sign, p <= 32, k <= 2048) advance block by block together, each kernel of
 // a block step launched once for the whole group over a device array of
 // per-problem descriptors (pointers, n, seed, prefix sums of the flattened
 // grids).  The descriptors and every problem's workspace live in the
@@ -743,7 +743,7 @@ struct LockGroup {
 
 bool lockstep_ok(const rbgs_problem& pr, const rbgs_sketch* sk, const rbgs_opts* opts) {
   return opts->variant == RBGS_VARIANT_LOWSYNC && sk->kind == RBGS_SKETCH_SPARSE_SIGN &&
-         pr.p <= 16 && pr.k <= 1024;
+         pr.p <= 32 && pr.k <= 2048;
 }
 
 // Groups, arena layout and descriptor upload (waits for the copy).
@@ -788,7 +788,7 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
   size_t off = 0;
   std::vector<std::vector<BatchItem>> host(groups.size());
   std::vector<size_t> items_off(groups.size());
-  std::vector<std::vector<size_t>> offs(groups.size());  // per problem: 11 buffer offsets
+  std::vector<std::vector<size_t>> offs(groups.size());  // per problem: 12 buffer offsets
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     LockGroup& g = groups[gi];
     const int64_t np = (int64_t)g.idx.size();
@@ -830,7 +830,8 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
       const int64_t m = g.m, k = g.k, b = g.p;
       std::vector<size_t> o;
       for (size_t doubles : {(size_t)(k * m), (size_t)(k * m), (size_t)(k * b), (size_t)(m * m),
-                             (size_t)(m * b), (size_t)(m * b), (size_t)(G * k * m), (size_t)1}) {
+                             (size_t)(m * b), (size_t)(m * b), (size_t)(G * k * m), (size_t)1,
+                             qr_stack_size(k, (int)b), (size_t)1}) {
         o.push_back(off);
         off += r256(doubles * 8);
       }
@@ -860,7 +861,7 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
     const size_t np = g.idx.size();
     for (size_t q = 0; q < np; ++q) {
       BatchItem& it = host[gi][q];
-      const size_t* o = &offs[gi][q * 10];
+      const size_t* o = &offs[gi][q * 12];
       it.S = (double*)(base + o[0]);
       it.P = (double*)(base + o[1]);
       it.E = (double*)(base + o[2]);
@@ -869,11 +870,13 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
       it.Yb = (double*)(base + o[5]);
       it.part = (double*)(base + o[6]);
       it.flag = (int64_t*)(base + o[7]);
-      uint16_t* plan = (uint16_t*)(base + o[8]);
+      it.stack = (double*)(base + o[8]);
+      it.counter = (unsigned*)(base + o[9]);
+      uint16_t* plan = (uint16_t*)(base + o[10]);
       it.plan_off_w = plan;
-      it.plan_ent_w = plan + o[9];
+      it.plan_ent_w = plan + o[11];
       it.plan_off = plan;
-      it.plan_ent = plan + o[9];
+      it.plan_ent = plan + o[11];
     }
     g.items = (BatchItem*)(base + items_off[gi]);
     HIP_TRY(h, hipMemcpy(g.items, host[gi].data(), sizeof(BatchItem) * np, hipMemcpyHostToDevice),

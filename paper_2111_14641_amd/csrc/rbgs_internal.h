@@ -181,7 +181,8 @@ struct SketchDesc {
 struct BatchItem {
   const void* W;
   void* Q;
-  double *R, *S, *P, *E, *G, *Cb, *Yb, *part;
+  double *R, *S, *P, *E, *G, *Cb, *Yb, *part, *stack;
+  unsigned* counter;
   const uint16_t* plan_off;
   const uint16_t* plan_ent;
   uint16_t* plan_off_w;     // the same plan, writable, for the plan kernel

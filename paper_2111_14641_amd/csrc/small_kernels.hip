@@ -429,9 +429,10 @@ __device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned t
 // R_(i,i) (positive diagonal) of the k x bw matrix src (ld k): workgroup g
 // factors chunk g in LDS; the last workgroup factors the stack of chunk R
 // factors (all remaining levels of the tree) and writes R_(i,i).
-__global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
-    const double* __restrict__ src, int64_t k, int bw, double* __restrict__ stack,
-    unsigned* counter, double* __restrict__ Rii, int64_t ldr, int64_t* flag, int64_t col0) {
+__device__ __forceinline__ void qr_fused_body(const double* __restrict__ src, int64_t k, int bw,
+                                              double* __restrict__ stack, unsigned* counter,
+                                              double* __restrict__ Rii, int64_t ldr,
+                                              int64_t* flag, int64_t col0, int64_t chunk) {
   __shared__ double xb[2 * (kQrThreads / 4) * kQrRpt];
   __shared__ double sg[2 + kQrMaxB];
   const int CH = qr_chunk_rows(bw);
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
     return;
   }
   const int64_t ld1 = nch * bw;
-  qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, blockIdx.x, xb, sg);
+  qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, chunk, xb, sg);
   if (!last_block_arrives(counter, (unsigned)nch)) return;
   // remaining levels in this workgroup
   const double* lsrc = stack;
@@ -459,6 +460,21 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
   }
   qr_chunk(lsrc, ld_in, lrows, bw, Rii, ldr, 1, flag, col0, 0, xb, sg);
   if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
+    const double* __restrict__ src, int64_t k, int bw, double* __restrict__ stack,
+    unsigned* counter, double* __restrict__ Rii, int64_t ldr, int64_t* flag, int64_t col0) {
+  qr_fused_body(src, k, bw, stack, counter, Rii, ldr, flag, col0, blockIdx.x);
+}
+
+// Lock-step batch (blockIdx.y = problem): the Householder tree of S'_(i).
+__global__ __launch_bounds__(kQrThreads) void qr_fused_batched_kernel(const BatchItem* items,
+                                                                      int64_t k, int bw,
+                                                                      int64_t c0) {
+  const BatchItem& it = items[blockIdx.y];
+  qr_fused_body(c0 == 0 ? it.P : it.E, k, bw, it.stack, it.counter, it.R + c0 + c0 * it.ldr,
+                it.ldr, it.flag, c0, blockIdx.x);
 }
 
 // One level of a Householder TSQR tree over a tall rows_in x bw matrix:
@@ -623,7 +639,10 @@ __global__ void init_batched_kernel(const BatchItem* items, int64_t m) {
   const BatchItem& it = items[blockIdx.y];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < m * m) it.R[(idx % m) + it.ldr * (idx / m)] = 0.0;
-  if (idx == 0) *it.flag = -1;
+  if (idx == 0) {
+    *it.flag = -1;
+    *it.counter = 0u;
+  }
 }
 
 // Deterministic test matrix for the autotuner: x[r][c] = a hash of (r, c)
@@ -701,7 +720,13 @@ hipError_t launch_resid_batched(const BatchItem* items, int nprob, int64_t k, in
 
 hipError_t launch_qr_batched(const BatchItem* items, int nprob, int64_t k, int bw, int64_t c0,
                              hipStream_t st) {
-  if (bw > 16 || k > 1024) return hipErrorInvalidValue;
+  if (bw > kQrMaxB) return hipErrorInvalidValue;
+  if (bw > 16 || k > 1024) {
+    const int64_t CH = qr_chunk_rows(bw);
+    hipLaunchKernelGGL(qr_fused_batched_kernel, dim3((unsigned)ceil_div(k, CH), (unsigned)nprob),
+                       dim3(kQrThreads), 0, st, items, k, bw, c0);
+    return hipGetLastError();
+  }
 #define RBGS_QWB(R)                                                                            \
   hipLaunchKernelGGL(qr_wave_batched_kernel<R>, dim3((unsigned)nprob), dim3(kQwThreads), 0, st, \
                      items, k, bw, c0)

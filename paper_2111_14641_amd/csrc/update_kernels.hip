@@ -377,17 +377,21 @@ bool update_vec_ok(bool f32, const void* Q, int64_t ldq) {
 
 hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items, int nprob,
                                  int64_t total_tiles, int64_t K, int bw, hipStream_t st) {
-  if (bw > 16) return hipErrorInvalidValue;
+  if (bw > kMaxB) return hipErrorInvalidValue;
   dim3 grid((unsigned)total_tiles);
-  if (f32 && f32_math)
-    hipLaunchKernelGGL((update_batched_kernel<float, float, 1>), grid, dim3(kUpThreads), 0, st,
-                       items, nprob, (int)K, bw);
-  else if (f32)
-    hipLaunchKernelGGL((update_batched_kernel<float, double, 1>), grid, dim3(kUpThreads), 0, st,
-                       items, nprob, (int)K, bw);
-  else
-    hipLaunchKernelGGL((update_batched_kernel<double, double, 1>), grid, dim3(kUpThreads), 0, st,
-                       items, nprob, (int)K, bw);
+#define RBGS_UPB(T, C, NB)                                                                      \
+  hipLaunchKernelGGL((update_batched_kernel<T, C, NB>), grid, dim3(kUpThreads), 0, st, items, \
+                     nprob, (int)K, bw)
+  if (bw <= 16) {
+    if (f32 && f32_math) RBGS_UPB(float, float, 1);
+    else if (f32) RBGS_UPB(float, double, 1);
+    else RBGS_UPB(double, double, 1);
+  } else {
+    if (f32 && f32_math) RBGS_UPB(float, float, 2);
+    else if (f32) RBGS_UPB(float, double, 2);
+    else RBGS_UPB(double, double, 2);
+  }
+#undef RBGS_UPB
   return hipGetLastError();
 }
 

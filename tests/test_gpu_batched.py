@@ -120,10 +120,12 @@ def test_autotuned_batch_fp32_metrics(gpu_lib):
     assert B.autotune(Wh[2].shape[0], Wh[2].shape[1]) == (ps[2], ks[2])
 
 
-LOCK = [  # n, m, p, k: two lock-step groups (same m, p, k) and two problems on the streams
+LOCK = [  # n, m, p, k: four lock-step groups (same m, p, k) and one problem on the streams
     (3000, 48, 16, 128), (20001, 48, 16, 128), (1025, 48, 16, 128), (70000, 48, 16, 128),
     (4096, 40, 8, 96), (9999, 40, 8, 96), (2500, 40, 8, 96),
-    (6000, 48, 32, 128), (5000, 40, 16, 96),
+    (6000, 48, 32, 128), (8000, 48, 32, 128),      # 32-wide blocks: Householder tree, 2 x 16 update
+    (4000, 40, 16, 1104), (4500, 40, 16, 1104),    # k > 1024: two sketch rows per thread, tree
+    (5000, 40, 16, 96),
 ]
 
 
