@@ -32,6 +32,9 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 #ifndef RBGS_UP_WLATE
 #define RBGS_UP_WLATE 0   // 1: load the W_(i) row in the epilogue instead of before the product
 #endif
+#ifndef RBGS_UP_WSYNC
+#define RBGS_UP_WSYNC 1   // wave-level ordering between the slab writes and reads
+#endif
 #ifndef RBGS_UP_MINW
 #define RBGS_UP_MINW 0    // > 0: ask the compiler for this many waves per SIMD
 #endif
@@ -243,7 +246,14 @@ __device__ __forceinline__ void update_tile(
           for (int e = 0; e < 4; ++e)
             ct[(VEC * M::row(kk, e) + v) * CT_LD + (li - h * SLAB)] = acc[v][nb][e];
       }
+      // the slab region of a wave is written and read by that wave only
+#if RBGS_UP_WSYNC
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#else
       __syncthreads();
+#endif
       const int lr = lane < WROWS ? lane : 0;
 #pragma unroll
       for (int c = 0; c < SLAB; ++c) {
