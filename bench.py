@@ -78,8 +78,11 @@ def accuracy(W, Q, R, cert):
 
 
 def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64"):
-    """Times `steps` QRs on a dedicated stream.  With profile_update, HIP events
-    bracket every update launch inside the timed region (the roofline figure)."""
+    """Times `steps` QRs on a dedicated stream.  With profile_update, a second
+    timed region of `steps` QRs follows in which HIP events bracket every
+    update launch on its stream (the roofline figure); the events themselves
+    add a few microseconds around each launch, so the step time is taken from
+    the first region."""
     import torch
     from paper_2111_14641_amd import binding as B
     n, m = W.shape
@@ -94,8 +97,6 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
         for _ in range(warmup):
             run()
         torch.cuda.synchronize()
-        if profile_update:
-            B.profile_enable(True, classes=["update"])
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -107,7 +108,13 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
         ms = t0.elapsed_time(t1) / steps
         upd = None
         if profile_update:
-            upd = B.profile_get("update")
+            B.profile_enable(True, classes=["update"])
+            t0.record(stream)
+            for _ in range(steps):
+                run()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            upd = B.profile_get("update") + (t0.elapsed_time(t1) / steps,)
             B.profile_enable(False)
     s = 4 if W.dtype == torch.float32 else 8
     gbs = alg_bytes(n, m, p, s) / (ms * 1e-3) / 1e9
@@ -330,7 +337,9 @@ def main():
     ap.add_argument("--no-gaussian", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
-    ap.add_argument("--forms", default="all", help="'headline' to time only the headline form")
+    ap.add_argument("--forms", default="all", choices=["all", "headline", "srht", "batched"],
+                    help="'headline': only the headline form; 'srht' / 'batched': the headline "
+                         "and that form (for profiling one form)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -373,11 +382,6 @@ def main():
                                                  max(3, args.steps // 4), 1)
         print("[bench] Cholesky-QR post-processing", file=sys.stderr, flush=True)
         forms["post_cholqr_f32"] = post_form(W32, p, "sparse", k, THETA_SEED_LARGE)
-        print("[bench] SRHT sketch", file=sys.stderr, flush=True)
-        forms["f32_srht_lowsync"], _ = time_form(W32, p, "srht", k, THETA_SEED_LARGE, "lowsync",
-                                                 max(3, args.steps // 4), 1)
-        forms["f64_srht_lowsync"], _ = time_form(W64, p, "srht", k, THETA_SEED_LARGE, "lowsync",
-                                                 max(3, args.steps // 4), 1)
         print("[bench] two-pass inter-block forms", file=sys.stderr, flush=True)
         forms["f32_sparse_twice"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "twice",
                                                  max(3, args.steps // 4), 1)
@@ -392,15 +396,21 @@ def main():
             forms["f32_rademacher_lowsync"], _ = time_form(W32, p, "rademacher", k,
                                                            THETA_SEED_LARGE, "lowsync",
                                                            max(2, args.steps // 10), 1)
+    if args.forms in ("all", "srht"):
+        print("[bench] SRHT sketch", file=sys.stderr, flush=True)
+        forms["f32_srht_lowsync"], _ = time_form(W32, p, "srht", k, THETA_SEED_LARGE, "lowsync",
+                                                 max(3, args.steps // 4), 1)
+        forms["f64_srht_lowsync"], _ = time_form(W64, p, "srht", k, THETA_SEED_LARGE, "lowsync",
+                                                 max(3, args.steps // 4), 1)
     del W64
-    if args.forms == "all" and not args.no_batched:
+    if args.forms in ("all", "batched") and not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         forms["batched_512_f32"] = batched_form()
     if args.forms == "all" and not args.no_gmres:
         print("[bench] block GMRES", file=sys.stderr, flush=True)
         forms["gmres_convdiff_1024_f32basis"] = gmres_form()
     copy_gbs = copy_bandwidth()
-    upd_ms, upd_cnt, upd_bytes = upd
+    upd_ms, upd_cnt, upd_bytes, upd_step_ms = upd
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(n, m, p, k),
@@ -408,7 +418,8 @@ def main():
                     alg_bytes_per_launch=round(upd_bytes / max(upd_cnt, 1)),
                     kernel="update_kernel<float,double,1> (step 3 + substitution, low-sync)",
                     launches=upd_cnt, avg_launch_us=round(upd_ms / max(upd_cnt, 1) * 1e3, 2),
-                    share_of_step=round(upd_ms / args.steps / head["ms"], 3),
+                    share_of_step=round(upd_ms / args.steps / upd_step_ms, 3),
+                    events_region_ms_per_step=round(upd_step_ms, 4),
                     copy_GBps=round(copy_gbs, 1), frac_of_copy=round(achieved / copy_gbs, 4))
     speedup = None
     if "f64_sparse_lowsync" in forms:
