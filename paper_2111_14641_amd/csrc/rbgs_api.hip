@@ -429,7 +429,10 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   // small factors of a block use few compute units, so these sketches mostly
   // fill idle ones.  Block i waits for its sketch before its least squares.
   const int64_t nblk = (m + b - 1) / b;
-  r.overlap = hoist && !h->no_overlap && d.kind != kIdentity && nblk > 1;
+  // (dense sketches are generator-bound: their W is sketched in one pass that
+  // shares every generated entry among four column groups, not block by block)
+  r.overlap = hoist && !h->no_overlap && d.kind != kIdentity && d.kind != kGaussian &&
+              d.kind != kRademacher && nblk > 1;
   size_t part2_need = 0;
   if (r.overlap) {
     part2_need = sketch_partial_doubles(d, n, std::min<int64_t>(b, m), kSideGroups);

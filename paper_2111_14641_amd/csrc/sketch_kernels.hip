@@ -330,41 +330,47 @@ __global__ __launch_bounds__(kSpThreads) void sketch_sparse_batched_kernel(
 constexpr int kGaThreads = 256;
 constexpr int kGaTile = 128;
 
-template <typename T, int KIND>
+// NCG column groups of 16 per workgroup share every generated entry of Theta
+// (the generator dominates; one call feeds 4 NCG matrix-core instructions).
+template <typename T, int KIND, int NCG>
 __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int64_t row0, int k,
     uint32_t key0, uint32_t key1, int64_t rows_per_wg, double* __restrict__ partial) {
-  __shared__ double xs[kGaTile * kSketchCols];  // [rr][c]
+  constexpr int NC = kSketchCols * NCG;           // columns per workgroup
+  constexpr int TILE = kGaTile / NCG;             // rows staged per step
+  __shared__ double xs[TILE * NC];                // [rr][c]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
   const int tbase = blockIdx.y * 256 + wave * 64;
-  const int col0 = blockIdx.z * kSketchCols;
-  const int nc = min(kSketchCols, ncols - col0);
+  const int col0 = blockIdx.z * NC;
+  const int nc = min(NC, ncols - col0);
   const int64_t rbeg = (int64_t)g * rows_per_wg;
   const int64_t rend = min(n, rbeg + rows_per_wg);
   const uint32_t j = (uint32_t)(tbase / 4 + (lane & 15));
   const bool jvalid = (int)(4 * j) < k;
   const int kk = lane >> 4;
 
-  double4_t acc[4];
+  double4_t acc[NCG][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[cg][q] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t tile0 = rbeg; tile0 < rend; tile0 += kGaTile) {
-    const int trows = (int)min((int64_t)kGaTile, rend - tile0);
+  for (int64_t tile0 = rbeg; tile0 < rend; tile0 += TILE) {
+    const int trows = (int)min((int64_t)TILE, rend - tile0);
     // unconditional loads from clamped addresses, then masked
-    T v[kGaTile * kSketchCols / kGaThreads];
+    T v[TILE * NC / kGaThreads];
 #pragma unroll
-    for (int i = 0; i < kGaTile * kSketchCols / kGaThreads; ++i) {
+    for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
       const int e = tid + i * kGaThreads;
-      const int c = e / kGaTile, rr = e % kGaTile;
+      const int c = e / TILE, rr = e % TILE;
       v[i] = X[(tile0 + (rr < trows ? rr : trows - 1)) + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
     }
 #pragma unroll
-    for (int i = 0; i < kGaTile * kSketchCols / kGaThreads; ++i) {
+    for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
       const int e = tid + i * kGaThreads;
-      const int c = e / kGaTile, rr = e % kGaTile;
-      xs[rr * kSketchCols + c] = (rr < trows && c < nc) ? to_f64(v[i]) : 0.0;
+      const int c = e / TILE, rr = e % TILE;
+      xs[rr * NC + c] = (rr < trows && c < nc) ? to_f64(v[i]) : 0.0;
     }
     __syncthreads();
     for (int rr = 0; rr < trows; rr += 4) {
@@ -373,25 +379,37 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
         if constexpr (KIND == kRademacher) rademacher4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
         else gauss4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
       }
-      const double b = xs[(rr + kk) * kSketchCols + (lane & 15)];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)z[q], b, acc[q], 0, 0, 0);
+      for (int cg = 0; cg < NCG; ++cg) {
+        const double b = xs[(rr + kk) * NC + cg * kSketchCols + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[cg][q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)z[q], b, acc[cg][q], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  const int c = col0 + (lane & 15);
-  if ((lane & 15) < nc) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+  for (int cg = 0; cg < NCG; ++cg) {
+    const int cl = cg * kSketchCols + (lane & 15);
+    if (cl < nc) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        // v_mfma_f64_16x16x4f64 output: register v of lane l holds row l/16 + 4v
-        const int t = 4 * (tbase / 4 + (lane >> 4) + 4 * v) + q;
-        if (t < k) partial[((int64_t)g * ncols + c) * k + t] = acc[q][v];
-      }
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // v_mfma_f64_16x16x4f64 output: register v of lane l holds row l/16 + 4v
+          const int t = 4 * (tbase / 4 + (lane >> 4) + 4 * v) + q;
+          if (t < k) partial[((int64_t)g * ncols + col0 + cl) * k + t] = acc[cg][q][v];
+        }
+    }
   }
 }
+
+#ifndef RBGS_GA_WGS
+#define RBGS_GA_WGS 2048   // workgroups of a dense sketch launch (about 8 waves per SIMD)
+#endif
+// Column groups of 16 per workgroup of the dense sketch kernel.
+static int dense_ncg(int64_t groups) { return groups >= 4 ? 4 : (groups >= 2 ? 2 : 1); }
 
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of the partial sums, scaled once in FP64.
@@ -628,12 +646,12 @@ static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups) {
   // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
-  // over the column groups.  Dense (Gaussian, Rademacher): about 512
+  // over the column groups.  Dense (Gaussian, Rademacher): about RBGS_GA_WGS
   // workgroups of 256 threads.  Each row range is at least one tile long.
   const int64_t groups = ceil_div(ncols, kSketchCols);
   int64_t G, tile;
   if (sk.kind == kGaussian || sk.kind == kRademacher) {
-    G = ceil_div(512, groups * ceil_div(sk.k, 256));
+    G = ceil_div(RBGS_GA_WGS, ceil_div(groups, dense_ncg(groups)) * ceil_div(sk.k, 256));
     tile = kGaTile;
   } else if (sk.kind == kSrht) {
     // one 1024-thread workgroup per CU; a range may start mid-chunk, so it
@@ -716,16 +734,25 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
                            sk.key1, cpw, partial);
     }
   } else {
+    const int ncg = dense_ncg(groups);
     const int64_t rpw = ceil_div(ceil_div(n, G), kGaTile) * kGaTile;
-    dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)groups);
-#define RBGS_GA(T, KIND)                                                                         \
-  hipLaunchKernelGGL((sketch_gauss_kernel<T, KIND>), grid, dim3(kGaThreads), 0, st, (const T*)X, \
-                     ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1, rpw, partial)
+    dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)ceil_div(groups, ncg));
+#define RBGS_GA(T, KIND, NCG)                                                                   \
+  hipLaunchKernelGGL((sketch_gauss_kernel<T, KIND, NCG>), grid, dim3(kGaThreads), 0, st,       \
+                     (const T*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1, rpw, \
+                     partial)
+#define RBGS_GA_NCG(T, KIND)                                 \
+  do {                                                       \
+    if (ncg == 4) RBGS_GA(T, KIND, 4);                       \
+    else if (ncg == 2) RBGS_GA(T, KIND, 2);                  \
+    else RBGS_GA(T, KIND, 1);                                \
+  } while (0)
     if (sk.kind == kRademacher) {
-      if (f32) RBGS_GA(float, kRademacher); else RBGS_GA(double, kRademacher);
+      if (f32) RBGS_GA_NCG(float, kRademacher); else RBGS_GA_NCG(double, kRademacher);
     } else {
-      if (f32) RBGS_GA(float, kGaussian); else RBGS_GA(double, kGaussian);
+      if (f32) RBGS_GA_NCG(float, kGaussian); else RBGS_GA_NCG(double, kGaussian);
     }
+#undef RBGS_GA_NCG
 #undef RBGS_GA
   }
   return hipGetLastError();
