@@ -381,6 +381,7 @@ struct QrRun {
   int64_t* flag;
   unsigned* counters;
   bool overlap;  // sketches of blocks 1.. of W on the side stream (rbgs_qr only)
+  bool pair;     // dense sketches: W_(i+1) sketched together with Q_(i) (rbgs_qr only)
 };
 
 // Workspace, zeroed R, breakdown flag, sketch plan.  `hoist` says whether all
@@ -420,9 +421,18 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   const size_t o_P = carve((size_t)k * m);
   const size_t o_E = carve((size_t)k * b);
   // partial sums for every sketch width used: all of W, a full block, the last block
-  size_t part_need = std::max(hoist ? sketch_partial_doubles(d, n, m) : 0,
+  const bool dense = d.kind == kGaussian || d.kind == kRademacher;
+  r.pair = hoist && dense && (m + b - 1) / b > 1;
+  size_t part_need = std::max(hoist && !r.pair ? sketch_partial_doubles(d, n, m) : 0,
                               sketch_partial_doubles(d, n, std::min<int64_t>(b, m)));
   if (m % b) part_need = std::max(part_need, sketch_partial_doubles(d, n, m % b));
+  if (r.pair) {
+    for (int64_t bw1 : {(int64_t)b, m % b}) {
+      if (bw1 == 0) continue;
+      const int64_t slots = dense_pair_slots(b, bw1);
+      part_need = std::max(part_need, (size_t)sketch_num_partials(d, n, slots, 0) * slots * k);
+    }
+  }
   const size_t o_part = carve(part_need);
   // The sketches of blocks 1.. of W run on a side stream while the main
   // stream works through earlier blocks (they only read W and the plan); the
@@ -486,6 +496,9 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   if (!hoist) return RBGS_OK;
   // ---- step 1 ahead of the loop: P = Theta W (W_(i) is not modified before
   // block i, so sketching it early gives the same P_(i)) --------------------
+  // Dense sketches: P_(1) here, P_(i+1) with S_(i) at the end of block i.
+  if (r.pair) return do_sketch(h, d, r.f32, W, ldw, n, std::min<int64_t>(b, m), 0, r.P, k, r.part,
+                               r.plan, st);
   if (!r.overlap) return do_sketch(h, d, r.f32, W, ldw, n, m, 0, r.P, k, r.part, r.plan, st);
   rs = ensure_side(h, (size_t)nblk + 1);
   if (rs != RBGS_OK) return rs;
@@ -626,6 +639,27 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     }
   }
   // ---- step 5: S_(i) = Theta Q_(i) ----------------------------------------
+  if (r.pair && c0 + b < m) {
+    // ... together with step 1 of block i+1, P_(i+1) = Theta W_(i+1): one pass
+    // over Theta, one reduction per block (the low-synchronization form)
+    const int64_t bw1 = std::min<int64_t>(b, m - c0 - b);
+    const void* W1 = r.Wb + r.es * (size_t)((c0 + b) * r.ldw);
+    const int64_t slots = dense_pair_slots(bw, bw1);
+    const int G = sketch_num_partials(d, n, slots, 0);
+    const double sc = sketch_scale(d);
+    {
+      ProfScope ps(h, kProfSketch, r.es * (double)n * (bw + bw1), st);
+      HIP_TRY(h, launch_sketch_dense_pair(d, r.f32, Qi, r.ldq, bw, W1, r.ldw, bw1, n, 0, r.part, st),
+              "sketch of Q_(i) and W_(i+1)");
+    }
+    ProfScope ps(h, kProfReduce, 8.0 * k * (bw + bw1), st);
+    HIP_TRY(h, launch_sketch_reduce(r.part, G, k, bw, sc, r.S + c0 * k, k, st, slots),
+            "sketch reduction");
+    HIP_TRY(h, launch_sketch_reduce(r.part + (slots - bw1) * k, G, k, bw1, sc, r.P + (c0 + b) * k, k,
+                                    st, slots),
+            "sketch reduction");
+    return RBGS_OK;
+  }
   return do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.S + c0 * k, k, r.part, r.plan, st);
 }
 

@@ -255,9 +255,20 @@ hipError_t launch_sparse_plan(const SketchDesc& sk, int64_t n, int64_t row0, uin
 hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X, int64_t ldx,
                                   int64_t n, int64_t ncols, int64_t row0, double* partial,
                                   const uint16_t* plan, hipStream_t st, int max_groups = 0);
-// out[t + c*ldo] = scale * sum_g partial[g][c][t]
+// out[t + c*ldo] = scale * sum_g partial[g][c][t] for c < ncols; the partial
+// sums hold part_cols columns per row group (0: ncols).
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
-                                double scale, double* out, int64_t ldo, hipStream_t st);
+                                double scale, double* out, int64_t ldo, hipStream_t st,
+                                int64_t part_cols = 0);
+// Dense (Gaussian, Rademacher) sketch of two column blocks in one pass that
+// shares every generated entry: X0 (n0 columns) into slots [0, S0), X1 (n1
+// columns) into slots [S0, S0 + n1), S0 = n0 rounded up to 16;
+// dense_pair_slots(n0, n1) = S0 + n1 slots of partial sums per row group
+// (sketch_num_partials(sk, n, slots) row groups).
+int64_t dense_pair_slots(int64_t n0, int64_t n1);
+hipError_t launch_sketch_dense_pair(const SketchDesc& sk, bool f32, const void* X0, int64_t ldx0,
+                                    int64_t n0, const void* X1, int64_t ldx1, int64_t n1,
+                                    int64_t n, int64_t row0, double* partial, hipStream_t st);
 // Identity sketch: out = X (converted to FP64).
 hipError_t launch_sketch_identity(bool f32, const void* X, int64_t ldx, int64_t n, int64_t ncols,
                                   double* out, int64_t ldo, hipStream_t st);

@@ -332,18 +332,36 @@ constexpr int kGaTile = 128;
 
 // NCG column groups of 16 per workgroup share every generated entry of Theta
 // (the generator dominates; one call feeds 4 NCG matrix-core instructions).
+//
+// Two sources (the low-sync step that sketches Q_(i) and W_(i+1) together):
+// the ncols columns of X take column slots [0, S0), S0 = ncols rounded up to
+// a multiple of 16, and the n1 columns of X2 the slots [S0, S0 + n1); partial
+// sums are indexed by slot (NS = S0 + n1 slots).  With n1 == 0 the slots are
+// the columns of X (NS = ncols).
 template <typename T, int KIND, int NCG>
 __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int64_t row0, int k,
-    uint32_t key0, uint32_t key1, int64_t rows_per_wg, double* __restrict__ partial) {
-  constexpr int NC = kSketchCols * NCG;           // columns per workgroup
+    uint32_t key0, uint32_t key1, int64_t rows_per_wg, double* __restrict__ partial,
+    const T* __restrict__ X2, int64_t ldx2, int n1) {
+  constexpr int NC = kSketchCols * NCG;           // column slots per workgroup
   constexpr int TILE = kGaTile / NCG;             // rows staged per step
   __shared__ double xs[TILE * NC];                // [rr][c]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
   const int tbase = blockIdx.y * 256 + wave * 64;
   const int col0 = blockIdx.z * NC;
-  const int nc = min(NC, ncols - col0);
+  const int S0 = n1 > 0 ? (ncols + kSketchCols - 1) / kSketchCols * kSketchCols : ncols;
+  const int NS = n1 > 0 ? S0 + n1 : ncols;
+  // slot -> (source, column, valid); columns of invalid slots are clamped
+  auto slot_src = [&](int slot, bool& ok) -> const T* {
+    if (slot < S0 || n1 == 0) {
+      ok = slot < ncols;
+      return X + (int64_t)(slot < ncols ? slot : ncols - 1) * ldx;
+    }
+    const int c2 = slot - S0;
+    ok = c2 < n1;
+    return X2 + (int64_t)(c2 < n1 ? c2 : n1 - 1) * ldx2;
+  };
   const int64_t rbeg = (int64_t)g * rows_per_wg;
   const int64_t rend = min(n, rbeg + rows_per_wg);
   const uint32_t j = (uint32_t)(tbase / 4 + (lane & 15));
@@ -360,17 +378,19 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
     const int trows = (int)min((int64_t)TILE, rend - tile0);
     // unconditional loads from clamped addresses, then masked
     T v[TILE * NC / kGaThreads];
+    bool okc[TILE * NC / kGaThreads];
 #pragma unroll
     for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
       const int e = tid + i * kGaThreads;
       const int c = e / TILE, rr = e % TILE;
-      v[i] = X[(tile0 + (rr < trows ? rr : trows - 1)) + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+      const T* src = slot_src(col0 + c, okc[i]);
+      v[i] = src[tile0 + (rr < trows ? rr : trows - 1)];
     }
 #pragma unroll
     for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
       const int e = tid + i * kGaThreads;
       const int c = e / TILE, rr = e % TILE;
-      xs[rr * NC + c] = (rr < trows && c < nc) ? to_f64(v[i]) : 0.0;
+      xs[rr * NC + c] = (rr < trows && okc[i]) ? to_f64(v[i]) : 0.0;
     }
     __syncthreads();
     for (int rr = 0; rr < trows; rr += 4) {
@@ -391,15 +411,17 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
   }
 #pragma unroll
   for (int cg = 0; cg < NCG; ++cg) {
-    const int cl = cg * kSketchCols + (lane & 15);
-    if (cl < nc) {
+    const int slot = col0 + cg * kSketchCols + (lane & 15);
+    bool ok;
+    (void)slot_src(slot, ok);
+    if (ok) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           // v_mfma_f64_16x16x4f64 output: register v of lane l holds row l/16 + 4v
           const int t = 4 * (tbase / 4 + (lane >> 4) + 4 * v) + q;
-          if (t < k) partial[((int64_t)g * ncols + col0 + cl) * k + t] = acc[cg][q][v];
+          if (t < k) partial[((int64_t)g * NS + slot) * k + t] = acc[cg][q][v];
         }
     }
   }
@@ -420,7 +442,7 @@ constexpr int kRedLanes = 8;
 __device__ __forceinline__ void sketch_reduce_body(const double* __restrict__ partial, int G,
                                                    int64_t k, int64_t ncols, double scale,
                                                    double* __restrict__ out, int64_t ldo,
-                                                   int64_t gid) {
+                                                   int64_t gid, int64_t part_cols) {
   const int q = (int)(gid % kRedLanes);
   const int64_t idx = gid / kRedLanes;
   const bool ok = idx < k * ncols;
@@ -428,7 +450,7 @@ __device__ __forceinline__ void sketch_reduce_body(const double* __restrict__ pa
   double s0 = 0.0, s1 = 0.0;
   if (ok) {
     const double* p = partial + c * k + t;
-    const int64_t stride = ncols * k;
+    const int64_t stride = part_cols * k;
     int g = q;
     for (; g + kRedLanes < G; g += 2 * kRedLanes) {
       s0 += p[(int64_t)g * stride];
@@ -445,9 +467,9 @@ __device__ __forceinline__ void sketch_reduce_body(const double* __restrict__ pa
 __global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __restrict__ partial,
                                                             int G, int64_t k, int64_t ncols,
                                                             double scale, double* __restrict__ out,
-                                                            int64_t ldo) {
+                                                            int64_t ldo, int64_t part_cols) {
   sketch_reduce_body(partial, G, k, ncols, scale, out, ldo,
-                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x, part_cols);
 }
 
 // Lock-step batch: blockIdx.y = problem; which = 0: into P, 1: into S (columns c0 ..).
@@ -458,7 +480,7 @@ __global__ __launch_bounds__(256) void sketch_reduce_batched_kernel(const BatchI
   const BatchItem& it = items[blockIdx.y];
   double* out = which == 0 ? it.P : it.S + c0 * k;
   sketch_reduce_body(it.part, it.sk_G, k, ncols, scale, out, k,
-                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncols);
 }
 
 template <typename T>
@@ -740,7 +762,7 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
 #define RBGS_GA(T, KIND, NCG)                                                                   \
   hipLaunchKernelGGL((sketch_gauss_kernel<T, KIND, NCG>), grid, dim3(kGaThreads), 0, st,       \
                      (const T*)X, ldx, n, (int)ncols, row0, (int)sk.k, sk.key0, sk.key1, rpw, \
-                     partial)
+                     partial, (const T*)X, ldx, 0)
 #define RBGS_GA_NCG(T, KIND)                                 \
   do {                                                       \
     if (ncg == 4) RBGS_GA(T, KIND, 4);                       \
@@ -759,10 +781,43 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
 }
 
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
-                                double scale, double* out, int64_t ldo, hipStream_t st) {
+                                double scale, double* out, int64_t ldo, hipStream_t st,
+                                int64_t part_cols) {
   const int64_t total = k * ncols * kRedLanes;
   hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
-                     partial, G, k, ncols, scale, out, ldo);
+                     partial, G, k, ncols, scale, out, ldo, part_cols > 0 ? part_cols : ncols);
+  return hipGetLastError();
+}
+
+int64_t dense_pair_slots(int64_t n0, int64_t n1) { return ceil_div(n0, kSketchCols) * kSketchCols + n1; }
+
+hipError_t launch_sketch_dense_pair(const SketchDesc& sk, bool f32, const void* X0, int64_t ldx0,
+                                    int64_t n0, const void* X1, int64_t ldx1, int64_t n1,
+                                    int64_t n, int64_t row0, double* partial, hipStream_t st) {
+  if (sk.kind != kGaussian && sk.kind != kRademacher) return hipErrorInvalidValue;
+  const int64_t NS = dense_pair_slots(n0, n1);
+  const int G = sketch_num_partials(sk, n, NS, 0);
+  const int64_t groups = ceil_div(NS, kSketchCols);
+  const int ncg = dense_ncg(groups);
+  const int64_t rpw = ceil_div(ceil_div(n, G), kGaTile) * kGaTile;
+  dim3 grid(G, (unsigned)ceil_div(sk.k, 256), (unsigned)ceil_div(groups, ncg));
+#define RBGS_GP(T, KIND, NCG)                                                                    \
+  hipLaunchKernelGGL((sketch_gauss_kernel<T, KIND, NCG>), grid, dim3(kGaThreads), 0, st,        \
+                     (const T*)X0, ldx0, n, (int)n0, row0, (int)sk.k, sk.key0, sk.key1, rpw,   \
+                     partial, (const T*)X1, ldx1, (int)n1)
+#define RBGS_GP_NCG(T, KIND)                                 \
+  do {                                                       \
+    if (ncg == 4) RBGS_GP(T, KIND, 4);                       \
+    else if (ncg == 2) RBGS_GP(T, KIND, 2);                  \
+    else RBGS_GP(T, KIND, 1);                                \
+  } while (0)
+  if (sk.kind == kRademacher) {
+    if (f32) RBGS_GP_NCG(float, kRademacher); else RBGS_GP_NCG(double, kRademacher);
+  } else {
+    if (f32) RBGS_GP_NCG(float, kGaussian); else RBGS_GP_NCG(double, kGaussian);
+  }
+#undef RBGS_GP_NCG
+#undef RBGS_GP
   return hipGetLastError();
 }
 
