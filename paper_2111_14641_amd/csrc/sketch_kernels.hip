@@ -162,19 +162,14 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 // exact sign (fma with +-1).  The next tile is prefetched into registers while
 // the current one is summed; every prefetch load is unconditional (clamped
 // index, masked value).
-#ifndef RBGS_SP_STAGE64
-#define RBGS_SP_STAGE64 0
-#endif
-#ifndef RBGS_SP_UNROLL2
-#define RBGS_SP_UNROLL2 0
-#endif
 template <typename T, int TPT>
 __device__ __forceinline__ void sketch_sparse_body(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
     int64_t tiles_per_wg, double* __restrict__ partial, int g, int cg) {
-  // staging type in LDS: the storage type, or FP64 (converted once per row)
-  typedef typename std::conditional<RBGS_SP_STAGE64 != 0, double, T>::type ST;
+  // staging type in LDS: the storage type (FP64 staging doubles the LDS
+  // traffic of the gathers and was not faster)
+  typedef T ST;
   typedef ST V4 __attribute__((ext_vector_type(4)));
   typedef unsigned short U8 __attribute__((ext_vector_type(8)));
   constexpr int XC = kSketchCols + (sizeof(ST) == 4 ? 4 : 0);  // padded row (16-byte aligned)
@@ -236,49 +231,20 @@ __device__ __forceinline__ void sketch_sparse_body(
     for (int j = 0; j < TPT; ++j) {
       const int t = tid + j * kSpThreads;
       if (t < k) {
-        // two entries per pass (more loads in flight); an odd count leaves
-        // the second slot empty: it re-reads the first row and adds nothing
+        // one entry per pass; the next entry is read while this one is summed
         const int b = off[t], e = off[t + 1];
-        if constexpr (sizeof(ST) == 8 || TPT > 1 || RBGS_SP_UNROLL2 == 0) {
-          // (register budget: one entry per pass; the next entry is read
-          // while this one is summed)
-          uint32_t vn = ent[b < e ? b : 0];
-          for (int i = b; i < e; ++i) {
-            const uint32_t v = vn;
-            vn = ent[i + 1 < e ? i + 1 : i];
-            const V4* xr = (const V4*)(xs + (v >> 1) * XC);
-            const double sg = (v & 1u) ? -1.0 : 1.0;
-#pragma unroll
-            for (int q = 0; q < kSketchCols / 4; ++q) {
-              const V4 x = xr[q];
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                acc[j][4 * q + u] = fma(sg, (double)x[u], acc[j][4 * q + u]);
-            }
-          }
-        } else
-        for (int i = b; i < e; i += 2) {
-          const bool two = i + 1 < e;
-          const uint32_t v0 = ent[i];
-          const uint32_t v1 = ent[two ? i + 1 : i];
-          const V4* xr0 = (const V4*)(xs + (v0 >> 1) * XC);
-          const V4* xr1 = (const V4*)(xs + (v1 >> 1) * XC);
-          const double s0 = (v0 & 1u) ? -1.0 : 1.0;
-          const double s1 = two ? ((v1 & 1u) ? -1.0 : 1.0) : 0.0;
-          V4 x0[kSketchCols / 4], x1[kSketchCols / 4];
+        uint32_t vn = ent[b < e ? b : 0];
+        for (int i = b; i < e; ++i) {
+          const uint32_t v = vn;
+          vn = ent[i + 1 < e ? i + 1 : i];
+          const V4* xr = (const V4*)(xs + (v >> 1) * XC);
+          const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
           for (int q = 0; q < kSketchCols / 4; ++q) {
-            x0[q] = xr0[q];
-            x1[q] = xr1[q];
-          }
+            const V4 x = xr[q];
 #pragma unroll
-          for (int q = 0; q < kSketchCols / 4; ++q) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const ST y1 = two ? x1[q][u] : (ST)0;
-              acc[j][4 * q + u] = fma(s0, (double)x0[q][u], acc[j][4 * q + u]);
-              acc[j][4 * q + u] = fma(s1, (double)y1, acc[j][4 * q + u]);
-            }
+            for (int u = 0; u < 4; ++u)
+              acc[j][4 * q + u] = fma(sg, (double)x[u], acc[j][4 * q + u]);
           }
         }
       }

@@ -23,17 +23,8 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 #ifndef RBGS_UP_UNROLL
 #define RBGS_UP_UNROLL 4
 #endif
-#ifndef RBGS_UP_PINGPONG
-#define RBGS_UP_PINGPONG 1
-#endif
 #ifndef RBGS_UP_SLAB
 #define RBGS_UP_SLAB 16   // columns of the product per pass through LDS in the epilogue
-#endif
-#ifndef RBGS_UP_WLATE
-#define RBGS_UP_WLATE 0   // 1: load the W_(i) row in the epilogue instead of before the product
-#endif
-#ifndef RBGS_UP_WSYNC
-#define RBGS_UP_WSYNC 1   // wave-level ordering between the slab writes and reads
 #endif
 #ifndef RBGS_UP_MINW
 #define RBGS_UP_MINW 0    // > 0: ask the compiler for this many waves per SIMD
@@ -138,15 +129,13 @@ __device__ __forceinline__ void update_tile(
   const bool own = lane < WROWS && (!TAIL || row < n);
   const int bwc = bw - 1;
 
-  // W_(i) row of this lane (loaded first so its latency overlaps the product,
-  // or in the epilogue to free registers during the product)
+  // W_(i) row of this lane, loaded first so its latency overlaps the product
   T wrow[NCOL];
-  auto load_w = [&]() {
+  {
     const int64_t rr = TAIL ? (row < n ? row : n - 1) : (lane < WROWS ? row : wrow0);
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) wrow[c] = W[rr + (int64_t)(c < bw ? c : bwc) * ldw];
-  };
-  if (!RBGS_UP_WLATE) load_w();
+  }
   if (Rii != nullptr) {
     for (int e = threadIdx.x; e < NCOL * NCOL; e += kUpThreads) {
       const int r = e % NCOL, c = e / NCOL;
@@ -208,7 +197,6 @@ __device__ __forceinline__ void update_tile(
     }
     __syncthreads();
     constexpr int GS = 4 * kUnroll;
-#if RBGS_UP_PINGPONG
     // ping-pong: the loads of group g+1 are in flight during the products of group g
     T a0[kUnroll][VEC], a1[kUnroll][VEC];
     load_group(a0, kc0, 0);
@@ -220,17 +208,9 @@ __device__ __forceinline__ void update_tile(
         mma_group(a1, kc, ks0 + GS);
       }
     }
-#else
-    for (int ks0 = 0; ks0 < kc; ks0 += GS) {
-      T a0[kUnroll][VEC];
-      load_group(a0, kc0, ks0);
-      mma_group(a0, kc, ks0);
-    }
-#endif
   }
   // Epilogue: lane owns row wrow0 + lane (lanes >= WROWS idle); the product is
   // moved through LDS one slab of SLAB columns at a time.
-  if (RBGS_UP_WLATE) load_w();
   constexpr int SLAB = Sh::SLAB;
   C* ct = ubuf + wave * WROWS * CT_LD;
   double x[NCOL];
@@ -246,14 +226,11 @@ __device__ __forceinline__ void update_tile(
           for (int e = 0; e < 4; ++e)
             ct[(VEC * M::row(kk, e) + v) * CT_LD + (li - h * SLAB)] = acc[v][nb][e];
       }
-      // the slab region of a wave is written and read by that wave only
-#if RBGS_UP_WSYNC
+      // the slab region of a wave is written and read by that wave only:
+      // wave-level ordering suffices
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#else
-      __syncthreads();
-#endif
       const int lr = lane < WROWS ? lane : 0;
 #pragma unroll
       for (int c = 0; c < SLAB; ++c) {
