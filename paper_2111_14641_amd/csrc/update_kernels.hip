@@ -21,7 +21,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 #ifndef RBGS_UP_UNROLL
-#define RBGS_UP_UNROLL 4
+#define RBGS_UP_UNROLL 4   // FP32 storage; FP64 storage (twice the bytes per load) uses half
 #endif
 #ifndef RBGS_UP_SLAB
 #define RBGS_UP_SLAB 16   // columns of the product per pass through LDS in the epilogue
@@ -32,7 +32,11 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kUpThreads = 256;
 constexpr int kKC = 128;                  // rows of R per LDS chunk
-constexpr int kUnroll = RBGS_UP_UNROLL;   // K-steps whose loads are issued together
+// K-steps whose loads are issued together (measured: 4 for FP32, 2 for FP64 storage)
+template <typename T>
+struct UpUnroll {
+  static constexpr int N = sizeof(T) == 4 ? RBGS_UP_UNROLL : (RBGS_UP_UNROLL + 1) / 2;
+};
 constexpr int kMaxB = 32;
 
 // Matrix-core operations by compute type.  Output layout of the 16x16x4
@@ -151,6 +155,7 @@ __device__ __forceinline__ void update_tile(
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[v][nb] = (typename M::acc_t){0, 0, 0, 0};
 
+  constexpr int kUnroll = UpUnroll<T>::N;
   // A operand group: kUnroll K-steps of 4 columns, one 16-byte load per step.
   auto load_group = [&](T (&a)[kUnroll][VEC], int kc0, int ks0) {
 #pragma unroll
