@@ -10,6 +10,8 @@ namespace rbgs {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 template <typename T>
 __device__ __forceinline__ double to_f64(T x) {
   return (double)x;
@@ -19,16 +21,15 @@ __device__ __forceinline__ double to_f64(T x) {
 // Sparse sign: every row r of X contributes +-X[r, :] to zeta target rows of
 // the sketch (one per segment of L = k/zeta rows).  Per tile of rows the
 // (row, target) pairs are counting-sorted by target in LDS; each thread owns
-// one or two targets, sums the rows of its bucket in increasing row order in
-// FP64 registers, and keeps its running sums across tiles.  No thread ever
+// one or more targets, sums the rows of its buckets in increasing row order
+// in FP64 registers, and keeps its running sums across tiles.  No thread ever
 // updates another thread's sums, so there are no floating-point atomics and
 // the summation order is fixed.
 // ---------------------------------------------------------------------------
-constexpr int kSpThreads = 1024;
+constexpr int kSpThreads = 1024;  // plan kernels
 constexpr int kSpTile = 1024;  // rows per tile (one row per thread)
 constexpr int kSpMaxK = 2048;
 constexpr int kSpMaxZeta = 8;
-constexpr int kSpEntVec = kSpTile * kSpMaxZeta / kSpThreads;  // plan entries per thread (8)
 
 __device__ __forceinline__ void block_exclusive_scan_2048(int* cnt, int* off, int* cur, int k) {
   // Each thread scans two consecutive counters; wave prefix sums via shuffles;
@@ -155,81 +156,124 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
                    (int64_t)blockIdx.x - it.plan_tile0);
 }
 
-// Sparse-sign partial sums from a plan.  A workgroup owns a range of tiles and
-// one group of up to 16 columns; thread t owns targets t (and t + 1024).  Per
-// tile the rows are staged in LDS in the storage precision (exact), thread r
-// staging row r, and each thread sums its bucket in row order in FP64 with an
-// exact sign (fma with +-1).  The next tile is prefetched into registers while
-// the current one is summed; every prefetch load is unconditional (clamped
-// index, masked value).
+// Sparse-sign partial sums from a plan.  A workgroup of NT threads owns a
+// range of tiles and a slice of NC columns; thread t owns targets t + NT j
+// (j < TPT).  Per tile the rows are staged in LDS in the storage precision
+// (exact), and each thread sums the rows of its buckets in row order in FP64
+// with an exact sign (fma with +-1), keeping its running sums in registers
+// across tiles.  The next tile is prefetched into registers while the current
+// one is summed; every prefetch load is unconditional (clamped index).  The
+// shape is chosen per storage type (measured): FP32 rows are narrow enough to
+// stage 16 columns for 1024 threads; FP64 takes 4 columns for 512 threads, so
+// three workgroups share a CU and hide one another's barriers.  The slices of
+// one row range are G apart in blockIdx.x (a multiple of 8 when G is), so
+// they run on the same XCD and share the plan through its L2.
+#ifndef RBGS_SPQ_NT32
+#define RBGS_SPQ_NT32 1024   // FP32 storage: threads per workgroup
+#endif
+#ifndef RBGS_SPQ_NC32
+#define RBGS_SPQ_NC32 16     // FP32 storage: columns per workgroup
+#endif
+#ifndef RBGS_SPQ_NT64
+#define RBGS_SPQ_NT64 512    // FP64 storage
+#endif
+#ifndef RBGS_SPQ_NC64
+#define RBGS_SPQ_NC64 4
+#endif
+template <typename T>
+struct SpqShape {
+  static constexpr int NT = sizeof(T) == 4 ? RBGS_SPQ_NT32 : RBGS_SPQ_NT64;
+  static constexpr int NC = sizeof(T) == 4 ? RBGS_SPQ_NC32 : RBGS_SPQ_NC64;
+};
+
 template <typename T, int TPT>
-__device__ __forceinline__ void sketch_sparse_body(
+__device__ __forceinline__ void sketch_sparse_q_body(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
-    int64_t tiles_per_wg, double* __restrict__ partial, int g, int cg) {
-  // staging type in LDS: the storage type (FP64 staging doubles the LDS
-  // traffic of the gathers and was not faster)
-  typedef T ST;
-  typedef ST V4 __attribute__((ext_vector_type(4)));
+    int64_t tiles_per_wg, double* __restrict__ partial, int g, int cs) {
+  constexpr int NT = SpqShape<T>::NT;
+  constexpr int NC = SpqShape<T>::NC;
+  static_assert(NC % 4 == 0, "columns per workgroup: a multiple of 4");
+  typedef T V4 __attribute__((ext_vector_type(4)));
   typedef unsigned short U8 __attribute__((ext_vector_type(8)));
-  constexpr int XC = kSketchCols + (sizeof(ST) == 4 ? 4 : 0);  // padded row (16-byte aligned)
-  __shared__ __attribute__((aligned(32))) ST xs[kSpTile * XC];  // [rr][c]
-  __shared__ __attribute__((aligned(16))) uint16_t ent[kSpTile * kSpMaxZeta];
+  constexpr int RPT = kSpTile / NT;                    // staged rows per thread
+  constexpr int EVT = kSpTile * kSpMaxZeta / 8 / NT;   // entry vectors per thread
+  // row stride: FP32 rows of 8 or more columns are padded by 16 bytes so that
+  // rows gathered at random start on more distinct banks
+  constexpr int XC = NC + ((sizeof(T) == 4 && NC >= 8) ? 4 : 0);
+  __shared__ __attribute__((aligned(32))) T xs[kSpTile * XC];  // [rr][c]
+  __shared__ __attribute__((aligned(16))) U8 ent8[kSpTile * kSpMaxZeta / 8];
   __shared__ uint16_t off[kSpMaxK + 1];
+  const uint16_t* ent = (const uint16_t*)ent8;
 
   const int tid = threadIdx.x;
-  const int col0 = cg * kSketchCols;
-  const int nc = min(kSketchCols, ncols - col0);
+  const int col0 = cs * NC;
+  const int nc = min(NC, ncols - col0);
   const int64_t ntiles = (n + kSpTile - 1) / kSpTile;
   const int64_t tbeg = (int64_t)g * tiles_per_wg;
   const int64_t tend = min(ntiles, tbeg + tiles_per_wg);
   const int E = kSpTile * zeta;  // plan entries per tile (a multiple of 8)
   const int nvec = E / 8;
 
-  double acc[TPT][kSketchCols];
+  double acc[TPT][NC];
 #pragma unroll
   for (int j = 0; j < TPT; ++j)
 #pragma unroll
-    for (int c = 0; c < kSketchCols; ++c) acc[j][c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[j][c] = 0.0;
 
-  T px[kSketchCols];
-  U8 pe;
+  T px[RPT][NC];
+  U8 pe[EVT];
   uint16_t po[TPT + 1];
   auto fetch = [&](int64_t tile) {
     const int64_t r0 = tile * kSpTile;
     const int trows = (int)min((int64_t)kSpTile, n - r0);
-    // Rows past the end and columns past nc are loaded from clamped
-    // addresses and never masked: no plan entry names such a row, and the sums
-    // of such columns are never stored.  (A masked value would let the
-    // compiler move each load under a branch and wait for it there.)
-    const int64_t rr = r0 + (tid < trows ? tid : trows - 1);
+    // clamped, unmasked loads: no plan entry names a row past the end, and
+    // the sums of columns past nc are never stored
 #pragma unroll
-    for (int c = 0; c < kSketchCols; ++c) px[c] = X[rr + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
-    pe = ((const U8*)(plan_ent + tile * (int64_t)E))[tid < nvec ? tid : nvec - 1];
+    for (int q = 0; q < RPT; ++q) {
+      const int rr = tid + NT * q;
+      const int64_t r = r0 + (rr < trows ? rr : trows - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        px[q][c] = X[r + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+    }
+    const U8* pv = (const U8*)(plan_ent + tile * (int64_t)E);
+#pragma unroll
+    for (int q = 0; q < EVT; ++q) {
+      const int v = tid + NT * q;
+      pe[q] = pv[v < nvec ? v : nvec - 1];
+    }
     const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
 #pragma unroll
     for (int i = 0; i <= TPT; ++i) {
-      const int t = tid + i * kSpThreads;
+      const int t = tid + i * NT;
       po[i] = so[t <= k ? t : k];
     }
   };
   if (tbeg < tend) fetch(tbeg);
   for (int64_t tile = tbeg; tile < tend; ++tile) {
-    V4* xw = (V4*)(xs + tid * XC);
 #pragma unroll
-    for (int q = 0; q < kSketchCols / 4; ++q)
-      xw[q] = (V4){(ST)px[4 * q], (ST)px[4 * q + 1], (ST)px[4 * q + 2], (ST)px[4 * q + 3]};
-    if (tid < nvec) ((U8*)ent)[tid] = pe;
+    for (int q = 0; q < RPT; ++q) {
+      V4* xw = (V4*)(xs + (tid + NT * q) * XC);
+#pragma unroll
+      for (int w = 0; w < NC / 4; ++w)
+        xw[w] = (V4){px[q][4 * w], px[q][4 * w + 1], px[q][4 * w + 2], px[q][4 * w + 3]};
+    }
+#pragma unroll
+    for (int q = 0; q < EVT; ++q) {
+      const int v = tid + NT * q;
+      if (v < nvec) ent8[v] = pe[q];
+    }
 #pragma unroll
     for (int i = 0; i <= TPT; ++i) {
-      const int t = tid + i * kSpThreads;
+      const int t = tid + i * NT;
       if (t <= k) off[t] = po[i];
     }
     if (tile + 1 < tend) fetch(tile + 1);   // in flight while this tile is summed
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < TPT; ++j) {
-      const int t = tid + j * kSpThreads;
+      const int t = tid + j * NT;
       if (t < k) {
         // one entry per pass; the next entry is read while this one is summed
         const int b = off[t], e = off[t + 1];
@@ -240,11 +284,10 @@ __device__ __forceinline__ void sketch_sparse_body(
           const V4* xr = (const V4*)(xs + (v >> 1) * XC);
           const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-          for (int q = 0; q < kSketchCols / 4; ++q) {
-            const V4 x = xr[q];
+          for (int w = 0; w < NC / 4; ++w) {
+            const V4 x = xr[w];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-              acc[j][4 * q + u] = fma(sg, (double)x[u], acc[j][4 * q + u]);
+            for (int u = 0; u < 4; ++u) acc[j][4 * w + u] = fma(sg, (double)x[u], acc[j][4 * w + u]);
           }
         }
       }
@@ -253,35 +296,64 @@ __device__ __forceinline__ void sketch_sparse_body(
   }
 #pragma unroll
   for (int j = 0; j < TPT; ++j) {
-    const int t = tid + j * kSpThreads;
+    const int t = tid + j * NT;
     if (t < k) {
 #pragma unroll
-      for (int c = 0; c < kSketchCols; ++c)
+      for (int c = 0; c < NC; ++c)
         if (c < nc) partial[((int64_t)g * ncols + col0 + c) * k + t] = acc[j][c];
     }
   }
 }
 
+// blockIdx.x = row range g + G * slice.
 template <typename T, int TPT>
-__global__ __launch_bounds__(kSpThreads) void sketch_sparse_kernel(
+__global__ __launch_bounds__(SpqShape<T>::NT) void sketch_sparse_q_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
-    int64_t tiles_per_wg, double* __restrict__ partial) {
-  sketch_sparse_body<T, TPT>(X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg, partial,
-                             blockIdx.x, blockIdx.y);
+    int64_t tiles_per_wg, double* __restrict__ partial, int G) {
+  const int g = (int)(blockIdx.x % (unsigned)G);
+  const int cs = (int)(blockIdx.x / (unsigned)G);
+  sketch_sparse_q_body<T, TPT>(X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg,
+                               partial, g, cs);
 }
 
-// Lock-step batch: workgroup -> (problem, row group) over the flattened
-// groups; which = 0 sketches W (columns 0 ..), which = 1 Q (columns c0 ..).
+// Lock-step batch: blockIdx.x -> (problem, row range) over the flattened
+// ranges, blockIdx.y = column slice; which = 0 sketches W (columns 0 ..),
+// which = 1 Q (columns c0 ..).
 template <typename T, int TPT>
-__global__ __launch_bounds__(kSpThreads) void sketch_sparse_batched_kernel(
+__global__ __launch_bounds__(SpqShape<T>::NT) void sketch_sparse_q_batched_kernel(
     const BatchItem* items, int nprob, int which, int64_t c0, int ncols, int k, int zeta) {
   const int p = batch_find(nprob, blockIdx.x, [&](int q) { return items[q].sk_wg0; });
   const BatchItem& it = items[p];
   const T* X = which == 0 ? (const T*)it.W : (const T*)it.Q + c0 * it.ldq;
   const int64_t ldx = which == 0 ? it.ldw : it.ldq;
-  sketch_sparse_body<T, TPT>(X, ldx, it.n, ncols, k, zeta, it.plan_off, it.plan_ent, it.sk_tpw,
-                             it.part, (int)((int64_t)blockIdx.x - it.sk_wg0), blockIdx.y);
+  sketch_sparse_q_body<T, TPT>(X, ldx, it.n, ncols, k, zeta, it.plan_off, it.plan_ent, it.sk_tpw,
+                               it.part, (int)((int64_t)blockIdx.x - it.sk_wg0), blockIdx.y);
+}
+
+template <typename T>
+static hipError_t launch_sparse_q(const T* X, int64_t ldx, int64_t n, int64_t ncols, int k,
+                                  int zeta, const uint16_t* plan_off, const uint16_t* plan_ent,
+                                  int64_t tpw, double* partial, int G, hipStream_t st) {
+  constexpr int NT = SpqShape<T>::NT;
+  const unsigned slices = (unsigned)ceil_div(ncols, SpqShape<T>::NC);
+  const int tpt = (int)ceil_div(k, NT);
+#define RBGS_SPQ(TPT)                                                                          \
+  hipLaunchKernelGGL((sketch_sparse_q_kernel<T, TPT>), dim3((unsigned)G * slices), dim3(NT), 0, \
+                     st, X, ldx, n, (int)ncols, k, zeta, plan_off, plan_ent, tpw, partial, G)
+  constexpr int kMaxTpt = kSpMaxK / NT;
+  if (tpt > kMaxTpt) return hipErrorInvalidValue;
+  if (tpt <= 1) {
+    RBGS_SPQ(1);
+  } else if (tpt <= 2) {
+    if constexpr (kMaxTpt >= 2) RBGS_SPQ(2);
+  } else if (tpt <= 4) {
+    if constexpr (kMaxTpt >= 4) RBGS_SPQ(4);
+  } else {
+    if constexpr (kMaxTpt >= 8) RBGS_SPQ(8);
+  }
+#undef RBGS_SPQ
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -630,7 +702,6 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups) {
   // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
@@ -687,17 +758,11 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
     if (plan_off == nullptr || plan_ent == nullptr) return hipErrorInvalidValue;
     const int64_t ntiles = ceil_div(n, kSpTile);
     const int64_t tpw = ceil_div(ntiles, G);
-    dim3 grid(G, (unsigned)groups);
-    const bool two = sk.k > kSpThreads;
-#define RBGS_SP(T, TPT)                                                                          \
-  hipLaunchKernelGGL((sketch_sparse_kernel<T, TPT>), grid, dim3(kSpThreads), 0, st, (const T*)X, \
-                     ldx, n, (int)ncols, (int)sk.k, sk.zeta, plan_off, plan_ent, tpw, partial)
-    if (f32) {
-      if (two) RBGS_SP(float, 2); else RBGS_SP(float, 1);
-    } else {
-      if (two) RBGS_SP(double, 2); else RBGS_SP(double, 1);
-    }
-#undef RBGS_SP
+    if (f32)
+      return launch_sparse_q((const float*)X, ldx, n, ncols, (int)sk.k, sk.zeta, plan_off,
+                             plan_ent, tpw, partial, G, st);
+    return launch_sparse_q((const double*)X, ldx, n, ncols, (int)sk.k, sk.zeta, plan_off,
+                           plan_ent, tpw, partial, G, st);
   } else if (sk.kind == kSrht) {
     const int64_t nchunks = (row0 + n - 1) / kHrChunk + 1 - row0 / kHrChunk;
     const int64_t cpw = ceil_div(nchunks, G);
@@ -798,21 +863,39 @@ hipError_t launch_plan_batched(const BatchItem* items, int nprob, int64_t total_
   return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_sparse_q_batched(const BatchItem* items, int nprob, int64_t total_wgs,
+                                          int which, int64_t c0, int64_t ncols, int k, int zeta,
+                                          hipStream_t st) {
+  constexpr int NT = SpqShape<T>::NT;
+  constexpr int kMaxTpt = kSpMaxK / NT;
+  const int tpt = (int)ceil_div(k, NT);
+  if (tpt > kMaxTpt) return hipErrorInvalidValue;
+  dim3 grid((unsigned)total_wgs, (unsigned)ceil_div(ncols, SpqShape<T>::NC));
+#define RBGS_SPQB(TPT)                                                                       \
+  hipLaunchKernelGGL((sketch_sparse_q_batched_kernel<T, TPT>), grid, dim3(NT), 0, st, items, \
+                     nprob, which, c0, (int)ncols, k, zeta)
+  if (tpt <= 1) {
+    RBGS_SPQB(1);
+  } else if (tpt <= 2) {
+    if constexpr (kMaxTpt >= 2) RBGS_SPQB(2);
+  } else if (tpt <= 4) {
+    if constexpr (kMaxTpt >= 4) RBGS_SPQB(4);
+  } else {
+    if constexpr (kMaxTpt >= 8) RBGS_SPQB(8);
+  }
+#undef RBGS_SPQB
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_batched(bool f32, const BatchItem* items, int nprob, int64_t total_wgs,
                                  int which, int64_t c0, int64_t ncols, int k, int zeta,
                                  double scale, hipStream_t st) {
   if (k > kSpMaxK) return hipErrorInvalidValue;
-  dim3 grid((unsigned)total_wgs, (unsigned)ceil_div(ncols, kSketchCols));
-  const bool two = k > kSpThreads;
-#define RBGS_SPB(T, TPT)                                                                    \
-  hipLaunchKernelGGL((sketch_sparse_batched_kernel<T, TPT>), grid, dim3(kSpThreads), 0, st, \
-                     items, nprob, which, c0, (int)ncols, k, zeta)
-  if (f32) {
-    if (two) RBGS_SPB(float, 2); else RBGS_SPB(float, 1);
-  } else {
-    if (two) RBGS_SPB(double, 2); else RBGS_SPB(double, 1);
-  }
-#undef RBGS_SPB
+  const hipError_t e =
+      f32 ? launch_sparse_q_batched<float>(items, nprob, total_wgs, which, c0, ncols, k, zeta, st)
+          : launch_sparse_q_batched<double>(items, nprob, total_wgs, which, c0, ncols, k, zeta, st);
+  if (e != hipSuccess) return e;
   const int64_t total = (int64_t)k * ncols * kRedLanes;
   hipLaunchKernelGGL(sketch_reduce_batched_kernel, dim3((unsigned)ceil_div(total, 256), (unsigned)nprob),
                      dim3(256), 0, st, items, which, c0, (int64_t)k, ncols, scale);
