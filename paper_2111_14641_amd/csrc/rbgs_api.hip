@@ -40,9 +40,6 @@ struct rbgs_handle_s {
   int64_t prof_cnt[kProfClasses] = {0};
   double prof_bytes[kProfClasses] = {0};
   double* host_cert = nullptr;  // pinned, 4 doubles + flag
-  hipStream_t side = nullptr;   // sketches of later blocks of W run here (default priority)
-  std::vector<hipEvent_t> sync_ev;  // ordering between the caller's stream and `side`
-  bool no_overlap = false;      // set on the lanes of a batch: everything on one stream
   // batched calls: lanes (child handles with their own stream and workspace)
   std::vector<rbgs_handle> lanes;
   std::vector<hipStream_t> lane_streams;
@@ -131,29 +128,6 @@ struct ProfScope {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-#ifndef RBGS_SIDE_GROUPS
-#define RBGS_SIDE_GROUPS 128
-#endif
-constexpr int kSideGroups = RBGS_SIDE_GROUPS;  // partial groups of a side-stream sketch
-
-// The side stream (created once, default priority, not blocking on the null
-// stream) and at least `nev` ordering events.
-rbgs_status ensure_side(rbgs_handle h, size_t nev) {
-  if (!h->side && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipGetLastError();
-    h->side = nullptr;
-    return fail(h, RBGS_EDEVICE, "side stream creation failed");
-  }
-  while (h->sync_ev.size() < nev) {
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(h, RBGS_EDEVICE, "event creation failed");
-    }
-    h->sync_ev.push_back(e);
-  }
-  return RBGS_OK;
-}
 
 rbgs_status ensure_ws(rbgs_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return RBGS_OK;
@@ -315,7 +289,7 @@ rbgs_status rbgs_create(rbgs_handle* h, int device) {
 rbgs_status rbgs_destroy(rbgs_handle h) {
   if (!h) return RBGS_OK;
   for (auto c : h->lanes) rbgs_destroy(c);
-  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert || h->side ||
+  if (h->ws || !h->recs.empty() || !h->pool.empty() || h->host_cert ||
       !h->lane_streams.empty() || h->graph || h->kry || h->bws) {
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
@@ -324,8 +298,6 @@ rbgs_status rbgs_destroy(rbgs_handle h) {
       (void)hipEventDestroy(r.b);
     }
     for (auto e : h->pool) (void)hipEventDestroy(e);
-    for (auto e : h->sync_ev) (void)hipEventDestroy(e);
-    if (h->side) (void)hipStreamDestroy(h->side);
     for (auto e : h->lane_ev) (void)hipEventDestroy(e);
     for (auto q : h->lane_streams) (void)hipStreamDestroy(q);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
@@ -376,11 +348,10 @@ struct QrRun {
   int64_t ldq;
   double* R;
   int64_t ldr;
-  double *S, *P, *E, *part, *part2, *stack, *G, *Cb, *Yb, *cscratch, *cout, *Rt, *tall;
+  double *S, *P, *E, *part, *stack, *G, *Cb, *Yb, *cscratch, *cout, *Rt, *tall;
   uint16_t* plan;
   int64_t* flag;
   unsigned* counters;
-  bool overlap;  // sketches of blocks 1.. of W on the side stream (rbgs_qr only)
   bool pair;     // dense sketches: W_(i+1) sketched together with Q_(i) (rbgs_qr only)
 };
 
@@ -434,21 +405,6 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
     }
   }
   const size_t o_part = carve(part_need);
-  // The sketches of blocks 1.. of W run on a side stream while the main
-  // stream works through earlier blocks (they only read W and the plan); the
-  // small factors of a block use few compute units, so these sketches mostly
-  // fill idle ones.  Block i waits for its sketch before its least squares.
-  const int64_t nblk = (m + b - 1) / b;
-  // (dense sketches are generator-bound: their W is sketched in one pass that
-  // shares every generated entry among four column groups, not block by block)
-  r.overlap = hoist && !h->no_overlap && d.kind != kIdentity && d.kind != kGaussian &&
-              d.kind != kRademacher && nblk > 1;
-  size_t part2_need = 0;
-  if (r.overlap) {
-    part2_need = sketch_partial_doubles(d, n, std::min<int64_t>(b, m), kSideGroups);
-    if (m % b) part2_need = std::max(part2_need, sketch_partial_doubles(d, n, m % b, kSideGroups));
-  }
-  const size_t o_part2 = carve(part2_need);
   const size_t o_stack = carve(qr_stack_size(k, b));
   const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
@@ -473,7 +429,6 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.P = (double*)(base + o_P);
   r.E = (double*)(base + o_E);
   r.part = (double*)(base + o_part);
-  r.part2 = (double*)(base + o_part2);
   r.stack = (double*)(base + o_stack);
   r.plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
   r.flag = (int64_t*)(base + o_flag);
@@ -499,23 +454,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   // Dense sketches: P_(1) here, P_(i+1) with S_(i) at the end of block i.
   if (r.pair) return do_sketch(h, d, r.f32, W, ldw, n, std::min<int64_t>(b, m), 0, r.P, k, r.part,
                                r.plan, st);
-  if (!r.overlap) return do_sketch(h, d, r.f32, W, ldw, n, m, 0, r.P, k, r.part, r.plan, st);
-  rs = ensure_side(h, (size_t)nblk + 1);
-  if (rs != RBGS_OK) return rs;
-  hipEvent_t ev_start = h->sync_ev[nblk];
-  HIP_TRY(h, hipEventRecord(ev_start, st), "event record");
-  HIP_TRY(h, hipStreamWaitEvent(h->side, ev_start, 0), "stream wait");
-  rs = do_sketch(h, d, r.f32, W, ldw, n, std::min<int64_t>(b, m), 0, r.P, k, r.part, r.plan, st);
-  if (rs != RBGS_OK) return rs;
-  for (int64_t blk = 1; blk < nblk; ++blk) {
-    const int64_t c0 = blk * b;
-    const int64_t bwb = std::min<int64_t>(b, m - c0);
-    rs = do_sketch(h, d, r.f32, r.Wb + r.es * (size_t)(c0 * ldw), ldw, n, bwb, 0, r.P + c0 * k, k,
-                   r.part2, r.plan, h->side, kSideGroups);
-    if (rs != RBGS_OK) return rs;
-    HIP_TRY(h, hipEventRecord(h->sync_ev[blk], h->side), "event record");
-  }
-  return RBGS_OK;
+  return do_sketch(h, d, r.f32, W, ldw, n, m, 0, r.P, k, r.part, r.plan, st);
 }
 
 // Steps 1 (unless hoisted) to 5 of block i = c0 / b, reading W_(i) at Wi (ld
@@ -538,7 +477,6 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     rs = do_sketch(h, d, r.f32, Wi, ldwi, n, bw, 0, Pi, k, r.part, r.plan, st);
     if (rs != RBGS_OK) return rs;
   }
-  if (r.overlap && K > 0) HIP_TRY(h, hipStreamWaitEvent(st, h->sync_ev[c0 / b], 0), "stream wait");
   // ---- step 2: sketched least squares by l Richardson sweeps ----------
   // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
   // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.
@@ -731,7 +669,6 @@ rbgs_status ensure_lanes(rbgs_handle h, int L) {
   while ((int)h->lanes.size() < L) {
     rbgs_handle c = nullptr;
     if (rbgs_create(&c, h->device) != RBGS_OK) return fail(h, RBGS_ENOMEM, "lane handle");
-    c->no_overlap = true;
     h->lanes.push_back(c);
   }
   while ((int)h->lane_streams.size() < L) {

@@ -180,19 +180,34 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 #ifndef RBGS_SPQ_NC64
 #define RBGS_SPQ_NC64 4
 #endif
-template <typename T>
+#ifndef RBGS_SPQ_NT32M
+#define RBGS_SPQ_NT32M 1024  // FP32 storage, sketches of more than 16 columns
+#endif
+#ifndef RBGS_SPQ_NC32M
+#define RBGS_SPQ_NC32M 16
+#endif
+#ifndef RBGS_SPQ_NT64M
+#define RBGS_SPQ_NT64M 512   // FP64 storage, sketches of more than 16 columns
+#endif
+#ifndef RBGS_SPQ_NC64M
+#define RBGS_SPQ_NC64M 4
+#endif
+// MANY: the sketch has more than one 16-column group (all of W at once)
+template <typename T, bool MANY = false>
 struct SpqShape {
-  static constexpr int NT = sizeof(T) == 4 ? RBGS_SPQ_NT32 : RBGS_SPQ_NT64;
-  static constexpr int NC = sizeof(T) == 4 ? RBGS_SPQ_NC32 : RBGS_SPQ_NC64;
+  static constexpr int NT = sizeof(T) == 4 ? (MANY ? RBGS_SPQ_NT32M : RBGS_SPQ_NT32)
+                                           : (MANY ? RBGS_SPQ_NT64M : RBGS_SPQ_NT64);
+  static constexpr int NC = sizeof(T) == 4 ? (MANY ? RBGS_SPQ_NC32M : RBGS_SPQ_NC32)
+                                           : (MANY ? RBGS_SPQ_NC64M : RBGS_SPQ_NC64);
 };
 
-template <typename T, int TPT>
+template <typename T, int TPT, bool MANY = false>
 __device__ __forceinline__ void sketch_sparse_q_body(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
     int64_t tiles_per_wg, double* __restrict__ partial, int g, int cs) {
-  constexpr int NT = SpqShape<T>::NT;
-  constexpr int NC = SpqShape<T>::NC;
+  constexpr int NT = SpqShape<T, MANY>::NT;
+  constexpr int NC = SpqShape<T, MANY>::NC;
   static_assert(NC % 4 == 0, "columns per workgroup: a multiple of 4");
   typedef T V4 __attribute__((ext_vector_type(4)));
   typedef unsigned short U8 __attribute__((ext_vector_type(8)));
@@ -306,15 +321,15 @@ __device__ __forceinline__ void sketch_sparse_q_body(
 }
 
 // blockIdx.x = row range g + G * slice.
-template <typename T, int TPT>
-__global__ __launch_bounds__(SpqShape<T>::NT) void sketch_sparse_q_kernel(
+template <typename T, int TPT, bool MANY>
+__global__ __launch_bounds__((SpqShape<T, MANY>::NT)) void sketch_sparse_q_kernel(
     const T* __restrict__ X, int64_t ldx, int64_t n, int ncols, int k, int zeta,
     const uint16_t* __restrict__ plan_off, const uint16_t* __restrict__ plan_ent,
     int64_t tiles_per_wg, double* __restrict__ partial, int G) {
   const int g = (int)(blockIdx.x % (unsigned)G);
   const int cs = (int)(blockIdx.x / (unsigned)G);
-  sketch_sparse_q_body<T, TPT>(X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg,
-                               partial, g, cs);
+  sketch_sparse_q_body<T, TPT, MANY>(X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg,
+                                     partial, g, cs);
 }
 
 // Lock-step batch: blockIdx.x -> (problem, row range) over the flattened
@@ -331,16 +346,17 @@ __global__ __launch_bounds__(SpqShape<T>::NT) void sketch_sparse_q_batched_kerne
                                it.part, (int)((int64_t)blockIdx.x - it.sk_wg0), blockIdx.y);
 }
 
-template <typename T>
+template <typename T, bool MANY>
 static hipError_t launch_sparse_q(const T* X, int64_t ldx, int64_t n, int64_t ncols, int k,
                                   int zeta, const uint16_t* plan_off, const uint16_t* plan_ent,
                                   int64_t tpw, double* partial, int G, hipStream_t st) {
-  constexpr int NT = SpqShape<T>::NT;
-  const unsigned slices = (unsigned)ceil_div(ncols, SpqShape<T>::NC);
+  constexpr int NT = SpqShape<T, MANY>::NT;
+  const unsigned slices = (unsigned)ceil_div(ncols, SpqShape<T, MANY>::NC);
   const int tpt = (int)ceil_div(k, NT);
-#define RBGS_SPQ(TPT)                                                                          \
-  hipLaunchKernelGGL((sketch_sparse_q_kernel<T, TPT>), dim3((unsigned)G * slices), dim3(NT), 0, \
-                     st, X, ldx, n, (int)ncols, k, zeta, plan_off, plan_ent, tpw, partial, G)
+#define RBGS_SPQ(TPT)                                                                         \
+  hipLaunchKernelGGL((sketch_sparse_q_kernel<T, TPT, MANY>), dim3((unsigned)G * slices),      \
+                     dim3(NT), 0, st, X, ldx, n, (int)ncols, k, zeta, plan_off, plan_ent, tpw, \
+                     partial, G)
   constexpr int kMaxTpt = kSpMaxK / NT;
   if (tpt > kMaxTpt) return hipErrorInvalidValue;
   if (tpt <= 1) {
@@ -758,11 +774,17 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
     if (plan_off == nullptr || plan_ent == nullptr) return hipErrorInvalidValue;
     const int64_t ntiles = ceil_div(n, kSpTile);
     const int64_t tpw = ceil_div(ntiles, G);
+    if (f32 && ncols > kSketchCols)
+      return launch_sparse_q<float, true>((const float*)X, ldx, n, ncols, (int)sk.k, sk.zeta,
+                                          plan_off, plan_ent, tpw, partial, G, st);
     if (f32)
-      return launch_sparse_q((const float*)X, ldx, n, ncols, (int)sk.k, sk.zeta, plan_off,
-                             plan_ent, tpw, partial, G, st);
-    return launch_sparse_q((const double*)X, ldx, n, ncols, (int)sk.k, sk.zeta, plan_off,
-                           plan_ent, tpw, partial, G, st);
+      return launch_sparse_q<float, false>((const float*)X, ldx, n, ncols, (int)sk.k, sk.zeta,
+                                           plan_off, plan_ent, tpw, partial, G, st);
+    if (ncols > kSketchCols)
+      return launch_sparse_q<double, true>((const double*)X, ldx, n, ncols, (int)sk.k, sk.zeta,
+                                           plan_off, plan_ent, tpw, partial, G, st);
+    return launch_sparse_q<double, false>((const double*)X, ldx, n, ncols, (int)sk.k, sk.zeta,
+                                          plan_off, plan_ent, tpw, partial, G, st);
   } else if (sk.kind == kSrht) {
     const int64_t nchunks = (row0 + n - 1) / kHrChunk + 1 - row0 / kHrChunk;
     const int64_t cpw = ceil_div(nchunks, G);

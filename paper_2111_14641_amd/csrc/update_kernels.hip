@@ -1,16 +1,25 @@
 // Tall-skinny update of Algorithm RBGS, step 3:  Q'_(i) = W_(i) - Q_(1:i-1) R_(1:i-1,i),
 // optionally followed in the same pass by the substitution of steps 4-5,
-// Q_(i) = Q'_(i) R_(i,i)^{-1} (row by row, FP64 arithmetic).
+// Q_(i) = Q'_(i) R_(i,i)^{-1} (FP64 arithmetic).
 //
-// The product runs on matrix cores, in FP64 (v_mfma_f64_16x16x4f64; FP32 data
-// are converted exactly) or, on request for FP32 storage, in FP32
-// (v_mfma_f32_16x16x4f32 with FP32 accumulation).  Each lane loads VEC
-// consecutive rows of one column of Q with one 16-byte load; element v of that
-// vector feeds the A operand of accumulator v, so accumulator v covers rows
-// VEC*i + v of the wave's row strip and one load feeds VEC*NB matrix-core
-// instructions.  R is staged in LDS in chunks of kKC rows.  The epilogue moves
-// the product through LDS so that each lane owns one full row for the
-// substitution and the stores are coalesced column by column.
+// Two forms.  The persistent form (update_p_kernel: FP64 arithmetic, bw <= 16,
+// K <= kUpPMaxK, the common case) keeps R_(1:i-1,i) in LDS for the whole
+// launch and applies the substitution as a second matrix-core product; it is
+// described where it is defined.  The general form (update_kernel: any width
+// up to 32, any K, and FP32 arithmetic) is below.
+//
+// General form.  The product runs on matrix cores, in FP64
+// (v_mfma_f64_16x16x4f64; FP32 data are converted exactly) or, on request for
+// FP32 storage, in FP32 (v_mfma_f32_16x16x4f32 with FP32 accumulation).  Each
+// lane loads VEC consecutive rows of one column of Q with one 16-byte load;
+// element v of that vector feeds the A operand of accumulator v, so
+// accumulator v covers rows VEC*i + v of the wave's row strip and one load
+// feeds VEC*NB matrix-core instructions.  R is staged in LDS in chunks of kKC
+// rows.  The epilogue moves the product through LDS so that each lane owns one
+// full row for the substitution and the stores are coalesced column by column.
+#include <algorithm>
+#include <type_traits>
+
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -298,6 +307,201 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
                                 tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form for FP64 arithmetic, bw <= 16 and K <= kUpPMaxK: each
+// workgroup stages R_(1:i-1,i) in LDS once and walks tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... without further barriers.  The product is formed
+// transposed, (Q R)^T = R^T Q^T (the R entry is the A operand, the Q element
+// the B operand), so lane (kk, li) ends with rows VEC li + v of the wave's
+// strip and columns kk + 4 e: each row is spread over the four lanes
+// (0..3, li).  The forward substitution of steps 4-5 runs on those registers
+// column by column, the solved entry handed across the four lanes by a lane
+// shuffle, so W, the result and the stores stay in registers: no LDS round
+// trip, no epilogue barrier.
+// ---------------------------------------------------------------------------
+constexpr int kUpPMaxK = 512;   // rows of R_(1:i-1,i) held in LDS (64 KB)
+#ifndef RBGS_UP_PUNROLL
+#define RBGS_UP_PUNROLL 2
+#endif
+constexpr int kUpPUnroll = RBGS_UP_PUNROLL;  // K-steps of loads issued together (measured)
+
+template <typename T, bool TAIL>
+__device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* __restrict__ Q,
+                                              int64_t ldq, T* Qout, int64_t ldqo,
+                                              const double* Rs, const double* Ru,
+                                              const double* Rinv, bool subst,
+                                              int64_t tile0, int64_t n, int K, int bw) {
+  typedef Mfma<double> M;
+  constexpr int VEC = Vec16<T>::N;
+  constexpr int WROWS = 16 * VEC;
+  typedef typename Vec16<T>::t VT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t arow = tile0 + (int64_t)wave * WROWS + (int64_t)VEC * li;  // this lane's rows
+  const int bwc = bw - 1;
+
+  // The accumulators start at -W_(i) (transposed layout: acc[v][e] holds
+  // row arow + v, column kk + 4 e), so W is not held through the product; its
+  // loads are issued together with the first group of Q.
+  constexpr int kUnroll = kUpPUnroll;
+  constexpr int GS = 4 * kUnroll;
+  auto load_group = [&](T (&a)[kUnroll][VEC], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      int col = ks0 + 4 * u + kk;
+      col = col < K ? col : K - 1;  // padded steps are skipped
+      const T* src = Q + arow + (int64_t)col * ldq;
+      if (!TAIL) {
+        const VT vv = *reinterpret_cast<const VT*>(src);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[u][v] = vv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const T x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
+          a[u][v] = in ? x : (T)0;
+        }
+      }
+    }
+  };
+  M::acc_t acc[VEC];
+  auto mma_group = [&](const T (&a)[kUnroll][VEC], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ks0 + 4 * u < K) {
+        const double b = Rs[(ks0 + 4 * u + kk) * 16 + li];  // R[ks + kk][li] = R^T[li][ks + kk]
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = M::mma(b, (double)a[u][v], acc[v]);
+      }
+    }
+  };
+  T a0[kUnroll][VEC], a1[kUnroll][VEC];
+  {
+    T w[4][VEC];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = kk + 4 * e < bw ? kk + 4 * e : bwc;
+      if (!TAIL) {
+        const VT vv = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) w[e][v] = vv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
+          w[e][v] = in ? x : (T)0;
+        }
+      }
+    }
+    if (K > 0) load_group(a0, 0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+      acc[v] = (M::acc_t){-(double)w[0][v], -(double)w[1][v], -(double)w[2][v], -(double)w[3][v]};
+  }
+  for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
+    if (ks0 + GS < K) load_group(a1, ks0 + GS);
+    mma_group(a0, ks0);
+    if (ks0 + GS < K) {
+      if (ks0 + 2 * GS < K) load_group(a0, ks0 + 2 * GS);
+      mma_group(a1, ks0 + GS);
+    }
+  }
+  // step 3: acc = Q R - W = -Q'_(i) (FP64)
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = -acc[v];
+  // steps 4-5: forward substitution x R_(i,i) = q' for every row, column by
+  // column in FP64: x_c = q'_c / R_cc (as q'_c (1 / R_cc)), then
+  // q'_c' -= x_c R_cc' for c' > c.  Column c of this lane's rows sits in lane
+  // (c % 4, li), element c / 4; it is handed to the lanes holding the other
+  // columns of the same rows by a lane shuffle.  Ru holds the strictly upper
+  // part of R_(i,i) (zero elsewhere and past bw), so the update needs no mask.
+  if (subst) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < bw) {
+        const int kc = c & 3, ec = c >> 2;
+        const double rinv = Rinv[c];
+        double xb[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][ec] * rinv, 16 * kc + li, 64);
+        if (kk == kc) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][ec] = xb[v];
+        }
+        double ru[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = kk + 4 * e;
+    if (c < bw) {
+      T* dst = Qout + arow + (int64_t)c * ldqo;
+      if (!TAIL) {
+        VT vv;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][e];
+        *reinterpret_cast<VT*>(dst) = vv;
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if (arow + v < n) dst[v] = (T)acc[v][e];
+      }
+    }
+  }
+}
+
+// LDS: Rs [Kp][16] (rows >= K zero); Ru [16][16] (column-major) = strictly
+// upper part of R_(i,i), zero past bw; Rinv [16] = 1 / R_cc (1 past bw).  FP64.
+template <typename T>
+__global__ __launch_bounds__(kUpThreads, 4) void update_p_kernel(
+    const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
+    const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t ntiles,
+    int64_t nfull, int64_t n, int K, int Kp, int bw) {
+  extern __shared__ __attribute__((aligned(16))) double up_lds[];
+  double* Rs = up_lds;
+  double* Ru = up_lds + (int64_t)Kp * 16;
+  double* Rinv = Ru + 256;
+  constexpr int TILE = 4 * 16 * Vec16<T>::N;
+  for (int e = threadIdx.x; e < Kp * 16; e += kUpThreads) {
+    const int r = e >> 4, c = e & 15;
+    const bool in = r < K && c < bw;
+    const double v = Rk[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
+    Rs[e] = in ? v : 0.0;
+  }
+  const bool subst = Rii != nullptr;
+  if (subst) {
+    {
+      const int e = threadIdx.x;  // 256 threads, one entry each
+      const int r = e & 15, c = e >> 4;
+      const bool in = r < c && c < bw;
+      const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
+      Ru[e] = in ? v : 0.0;
+    }
+    if (threadIdx.x < 16) {
+      const int c = threadIdx.x;
+      Rinv[c] = c < bw ? 1.0 / Rii[c + (int64_t)c * ldr] : 1.0;
+    }
+  }
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    if (tile < nfull)
+      update_p_tile<T, false>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
+                              bw);
+    else
+      update_p_tile<T, true>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
+                             bw);
+  }
+}
+
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t ldq,
@@ -339,10 +543,38 @@ static hipError_t launch_update_nb(const void* W, int64_t ldw, const void* Q, in
   return hipGetLastError();
 }
 
+#ifndef RBGS_UP_PWGS
+#define RBGS_UP_PWGS 1024   // workgroups of the persistent form (4 per CU)
+#endif
+
+static bool aligned16(const void* p, int64_t ld, int vec) {
+  return (ld % vec) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
+}
+
+template <typename T>
+static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int64_t ldq,
+                                  void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
+                                  int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
+  constexpr int VEC = Vec16<T>::N;
+  constexpr int TILE = 4 * 16 * VEC;
+  const bool vec_ok = aligned16(W, ldw, VEC) && aligned16(Qout, ldqo, VEC) &&
+                      (K == 0 || aligned16(Q, ldq, VEC));
+  const int64_t ntiles = ceil_div(n, TILE);
+  const int64_t nfull = vec_ok ? n / TILE : 0;
+  const int Kp = (int)((K + 3) / 4 * 4);
+  const size_t lds = ((size_t)Kp * 16 + 256 + 16) * sizeof(double);
+  const unsigned grid = (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
+  hipLaunchKernelGGL((update_p_kernel<T>), dim3(grid), dim3(kUpThreads), lds, st, (const T*)W, ldw,
+                     (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, (int)K, Kp, bw);
+  return hipGetLastError();
+}
+
 template <typename T, typename C>
 static hipError_t launch_update_t(const void* W, int64_t ldw, const void* Q, int64_t ldq,
                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
                                   int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
+  if (std::is_same<C, double>::value && bw <= 16 && K <= kUpPMaxK)
+    return launch_update_p<T>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   if (bw <= 16) return launch_update_nb<T, C, 1>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   return launch_update_nb<T, C, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
 }
