@@ -320,10 +320,17 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
 // trip, no epilogue barrier.
 // ---------------------------------------------------------------------------
 constexpr int kUpPMaxK = 512;   // rows of R_(1:i-1,i) held in LDS (64 KB)
-#ifndef RBGS_UP_PUNROLL
-#define RBGS_UP_PUNROLL 2
+#ifndef RBGS_UP_PUNROLL32
+#define RBGS_UP_PUNROLL32 2
 #endif
-constexpr int kUpPUnroll = RBGS_UP_PUNROLL;  // K-steps of loads issued together (measured)
+#ifndef RBGS_UP_PUNROLL64
+#define RBGS_UP_PUNROLL64 2
+#endif
+// K-steps of loads issued together (measured)
+template <typename T>
+struct UpPUnroll {
+  static constexpr int N = sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64;
+};
 
 template <typename T, bool TAIL>
 __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* __restrict__ Q,
@@ -343,7 +350,7 @@ __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* 
   // The accumulators start at -W_(i) (transposed layout: acc[v][e] holds
   // row arow + v, column kk + 4 e), so W is not held through the product; its
   // loads are issued together with the first group of Q.
-  constexpr int kUnroll = kUpPUnroll;
+  constexpr int kUnroll = UpPUnroll<T>::N;
   constexpr int GS = 4 * kUnroll;
   auto load_group = [&](T (&a)[kUnroll][VEC], int ks0) {
 #pragma unroll
@@ -430,13 +437,14 @@ __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* 
 #pragma unroll
           for (int v = 0; v < VEC; ++v) acc[v][ec] = xb[v];
         }
+        // columns kk + 4 e with e < ec are below c in every lane: nothing to do
         double ru[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
+        for (int e = ec; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
 #pragma unroll
         for (int v = 0; v < VEC; ++v)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
+          for (int e = ec; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
       }
     }
   }
