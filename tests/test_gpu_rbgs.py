@@ -294,3 +294,48 @@ def test_rank_deficient_in_fp64(gpu_lib, store):
     assert cert["delta"] < 0.1 and cert["delta_tilde"] < 1e-6
     # the first block is well conditioned: its R factor is unique
     assert rel(R[:16, :16], o["R"][:16, :16]) < (1e-12 if store == "f64" else 1e-6)
+
+
+def test_update_falls_back_past_lds_capacity(gpu_lib):
+    """Blocks whose K = c0 exceeds the rows of R the persistent update keeps in
+    LDS (512) take the general update kernel; both forms in one factorization
+    agree with the oracle at the FP64 tolerance."""
+    n, m, b, k = 3000, 560, 16, 576
+    W = svd_matrix(n, m, np.logspace(0, -2, m), seed=91)
+    say("update forms", n, m, b, k)
+    Q, R, S, cert = gpu_qr(W, b, "sparse", k, 29, "lowsync")
+    o = oracle_qr(W, b, "sparse", k, 29, "lowsync")
+    assert rel(R, o["R"]) < 1e-12
+    assert rel(Q, o["Q"]) < 1e-11
+    assert factorization_error(W, Q, R) < 1e-14
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+@pytest.mark.parametrize("ldw_pad,ldq_pad", [(0, 0), (8, 4), (3, 5), (4, 1)])
+def test_leading_dimensions_give_identical_results(gpu_lib, store, ldw_pad, ldq_pad):
+    """W and Q inside larger column-major buffers (ld > n): 16-byte aligned
+    leading dimensions keep the vector path, others take the guarded path for
+    every tile.  Every element is computed by the same operations in the same
+    order either way, so the results equal those with ld = n bit for bit."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    n, m, b, k = 5000, 48, 16, 256
+    W = svd_matrix(n, m, np.logspace(0, -3, m), seed=5)
+    dt = torch.float64 if store == "f64" else torch.float32
+    say("leading dimensions", store, ldw_pad, ldq_pad)
+    W0 = B.colmajor(n, m, dt)
+    W0.copy_(torch.from_numpy(W))
+    Q0, R0, _, _ = B.rbgs_qr(W0, b, "sparse", k, 3, None, "lowsync", 4)
+    Wb = B.colmajor(n + ldw_pad, m, dt)
+    Wb.fill_(float("nan"))          # padding rows must never be read into a result
+    Wv = Wb[:n]
+    Wv.copy_(W0)
+    Qb = B.colmajor(n + ldq_pad, m, dt)
+    Qb.fill_(7.0)
+    Qv = Qb[:n]
+    Q1, R1, _, _ = B.rbgs_qr(Wv, b, "sparse", k, 3, None, "lowsync", 4, Q=Qv)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R0)
+    assert torch.equal(Q1, Q0)
+    if ldq_pad:
+        assert bool((Qb[n:] == 7.0).all())   # nothing written past row n
