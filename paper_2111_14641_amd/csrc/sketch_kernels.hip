@@ -490,51 +490,48 @@ static int dense_ncg(int64_t groups) { return groups >= 4 ? 4 : (groups >= 2 ? 2
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of the partial sums, scaled once in FP64.
 // ---------------------------------------------------------------------------
-// 8 lanes per output: lane q sums g = q, q+8, ... in order, then the eight
-// partial sums are combined by a fixed butterfly.
-constexpr int kRedLanes = 8;
+// A workgroup of kRdWaves waves owns 64 consecutive outputs (consecutive
+// sketch rows t of one column, so every load of a wave is one contiguous
+// 512-byte segment); wave w sums the partials g = w, w + kRdWaves, ... in
+// order, and the wave sums are added in the order w = 0, 1, .. through LDS.
+constexpr int kRdWaves = 16;
 __device__ __forceinline__ void sketch_reduce_body(const double* __restrict__ partial, int G,
                                                    int64_t k, int64_t ncols, double scale,
                                                    double* __restrict__ out, int64_t ldo,
-                                                   int64_t gid, int64_t part_cols) {
-  const int q = (int)(gid % kRedLanes);
-  const int64_t idx = gid / kRedLanes;
+                                                   int64_t idx0, int64_t part_cols) {
+  __shared__ double red[kRdWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t idx = idx0 + lane;
   const bool ok = idx < k * ncols;
-  const int64_t t = idx % k, c = idx / k;
-  double s0 = 0.0, s1 = 0.0;
-  if (ok) {
-    const double* p = partial + c * k + t;
-    const int64_t stride = part_cols * k;
-    int g = q;
-    for (; g + kRedLanes < G; g += 2 * kRedLanes) {
-      s0 += p[(int64_t)g * stride];
-      s1 += p[(int64_t)(g + kRedLanes) * stride];
-    }
-    if (g < G) s0 += p[(int64_t)g * stride];
-  }
-  double s = s0 + s1;
+  const int64_t ic = ok ? idx : 0;
+  const int64_t t = ic % k, c = ic / k;
+  const double* p = partial + c * k + t;
+  const int64_t stride = part_cols * k;
+  double s = 0.0;
+#pragma unroll 4
+  for (int g = wave; g < G; g += kRdWaves) s += p[(int64_t)g * stride];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0) {
+    double tot = red[0][lane];
 #pragma unroll
-  for (int d = 1; d < kRedLanes; d <<= 1) s += __shfl_xor(s, d, 64);
-  if (ok && q == 0) out[t + c * ldo] = scale * s;
+    for (int w = 1; w < kRdWaves; ++w) tot += red[w][lane];
+    if (ok) out[t + c * ldo] = scale * tot;
+  }
 }
 
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* __restrict__ partial,
-                                                            int G, int64_t k, int64_t ncols,
-                                                            double scale, double* __restrict__ out,
-                                                            int64_t ldo, int64_t part_cols) {
-  sketch_reduce_body(partial, G, k, ncols, scale, out, ldo,
-                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x, part_cols);
+__global__ __launch_bounds__(kRdWaves * 64) void sketch_reduce_kernel(
+    const double* __restrict__ partial, int G, int64_t k, int64_t ncols, double scale,
+    double* __restrict__ out, int64_t ldo, int64_t part_cols) {
+  sketch_reduce_body(partial, G, k, ncols, scale, out, ldo, (int64_t)blockIdx.x * 64, part_cols);
 }
 
 // Lock-step batch: blockIdx.y = problem; which = 0: into P, 1: into S (columns c0 ..).
-__global__ __launch_bounds__(256) void sketch_reduce_batched_kernel(const BatchItem* items,
-                                                                    int which, int64_t c0,
-                                                                    int64_t k, int64_t ncols,
-                                                                    double scale) {
+__global__ __launch_bounds__(kRdWaves * 64) void sketch_reduce_batched_kernel(
+    const BatchItem* items, int which, int64_t c0, int64_t k, int64_t ncols, double scale) {
   const BatchItem& it = items[blockIdx.y];
   double* out = which == 0 ? it.P : it.S + c0 * k;
-  sketch_reduce_body(it.part, it.sk_G, k, ncols, scale, out, k,
-                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncols);
+  sketch_reduce_body(it.part, it.sk_G, k, ncols, scale, out, k, (int64_t)blockIdx.x * 64, ncols);
 }
 
 template <typename T>
@@ -836,9 +833,9 @@ hipError_t launch_sketch_partials(const SketchDesc& sk, bool f32, const void* X,
 hipError_t launch_sketch_reduce(const double* partial, int G, int64_t k, int64_t ncols,
                                 double scale, double* out, int64_t ldo, hipStream_t st,
                                 int64_t part_cols) {
-  const int64_t total = k * ncols * kRedLanes;
-  hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st,
-                     partial, G, k, ncols, scale, out, ldo, part_cols > 0 ? part_cols : ncols);
+  hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(k * ncols, 64)),
+                     dim3(kRdWaves * 64), 0, st, partial, G, k, ncols, scale, out, ldo,
+                     part_cols > 0 ? part_cols : ncols);
   return hipGetLastError();
 }
 
@@ -918,9 +915,9 @@ hipError_t launch_sketch_batched(bool f32, const BatchItem* items, int nprob, in
       f32 ? launch_sparse_q_batched<float>(items, nprob, total_wgs, which, c0, ncols, k, zeta, st)
           : launch_sparse_q_batched<double>(items, nprob, total_wgs, which, c0, ncols, k, zeta, st);
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)k * ncols * kRedLanes;
-  hipLaunchKernelGGL(sketch_reduce_batched_kernel, dim3((unsigned)ceil_div(total, 256), (unsigned)nprob),
-                     dim3(256), 0, st, items, which, c0, (int64_t)k, ncols, scale);
+  hipLaunchKernelGGL(sketch_reduce_batched_kernel,
+                     dim3((unsigned)ceil_div((int64_t)k * ncols, 64), (unsigned)nprob),
+                     dim3(kRdWaves * 64), 0, st, items, which, c0, (int64_t)k, ncols, scale);
   return hipGetLastError();
 }
 
