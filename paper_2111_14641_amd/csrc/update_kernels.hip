@@ -332,16 +332,18 @@ struct UpPUnroll {
   static constexpr int N = sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64;
 };
 
-template <typename T, bool TAIL>
-__device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* __restrict__ Q,
-                                              int64_t ldq, T* Qout, int64_t ldqo,
-                                              const double* Rs, const double* Ru,
-                                              const double* Rinv, bool subst,
-                                              int64_t tile0, int64_t n, int K, int bw) {
+// One tile with guarded element loads and stores (rows >= n are neither read
+// nor written; any alignment).  Same arithmetic as update_p_full_tiles.
+template <typename T>
+__device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
+                                                      const T* __restrict__ Q, int64_t ldq,
+                                                      T* Qout, int64_t ldqo, const double* Rs,
+                                                      const double* Ru, const double* Rinv,
+                                                      bool subst, int64_t tile0, int64_t n,
+                                                      int K, int bw) {
   typedef Mfma<double> M;
   constexpr int VEC = Vec16<T>::N;
   constexpr int WROWS = 16 * VEC;
-  typedef typename Vec16<T>::t VT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, li = lane & 15;
   const int64_t arow = tile0 + (int64_t)wave * WROWS + (int64_t)VEC * li;  // this lane's rows
@@ -357,18 +359,11 @@ __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* 
     for (int u = 0; u < kUnroll; ++u) {
       int col = ks0 + 4 * u + kk;
       col = col < K ? col : K - 1;  // padded steps are skipped
-      const T* src = Q + arow + (int64_t)col * ldq;
-      if (!TAIL) {
-        const VT vv = *reinterpret_cast<const VT*>(src);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) a[u][v] = vv[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const bool in = arow + v < n;
-          const T x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
-          a[u][v] = in ? x : (T)0;
-        }
+      for (int v = 0; v < VEC; ++v) {
+        const bool in = arow + v < n;
+        const T x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
+        a[u][v] = in ? x : (T)0;
       }
     }
   };
@@ -389,17 +384,11 @@ __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* 
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int c = kk + 4 * e < bw ? kk + 4 * e : bwc;
-      if (!TAIL) {
-        const VT vv = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) w[e][v] = vv[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-          const bool in = arow + v < n;
-          const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
-          w[e][v] = in ? x : (T)0;
-        }
+      for (int v = 0; v < VEC; ++v) {
+        const bool in = arow + v < n;
+        const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
+        w[e][v] = in ? x : (T)0;
       }
     }
     if (K > 0) load_group(a0, 0);
@@ -453,17 +442,127 @@ __device__ __forceinline__ void update_p_tile(const T* W, int64_t ldw, const T* 
     const int c = kk + 4 * e;
     if (c < bw) {
       T* dst = Qout + arow + (int64_t)c * ldqo;
-      if (!TAIL) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        if (arow + v < n) dst[v] = (T)acc[v][e];
+    }
+  }
+}
+
+// The full tiles of one workgroup (tile = first, first + stride, .. < nfull),
+// software-pipelined across tiles: the W vectors and the first group of Q of
+// the next tile are loaded before the substitution and stores of the current
+// one, so the wait for them does not also wait for those stores (stores share
+// the vector-memory counter on this target).  Same arithmetic, in the same
+// order, as update_p_tile<T, false>.
+template <typename T>
+__device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
+                                                    const T* __restrict__ Q, int64_t ldq,
+                                                    T* Qout, int64_t ldqo, const double* Rs,
+                                                    const double* Ru, const double* Rinv,
+                                                    bool subst, int64_t first, int64_t stride,
+                                                    int64_t nfull, int K, int bw) {
+  typedef Mfma<double> M;
+  constexpr int VEC = Vec16<T>::N;
+  constexpr int WROWS = 16 * VEC;
+  constexpr int TILE = 4 * WROWS;
+  typedef typename Vec16<T>::t VT;
+  constexpr int kUnroll = UpPUnroll<T>::N;
+  constexpr int GS = 4 * kUnroll;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;  // row of this lane in a tile
+  const int bwc = bw - 1;
+
+  auto load_w = [&](VT (&wv)[4], int64_t arow) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = kk + 4 * e < bw ? kk + 4 * e : bwc;
+      wv[e] = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
+    }
+  };
+  auto load_group = [&](VT (&a)[kUnroll], int64_t arow, int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      int col = ks0 + 4 * u + kk;
+      col = col < K ? col : K - 1;
+      a[u] = *reinterpret_cast<const VT*>(Q + arow + (int64_t)col * ldq);
+    }
+  };
+  M::acc_t acc[VEC];
+  auto mma_group = [&](const VT (&a)[kUnroll], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ks0 + 4 * u < K) {
+        const double b = Rs[(ks0 + 4 * u + kk) * 16 + li];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = M::mma(b, (double)a[u][v], acc[v]);
+      }
+    }
+  };
+
+  int64_t tile = first;
+  if (tile >= nfull) return;
+  VT wv[4], a0[kUnroll], a1[kUnroll];
+  load_w(wv, tile * TILE + roff);
+  if (K > 0) load_group(a0, tile * TILE + roff, 0);
+  for (;;) {
+    const int64_t arow = tile * TILE + roff;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+      acc[v] = (M::acc_t){-(double)wv[0][v], -(double)wv[1][v], -(double)wv[2][v],
+                          -(double)wv[3][v]};
+    for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
+      if (ks0 + GS < K) load_group(a1, arow, ks0 + GS);
+      mma_group(a0, ks0);
+      if (ks0 + GS < K) {
+        if (ks0 + 2 * GS < K) load_group(a0, arow, ks0 + 2 * GS);
+        mma_group(a1, ks0 + GS);
+      }
+    }
+    const int64_t next = tile + stride;
+    const bool more = next < nfull;
+    if (more) {
+      load_w(wv, next * TILE + roff);
+      if (K > 0) load_group(a0, next * TILE + roff, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = -acc[v];
+    if (subst) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < bw) {
+          const int kc = c & 3, ec = c >> 2;
+          const double rinv = Rinv[c];
+          double xb[VEC];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][ec] * rinv, 16 * kc + li, 64);
+          if (kk == kc) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v][ec] = xb[v];
+          }
+          double ru[4];
+#pragma unroll
+          for (int e = ec; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+#pragma unroll
+            for (int e = ec; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = kk + 4 * e;
+      if (c < bw) {
         VT vv;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][e];
-        *reinterpret_cast<VT*>(dst) = vv;
-      } else {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v)
-          if (arow + v < n) dst[v] = (T)acc[v][e];
+        *reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo) = vv;
       }
     }
+    if (!more) break;
+    tile = next;
   }
 }
 
@@ -500,14 +599,14 @@ __global__ __launch_bounds__(kUpThreads, 4) void update_p_kernel(
     }
   }
   __syncthreads();
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if (tile < nfull)
-      update_p_tile<T, false>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
-                              bw);
-    else
-      update_p_tile<T, true>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
-                             bw);
-  }
+  update_p_full_tiles<T>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x, gridDim.x,
+                         nfull, K, bw);
+  // the guarded tiles (a ragged last tile, or every tile when a pointer or
+  // leading dimension is not 16-byte aligned) come after the full ones
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    if (tile >= nfull)
+      update_p_guarded_tile<T>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
+                               bw);
 }
 
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
