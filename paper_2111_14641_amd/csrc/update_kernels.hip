@@ -670,7 +670,12 @@ static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int
   const int64_t nfull = vec_ok ? n / TILE : 0;
   const int Kp = (int)((K + 3) / 4 * 4);
   const size_t lds = ((size_t)Kp * 16 + 256 + 16) * sizeof(double);
-  const unsigned grid = (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
+  // FP32 storage: as many workgroups as give every one the same number of
+  // tiles (no partly empty last round; measured -0.6 % on the step, while
+  // FP64 storage, with twice the tiles, is better with all 1024)
+  const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS);
+  const unsigned grid = sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
+                                       : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
   hipLaunchKernelGGL((update_p_kernel<T>), dim3(grid), dim3(kUpThreads), lds, st, (const T*)W, ldw,
                      (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, (int)K, Kp, bw);
   return hipGetLastError();
