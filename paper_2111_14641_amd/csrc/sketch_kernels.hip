@@ -163,17 +163,17 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 // with an exact sign (fma with +-1), keeping its running sums in registers
 // across tiles.  The next tile is prefetched into registers while the current
 // one is summed; every prefetch load is unconditional (clamped index).  The
-// shape is chosen per storage type and width (measured): FP32 rows are
-// narrow enough to stage 16 columns for 1024 threads; FP64 takes 4 columns
-// (1024 threads for a 16-column sketch, 512 for all of W at once), so several
-// workgroups share a CU and hide one another's barriers.  The slices of
+// shape is chosen per storage type and width (measured): 1024 threads with 8
+// FP32 columns (68 KB of LDS, two workgroups per CU) or 4 FP64 columns (1024
+// threads for a 16-column sketch, 512 for all of W at once), so several
+// workgroups share a CU and hide one another's latency and barriers.  The slices of
 // one row range are G apart in blockIdx.x (a multiple of 8 when G is), so
 // they run on the same XCD and share the plan through its L2.
 #ifndef RBGS_SPQ_NT32
 #define RBGS_SPQ_NT32 1024   // FP32 storage: threads per workgroup
 #endif
 #ifndef RBGS_SPQ_NC32
-#define RBGS_SPQ_NC32 16     // FP32 storage: columns per workgroup
+#define RBGS_SPQ_NC32 8      // FP32 storage: columns per workgroup
 #endif
 #ifndef RBGS_SPQ_NT64
 #define RBGS_SPQ_NT64 1024   // FP64 storage
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 #define RBGS_SPQ_NT32M 1024  // FP32 storage, sketches of more than 16 columns
 #endif
 #ifndef RBGS_SPQ_NC32M
-#define RBGS_SPQ_NC32M 16
+#define RBGS_SPQ_NC32M 8
 #endif
 #ifndef RBGS_SPQ_NT64M
 #define RBGS_SPQ_NT64M 512   // FP64 storage, sketches of more than 16 columns
