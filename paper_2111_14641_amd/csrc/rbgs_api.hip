@@ -441,9 +441,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.Rt = twice ? (double*)(base + o_Rt) : nullptr;
   r.tall = tall_need ? (double*)(base + o_tall) : nullptr;
   hipStream_t st = r.st;
-  HIP_TRY(h, launch_zero(R, ldr, m, m, st), "zero R");
-  HIP_TRY(h, launch_set_i64(r.flag, -1, st), "flag");
-  HIP_TRY(h, launch_set_u32(r.counters, 2, 0u, st), "counters");
+  HIP_TRY(h, launch_qr_init(R, ldr, m, r.flag, r.counters, 2, st), "init");
   if (r.plan) {
     ProfScope ps(h, kProfSketch, 0.0, st);
     HIP_TRY(h, launch_sparse_plan(d, n, 0, r.plan, st), "sketch plan");

@@ -356,10 +356,11 @@ hipError_t launch_cholesky(double* A, int64_t m, int64_t* flag, hipStream_t st);
 // R <- A R for upper triangular m x m A and R; T: m x m scratch.
 hipError_t launch_trmm_full(const double* A, int64_t lda, double* R, int64_t ldr, int64_t m,
                             double* T, hipStream_t st);
-hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 // Fill an m x m column-major matrix (ld) with zeros.
-hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+// R = 0 (m x m), *flag = -1, counters[0 .. ncnt) = 0, in one launch.
+hipError_t launch_qr_init(double* R, int64_t ldr, int64_t m, int64_t* flag, unsigned* counters,
+                          int ncnt, hipStream_t st);
 // Certificates: out[0] = ||I - S^T S||_F^2, out[1] = ||P - S R||_F^2, out[2] = ||P||_F^2,
 // out[3] = 1 if any entry of R or S is not finite.  `scratch` >= cert_scratch_size(k, m).
 size_t cert_scratch_size(int64_t k, int64_t m);

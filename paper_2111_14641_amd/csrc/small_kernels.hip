@@ -230,31 +230,24 @@ size_t qr_stack_size(int64_t k, int bw) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void zero_kernel(double* A, int64_t ld, int64_t rows, int64_t cols) {
+// Start of a factorization in one launch: R = 0 (m x m, ld ldr), the
+// breakdown flag = -1 and ncnt arrival counters = 0.
+__global__ void qr_init_kernel(double* R, int64_t ldr, int64_t m, int64_t* flag,
+                               unsigned* counters, int ncnt) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  A[(idx % rows) + (idx / rows) * ld] = 0.0;
+  if (idx < m * m) R[(idx % m) + (idx / m) * ldr] = 0.0;
+  if (idx == 0) *flag = -1;
+  if (idx < ncnt) counters[idx] = 0u;
 }
-
 __global__ void set_i64_kernel(int64_t* p, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-hipError_t launch_zero(double* A, int64_t ld, int64_t rows, int64_t cols, hipStream_t st) {
-  const int64_t total = rows * cols;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, A, ld,
-                     rows, cols);
-  return hipGetLastError();
-}
-
-__global__ void set_u32_kernel(unsigned* p, int n, unsigned v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-hipError_t launch_set_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
-  hipLaunchKernelGGL(set_u32_kernel, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, st, p, n, v);
+hipError_t launch_qr_init(double* R, int64_t ldr, int64_t m, int64_t* flag, unsigned* counters,
+                          int ncnt, hipStream_t st) {
+  const int64_t total = std::max<int64_t>(m * m, ncnt);
+  hipLaunchKernelGGL(qr_init_kernel, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, R, ldr,
+                     m, flag, counters, ncnt);
   return hipGetLastError();
 }
 
