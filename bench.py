@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RBGS QR time & HBM GB/s at n=1e6 m=256: FP32/BF16x3 vs FP64 at equal error"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix-core peak
 LS_ITERS = 4   # Richardson sweeps of the least-squares step
 
 
@@ -77,12 +78,16 @@ def accuracy(W, Q, R, cert):
     return dict(rel_err=err, cond2_Q=cond, delta=cert["delta"], delta_tilde=cert["delta_tilde"])
 
 
-def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64"):
+def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64",
+              profile_sketch=False):
     """Times `steps` QRs on a dedicated stream.  With profile_update, a second
     timed region of `steps` QRs follows in which HIP events bracket every
     update launch on its stream (the roofline figure); the events themselves
     add a few microseconds around each launch, so the step time is taken from
-    the first region."""
+    the first region.  With profile_sketch (dense operators), events bracket
+    every sketch launch in a further region and the sketch's matrix-core rate
+    is reported: 2 k n c flops per launch over c sketched columns, against the
+    FP64 dense matrix-core peak."""
     import torch
     from paper_2111_14641_amd import binding as B
     n, m = W.shape
@@ -116,9 +121,21 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
             torch.cuda.synchronize()
             upd = B.profile_get("update") + (t0.elapsed_time(t1) / steps,)
             B.profile_enable(False)
+        sk = {}
+        if profile_sketch:
+            B.profile_enable(True, classes=["sketch"])
+            for _ in range(steps):
+                run()
+            torch.cuda.synchronize()
+            sk_ms, sk_cnt, sk_bytes = B.profile_get("sketch")
+            B.profile_enable(False)
+            es = 4 if W.dtype == torch.float32 else 8
+            tflops = 2.0 * k * (sk_bytes / es) / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else 0.0
+            sk = dict(sketch_ms_per_step=sk_ms / steps, sketch_launches_per_step=sk_cnt // steps,
+                      sketch_TFLOPs=tflops, sketch_mfma_frac=tflops / FP64_MFMA_PEAK_TFLOPS)
     s = 4 if W.dtype == torch.float32 else 8
     gbs = alg_bytes(n, m, p, s) / (ms * 1e-3) / 1e9
-    return dict(ms=ms, alg_GBps=gbs, **acc), upd
+    return dict(ms=ms, alg_GBps=gbs, **acc, **sk), upd
 
 
 def post_form(W, p, kind, k, seed, reps=3):
@@ -337,9 +354,10 @@ def main():
     ap.add_argument("--no-gaussian", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
-    ap.add_argument("--forms", default="all", choices=["all", "headline", "srht", "batched"],
-                    help="'headline': only the headline form; 'srht' / 'batched': the headline "
-                         "and that form (for profiling one form)")
+    ap.add_argument("--forms", default="all", choices=["all", "headline", "srht", "batched", "gaussian"],
+                    help="'headline': only the headline form; 'srht' / 'batched': the headline and "
+                         "that form; 'gaussian': the headline and the FP32 Gaussian and "
+                         "Rademacher forms (for profiling one form)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -367,6 +385,14 @@ def main():
     forms["f32_sparse_lowsync"] = head
     print("[bench] kernel breakdown", file=sys.stderr, flush=True)
     kernel_ms = kernel_breakdown(W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync")
+    if args.forms == "gaussian":
+        print("[bench] gaussian sketch", file=sys.stderr, flush=True)
+        forms["f32_gauss_lowsync"], _ = time_form(W32, p, "gaussian", k, THETA_SEED_LARGE,
+                                                  "lowsync", max(2, args.steps // 10), 1,
+                                                  profile_sketch=True)
+        forms["f32_rademacher_lowsync"], _ = time_form(W32, p, "rademacher", k, THETA_SEED_LARGE,
+                                                       "lowsync", max(2, args.steps // 10), 1,
+                                                       profile_sketch=True)
     if args.forms == "all":
         print("[bench] fp64 sparse lowsync", file=sys.stderr, flush=True)
         forms["f64_sparse_lowsync"], _ = time_form(W64, p, "sparse", k, THETA_SEED_LARGE, "lowsync",
@@ -390,12 +416,15 @@ def main():
         if not args.no_gaussian:
             print("[bench] gaussian forms", file=sys.stderr, flush=True)
             forms["f32_gauss_lowsync"], _ = time_form(W32, p, "gaussian", k, THETA_SEED_LARGE,
-                                                      "lowsync", max(2, args.steps // 10), 1)
+                                                      "lowsync", max(2, args.steps // 10), 1,
+                                                      profile_sketch=True)
             forms["f64_gauss_lowsync"], _ = time_form(W64, p, "gaussian", k, THETA_SEED_LARGE,
-                                                      "lowsync", max(2, args.steps // 10), 1)
+                                                      "lowsync", max(2, args.steps // 10), 1,
+                                                      profile_sketch=True)
             forms["f32_rademacher_lowsync"], _ = time_form(W32, p, "rademacher", k,
                                                            THETA_SEED_LARGE, "lowsync",
-                                                           max(2, args.steps // 10), 1)
+                                                           max(2, args.steps // 10), 1,
+                                                           profile_sketch=True)
     if args.forms in ("all", "srht"):
         print("[bench] SRHT sketch", file=sys.stderr, flush=True)
         forms["f32_srht_lowsync"], _ = time_form(W32, p, "srht", k, THETA_SEED_LARGE, "lowsync",

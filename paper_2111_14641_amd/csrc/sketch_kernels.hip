@@ -448,18 +448,42 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
       xs[rr * NC + c] = (rr < trows && okc[i]) ? to_f64(v[i]) : 0.0;
     }
     __syncthreads();
-    for (int rr = 0; rr < trows; rr += 4) {
-      float z[4] = {0.f, 0.f, 0.f, 0.f};
-      if (jvalid && rr + kk < trows) {
-        if constexpr (KIND == kRademacher) rademacher4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
-        else gauss4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
+    for (int rc = 0; rc < trows; rc += 64) {
+      // Rademacher: the 16 lanes of a row read 4 bits each of one Philox call
+      // (the wave's 64 targets lie in one 128-target call, in words q0 and
+      // q0 + 1), so lane l makes the call of row rc + l once per 64 rows and
+      // the steps fetch the two words from that lane
+      uint32_t wa = 0u, wb = 0u;
+      if constexpr (KIND == kRademacher) {
+        const uint64_t r = (uint64_t)(row0 + tile0 + rc + lane);
+        const u32x4 x = philox4x32_10((uint32_t)r, (uint32_t)(r >> 32), (uint32_t)(tbase / 4) >> 5,
+                                      kTagRademacher, key0, key1);
+        const bool hi = (((uint32_t)(tbase / 4) >> 3) & 3u) != 0u;   // q0 = 0 or 2
+        wa = hi ? x.z : x.x;
+        wb = hi ? x.w : x.y;
       }
+      const int rcend = min(trows, rc + 64);
+      for (int rr = rc; rr < rcend; rr += 4) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        const bool zok = jvalid && rr + kk < trows;
+        if constexpr (KIND == kRademacher) {
+          // every lane takes part in the exchange; invalid entries are zeroed
+          const int src = rr - rc + kk;
+          const uint32_t a = (uint32_t)__shfl((int)wa, src);
+          const uint32_t b = (uint32_t)__shfl((int)wb, src);
+          const uint32_t bits = ((lane & 8) ? b : a) >> (4u * (uint32_t)(lane & 7));
 #pragma unroll
-      for (int cg = 0; cg < NCG; ++cg) {
-        const double b = xs[(rr + kk) * NC + cg * kSketchCols + (lane & 15)];
+          for (int i = 0; i < 4; ++i) z[i] = zok ? (((bits >> i) & 1u) ? -1.0f : 1.0f) : 0.f;
+        } else {
+          if (zok) gauss4((uint64_t)(row0 + tile0 + rr + kk), j, key0, key1, z);
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          acc[cg][q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)z[q], b, acc[cg][q], 0, 0, 0);
+        for (int cg = 0; cg < NCG; ++cg) {
+          const double b = xs[(rr + kk) * NC + cg * kSketchCols + (lane & 15)];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc[cg][q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)z[q], b, acc[cg][q], 0, 0, 0);
+        }
       }
     }
     __syncthreads();

@@ -113,7 +113,8 @@ def abs_sketch(kind, k, seed, X, row0, zeta=8):
                                     ("sparse", 2048), ("sparse", 64), ("rademacher", 256),
                                     ("rademacher", 100), ("srht", 256), ("srht", 2048),
                                     ("srht", 30)])
-@pytest.mark.parametrize("n,c,row0", [(4097, 16, 0), (1000, 5, 31), (70000, 33, 1 << 20), (3, 1, 0)])
+@pytest.mark.parametrize("n,c,row0", [(4097, 16, 0), (1000, 5, 31), (70000, 33, 1 << 20), (3, 1, 0),
+                                      (3000, 70, 5)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_sketch_apply_matches_oracle(gpu_lib, kind, k, n, c, row0, dtype):
     """FP64 accumulation of exact products (fp32 entries of Z or +-1 times the
