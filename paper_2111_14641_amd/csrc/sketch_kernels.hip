@@ -429,25 +429,33 @@ __global__ __launch_bounds__(kGaThreads) void sketch_gauss_kernel(
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[cg][q] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
+  // unconditional loads from clamped addresses (rows of the tile only), masked
+  // when staged; the next tile is loaded while the current one is summed
+  constexpr int NV = TILE * NC / kGaThreads;
+  T v[NV];
+  bool okc[NV];
+  const T* srcp[NV];   // each element's column does not change from tile to tile
+#pragma unroll
+  for (int i = 0; i < NV; ++i) srcp[i] = slot_src(col0 + (tid + i * kGaThreads) / TILE, okc[i]);
+  auto load_tile = [&](int64_t t0) {
+    const int tr = (int)min((int64_t)TILE, rend - t0);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int rr = (tid + i * kGaThreads) % TILE;
+      v[i] = srcp[i][t0 + (rr < tr ? rr : tr - 1)];
+    }
+  };
+  if (rbeg < rend) load_tile(rbeg);
   for (int64_t tile0 = rbeg; tile0 < rend; tile0 += TILE) {
     const int trows = (int)min((int64_t)TILE, rend - tile0);
-    // unconditional loads from clamped addresses, then masked
-    T v[TILE * NC / kGaThreads];
-    bool okc[TILE * NC / kGaThreads];
 #pragma unroll
-    for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
-      const int e = tid + i * kGaThreads;
-      const int c = e / TILE, rr = e % TILE;
-      const T* src = slot_src(col0 + c, okc[i]);
-      v[i] = src[tile0 + (rr < trows ? rr : trows - 1)];
-    }
-#pragma unroll
-    for (int i = 0; i < TILE * NC / kGaThreads; ++i) {
+    for (int i = 0; i < NV; ++i) {
       const int e = tid + i * kGaThreads;
       const int c = e / TILE, rr = e % TILE;
       xs[rr * NC + c] = (rr < trows && okc[i]) ? to_f64(v[i]) : 0.0;
     }
     __syncthreads();
+    if (tile0 + TILE < rend) load_tile(tile0 + TILE);
     for (int rc = 0; rc < trows; rc += 64) {
       // Rademacher: the 16 lanes of a row read 4 bits each of one Philox call
       // (the wave's 64 targets lie in one 128-target call, in words q0 and
