@@ -94,12 +94,13 @@ __device__ __forceinline__ void gauss_sincos(uint32_t w, float& c, float& s) {
   pc = f32c(0x3D2AAAABu) + a2 * pc;                         //  1/4!
   pc = f32c(0xBF000000u) + a2 * pc;                         // -1/2
   const float ca = 1.0f + a2 * pc;
-  switch (q) {
-    case 0: c = ca; s = sa; break;
-    case 1: c = -sa; s = ca; break;
-    case 2: c = -ca; s = -sa; break;
-    default: c = sa; s = -ca; break;
-  }
+  // q quarter turns: (cos, sin) = (ca, sa), (-sa, ca), (-ca, -sa), (sa, -ca) for q = 0..3,
+  // by selects and sign-bit flips (exact negation; a 4-way switch would run every path)
+  const bool sw = (q & 1u) != 0u;
+  const uint32_t cneg = ((q ^ (q >> 1)) & 1u) << 31;  // q = 1, 2
+  const uint32_t sneg = (q >> 1) << 31;               // q = 2, 3
+  c = __uint_as_float(__float_as_uint(sw ? sa : ca) ^ cneg);
+  s = __uint_as_float(__float_as_uint(sw ? ca : sa) ^ sneg);
 }
 
 // Box-Muller: radius word wr, angle word wa -> (rho cos phi, rho sin phi).
