@@ -374,13 +374,16 @@ static hipError_t launch_sparse_q(const T* X, int64_t ldx, int64_t n, int64_t nc
 }
 
 // ---------------------------------------------------------------------------
-// Gaussian: out = Z X on FP64 matrix cores (v_mfma_f64_16x16x4f64) with Z
-// regenerated from Philox for every 4-row step.  A wave owns 64 targets: lane
-// l generates the four entries Z[4(jb + l%16) + q][r], r = step row + l/16,
-// from one Philox call, and entry q feeds the A operand of accumulator q, so
-// accumulator q holds targets 4(jb + i) + q, i = 0..15.  The B operand is the
-// X tile staged in LDS (FP64).  A workgroup covers 256 targets and one
-// 16-column group of X over its row range.
+// Dense sketches (Gaussian, Rademacher): out = Z X on FP64 matrix cores
+// (v_mfma_f64_16x16x4f64) with Z regenerated from Philox in every pass.  A wave
+// owns 64 targets: in each 4-row step lane l holds the four entries
+// Z[4(jb + l%16) + q][r], r = step row + l/16 (Gaussian: one Philox call per
+// lane and step; Rademacher: the bits of one call per row, made once per 64
+// rows by lane r%64 and fetched by lane exchange), and entry q feeds the A
+// operand of accumulator q, so accumulator q holds targets 4(jb + i) + q,
+// i = 0..15.  The B operand is the X tile staged in LDS (FP64); the next tile
+// is loaded into registers while the current one is summed.  A workgroup
+// covers 256 targets and NCG 16-column groups of X over its row range.
 // ---------------------------------------------------------------------------
 constexpr int kGaThreads = 256;
 constexpr int kGaTile = 128;
