@@ -46,6 +46,34 @@ constexpr uint32_t kTagSrht = 0x53524854u;
 // fp32 constants by bit pattern (correctly rounded values of the named reals).
 __device__ __forceinline__ float f32c(uint32_t b) { return __uint_as_float(b); }
 
+// n / d correctly rounded, for the operands of gauss_ln_u24 only (d = f + 1 in
+// [1.7, 2.5], n = f - 1: normal, far from overflow and underflow).  The steps
+// of the IEEE single-precision division: reciprocal estimate, one Newton step,
+// quotient, two residual corrections by fused multiply-add (Markstein).  The
+// general division adds operand scaling and special-case fix-ups, which leave
+// every value in this range unchanged; so the result is the IEEE quotient.
+__device__ __forceinline__ float div_rn_gauss(float n, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(fmaf(-d, r, 1.0f), r, r);
+  float q = n * r;
+  q = fmaf(fmaf(-d, q, n), r, q);
+  return fmaf(fmaf(-d, q, n), r, q);
+}
+
+// sqrt(x) correctly rounded for the radius argument x = -2 ln u of gauss_pair
+// (u in [2^-24, 1 - 2^-24], so x in [1.1e-7, 33.3]: normal and positive).
+// Hardware estimate, then the neighbour chosen by the sign of the residual
+// x - s s' (Tuckerman's rounding test).  The general square root adds scaling
+// of inputs below 2^-96 and special cases for 0, inf and NaN, none of which
+// occur here; so the result is the IEEE square root.
+__device__ __forceinline__ float sqrt_rn_gauss(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+  const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+  const float r = fmaf(-sm, s, x) <= 0.0f ? sm : s;
+  return fmaf(-sp, s, x) > 0.0f ? sp : r;
+}
+
 // Natural logarithm of u = (2*(w >> 9) + 1) * 2^-24 in single precision:
 // write N = 2*(w>>9)+1 = f * 2^e with f in [sqrt(2)/2, sqrt(2)], then
 // ln u = (e - 24) ln 2 + 2 atanh(s), s = (f-1)/(f+1), using the odd series of
@@ -61,7 +89,7 @@ __device__ __forceinline__ float gauss_ln_u24(uint32_t w) {
     f = f * 0.5f;
     e += 1;
   }
-  const float s = (f - 1.0f) / (f + 1.0f);
+  const float s = div_rn_gauss(f - 1.0f, f + 1.0f);
   const float s2 = s * s;
   float p = f32c(0x3E124925u) + s2 * f32c(0x3DE38E39u);  // 1/7 + s2/9
   p = f32c(0x3E4CCCCDu) + s2 * p;                         // 1/5
@@ -106,7 +134,7 @@ __device__ __forceinline__ void gauss_sincos(uint32_t w, float& c, float& s) {
 // Box-Muller: radius word wr, angle word wa -> (rho cos phi, rho sin phi).
 __device__ __forceinline__ void gauss_pair(uint32_t wr, uint32_t wa, float& z0, float& z1) {
 #pragma clang fp contract(off)
-  const float rho = sqrtf(-2.0f * gauss_ln_u24(wr));
+  const float rho = sqrt_rn_gauss(-2.0f * gauss_ln_u24(wr));
   float c, s;
   gauss_sincos(wa, c, s);
   z0 = rho * c;

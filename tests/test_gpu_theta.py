@@ -22,6 +22,9 @@ def to_np(t):
     (256, 1000, 0, 0x2111146410),
     (64, 333, 12345, 7),
     (1024, 300, 2**32 - 100, 99),      # crosses the 32-bit boundary of the row counter
+    # 2^25 Box-Muller pairs: about 98 % of the 2^23 values of each word the
+    # logarithm, square root and sine/cosine read
+    (1024, 65536, 5, 0x5EED),
 ])
 def test_gaussian_theta_bit_exact(gpu_lib, k, n, row0, seed):
     from paper_2111_14641_amd import binding as B
