@@ -27,6 +27,15 @@ FLAGS = [
 ]
 
 
+# Per-source additions.  The dense sketch keeps its matrix-core accumulators in
+# ordinary vector registers (the VGPR form of the MFMA instructions): with the
+# accumulation-register form the 16-column kernel copied all of them to and
+# from those registers around every 4-row step.
+SOURCE_FLAGS = {
+    "sketch_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -44,7 +53,7 @@ def build(verbose=False, jobs=4):
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
