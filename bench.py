@@ -7,9 +7,10 @@ width p = 16, sketch dimension k = 1024.  One step is one complete RBGS QR
 (all blocks: sketches, least squares, update, QR of the sketch, substitution,
 re-sketch) with W already resident in HBM.
 
-The headline form stores W and Q in FP32 (step 3 on FP32 matrix cores, all
-small factors and sketch accumulation in FP64) with the sparse-sign sketch and
-the low-synchronization variant.  The FP64 form and the Gaussian-sketch forms
+The headline form stores W and Q in FP32 (step 3 runs on FP64 matrix cores
+from the FP32 data, rounding only its result to FP32; all small factors and
+sketch accumulation are FP64) with the sparse-sign sketch and the
+low-synchronization variant.  The FP64 form and the Gaussian-sketch forms
 are timed on the same matrix and reported beside it, each with its accuracy
 (||W - QR||_F / ||W||_F, cond2(Q), Delta, Delta~).
 
@@ -337,6 +338,7 @@ def cpu_baseline(W64_host, p, k, seed, target_s=15.0):
         n_s *= 2
     gbs = alg_bytes(n_s, m, p, 8) / dt / 1e9
     return dict(value=gbs, unit="GB/s", cores=int(threads), kind="oracle",
+                blas_threads=int(threads), host_cpus=os.cpu_count(),
                 sample=f"FP64 oracle, low-sync sparse-sign RBGS on the first {n_s} rows of the "
                        f"workload (m={m}, p={p}, k={k}); one run, {dt:.2f} s")
 

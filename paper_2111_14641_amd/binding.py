@@ -5,6 +5,7 @@ the HIP kernels of librbgs.so.  PyTorch supplies device memory and the stream.
 If the library has not been built, importing functions from here raises
 immediately; there is no fallback implementation.
 """
+import atexit
 import ctypes
 import os
 
@@ -108,6 +109,15 @@ class Library:
     def __init__(self):
         self.lib = load_library()
         self.handles = {}
+        # Free every handle (workspace, events, streams, graphs) while the HIP
+        # runtime is still fully loaded, before interpreter and library teardown.
+        atexit.register(self.close)
+
+    def close(self):
+        """rbgs_destroy on every handle (it waits for the device first)."""
+        handles, self.handles = self.handles, {}
+        for h in handles.values():
+            self.lib.rbgs_destroy(h)
 
     @classmethod
     def get(cls):

@@ -1,0 +1,401 @@
+"""Bounds check of recorded kernel launches (test infrastructure, CPU only).
+
+The recording HIP stand-in (mock_hip.cpp) runs the library's real host code
+and logs every device allocation and every kernel launch with its grid, block
+and argument bytes.  For each kernel this module restates, from the kernel's
+source, the largest and smallest element index it can touch through each
+pointer argument for the recorded grid and arguments, and checks that the
+touched byte range lies inside one allocation that is live at the time of the
+launch.  Index expressions are evaluated over the whole grid with numpy where
+they depend on the thread, or at their extreme values where the kernel clamps
+or guards them.
+"""
+import struct
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Log parsing
+# ---------------------------------------------------------------------------
+
+
+class Launch:
+    def __init__(self, name, grid, block, shmem, raw):
+        self.name = name
+        self.grid = grid
+        self.block = block
+        self.shmem = shmem
+        self.raw = raw          # list of bytes objects, one per argument
+
+    def i(self, j):
+        """Argument j as a signed integer (any width)."""
+        b = self.raw[j]
+        return int.from_bytes(b, "little", signed=True)
+
+    def u(self, j):
+        return int.from_bytes(self.raw[j], "little", signed=False)
+
+    def f(self, j):
+        b = self.raw[j]
+        return struct.unpack("<d" if len(b) == 8 else "<f", b)[0]
+
+
+def parse_log(path):
+    events = []
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if not parts:
+                continue
+            if parts[0] == "alloc":
+                events.append(("alloc", int(parts[1]), int(parts[2])))
+            elif parts[0] == "free":
+                events.append(("free", int(parts[1])))
+            elif parts[0] == "launch":
+                name = parts[1]
+                grid = tuple(int(x) for x in parts[2:5])
+                block = tuple(int(x) for x in parts[5:8])
+                shmem = int(parts[8])
+                nargs = int(parts[9])
+                raw = [bytes.fromhex(h) for h in parts[10:10 + nargs]]
+                events.append(("launch", Launch(name, grid, block, shmem, raw)))
+            elif parts[0] == "copy":
+                events.append(("copy", int(parts[1]), int(parts[2]), int(parts[3]), int(parts[4])))
+    return events
+
+
+# ---------------------------------------------------------------------------
+# Access records: (argument index, element bytes, min index, max index)
+# ---------------------------------------------------------------------------
+def cdiv(a, b):
+    return -(-a // b)
+
+
+def acc(j, es, lo, hi):
+    return (j, es, int(lo), int(hi))
+
+
+def _qr_init(L):
+    # (R, ldr, m, flag, counters, ncnt)
+    ldr, m, ncnt = L.i(1), L.i(2), L.i(5)
+    out = [acc(0, 8, 0, (m - 1) + (m - 1) * ldr), acc(3, 8, 0, 0)]
+    if ncnt > 0:
+        out.append(acc(4, 4, 0, ncnt - 1))
+    threads = L.grid[0] * L.block[0]
+    assert threads >= max(m * m, ncnt, 1)
+    return out
+
+
+def _sketch_reduce(L):
+    # (partial, G, k, ncols, scale, out, ldo, part_cols)
+    G, k, ncols, ldo, pc = L.i(1), L.i(2), L.i(3), L.i(6), L.i(7)
+    nthr_out = L.grid[0] * 64
+    assert nthr_out >= k * ncols, "reduction grid does not cover the outputs"
+    assert L.block[0] == 16 * 64
+    return [acc(0, 8, 0, (k * ncols - 1) + (G - 1) * pc * k),
+            acc(5, 8, 0, (k - 1) + (ncols - 1) * ldo)]
+
+
+def _gram_sty(L):
+    # (S, k, K, X0, n0, X1, n1, out0, ldo0, out1, ldo1, out1t, ldo1t)
+    k, K, n0, n1 = L.i(1), L.i(2), L.i(4), L.i(6)
+    ldo0, ldo1, ldo1t = L.i(8), L.i(10), L.i(12)
+    ncol = n0 + n1
+    assert L.grid[0] * L.block[0] // 64 >= K * ncol
+    out = [acc(0, 8, 0, K * k - 1)]
+    if n0 > 0:
+        out += [acc(3, 8, 0, n0 * k - 1), acc(7, 8, 0, (K - 1) + (n0 - 1) * ldo0)]
+    if n1 > 0:
+        out += [acc(5, 8, 0, n1 * k - 1), acc(9, 8, 0, (K - 1) + (n1 - 1) * ldo1)]
+        if L.u(11) != 0:
+            out.append(acc(11, 8, 0, (n1 - 1) + (K - 1) * ldo1t))
+    return out
+
+
+def _gram_sweep(L):
+    # (G, ldg, K, C, Y, ldy, Ynew, ldyn, bw)
+    ldg, K, ldy, ldyn, bw = L.i(1), L.i(2), L.i(5), L.i(7), L.i(8)
+    assert L.grid[0] * L.block[0] // 16 >= K * bw
+    return [acc(0, 8, 0, (K - 1) * ldg + K - 1), acc(3, 8, 0, (K - 1) + (bw - 1) * K),
+            acc(4, 8, 0, (bw - 1) * ldy + K - 1), acc(6, 8, 0, (K - 1) + (bw - 1) * ldyn)]
+
+
+def _resid(L):
+    # (P, S, k, K, Y, ldy, E, bw)
+    k, K, ldy, bw = L.i(2), L.i(3), L.i(5), L.i(7)
+    assert K >= 1
+    assert L.grid[0] * L.block[0] // 16 >= k * bw
+    return [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(1, 8, 0, (k - 1) + (K - 1) * k),
+            acc(4, 8, 0, (bw - 1) * ldy + K - 1), acc(6, 8, 0, (k - 1) + (bw - 1) * k)]
+
+
+def qr_bwp(bw):
+    return 4 if bw <= 4 else (8 if bw <= 8 else (16 if bw <= 16 else 32))
+
+
+def qr_chunk_rows(bw):
+    return (256 // qr_bwp(bw)) * 16
+
+
+def _qr_fused(L):
+    # (src, k, bw, stack, counter, Rii, ldr, flag, col0)
+    k, bw, ldr = L.i(1), L.i(2), L.i(6)
+    CH = qr_chunk_rows(bw)
+    nch = cdiv(k, CH)
+    assert L.grid[0] == nch and L.block[0] == 256
+    out = [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(5, 8, 0, (bw - 1) + (bw - 1) * ldr),
+           acc(7, 8, 0, 0)]
+    if nch == 1:
+        return out
+    # level 1: chunk b writes rows [b bw, b bw + bw) of a (nch bw) x bw stack
+    ld1 = nch * bw
+    hi = ld1 * bw - 1
+    lrows, off = ld1, ld1 * bw
+    while lrows > CH:
+        n2 = cdiv(lrows, CH)
+        out_rows = n2 * bw
+        hi = max(hi, off + out_rows * bw - 1)      # writes of this level
+        off += out_rows * bw
+        lrows = out_rows
+    out += [acc(3, 8, 0, hi), acc(4, 4, 0, 0)]
+    return out
+
+
+def _qr_wave(L):
+    # (src, k, bw, Rii, ldr, flag, col0)
+    k, bw, ldr = L.i(1), L.i(2), L.i(4)
+    return [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(3, 8, 0, (bw - 1) + (bw - 1) * ldr),
+            acc(5, 8, 0, 0)]
+
+
+def _update_general(L, T, NB):
+    # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, nfull, n, K, bw)
+    es = 4 if T == "f" else 8
+    VEC = 16 // es
+    TILE = 4 * 16 * VEC
+    ldw, ldq, ldqo, ldr = L.i(1), L.i(3), L.i(5), L.i(8)
+    nfull, n, K, bw = L.i(9), L.i(10), L.i(11), L.i(12)
+    assert L.grid[0] == cdiv(n, TILE) and L.block[0] == 256
+    assert 1 <= bw <= 16 * NB
+    assert nfull * TILE <= n
+    last = n - 1
+    out = [acc(0, es, 0, last + (bw - 1) * ldw), acc(4, es, 0, last + (bw - 1) * ldqo)]
+    if K > 0:
+        out += [acc(2, es, 0, last + (K - 1) * ldq), acc(6, 8, 0, (K - 1) + (bw - 1) * ldr)]
+    if L.u(7) != 0:
+        out.append(acc(7, 8, 0, (bw - 1) + (bw - 1) * ldr))
+    return out
+
+
+def _update_persistent(L, T):
+    # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, K, Kp, bw)
+    es = 4 if T == "f" else 8
+    VEC = 16 // es
+    TILE = 4 * 16 * VEC
+    ldw, ldq, ldqo, ldr = L.i(1), L.i(3), L.i(5), L.i(8)
+    ntiles, nfull, n, K, Kp, bw = L.i(9), L.i(10), L.i(11), L.i(12), L.i(13), L.i(14)
+    assert ntiles == cdiv(n, TILE) and nfull * TILE <= n and bw <= 16 and K <= Kp <= 512
+    assert L.shmem >= (Kp * 16 + 256 + 16) * 8
+    last = n - 1
+    out = [acc(0, es, 0, last + (bw - 1) * ldw), acc(4, es, 0, last + (bw - 1) * ldqo),
+           acc(6, 8, 0, max(0, (K - 1) + (bw - 1) * ldr))]
+    if K > 0:
+        out.append(acc(2, es, 0, last + (K - 1) * ldq))
+    if L.u(7) != 0:
+        out.append(acc(7, 8, 0, (bw - 1) + (bw - 1) * ldr))
+    return out
+
+
+def _trsm(L, T):
+    # (Qb, ldq, Rii, ldr, n, bw)
+    es = 4 if T == "f" else 8
+    ldq, ldr, n, bw = L.i(1), L.i(3), L.i(4), L.i(5)
+    return [acc(0, es, 0, (n - 1) + (bw - 1) * ldq), acc(2, 8, 0, (bw - 1) + (bw - 1) * ldr)]
+
+
+def _sketch_gauss(L, T, NCG):
+    # (X, ldx, n, ncols, row0, k, key0, key1, rows_per_wg, partial, X2, ldx2, n1)
+    es = 4 if T == "f" else 8
+    ldx, n, ncols, k, rpw = L.i(1), L.i(2), L.i(3), L.i(5), L.i(8)
+    ldx2, n1 = L.i(11), L.i(12)
+    G = L.grid[0]
+    NC = 16 * NCG
+    S0 = cdiv(ncols, 16) * 16 if n1 > 0 else ncols
+    NS = S0 + n1 if n1 > 0 else ncols
+    assert L.block[0] == 256
+    assert L.grid[1] * 256 >= k, "targets not covered"
+    assert L.grid[2] * NC >= NS, "column slots not covered"
+    assert G * rpw >= n, "rows not covered"
+    rbeg = np.arange(G, dtype=np.int64) * rpw
+    rend = np.minimum(n, rbeg + rpw)
+    active = rbeg < rend
+    out = []
+    if active.any():
+        rmax = int(rend[active].max()) - 1
+        out.append(acc(0, es, 0, rmax + (ncols - 1) * ldx))
+        if n1 > 0:
+            out.append(acc(10, es, 0, rmax + (n1 - 1) * ldx2))
+    out.append(acc(9, 8, 0, G * NS * k - 1))
+    return out
+
+
+def _sketch_sparse_q(L, T, TPT, MANY):
+    # (X, ldx, n, ncols, k, zeta, plan_off, plan_ent, tiles_per_wg, partial, G)
+    es = 4 if T == "f" else 8
+    ldx, n, ncols, k, zeta, tpw, G = L.i(1), L.i(2), L.i(3), L.i(4), L.i(5), L.i(8), L.i(10)
+    if es == 4:
+        NT, NC = 1024, 8
+    else:
+        NT, NC = (512, 4) if MANY else (1024, 4)
+    assert L.block[0] == NT
+    assert TPT * NT >= k
+    slices = cdiv(ncols, NC)
+    assert L.grid[0] == G * slices
+    ntiles = cdiv(n, 1024)
+    assert G * tpw >= ntiles
+    E = 1024 * zeta
+    return [acc(0, es, 0, (n - 1) + (ncols - 1) * ldx),
+            acc(6, 2, 0, ntiles * (k + 1) - 1),
+            acc(7, 2, 0, ntiles * E - 1),
+            acc(9, 8, 0, G * ncols * k - 1)]
+
+
+def _sparse_plan(L):
+    # (n, row0, k, zeta, key0, key1, plan_off, plan_ent)
+    n, k, zeta = L.i(0), L.i(2), L.i(3)
+    ntiles = cdiv(n, 1024)
+    assert L.grid[0] == ntiles and L.block[0] == 1024 and k <= 2048 and zeta <= 8
+    return [acc(6, 2, 0, ntiles * (k + 1) - 1), acc(7, 2, 0, ntiles * 1024 * zeta - 1)]
+
+
+def _gram_defect(L):
+    # (S, k, m, out)
+    k, m = L.i(1), L.i(2)
+    assert L.grid[0] * 4 >= m * m
+    return [acc(0, 8, 0, (k - 1) + (m - 1) * k), acc(3, 8, 0, m * m - 1)]
+
+
+def _sketch_resid(L):
+    # (S, P, R, ldr, k, m, out, out2)
+    ldr, k, m = L.i(3), L.i(4), L.i(5)
+    assert L.grid[0] * 256 >= k and L.grid[1] == m
+    return [acc(0, 8, 0, (k - 1) + (m - 1) * k), acc(1, 8, 0, (k - 1) + (m - 1) * k),
+            acc(2, 8, 0, (m - 1) + (m - 1) * ldr), acc(6, 8, 0, (k - 1) + (m - 1) * k),
+            acc(7, 8, 0, (k - 1) + (m - 1) * k)]
+
+
+def _sum(L):
+    # (v, len, out)
+    return [acc(0, 8, 0, L.i(1) - 1), acc(2, 8, 0, 0)]
+
+
+def _finite(L):
+    # (S, R, ldr, k, m, out)
+    ldr, k, m = L.i(2), L.i(3), L.i(4)
+    return [acc(0, 8, 0, k * m - 1), acc(1, 8, 0, (m - 1) + (m - 1) * ldr),
+            acc(5, 8, 0, k * m + m * m - 1)]
+
+
+def _sketch_srht(L, T, TPT):
+    # (X, ldx, n, ncols, row0, k, logn, key0, key1, chunks_per_wg, partial)
+    es = 4 if T == "f" else 8
+    ldx, n, ncols, k = L.i(1), L.i(2), L.i(3), L.i(5)
+    G = L.grid[0]
+    return [acc(0, es, 0, (n - 1) + (ncols - 1) * ldx), acc(10, 8, 0, G * ncols * k - 1)]
+
+
+def _template_args(name):
+    """Template arguments of a mangled kernel name, e.g. IfdLi2EE -> ['f', 'd', 2]."""
+    base = kernel_base(name)
+    i = name.find("I", name.find(base) + len(base))
+    j = name.find("EE", i)
+    if i < 0 or j < 0 or i > j:
+        return []
+    body = name[i + 1:j + 1]
+    out, p = [], 0
+    while p < len(body):
+        c = body[p]
+        if c in "fd":
+            out.append(c)
+            p += 1
+        elif c == "b":                 # bool in a literal: Lb0E / Lb1E handled below
+            p += 1
+        elif c == "L":
+            q = body.find("E", p)
+            lit = body[p + 1:q]
+            if lit.startswith("i"):
+                out.append(int(lit[1:]))
+            elif lit.startswith("b"):
+                out.append(bool(int(lit[1:])))
+            p = q + 1
+        else:
+            p += 1
+    return out
+
+
+MIRRORS = {
+    "qr_init_kernel": _qr_init,
+    "sketch_reduce_kernel": _sketch_reduce,
+    "gram_sty_kernel": _gram_sty,
+    "gram_sweep_kernel": _gram_sweep,
+    "resid_kernel": _resid,
+    "qr_fused_kernel": _qr_fused,
+    "sparse_plan_kernel": _sparse_plan,
+    "gram_defect_kernel": _gram_defect,
+    "sketch_resid_kernel": _sketch_resid,
+    "sum_kernel": _sum,
+    "finite_kernel": _finite,
+}
+TEMPLATED = {
+    "update_kernel": lambda L, t: _update_general(L, t[0], t[2]),
+    "update_p_kernel": lambda L, t: _update_persistent(L, t[0]),
+    "trsm_kernel": lambda L, t: _trsm(L, t[0]),
+    "sketch_gauss_kernel": lambda L, t: _sketch_gauss(L, t[0], t[2]),
+    "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),
+    "sketch_srht_kernel": lambda L, t: _sketch_srht(L, t[0], t[1]),
+    "qr_wave_kernel": lambda L, t: _qr_wave(L),
+}
+
+
+def kernel_base(name):
+    """rbgs::<base> from a mangled name _ZN4rbgs<len><base>..."""
+    assert name.startswith("_ZN4rbgs")
+    p = len("_ZN4rbgs")
+    q = p
+    while name[q].isdigit():
+        q += 1
+    ln = int(name[p:q])
+    return name[q:q + ln]
+
+
+def check_events(events):
+    """Returns (violations, launches checked, names of kernels seen)."""
+    live = {}
+    violations = []
+    seen = set()
+    n = 0
+    for ev in events:
+        if ev[0] == "alloc":
+            live[ev[1]] = ev[2]
+        elif ev[0] == "free":
+            live.pop(ev[1], None)
+        elif ev[0] == "launch":
+            L = ev[1]
+            base = kernel_base(L.name)
+            seen.add(base)
+            if base in MIRRORS:
+                accesses = MIRRORS[base](L)
+            elif base in TEMPLATED:
+                accesses = TEMPLATED[base](L, _template_args(L.name))
+            else:
+                violations.append(f"no bounds mirror for kernel {base}")
+                continue
+            n += 1
+            for (j, es, lo, hi) in accesses:
+                ptr = L.u(j)
+                a0, a1 = ptr + lo * es, ptr + (hi + 1) * es
+                ok = any(b <= a0 and a1 <= b + sz for b, sz in live.items())
+                if not ok:
+                    violations.append(f"{base} grid {L.grid}: argument {j} touches "
+                                      f"[{a0:#x}, {a1:#x}) outside every live allocation")
+    return violations, n, seen

@@ -8,11 +8,14 @@ import numpy as np
 import pytest
 
 import oracle.rbgs as orb
+import parity_checks as pc
 from oracle.metrics import cond2, factorization_error
 from oracle.theta import Sketch
 from paper_2111_14641_amd.workloads import svd_matrix
 
 pytestmark = pytest.mark.gpu
+
+TOL64 = 4096 * 2.0**-53   # entry-wise, per-entry scales of tests/parity_checks.py
 
 SHAPES = [  # n, m, p, k
     (3000, 32, 16, 96),
@@ -65,6 +68,7 @@ def test_batched_matches_oracle(gpu_lib, kind):
         Rg, Qg = to_np(R), to_np(Q)
         assert np.linalg.norm(Rg - o["R"]) <= 1e-12 * np.linalg.norm(o["R"]), i
         assert np.linalg.norm(Qg - o["Q"]) <= 1e-11 * np.linalg.norm(o["Q"]), i
+        pc.assert_qrs_entrywise(Qg, Rg, None, o, None, TOL64, TOL64)
         assert factorization_error(W, Qg, Rg) < 1e-14
 
 
@@ -168,9 +172,12 @@ def test_lockstep_groups_match_oracle(gpu_lib, store, ls):
         if store == "f64":
             assert np.linalg.norm(Rg - o["R"]) <= 1e-12 * np.linalg.norm(o["R"]), i
             assert np.linalg.norm(Qg - o["Q"]) <= 1e-11 * np.linalg.norm(o["Q"]), i
+            pc.assert_qrs_entrywise(Qg, Rg, None, o, None, TOL64, TOL64)
             assert factorization_error(W, Qg, Rg) < 1e-14, i
         else:
             assert np.linalg.norm(Rg - o["R"]) <= 64 * 2.0**-24 * 10**decades * np.linalg.norm(o["R"]), i
+            tol32 = 64 * 2.0**-24 * 10**decades
+            pc.assert_qrs_entrywise(Qg, Rg, None, o, None, tol32, tol32)
             assert factorization_error(W, Qg, Rg) <= 1e-6, i
             assert cond2(Qg) <= 10, i
 

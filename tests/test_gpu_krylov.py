@@ -9,6 +9,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+import parity_checks as pc
 from oracle import krylov
 from oracle.theta import Sketch
 from paper_2111_14641_amd.workloads import convection_diffusion_csr, gmres_rhs
@@ -77,6 +78,11 @@ def test_arnoldi_matches_oracle(gpu_lib, kind):
     m = nb * bs
     assert np.linalg.norm(Rg - Ro) <= 1e-11 * np.linalg.norm(Ro)
     assert np.linalg.norm(Qg - Qo) <= 1e-10 * np.linalg.norm(Qo)
+    # entry-wise: R by its column norms; Q by the largest entry of its column
+    # (W_(i) = A Q_(i-1) depends on the basis, so Q = W R^{-1} gives no finer scale)
+    pc.assert_entrywise(Rg, Ro, pc.scale_R(Ro), 1e-11, "Arnoldi R")
+    pc.assert_entrywise(Qg, Qo, np.broadcast_to(np.abs(Qo).max(axis=0)[None, :], Qo.shape), 1e-10,
+                        "Arnoldi Q")
     An = np.linalg.norm(A.toarray(), 2)
     assert np.linalg.norm(A @ Qg[:, :m - bs] - Qg @ Rg[:, bs:]) <= 1e-12 * An * np.linalg.norm(Qg)
     assert cert["delta"] < 1e-10 and cert["breakdown_col"] == -1
@@ -118,6 +124,31 @@ def test_gmres_converges_like_the_oracle(gpu_lib, store):
     assert np.linalg.norm(to_np(X) - Xd) <= 1e-5 * np.linalg.norm(Xd)
     if store == "f64":
         np.testing.assert_allclose(hist[:3], ho[:3], rtol=1e-6)
+
+
+def test_gmres_history_matches_oracle_where_it_converges(gpu_lib):
+    """The workload's settings (8 right-hand sides, 40 blocks per cycle,
+    k = 1280, sparse sign) on the 64 x 64 grid, where restarted GMRES converges
+    without a preconditioner (the oracle reaches 1e-8 in 9 cycles): FP64 basis,
+    the relative residual at the start of every cycle and at the end against the
+    oracle's, entry by entry."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("gmres history 64^2")
+    N, bs, p, k, seed = 64, 8, 40, 1280, 0x2111146413
+    arrs, A = host_csr(N)
+    n = N * N
+    Bh = gmres_rhs(n, bs)
+    X, iters, rel, hist, ok = B.block_gmres(B.CSR(*arrs), dev(Bh, torch.float64), None, p, 12, 1e-8,
+                                           kind="sparse", k=k, seed=seed, store="f64")
+    Xo, ho = krylov.block_gmres(A, Bh, np.zeros((n, bs)), p, 12, 1e-8,
+                                Sketch("sparse", k, seed=seed).materialize(n))
+    say("history gpu", hist)
+    say("history oracle", ho)
+    assert ok and ho[-1] <= 1e-8
+    assert len(hist) == len(ho)
+    np.testing.assert_allclose(hist, ho, rtol=1e-6)
+    np.testing.assert_allclose(to_np(X), Xo, rtol=0, atol=1e-9 * np.abs(Xo).max())
 
 
 def test_gmres_full_grid_first_cycles(gpu_lib):

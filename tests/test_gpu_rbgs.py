@@ -1,15 +1,21 @@
 """RBGS QR on the GPU (through the C ABI) against the FP64 oracle.
 
-Tolerances (derived from the arithmetic; u = 2^-53, u32 = 2^-24):
+Every comparison of Q, R and S is made entry by entry against a per-entry
+scale derived from a perturbation bound (tests/parity_checks.py), and the
+certificates Delta, Delta~ are compared with the oracle's certificate routine
+evaluated on the GPU's own S and R.  The relative Frobenius checks stay beside
+them.  Tolerances (u = 2^-53, u32 = 2^-24):
 * FP64 storage, same Theta bits on both sides, so the two computations differ
-  only in summation order.  R is determined to a few u (its entries are
-  well-conditioned functions of the sketches), Q to about u cond(W) poly(m):
-  rel. diff of R <= 1e-12, of Q <= 1e-12 for cond(W) = 1e2 and <= 1e-6 for
-  cond(W) = 1e8.
+  only in summation order (and the GPU's multiplication by 1/R_cc in the
+  substitution).  Entry-wise: |x - x_or| <= TOL64 * scale with TOL64 = 4096 u
+  (a reordering of the oracle's own sums gives at most about 30 u on these
+  scales).  Norm-wise: R <= 1e-12, Q <= 1e-12 for cond(W) = 1e2 and <= 1e-6
+  for cond(W) = 1e8.
 * FP32 storage with FP64 arithmetic (only Q'_(i) is rounded to FP32) is
-  compared with the oracle run on the same fp32-rounded input: R <= 64 u32
-  cond(W) and the benchmark spec's metrics ||W - QR||_F/||W||_F <= 1e-6 and
-  cond2(Q) <= 10.
+  compared with the oracle run on the same fp32-rounded input: the rounding of
+  each stored Q_(i) (u32 |Q_(i)|) propagates through R^{-1}, so entry-wise
+  |x - x_or| <= 64 u32 cond(W) * scale, and the benchmark spec's metrics
+  ||W - QR||_F/||W||_F <= 1e-6 and cond2(Q) <= 10.
 """
 import sys
 
@@ -17,11 +23,16 @@ import numpy as np
 import pytest
 
 import oracle.rbgs as orb
+import parity_checks as pc
 from oracle.metrics import cond2, factorization_error
 from oracle.theta import Sketch
 from paper_2111_14641_amd.workloads import svd_matrix, small_single_qr, THETA_SEED_SMALL
 
 pytestmark = pytest.mark.gpu
+
+U64 = 2.0**-53
+U32 = 2.0**-24
+TOL64 = 4096 * U64
 
 
 def say(*a):
@@ -48,7 +59,18 @@ def gpu_qr(W, b, kind, k, seed, variant, store="f64", ls_iters=2, zeta=None, inp
 
 def oracle_qr(W, b, kind, k, seed, variant, ls_iters=2, zeta=None):
     th = Sketch(kind, k, seed=seed, zeta=zeta).materialize(W.shape[0])
-    return orb.rbgs(W, b, th, variant, "richardson", ls_iters)
+    o = orb.rbgs(W, b, th, variant, "richardson", ls_iters)
+    o["absT"] = pc.abs_theta(th, W.shape[0])
+    return o
+
+
+def check_entrywise(W, Q, R, S, cert, o, tol_r, tol_q=None, tol_s=None, certs=True):
+    """Entry-wise Q, R, S against the oracle and the certificates against the
+    oracle's routine on the GPU's S and R."""
+    pc.assert_qrs_entrywise(Q, R, S, o, o["absT"], tol_r, tol_q if tol_q is not None else tol_r,
+                            tol_s)
+    if certs and cert is not None and S is not None:
+        pc.check_certificates(cert, S, R, o["P"], pc.abs_theta_w_fro(o["absT"], W), W.shape[0])
 
 
 @pytest.fixture(scope="module")
@@ -66,6 +88,7 @@ def test_small_workload_fp64_matches_oracle(gpu_lib, small, variant):
     assert rel(R, o["R"]) < 1e-12
     assert rel(Q, o["Q"]) < 1e-6
     assert rel(S, o["S"]) < 1e-6
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
     assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
     assert factorization_error(W, Q, R) < 1e-14
     assert abs(cond2(Q) - cond2(o["Q"])) < 1e-6
@@ -85,6 +108,7 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     assert rel(R, o["R"]) < 1e-12
     assert rel(Q, o["Q"]) < 1e-12
     assert rel(S, o["S"]) < 1e-12
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
     assert cert["delta"] < 1e-12
 
 
@@ -120,6 +144,7 @@ def test_shapes_fp64(gpu_lib, n, m, b, k, kind, variant):
     o = oracle_qr(W, b, kind, k, 23, variant)
     assert rel(R, o["R"]) < 1e-12
     assert rel(Q, o["Q"]) < 1e-11
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
     assert factorization_error(W, Q, R) < 1e-14
     if kind == "identity":
         Qh, Rh = np.linalg.qr(W)
@@ -144,6 +169,13 @@ def test_fp32_storage_fp64_arithmetic(gpu_lib, variant, decades):
     assert rel(R, o["R"]) <= 64 * 2.0**-24 * 10**decades
     if decades == 2:
         assert rel(Q, o["Q"]) <= 64 * 2.0**-24 * 1e2
+    # entry-wise against the oracle on the same fp32 input; Q and S (whose
+    # columns inherit the FP32 rounding of the stored blocks) where W is
+    # numerically full rank in FP32
+    tol = 64 * U32 * 10**decades
+    check_entrywise(W, Q, R, S if decades == 2 else None, cert, o, tol,
+                    tol_q=tol if decades == 2 else np.inf)
+    pc.check_certificates(cert, S, R, o["P"], pc.abs_theta_w_fro(o["absT"], W), W.shape[0])
 
 
 @pytest.mark.parametrize("variant", ["plain", "lowsync"])
@@ -157,12 +189,18 @@ def test_fp32_arithmetic(gpu_lib, variant):
     Q, R, S, cert = gpu_qr(W, 8, "gaussian", 256, THETA_SEED_SMALL, variant, store="f32", math="f32")
     o = oracle_qr(W, 8, "gaussian", 256, THETA_SEED_SMALL, variant)
     assert rel(R, o["R"]) <= 64 * 2.0**-24 * 1e2
+    check_entrywise(W, Q, R, S, cert, o, 64 * U32 * 1e2)
     assert cond2(Q) <= 10 and cert["delta"] < 1e-3
     W8 = svd_matrix(10_000, 64, np.logspace(0, -8, 64), seed=31).astype(np.float32).astype(np.float64)
     Q, R, S, cert = gpu_qr(W8, 8, "gaussian", 256, THETA_SEED_SMALL, variant, store="f32", math="f32")
     assert factorization_error(W8, Q, R) <= 1e-6
     assert cert["delta"] > 0.1                 # certificate: not stable
     assert cond2(Q) > 10
+    # the certificate reports what the GPU's own S and R show
+    th8 = Sketch("gaussian", 256, seed=THETA_SEED_SMALL).materialize(W8.shape[0])
+    P8 = th8(W8)
+    pc.check_certificates(cert, S, R, P8, pc.abs_theta_w_fro(pc.abs_theta(th8, W8.shape[0]), W8),
+                          W8.shape[0])
 
 
 @pytest.mark.parametrize("variant", ["twice", "l2qr"])
@@ -175,6 +213,7 @@ def test_two_pass_forms_fp64_elementwise(gpu_lib, variant, kind, k):
     assert rel(R, o["R"]) < 1e-12
     assert rel(Q, o["Q"]) < 1e-12
     assert rel(S, o["S"]) < 1e-12
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
     assert cert["delta"] < 1e-12
 
 
@@ -195,6 +234,8 @@ def test_second_pass_restores_sketched_orthogonality(gpu_lib, decades):
         assert cert["delta_tilde"] < 100 * 2.0**-53 * 16
         assert factorization_error(W, Q, R) < 100 * 2.0**-53 * 16
         assert rel(R, o["R"]) < 1e-13 * 10.0**(decades / 2)
+        pc.assert_entrywise(R, o["R"], pc.scale_R(o["R"]), 1e-13 * 10.0**(decades / 2), "R")
+        pc.check_certificates(cert, S, R, o["P"], pc.abs_theta_w_fro(o["absT"], W), W.shape[0])
 
 
 @pytest.mark.parametrize("n,m,b,store", [(10_000, 64, 8, "f64"), (7777, 70, 16, "f64"),
@@ -228,6 +269,10 @@ def test_cholqr_post_processing(gpu_lib, n, m, b, store):
     tol = 1e-12 if store == "f64" else 64 * u
     assert rel(Rg, Ro) < tol
     assert rel(Qg, Qo) < tol
+    # entry-wise: R' R by the column scale; Q R'^{-1} by the scale of Q = W R^{-1}
+    etol = TOL64 if store == "f64" else 64 * u
+    pc.assert_entrywise(Rg, Ro, pc.scale_R(Ro), etol, "R post")
+    pc.assert_entrywise(Qg, Qo, pc.scale_Q(Qo, Ro), etol, "Q post")
     Qh, Rh = np.linalg.qr(W)
     d = np.sign(np.diag(Rh))
     assert rel(Rg, d[:, None] * Rh) < (1e-12 if store == "f64" else 1e-5)
@@ -294,6 +339,9 @@ def test_rank_deficient_in_fp64(gpu_lib, store):
     assert cert["delta"] < 0.1 and cert["delta_tilde"] < 1e-6
     # the first block is well conditioned: its R factor is unique
     assert rel(R[:16, :16], o["R"][:16, :16]) < (1e-12 if store == "f64" else 1e-6)
+    R11 = o["R"][:16, :16]
+    pc.assert_entrywise(R[:16, :16], R11, pc.scale_R(R11), TOL64 if store == "f64" else 64 * U32,
+                        "R_(1,1)")
 
 
 def test_update_falls_back_past_lds_capacity(gpu_lib):
@@ -307,6 +355,7 @@ def test_update_falls_back_past_lds_capacity(gpu_lib):
     o = oracle_qr(W, b, "sparse", k, 29, "lowsync")
     assert rel(R, o["R"]) < 1e-12
     assert rel(Q, o["Q"]) < 1e-11
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
     assert factorization_error(W, Q, R) < 1e-14
 
 

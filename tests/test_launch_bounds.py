@@ -1,0 +1,130 @@
+"""Host-side bounds check of every kernel launch of rbgs_qr (CPU, no GPU).
+
+The library's object files are linked with a recording stand-in for the HIP
+runtime (tests/launch_bounds/mock_hip.cpp) and driven through the C ABI
+(tests/launch_bounds/driver.cpp), so the real host code chooses every grid,
+workspace offset and argument.  tests/launch_bounds/check_launches.py restates
+each kernel's index expressions and checks that every global-memory access of
+every launch stays inside a live allocation.  The shapes include the full-size
+workloads (n = 10^6, m = 256, p = 16, k = 1024 and n = 4 10^6, m = 512,
+p = 32, k = 2048) with every sketch, storage and inter-block variant they use,
+and the small shapes the GPU parity tests run."""
+import glob
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HERE = os.path.join(ROOT, "tests", "launch_bounds")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+GAUSS, SPARSE, RADEM, SRHT = 0, 1, 3, 4
+F64, F32 = 0, 1
+PLAIN, LOWSYNC, TWICE, L2QR = 0, 1, 2, 3
+
+CASES = [
+    # n, m, p, k, kind, store, math, variant, ls, want_S, want_cert
+    (4_000_000, 512, 32, 2048, GAUSS, F32, 0, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F32, 0, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F64, 0, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F32, 1, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, GAUSS, F64, 0, LOWSYNC, 4, 1, 1),
+    (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 4, 1, 1),
+    (1_000_000, 256, 16, 1024, SPARSE, F64, 0, LOWSYNC, 4, 1, 1),
+    (1_000_000, 256, 16, 1024, GAUSS, F32, 0, LOWSYNC, 4, 0, 1),
+    (1_000_000, 256, 16, 1024, SPARSE, F32, 0, PLAIN, 4, 0, 1),
+    (1_000_000, 256, 16, 1024, SRHT, F32, 0, LOWSYNC, 4, 0, 1),
+    (10_000, 64, 8, 256, GAUSS, F64, 0, PLAIN, 2, 1, 1),
+    (4097, 30, 8, 128, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (3000, 70, 32, 512, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (5000, 96, 32, 256, GAUSS, F64, 0, LOWSYNC, 2, 1, 1),
+    (9000, 40, 16, 2048, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (3000, 560, 16, 576, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (4097, 30, 8, 132, RADEM, F64, 0, LOWSYNC, 2, 1, 1),
+    (10_000, 64, 8, 256, GAUSS, F32, 1, PLAIN, 2, 1, 1),
+]
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    objs = sorted(glob.glob(os.path.join(ROOT, "paper_2111_14641_amd", "_build", "*.o")))
+    if len(objs) < 6:
+        from paper_2111_14641_amd import build
+        build.build()
+        objs = sorted(glob.glob(os.path.join(ROOT, "paper_2111_14641_amd", "_build", "*.o")))
+    out = tmp_path_factory.mktemp("lb")
+    flags = ["-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+             "-I" + os.path.join(ROOT, "include"), "-w"]
+    for src in ("mock_hip.cpp", "driver.cpp"):
+        subprocess.run([CLANG, *flags, "-c", os.path.join(HERE, src), "-o",
+                        str(out / (src + ".o"))], check=True)
+    exe = str(out / "driver")
+    subprocess.run([CLANG, "-o", exe, str(out / "mock_hip.cpp.o"), str(out / "driver.cpp.o"), *objs],
+                   check=True)
+    return exe, out
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(str(v) for v in c[:4]) +
+                         f"-kind{c[4]}-store{c[5]}-math{c[6]}-var{c[7]}")
+def test_every_launch_stays_in_bounds(driver, case):
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / ("log_" + "_".join(str(v) for v in case) + ".txt"))
+    r = subprocess.run([exe, *[str(v) for v in case]], env={**os.environ, "RBGS_LAUNCH_LOG": log},
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    violations, n, seen = cl.check_events(cl.parse_log(log))
+    assert n > 0
+    assert not violations, "\n".join(violations[:20])
+
+
+def test_checker_catches_planted_out_of_bounds(driver):
+    """The checker must flag accesses past an allocation: on a recorded
+    4e6 x 512 Gaussian factorization, (a) the workspace shortened by one
+    element, (b) the last update launch given an output leading dimension one larger,
+    (c) one sketch reduction given one partial sum more, (d) a kernel without
+    a mirror."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / "planted.txt")
+    case = CASES[0]
+    subprocess.run([exe, *[str(v) for v in case]], env={**os.environ, "RBGS_LAUNCH_LOG": log},
+                   check=True, capture_output=True)
+    events = cl.parse_log(log)
+    assert not cl.check_events(events)[0]
+
+    def first(pred):
+        return next(i for i, e in enumerate(events) if pred(e))
+
+    # (a) the largest allocation (the workspace or W) one element shorter
+    ia = max((i for i, e in enumerate(events) if e[0] == "alloc"), key=lambda i: events[i][2])
+    bad = list(events)
+    bad[ia] = ("alloc", events[ia][1], events[ia][2] - 8)
+    assert cl.check_events(bad)[0]
+    # (b) the last update launch with an output leading dimension one larger
+    # (its last block of Q then ends 31 elements past the end of Q)
+    iu = max(i for i, e in enumerate(events)
+             if e[0] == "launch" and cl.kernel_base(e[1].name) == "update_kernel")
+    L = events[iu][1]
+    raw = list(L.raw)
+    raw[5] = (L.i(5) + 1).to_bytes(8, "little", signed=True)
+    bad = list(events)
+    bad[iu] = ("launch", cl.Launch(L.name, L.grid, L.block, L.shmem, raw))
+    assert any("update_kernel" in v for v in cl.check_events(bad)[0])
+    # (c) a reduction over one more partial sum than were written
+    ir = first(lambda e: e[0] == "launch" and cl.kernel_base(e[1].name) == "sketch_reduce_kernel")
+    L = events[ir][1]
+    raw = list(L.raw)
+    raw[1] = (L.i(1) + 4000).to_bytes(4, "little", signed=True)
+    bad = list(events)
+    bad[ir] = ("launch", cl.Launch(L.name, L.grid, L.block, L.shmem, raw))
+    assert any("sketch_reduce_kernel" in v for v in cl.check_events(bad)[0])
+    # (d) an unknown kernel
+    L = events[ir][1]
+    bad = list(events) + [("launch", cl.Launch("_ZN4rbgs9new_thingEv", (1, 1, 1), (64, 1, 1), 0, []))]
+    assert any("no bounds mirror" in v for v in cl.check_events(bad)[0])

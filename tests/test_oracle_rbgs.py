@@ -81,6 +81,64 @@ def test_invariants_and_certificates(small_case, variant):
     assert factorization_error(W, out["Q"], R) < 1e-14
 
 
+def _cert_case():
+    """S = U diag(sqrt(1 + e_j)) with U orthonormal gives S^T S = diag(1 + e_j),
+    so Delta = ||e||_2 exactly.  P = S R + F with S^T F = 0 gives P - S R = F
+    and ||P||_F^2 = ||S R||_F^2 + ||F||_F^2, so Delta~ = ||F||_F /
+    sqrt(||S R||_F^2 + ||F||_F^2).  ||P||_F is about 30, so dropping the
+    normalization (or applying it twice, or to the squares only) changes Delta~
+    by a large factor."""
+    rng = np.random.default_rng(7)
+    k, m = 40, 6
+    Ufull, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    U, Uperp = Ufull[:, :m], Ufull[:, m:]
+    e = np.array([0.3, -0.2, 0.1, 0.05, -0.4, 0.25])
+    S = U * np.sqrt(1.0 + e)[None, :]
+    R = np.triu(rng.standard_normal((m, m))) * 10.0 + np.diag(np.full(m, 5.0))
+    F = Uperp @ rng.standard_normal((k - m, m)) * 0.7
+    nF = np.linalg.norm(F)
+    nP = np.sqrt(np.linalg.norm(S @ R) ** 2 + nF ** 2)
+    return S, S @ R + F, R, float(np.linalg.norm(e)), float(nF / nP), nP
+
+
+def _cert_pin_holds():
+    S, P, R, delta_ref, dt_ref, _ = _cert_case()
+    delta, delta_tilde = orb.certificates(S, P, R)
+    return (abs(delta - delta_ref) <= 1e-13 * delta_ref
+            and abs(delta_tilde - dt_ref) <= 1e-12 * dt_ref)
+
+
+def test_certificates_on_known_matrices(monkeypatch):
+    """Step 6 of Algorithm RBGS on matrices whose certificates are known in
+    closed form (_cert_case), and planted mistakes in the certificate formulas
+    that this pin must catch."""
+    S, P, R, delta_ref, dt_ref, nP = _cert_case()
+    assert nP > 20.0
+    assert _cert_pin_holds()
+    # an exact factorization has Delta~ = 0 whatever the scale of P
+    assert orb.certificates(S, S @ R, R)[1] < 1e-15
+    # Delta~ is invariant under a common scaling of P and R (a normalized residual)
+    assert orb.certificates(S, 3.0 * P, 3.0 * R)[1] == pytest.approx(dt_ref, rel=1e-12)
+    # orthonormal columns: Delta = 0
+    U = S / np.linalg.norm(S, axis=0)[None, :]
+    assert orb.certificates(U, P, R)[0] < 1e-14
+    good = orb.certificates
+    fro = lambda A: np.linalg.norm(A, "fro")
+    mistakes = {
+        "Delta~ not normalized": lambda S, P, R: (good(S, P, R)[0], fro(P - S @ R)),
+        "Delta~ normalized twice": lambda S, P, R: (good(S, P, R)[0], fro(P - S @ R) / fro(P) ** 2),
+        "Delta~ squares normalized": lambda S, P, R: (good(S, P, R)[0], fro(P - S @ R) ** 2 / fro(P) ** 2),
+        "Delta~ with R transposed": lambda S, P, R: (good(S, P, R)[0], fro(P - S @ R.T) / fro(P)),
+        "Delta from S S^T": lambda S, P, R: (fro(np.eye(S.shape[0]) - S @ S.T), good(S, P, R)[1]),
+        "Delta squared": lambda S, P, R: (fro(np.eye(S.shape[1]) - S.T @ S) ** 2, good(S, P, R)[1]),
+    }
+    for name, bad in mistakes.items():
+        monkeypatch.setattr(orb, "certificates", bad)
+        assert not _cert_pin_holds(), name
+        monkeypatch.setattr(orb, "certificates", good)
+    assert _cert_pin_holds()
+
+
 def test_condition_number_equals_that_of_sketched_basis(small_case):
     """In exact arithmetic sigma(Q) = 1/sigma(Theta U) for U an orthonormal basis
     of range(W), so cond(Q) = cond(Theta U)."""
