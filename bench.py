@@ -79,8 +79,29 @@ def accuracy(W, Q, R, cert):
     return dict(rel_err=err, cond2_Q=cond, delta=cert["delta"], delta_tilde=cert["delta_tilde"])
 
 
+def accuracy_chunked(W, Q, R, cert, chunk=1 << 20):
+    """As `accuracy`, with the FP64 products formed over row chunks (for
+    matrices whose FP64 copies would be large)."""
+    import numpy as np
+    import torch
+    n, m = W.shape
+    num = torch.zeros((), dtype=torch.float64, device=W.device)
+    den = torch.zeros((), dtype=torch.float64, device=W.device)
+    G = torch.zeros((m, m), dtype=torch.float64, device=W.device)
+    for r0 in range(0, n, chunk):
+        Wc = W[r0:r0 + chunk].double()
+        Qc = Q[r0:r0 + chunk].double()
+        num += ((Wc - Qc @ R) ** 2).sum()
+        den += (Wc ** 2).sum()
+        G += Qc.t() @ Qc
+    ev = np.linalg.eigvalsh(G.cpu().numpy())
+    cond = float(np.sqrt(ev[-1] / ev[0])) if ev[0] > 0 else float("inf")
+    return dict(rel_err=float(torch.sqrt(num / den)), cond2_Q=cond, delta=cert["delta"],
+                delta_tilde=cert["delta_tilde"])
+
+
 def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64",
-              profile_sketch=False):
+              profile_sketch=False, chunked_metrics=False, keep_R=False):
     """Times `steps` QRs on a dedicated stream.  With profile_update, a second
     timed region of `steps` QRs follows in which HIP events bracket every
     update launch on its stream (the roofline figure); the events themselves
@@ -99,7 +120,8 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
     with torch.cuda.stream(stream):
         # accuracy run (with certificate) outside the timed region
         _, _, _, cert = run(want_cert=True)
-        acc = accuracy(W, Q, R, cert)
+        acc = (accuracy_chunked if chunked_metrics else accuracy)(W, Q, R, cert)
+        R_acc = R.clone() if keep_R else None
         for _ in range(warmup):
             run()
         torch.cuda.synchronize()
@@ -136,7 +158,10 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
                       sketch_TFLOPs=tflops, sketch_mfma_frac=tflops / FP64_MFMA_PEAK_TFLOPS)
     s = 4 if W.dtype == torch.float32 else 8
     gbs = alg_bytes(n, m, p, s) / (ms * 1e-3) / 1e9
-    return dict(ms=ms, alg_GBps=gbs, **acc, **sk), upd
+    res = dict(ms=ms, alg_GBps=gbs, **acc, **sk)
+    if keep_R:
+        res["_R"] = R_acc
+    return res, upd
 
 
 def post_form(W, p, kind, k, seed, reps=3):
@@ -249,6 +274,36 @@ def batched_form(count=512, reps=3):
                                                           for k, W in zip(ks, Ws))))
 
 
+def mixed_form(steps, warmup, maths=("f64", "f32")):
+    """The mixed-precision workload: W is n = 4e6 x m = 512, cond 1e10
+    (U diag(logspace(0, -10, 512)) V^T), p = 32, k = 2048, sparse sign,
+    low-sync; FP32 storage with each product arithmetic in `maths` against
+    FP64 storage.  Each form reports ms per QR, algorithmic GB/s,
+    ||W - QR||_F / ||W||_F against its stored input, cond2(Q), Delta,
+    Delta~ and ||R - R_64||_F / ||R_64||_F against the FP64 form's R."""
+    import torch
+    from paper_2111_14641_amd.workloads import mixed_single_qr_gpu, THETA_SEED_MIXED
+    p, k = 32, 2048
+    W64, W32 = mixed_single_qr_gpu(dtypes=("float64", "float32"))
+    torch.cuda.synchronize()
+    out = {}
+    print("[bench] mixed workload: fp64", file=sys.stderr, flush=True)
+    f64, _ = time_form(W64, p, "sparse", k, THETA_SEED_MIXED, "lowsync", steps, warmup,
+                       chunked_metrics=True, keep_R=True)
+    del W64
+    R64 = f64.pop("_R")
+    for mth in maths:
+        print(f"[bench] mixed workload: fp32 storage, {mth} arithmetic", file=sys.stderr, flush=True)
+        f, _ = time_form(W32, p, "sparse", k, THETA_SEED_MIXED, "lowsync", steps, warmup,
+                         math=mth, chunked_metrics=True, keep_R=True)
+        R = f.pop("_R")
+        f["rel_diff_R_vs_f64"] = float(torch.linalg.matrix_norm(R - R64) / torch.linalg.matrix_norm(R64))
+        f["speedup_vs_f64"] = f64["ms"] / f["ms"]
+        out[f"mixed_f32_{mth}math"] = f
+    out["mixed_f64"] = f64
+    return out
+
+
 def gmres_form(N=1024, bs=8, blocks=40, k=1280, max_cycles=60, tol=1e-8):
     """Restarted randomized block GMRES on the N x N convection-diffusion
     operator (n = N^2, FP64 CSR), bs Gaussian right-hand sides, `blocks` blocks
@@ -356,10 +411,12 @@ def main():
     ap.add_argument("--no-gaussian", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
-    ap.add_argument("--forms", default="all", choices=["all", "headline", "srht", "batched", "gaussian"],
-                    help="'headline': only the headline form; 'srht' / 'batched': the headline and "
-                         "that form; 'gaussian': the headline and the FP32 Gaussian and "
-                         "Rademacher forms (for profiling one form)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--forms", default="all",
+                    choices=["all", "headline", "srht", "batched", "gaussian", "mixed"],
+                    help="'headline': only the headline form; 'srht' / 'batched' / 'mixed': the "
+                         "headline and that form; 'gaussian': the headline and the FP32 Gaussian "
+                         "and Rademacher forms (for profiling one form)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -434,6 +491,8 @@ def main():
         forms["f64_srht_lowsync"], _ = time_form(W64, p, "srht", k, THETA_SEED_LARGE, "lowsync",
                                                  max(3, args.steps // 4), 1)
     del W64
+    if args.forms in ("all", "mixed") and not args.no_mixed:
+        forms.update(mixed_form(max(3, args.steps // 4), 1))
     if args.forms in ("all", "batched") and not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         forms["batched_512_f32"] = batched_form()

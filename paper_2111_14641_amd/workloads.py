@@ -15,11 +15,16 @@ returned in FP64, column-major (Fortran order), so that column j is contiguous.
   rank-deficient, which stands in for the matrix of the paper's first numerical
   example (Section 5.1), whose exact generator differs; with n = 10^6 and
   m = 256 this is the large single-QR workload.
-* `svd_matrix_gpu(n, m, sigma, seed)`: the same construction as `svd_matrix`
-  built on the GPU with torch (U from a seeded device Gaussian by two rounds of
-  Cholesky orthonormalization, V on the host), for sizes whose FP64 factors do
-  not fit comfortably in host memory; with n = 4 10^6, m = 512 and
-  sigma = logspace(0, -10, 512) this is the mixed-precision workload.
+* `svd_matrix_gpu(n, m, sigma, seed, dtypes)`: the same construction as
+  `svd_matrix` built on the GPU in row chunks, for sizes whose FP64 factors do
+  not fit comfortably in host memory: G is a seeded device Gaussian generated
+  chunk by chunk (chunk c from its own generator seeded with seed + c, so any
+  chunk can be regenerated), U = G M1 with M1 = L1^{-T} L2^{-T} from two rounds
+  of Cholesky orthonormalization whose Gram matrices are summed over the
+  chunks in a fixed order, V on the host, and W = G (M1 diag(sigma) V^T)
+  written chunk by chunk into one output tensor per requested dtype.  No torch
+  operation touches more than one chunk (2^18 rows).  With n = 4 10^6, m = 512
+  and sigma = logspace(0, -10, 512) this is the mixed-precision workload.
 * `batched_problems(count, seed)`: the batched workload, `count` FP32
   matrices on the GPU with n = round(2^u), u ~ U[14, 18], m drawn from
   {32, 64, 128, 256} and W = G diag(sigma) V^T, G a seeded Gaussian n x m
@@ -75,25 +80,45 @@ def oscillatory_matrix(n, m, seed, dtype=np.float64, chunk=1 << 17):
     return W
 
 
-def svd_matrix_gpu(n, m, sigma, seed, device="cuda"):
-    """W = U diag(sigma) V^T as an FP64 column-major CUDA tensor."""
+def _gpu_gaussian_chunk(r0, r1, m, seed, chunk, device):
     import torch
     g = torch.Generator(device=device)
-    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
-    U = torch.randn((n, m), generator=g, dtype=torch.float64, device=device)
+    g.manual_seed((int(seed) + r0 // chunk) & 0x7FFFFFFFFFFFFFFF)
+    return torch.randn((r1 - r0, m), generator=g, dtype=torch.float64, device=device)
+
+
+def svd_matrix_gpu(n, m, sigma, seed, device="cuda", dtypes=("float64",), chunk=1 << 18):
+    """W = U diag(sigma) V^T as column-major tensors on `device`, one per
+    entry of `dtypes` (torch dtype names), built in row chunks."""
+    import torch
+    ranges = [(r0, min(n, r0 + chunk)) for r0 in range(0, n, chunk)]
+    # two rounds of Cholesky orthonormalization of G; M1 = L1^{-T} L2^{-T}
+    M1 = np.eye(m)
     for _ in range(2):
-        L = torch.linalg.cholesky(U.t() @ U)
-        U = torch.linalg.solve_triangular(L.t(), U, upper=True, left=False)  # U L^{-T}
+        Mt = torch.from_numpy(M1).to(device)
+        A = np.zeros((m, m))
+        for r0, r1 in ranges:
+            X = _gpu_gaussian_chunk(r0, r1, m, seed, chunk, device) @ Mt
+            A += (X.t() @ X).cpu().numpy()
+            del X
+        A = 0.5 * (A + A.T)
+        L = np.linalg.cholesky(A)
+        M1 = M1 @ np.linalg.inv(L).T
     V = _orthonormal(np.random.default_rng(seed), m, m)
-    M = torch.from_numpy(np.asarray(sigma, dtype=np.float64)[:, None] * V.T).to(device)
-    W = torch.empty((m, n), dtype=torch.float64, device=device).t()
-    W.copy_(U @ M)
-    return W
+    M = torch.from_numpy(M1 @ (np.asarray(sigma, dtype=np.float64)[:, None] * V.T)).to(device)
+    outs = [torch.empty((m, n), dtype=getattr(torch, d), device=device).t() for d in dtypes]
+    for r0, r1 in ranges:
+        Wc = _gpu_gaussian_chunk(r0, r1, m, seed, chunk, device) @ M
+        for o in outs:
+            o[r0:r1].copy_(Wc)
+        del Wc
+    return outs[0] if len(outs) == 1 else tuple(outs)
 
 
-def mixed_single_qr_gpu(seed=0xDA7A02, n=4_000_000, m=512, decades=10.0):
+def mixed_single_qr_gpu(seed=0xDA7A02, n=4_000_000, m=512, decades=10.0,
+                        dtypes=("float64",)):
     """The mixed-precision single-QR workload (cond(W) = 10^decades), on the GPU."""
-    return svd_matrix_gpu(n, m, np.logspace(0.0, -decades, m), seed)
+    return svd_matrix_gpu(n, m, np.logspace(0.0, -decades, m), seed, dtypes=dtypes)
 
 
 def batched_problems(count=512, seed=0xDA7A04, device="cuda"):

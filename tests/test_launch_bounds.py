@@ -27,7 +27,9 @@ CASES = [
     # n, m, p, k, kind, store, math, variant, ls, want_S, want_cert
     (4_000_000, 512, 32, 2048, GAUSS, F32, 0, LOWSYNC, 4, 0, 1),
     (4_000_000, 512, 32, 2048, SPARSE, F32, 0, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F32, 0, LOWSYNC, 4, 1, 1),
     (4_000_000, 512, 32, 2048, SPARSE, F64, 0, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F64, 0, LOWSYNC, 4, 1, 1),
     (4_000_000, 512, 32, 2048, SPARSE, F32, 1, LOWSYNC, 4, 0, 1),
     (4_000_000, 512, 32, 2048, GAUSS, F64, 0, LOWSYNC, 4, 1, 1),
     (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 4, 1, 1),

@@ -13,15 +13,22 @@ def test_svd_matrix_has_the_prescribed_singular_values():
 
 
 def test_gpu_construction_on_the_cpu_device():
-    """The torch construction used for the 4e6 x 512 workload, run on the CPU
-    device at a small size: column-major, prescribed singular values,
-    deterministic for a seed."""
-    s = np.logspace(0, -6, 16)
-    W = wl.svd_matrix_gpu(3000, 16, s, 7, device="cpu")
-    assert W.stride() == (1, 3000)
-    assert np.allclose(np.linalg.svd(W.numpy(), compute_uv=False), s, rtol=1e-10, atol=0)
-    W2 = wl.svd_matrix_gpu(3000, 16, s, 7, device="cpu")
+    """The row-chunked torch construction used for the 4e6 x 512 workload, run
+    on the CPU device at a small size with several chunks and a ragged last
+    chunk: column-major, prescribed singular values (cond 1e10 as in the
+    workload), deterministic for a seed, the FP32 output the rounded FP64 one."""
+    s = np.logspace(0, -10, 16)
+    W, W32 = wl.svd_matrix_gpu(3000, 16, s, 7, device="cpu", dtypes=("float64", "float32"),
+                               chunk=1024)
+    assert W.stride() == (1, 3000) and W32.stride() == (1, 3000)
+    sv = np.linalg.svd(W.numpy(), compute_uv=False)
+    assert np.allclose(sv, s, rtol=1e-5, atol=0)
+    assert np.allclose(sv[:8], s[:8], rtol=1e-12, atol=0)
+    assert np.array_equal(W32.numpy(), W.numpy().astype(np.float32))
+    W2 = wl.svd_matrix_gpu(3000, 16, s, 7, device="cpu", chunk=1024)
     assert np.array_equal(W.numpy(), W2.numpy())
+    # the chunks are independent draws (no chunk repeats another)
+    assert not np.allclose(W.numpy()[:952], W.numpy()[1024:1976])
 
 
 def test_oscillatory_matrix_formula_and_chunking():
