@@ -178,6 +178,35 @@ RBGS_API rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t 
                     const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
                     double* R, int64_t ldr, double* S_out, rbgs_cert* cert);
 
+/* Bytes of the device scratch array that rbgs_qr_noalloc works in (64 MiB). */
+#define RBGS_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* rbgs_qr without any allocation, for callers that cannot allocate device or
+ * host memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments and results as
+ * rbgs_qr without the certificate (which needs a host wait); Q, R and S_out
+ * are bitwise identical to rbgs_qr's for the same inputs and options.
+ *  - Workspace: a fixed device array of RBGS_NOALLOC_SCRATCH_BYTES per device
+ *    (part of the library's code object, held until the process ends)
+ *    instead of the handle's workspace.  Its address is looked up on the first
+ *    call on each device; that first call must not be under graph capture.
+ *    The call itself makes no hipMalloc, hipFree, host-pinned allocation or
+ *    event creation (profiling is not recorded for it).
+ *  - A factorization whose workspace exceeds the array returns RBGS_ENOMEM
+ *    before anything is enqueued (rbgs_last_error gives the bytes needed; the
+ *    n = 10^6, m = 256, p = 16, k = 1024 sparse-sign FP32 factorization needs
+ *    about 62 MB and fits).
+ *  - Every call on one device shares that device's array, and the array keeps
+ *    the contents of the last call.  Calls that may overlap on one device
+ *    (other streams, other threads, other handles) race and must be ordered
+ *    by the caller.  Everything the factorization needs cleared is cleared by
+ *    its own kernels at the start of each call.
+ *  - Errors: as rbgs_qr (RBGS_EINVAL, RBGS_EUNSUPPORTED on the host;
+ *    RBGS_EDEVICE if a launch or the symbol lookup fails). */
+RBGS_API rbgs_status rbgs_qr_noalloc(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m,
+                            int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q,
+                            int64_t ldq, double* R, int64_t ldr, double* S_out);
+
 /* One problem of a batch.  W, Q, R as for rbgs_qr (device); the struct itself
  * is host memory. */
 typedef struct {

@@ -66,6 +66,8 @@ _SIGNATURES = {
     "rbgs_qr": ([_P, _P, _I64, _I64, _I64, _I64, ctypes.POINTER(rbgs_sketch),
                  ctypes.POINTER(rbgs_opts), _P, _I64, _P, _I64, _P, ctypes.POINTER(rbgs_cert)],
                 ctypes.c_int),
+    "rbgs_qr_noalloc": ([_P, _P, _I64, _I64, _I64, _I64, ctypes.POINTER(rbgs_sketch),
+                         ctypes.POINTER(rbgs_opts), _P, _I64, _P, _I64, _P], ctypes.c_int),
     "rbgs_qr_batched": ([_P, _I64, ctypes.POINTER(rbgs_problem), ctypes.POINTER(rbgs_sketch),
                          ctypes.POINTER(rbgs_opts), _I32], ctypes.c_int),
     "rbgs_autotune": ([_P, _I64, _I64, ctypes.POINTER(rbgs_sketch), ctypes.POINTER(rbgs_opts),
@@ -144,6 +146,10 @@ class Library:
         return self.lib.rbgs_qr(h, W, ldw, n, m, p, ctypes.byref(sk), ctypes.byref(opts), Q, ldq,
                                 R, ldr, S_out, ctypes.byref(cert) if cert is not None else None)
 
+    def rbgs_qr_noalloc(self, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out):
+        return self.lib.rbgs_qr_noalloc(h, W, ldw, n, m, p, ctypes.byref(sk), ctypes.byref(opts), Q,
+                                        ldq, R, ldr, S_out)
+
     def rbgs_qr_batched(self, h, count, probs, sk, opts, graph):
         return self.lib.rbgs_qr_batched(h, count, probs, ctypes.byref(sk), ctypes.byref(opts), graph)
 
@@ -207,11 +213,13 @@ def make_sketch(kind, k, seed, zeta=None):
 
 
 def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=None, variant="lowsync", ls_iters=4,
-            Q=None, R=None, want_S=False, want_cert=False, math="f64"):
+            Q=None, R=None, want_S=False, want_cert=False, math="f64", noalloc=False):
     """RBGS QR of a column-major CUDA tensor W (n x m, float32 or float64).
 
     math: arithmetic of the update (step 3): "f64" (default, any storage) or
     "f32" (FP32 storage only).
+    noalloc: call rbgs_qr_noalloc (the library's fixed device scratch array
+    instead of its workspace; no certificate).
 
     Returns (Q, R, S, cert): Q like W (or the given Q, e.g. W itself for an
     in-place factorization), R (m x m float64, column-major), S (k x m float64)
@@ -241,6 +249,13 @@ def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=None, variant="lowsync", l
     sk = make_sketch(kind, k, seed, zeta)
     opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters), _stream_ptr(W))
     cert = rbgs_cert() if want_cert else None
+    if noalloc:
+        if want_cert:
+            raise ValueError("rbgs_qr_noalloc computes no certificate")
+        st = lib.rbgs_qr_noalloc(h, wp, ldw, n, m, p, sk, opts, qp, ldq, rp, ldr,
+                                 S.data_ptr() if S is not None else None)
+        lib.check(st, h)
+        return Q, R, S, None
     st = lib.rbgs_qr(h, wp, ldw, n, m, p, sk, opts, qp, ldq, rp, ldr,
                      S.data_ptr() if S is not None else None, cert)
     if st == RBGS_EBREAKDOWN and cert is not None:

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -143,6 +144,34 @@ rbgs_status ensure_ws(rbgs_handle h, size_t bytes) {
     return fail(h, RBGS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
   }
   h->ws_bytes = want;
+  return RBGS_OK;
+}
+
+// Workspace of the no-allocation entry point: one copy of this array per
+// device, kept until the process ends.  Host code never uses the array's name
+// as an address: the device address of each device's copy is looked up once
+// with hipGetSymbolAddress (with that device current) and kept in
+// g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static_assert(kScratchBytes == (size_t)RBGS_NOALLOC_SCRATCH_BYTES, "scratch size");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of this device's scratch array; the device must be
+// current.
+rbgs_status scratch_for_device(rbgs_handle h, void** out) {
+  if (h->device >= kMaxScratchDevices) return fail(h, RBGS_EUNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[h->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(h, RBGS_EDEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[h->device] = p;
+  }
+  *out = g_scratch_ptr[h->device];
   return RBGS_OK;
 }
 
@@ -359,7 +388,8 @@ struct QrRun {
 // of W is available now (its sketch may be taken ahead of the loop).
 rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m,
                      int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q, int64_t ldq,
-                     double* R, int64_t ldr, double* S_out, bool hoist) {
+                     double* R, int64_t ldr, double* S_out, bool hoist, void* ext_ws = nullptr,
+                     size_t ext_bytes = 0) {
   r.h = h;
   r.d = make_desc(sk, n);
   r.f32 = opts->store == RBGS_STORE_F32;
@@ -422,9 +452,18 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
     if (m % b) tall_need = std::max(tall_need, qr_stack_size(n, (int)(m % b)));
   }
   const size_t o_tall = tall_need ? carve(tall_need) : 0;
-  rbgs_status rs = ensure_ws(h, off);
-  if (rs != RBGS_OK) return rs;
-  char* base = (char*)h->ws;
+  char* base;
+  if (ext_ws) {
+    if (off > ext_bytes)
+      return fail(h, RBGS_ENOMEM, "this factorization needs " + std::to_string(off) +
+                                      " bytes of workspace; the no-allocation entry point has " +
+                                      std::to_string(ext_bytes));
+    base = (char*)ext_ws;
+  } else {
+    rbgs_status rs = ensure_ws(h, off);
+    if (rs != RBGS_OK) return rs;
+    base = (char*)h->ws;
+  }
   r.S = S_out ? S_out : (double*)(base + o_S);
   r.P = (double*)(base + o_P);
   r.E = (double*)(base + o_E);
@@ -652,6 +691,31 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   }
   if (!cert) return RBGS_OK;
   return qr_certify(r, cert);
+}
+
+rbgs_status rbgs_qr_noalloc(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_t m,
+                            int64_t p, const rbgs_sketch* sk, const rbgs_opts* opts, void* Q,
+                            int64_t ldq, double* R, int64_t ldr, double* S_out) {
+  if (!h) return RBGS_EINVAL;
+  h->last_error.clear();
+  {
+    const rbgs_status vs = validate_qr(h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr);
+    if (vs != RBGS_OK) return vs;
+  }
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
+  void* ws = nullptr;
+  rbgs_status rs = scratch_for_device(h, &ws);
+  if (rs != RBGS_OK) return rs;
+  // profiling events are created on demand, so the call records none
+  const uint32_t mask = h->prof_mask;
+  h->prof_mask = 0;
+  QrRun r;
+  rs = qr_begin(r, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, true, ws, kScratchBytes);
+  for (int64_t c0 = 0; rs == RBGS_OK && c0 < m; c0 += p)
+    rs = qr_block(r, c0, r.Wb + r.es * (size_t)(c0 * ldw), ldw, false);
+  h->prof_mask = mask;
+  return rs;
 }
 
 // ---------------------------------------------------------------------------

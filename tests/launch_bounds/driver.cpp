@@ -2,7 +2,9 @@
 // (mock_hip.cpp): one rbgs_qr call per invocation, with the caller's W, Q, R
 // and S allocated through the stand-in, so that every address a kernel is given
 // can be matched to an allocation (test infrastructure).
-//   driver n m p k kind store math variant ls_iters want_S want_cert
+//   driver n m p k kind store math variant ls_iters want_S want_cert [noalloc]
+// noalloc = 1: rbgs_qr_noalloc (the library's scratch array; want_cert ignored),
+// called twice, the second time on the first half of the rows.
 // kind: 0 Gaussian, 1 sparse sign, 3 Rademacher, 4 SRHT; store/math/variant as
 // in include/rbgs.h.
 #include <hip/hip_runtime_api.h>
@@ -40,8 +42,16 @@ int main(int argc, char** argv) {
   o.ls_iters = ls;
   o.stream = nullptr;
   rbgs_cert cert;
-  rbgs_status st = rbgs_qr(h, W, n, n, m, p, &sk, &o, Q, n, (double*)R, m, (double*)S,
-                           want_cert ? &cert : nullptr);
+  const int noalloc = argc > 12 ? atoi(argv[12]) : 0;
+  rbgs_status st;
+  if (noalloc) {
+    st = rbgs_qr_noalloc(h, W, n, n, m, p, &sk, &o, Q, n, (double*)R, m, (double*)S);
+    if (st == RBGS_OK)
+      st = rbgs_qr_noalloc(h, W, n, n / 2, m, p, &sk, &o, Q, n, (double*)R, m, (double*)S);
+  } else {
+    st = rbgs_qr(h, W, n, n, m, p, &sk, &o, Q, n, (double*)R, m, (double*)S,
+                 want_cert ? &cert : nullptr);
+  }
   printf("status %d %s\n", (int)st, rbgs_last_error(h));
   rbgs_destroy(h);
   return st == RBGS_OK ? 0 : 1;

@@ -90,6 +90,20 @@ void __hipRegisterFunction(void**, const void* hostFunction, char* deviceFunctio
   names()[hostFunction] = deviceFunction;
 }
 
+// __device__ variables: their host shadow address -> size; a lookup of the
+// device address is logged as an allocation of that size (once per variable).
+std::map<const void*, size_t>& vars() {
+  static std::map<const void*, size_t> m;
+  return m;
+}
+std::map<const void*, uint64_t>& var_addr() {
+  static std::map<const void*, uint64_t> m;
+  return m;
+}
+void __hipRegisterVar(void**, void* var, char*, char*, int, size_t size, int, int) {
+  vars()[var] = size;
+}
+
 hipError_t __hipPushCallConfiguration(dim3 g, dim3 b, size_t shmem, hipStream_t st) {
   cfg_stack.push_back({g, b, shmem, st});
   return hipSuccess;
@@ -129,6 +143,18 @@ hipError_t hipMalloc(void** p, size_t bytes) {
   live[base] = bytes;
   *p = (void*)base;
   fprintf(log_file(), "alloc %llu %zu\n", (unsigned long long)base, bytes);
+  return hipSuccess;
+}
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  auto it = vars().find(symbol);
+  if (it == vars().end()) return hipErrorInvalidSymbol;
+  auto a = var_addr().find(symbol);
+  if (a == var_addr().end()) {
+    void* q = nullptr;
+    hipMalloc(&q, it->second);
+    a = var_addr().emplace(symbol, (uint64_t)q).first;
+  }
+  *p = (void*)a->second;
   return hipSuccess;
 }
 hipError_t hipFree(void* p) {

@@ -83,6 +83,49 @@ def test_every_launch_stays_in_bounds(driver, case):
     assert not violations, "\n".join(violations[:20])
 
 
+NOALLOC_CASES = [
+    # the no-allocation entry point (two calls, the second on half the rows)
+    (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 4, 1, 0),
+    (10_000, 64, 8, 256, GAUSS, F64, 0, PLAIN, 2, 1, 0),
+    (4097, 30, 8, 128, SPARSE, F64, 0, LOWSYNC, 2, 0, 0),
+    (5000, 96, 32, 256, GAUSS, F32, 0, LOWSYNC, 2, 1, 0),
+]
+
+
+@pytest.mark.parametrize("case", NOALLOC_CASES, ids=lambda c: "noalloc-" + "x".join(str(v) for v in c[:4]))
+def test_noalloc_launches_stay_in_the_scratch_array(driver, case):
+    """Every launch of rbgs_qr_noalloc stays inside the caller's arrays and
+    the library's scratch array (logged as one allocation of its size), and
+    the call allocates nothing else."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / ("noalloc_" + "_".join(str(v) for v in case) + ".txt"))
+    r = subprocess.run([exe, *[str(v) for v in case], "1"],
+                       env={**os.environ, "RBGS_LAUNCH_LOG": log}, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    events = cl.parse_log(log)
+    allocs = [e for e in events if e[0] == "alloc"]
+    # W, Q, R, (S), then the scratch array on the first call, nothing more
+    assert len(allocs) == (5 if case[9] else 4)
+    assert allocs[-1][2] == 64 << 20
+    violations, n, seen = cl.check_events(events)
+    assert n > 0
+    assert not violations, "\n".join(violations[:20])
+
+
+def test_noalloc_rejects_a_workspace_beyond_the_scratch_array(driver):
+    exe, out = driver
+    log = str(out / "noalloc_big.txt")
+    r = subprocess.run([exe, "4000000", "512", "32", "2048", str(SPARSE), str(F32), "0",
+                        str(LOWSYNC), "4", "0", "0", "1"],
+                       env={**os.environ, "RBGS_LAUNCH_LOG": log}, capture_output=True, text=True)
+    assert r.returncode == 1
+    assert "status -2" in r.stdout and "no-allocation entry point has 67108864" in r.stdout
+    assert "launch" not in open(log).read()
+
+
 def test_checker_catches_planted_out_of_bounds(driver):
     """The checker must flag accesses past an allocation: on a recorded
     4e6 x 512 Gaussian factorization, (a) the workspace shortened by one
