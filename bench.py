@@ -274,7 +274,7 @@ def batched_form(count=512, reps=3):
                                                           for k, W in zip(ks, Ws))))
 
 
-def mixed_form(steps, warmup, maths=("f64", "f32")):
+def mixed_form(steps, warmup, maths=("f64", "f32", "bf16x3")):
     """The mixed-precision workload: W is n = 4e6 x m = 512, cond 1e10
     (U diag(logspace(0, -10, 512)) V^T), p = 32, k = 2048, sparse sign,
     low-sync; FP32 storage with each product arithmetic in `maths` against
@@ -290,6 +290,7 @@ def mixed_form(steps, warmup, maths=("f64", "f32")):
     print("[bench] mixed workload: fp64", file=sys.stderr, flush=True)
     f64, _ = time_form(W64, p, "sparse", k, THETA_SEED_MIXED, "lowsync", steps, warmup,
                        chunked_metrics=True, keep_R=True)
+    f64["kernel_ms_per_step"] = kernel_breakdown(W64, p, "sparse", k, THETA_SEED_MIXED, "lowsync")
     del W64
     R64 = f64.pop("_R")
     for mth in maths:
@@ -299,6 +300,8 @@ def mixed_form(steps, warmup, maths=("f64", "f32")):
         R = f.pop("_R")
         f["rel_diff_R_vs_f64"] = float(torch.linalg.matrix_norm(R - R64) / torch.linalg.matrix_norm(R64))
         f["speedup_vs_f64"] = f64["ms"] / f["ms"]
+        f["kernel_ms_per_step"] = kernel_breakdown(W32, p, "sparse", k, THETA_SEED_MIXED, "lowsync",
+                                                   math=mth)
         out[f"mixed_f32_{mth}math"] = f
     out["mixed_f64"] = f64
     return out
@@ -460,6 +463,10 @@ def main():
         forms["f32_f32math_sparse_lowsync"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE,
                                                            "lowsync", args.steps, args.warmup,
                                                            math="f32")
+        print("[bench] fp32 storage with bf16x3 products", file=sys.stderr, flush=True)
+        forms["f32_bf16x3math_sparse_lowsync"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE,
+                                                              "lowsync", args.steps, args.warmup,
+                                                              math="bf16x3")
         print("[bench] fp32/fp64 sparse plain", file=sys.stderr, flush=True)
         forms["f32_sparse_plain"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "plain",
                                                  max(3, args.steps // 4), 1)

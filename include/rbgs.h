@@ -64,9 +64,17 @@ typedef enum { RBGS_STORE_F64 = 0, RBGS_STORE_F32 = 1 } rbgs_store;
  *       FP32 storage only.  Its rounding errors, of size u32 ||W||, exceed Q'_(i)
  *       itself once W is numerically rank deficient at FP32 level, and then the
  *       sketched orthogonality is lost (the certificate Delta exposes it).
+ *  BF16X3 split products on the bf16 matrix cores with FP32 accumulation; FP32
+ *       storage only.  Each FP32 element a of Q is split as a_hi = bf16(a),
+ *       a_lo = bf16(a - a_hi) and each element b of R_(1:i-1,i) as
+ *       b_hi = bf16(fl32(b)), b_lo = bf16(fl32(b - b_hi)) (round to nearest
+ *       even), and a b is taken as a_hi b_hi + a_hi b_lo + a_lo b_hi.  Each
+ *       product carries a relative error of about 3 2^-16 (the dropped
+ *       a_lo b_lo and the parts beyond two pieces), so the update is less
+ *       accurate than with F32 and loses the sketched orthogonality sooner.
  * The sketches, the least-squares problem, the QR of the sketch and the
  * substitution always run in FP64 (the "fine" unit roundoff of Section 2). */
-typedef enum { RBGS_MATH_F64 = 0, RBGS_MATH_F32 = 1 } rbgs_math;
+typedef enum { RBGS_MATH_F64 = 0, RBGS_MATH_F32 = 1, RBGS_MATH_BF16X3 = 2 } rbgs_math;
 
 /* Sketching operator Theta (Section 1.3).  Entries are defined from
  * Philox-4x32-10 (key = seed; column r of Theta = row r of W):

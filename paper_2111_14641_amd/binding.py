@@ -17,7 +17,7 @@ RBGS_OK, RBGS_EINVAL, RBGS_ENOMEM, RBGS_EDEVICE, RBGS_EBREAKDOWN, RBGS_ENOTCONV,
     0, -1, -2, -3, -4, -5, -6)
 # rbgs_store / rbgs_math / rbgs_sketch_kind / rbgs_variant
 STORE = {"f64": 0, "f32": 1}
-MATH = {"f64": 0, "f32": 1}
+MATH = {"f64": 0, "f32": 1, "bf16x3": 2}
 SKETCH = {"gaussian": 0, "sparse": 1, "identity": 2, "rademacher": 3, "srht": 4}
 VARIANT = {"plain": 0, "lowsync": 1, "twice": 2, "l2qr": 3}
 PROFILE = {"update": 0, "sketch": 1, "reduce": 2, "small": 3, "trsm": 4}

@@ -278,7 +278,7 @@ static rbgs_status validate_qr(rbgs_handle h, const void* W, int64_t ldw, int64_
   if (sk->k > n) return fail(h, RBGS_EINVAL, "sketch dimension k must be <= n");
   if (opts->store != RBGS_STORE_F64 && opts->store != RBGS_STORE_F32)
     return fail(h, RBGS_EINVAL, "unknown storage type");
-  if (opts->math != RBGS_MATH_F64 && opts->math != RBGS_MATH_F32)
+  if (opts->math != RBGS_MATH_F64 && opts->math != RBGS_MATH_F32 && opts->math != RBGS_MATH_BF16X3)
     return fail(h, RBGS_EINVAL, "unknown arithmetic");
   if (opts->store == RBGS_STORE_F64 && opts->math != RBGS_MATH_F64)
     return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
@@ -365,7 +365,8 @@ namespace {
 struct QrRun {
   rbgs_handle h;
   SketchDesc d;
-  bool f32, f32_math;
+  bool f32;
+  int math;  // kMathF64 / kMathF32 / kMathBf16x3
   size_t es;
   hipStream_t st;
   int64_t n, m, k;
@@ -393,7 +394,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.h = h;
   r.d = make_desc(sk, n);
   r.f32 = opts->store == RBGS_STORE_F32;
-  r.f32_math = opts->math == RBGS_MATH_F32;
+  r.math = opts->math;
   r.es = r.f32 ? 4 : 8;
   r.st = (hipStream_t)opts->stream;
   r.n = n;
@@ -557,7 +558,7 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     // ---- step 3 + substitution in one pass --------------------------
     {
       ProfScope ps(h, kProfUpdate, ub, st);
-      HIP_TRY(h, launch_update(r.f32, r.f32_math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, Rii, ldr, n,
+      HIP_TRY(h, launch_update(r.f32, r.math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, Rii, ldr, n,
                                K, bw, st),
               "update");
     }
@@ -565,7 +566,7 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     // ---- step 3: Q'_(i), stored in Q_(i) ------------------------------
     {
       ProfScope ps(h, kProfUpdate, ub, st);
-      HIP_TRY(h, launch_update(r.f32, r.f32_math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, nullptr, ldr,
+      HIP_TRY(h, launch_update(r.f32, r.math, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, nullptr, ldr,
                                n, K, bw, st),
               "update");
     }
@@ -925,7 +926,7 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
 rbgs_status enqueue_group(rbgs_handle h, const LockGroup& g, const rbgs_sketch* sk,
                           const rbgs_opts* opts, hipStream_t st) {
   const bool f32 = opts->store == RBGS_STORE_F32;
-  const bool f32_math = opts->math == RBGS_MATH_F32;
+  const int math = opts->math;
   const int np = (int)g.idx.size();
   const int64_t m = g.m, p = g.p, k = g.k;
   const int l = opts->ls_iters;
@@ -950,7 +951,7 @@ rbgs_status enqueue_group(rbgs_handle h, const LockGroup& g, const rbgs_sketch* 
       HIP_TRY(h, launch_resid_batched(g.items, np, k, K, bw, st), "batch S'");
     }
     HIP_TRY(h, launch_qr_batched(g.items, np, k, bw, c0, st), "batch qr of sketch");
-    HIP_TRY(h, launch_update_batched(f32, f32_math, g.items, np, g.up_tiles, K, bw, st),
+    HIP_TRY(h, launch_update_batched(f32, math, g.items, np, g.up_tiles, K, bw, st),
             "batch update");
     HIP_TRY(h, launch_sketch_batched(f32, g.items, np, g.sk_wgs, 1, c0, bw, (int)k, zeta, scale, st),
             "batch sketch of Q");
@@ -1494,7 +1495,7 @@ rbgs_status rbgs_cholqr_post(rbgs_handle h, int32_t store, void* Q, int64_t ldq,
   for (int64_t b0 = 0; b0 < m; b0 += 16) {
     const int bw = (int)std::min<int64_t>(16, m - b0);
     char* Qb = (char*)Q + es * (size_t)(b0 * ldq);
-    HIP_TRY(h, launch_update(f32, false, Qb, ldq, Q, ldq, Qb, ldq, G + b0 * m, G + b0 + b0 * m, m, n,
+    HIP_TRY(h, launch_update(f32, kMathF64, Qb, ldq, Q, ldq, Qb, ldq, G + b0 * m, G + b0 + b0 * m, m, n,
                              b0, bw, st),
             "substitution");
   }

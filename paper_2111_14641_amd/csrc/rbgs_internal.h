@@ -263,7 +263,7 @@ hipError_t launch_resid_batched(const BatchItem* items, int nprob, int64_t k, in
                                 hipStream_t st);
 hipError_t launch_qr_batched(const BatchItem* items, int nprob, int64_t k, int bw, int64_t c0,
                              hipStream_t st);
-hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items, int nprob,
+hipError_t launch_update_batched(bool f32, int math, const BatchItem* items, int nprob,
                                  int64_t total_tiles, int64_t K, int bw, hipStream_t st);
 hipError_t launch_init_batched(const BatchItem* items, int nprob, int64_t m, hipStream_t st);
 // rows per update tile (for the flattened prefix) and the unguarded tile count
@@ -313,9 +313,11 @@ hipError_t launch_theta_dense(const SketchDesc& sk, int64_t n, int64_t row0, flo
 // Q'_(i) = W_(i) - Q_(1:i-1) R_(1:i-1,i)  [then Q_(i) = Q'_(i) R_(i,i)^{-1} if Rii != nullptr]
 //   Rk: R_(1:i-1,i) in the R array (column-major, ld ldr), K rows, bw columns.
 //   Rii: R_(i,i) in the R array (ld ldr), bw x bw, or nullptr.
-//   f32: storage of W/Q is FP32 (else FP64); f32_math: FP32 matrix-core arithmetic
-//   (only with FP32 storage), else FP64 matrix-core arithmetic.
-hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, const void* Q,
+//   f32: storage of W/Q is FP32 (else FP64); math: kMathF64 (FP64 matrix-core
+//   arithmetic), kMathF32 (FP32 matrix cores) or kMathBf16x3 (split BF16x3
+//   products on the bf16 matrix cores); the last two with FP32 storage only.
+constexpr int kMathF64 = 0, kMathF32 = 1, kMathBf16x3 = 2;
+hipError_t launch_update(bool f32, int math, const void* W, int64_t ldw, const void* Q,
                          int64_t ldq, void* Qout, int64_t ldqo, const double* Rk,
                          const double* Rii, int64_t ldr, int64_t n, int64_t K, int bw,
                          hipStream_t st);

@@ -10,7 +10,8 @@
 //
 // General form.  The product runs on matrix cores, in FP64
 // (v_mfma_f64_16x16x4f64; FP32 data are converted exactly) or, on request for
-// FP32 storage, in FP32 (v_mfma_f32_16x16x4f32 with FP32 accumulation).  Each
+// FP32 storage, in FP32 (v_mfma_f32_16x16x4f32 with FP32 accumulation) or as
+// split BF16x3 products (v_mfma_f32_16x16x32_bf16, FP32 accumulation; below).  Each
 // lane loads VEC consecutive rows of one column of Q with one 16-byte load;
 // element v of that vector feeds the A operand of accumulator v, so
 // accumulator v covers rows VEC*i + v of the wave's row strip and one load
@@ -85,6 +86,16 @@ struct Vec16<double> {
   typedef f64x2 t;
 };
 
+// Compute-type tag of the split BF16x3 product: every FP32 element a of Q is
+// split as a_hi = bf16(a), a_lo = bf16(a - a_hi) (round to nearest even; a -
+// a_hi is exact in FP32), every FP64 element b of R_(1:i-1,i) as
+// b_hi = bf16(fl32(b)), b_lo = bf16(fl32(b - b_hi)), and a b is taken as
+// a_hi b_hi + a_hi b_lo + a_lo b_hi (the term a_lo b_lo and the parts of a and b
+// beyond the two pieces, each at most about 2^-16 |a b|, are dropped), on the
+// bf16 matrix cores with FP32 accumulation.
+struct Bf16x3 {};
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 // Forward substitution of one row: x R = q', R upper triangular (bw x bw,
 // bw <= NC) in LDS (column-major, ld NC).  FP64 arithmetic.
 template <int NC>
@@ -110,29 +121,129 @@ __device__ __forceinline__ void row_substitute(double* x, const double* Rs, int 
 // TAIL = true: guarded element loads, for the last partial tile or unaligned Q.
 template <typename T, typename C, int NB>
 struct UpdateShape {
+  static constexpr bool BF3 = std::is_same<C, Bf16x3>::value;
+  typedef typename std::conditional<BF3, float, C>::type CE;  // element type of the product
   static constexpr int VEC = Vec16<T>::N;
   static constexpr int WROWS = 16 * VEC;  // rows per wave
   static constexpr int TILE = 4 * WROWS;  // rows per workgroup
   static constexpr int NCOL = 16 * NB;
   static constexpr int SLAB = RBGS_UP_SLAB;
   static constexpr int CT_LD = SLAB + 1;  // one slab of the product per pass
-  static constexpr int RS_BYTES = kKC * NCOL * sizeof(C);
-  static constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(C);
+  // R chunk: kKC x NCOL as CE, or (BF16x3) hi and lo pieces as bf16
+  static constexpr int RS_BYTES = BF3 ? 2 * kKC * NCOL * 2 : kKC * NCOL * (int)sizeof(CE);
+  static constexpr int CT_BYTES = 4 * WROWS * CT_LD * sizeof(CE);
   static constexpr int U_BYTES = RS_BYTES > CT_BYTES ? RS_BYTES : CT_BYTES;
 };
+
+// BF16x3 product of one wave's row strip: acc[v][nb] += Q_(1:i-1) R_(1:i-1,i)
+// for rows arow + v.  A K-step group is 8 loads of 4 columns (32 columns); for
+// row element v the lane holds the 8 columns ks + kk + 4 j, j = 0..7, which
+// are the 8 consecutive K-slots 8 kk + j of the A operand of
+// v_mfma_f32_16x16x32_bf16 (row li).  The R chunk is staged in LDS in the same
+// slot order, hi and lo pieces apart: Rb[hl][s][nb][g][n][j] =
+// piece hl of R[kc0 + 32 s + g + 4 j][16 nb + n], so lane (g, n) reads its
+// 8-slot B operand as one 16-byte vector.  The output layout is that of the
+// FP32 16x16 instructions (row 4 (l / 16) + e, column l % 16).
+template <int NB, bool TAIL>
+__device__ __forceinline__ void product_bf16x3(float4_t (&acc)[4][NB], const float* __restrict__ Q,
+                                               int64_t ldq, const double* __restrict__ Rk,
+                                               int64_t ldr, int64_t arow, int64_t n, int K, int bw,
+                                               unsigned char* ubuf_raw) {
+  constexpr int VEC = 4;
+  constexpr int NCOL = 16 * NB;
+  constexpr int PIECE = kKC * NCOL;  // bf16 entries of one piece of a chunk
+  __bf16* Rb = reinterpret_cast<__bf16*>(ubuf_raw);
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4, li = lane & 15;
+  auto load8 = [&](float (&a)[8][VEC], int kc0, int ks0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      int col = kc0 + ks0 + 4 * j + kk;
+      col = col < K ? col : K - 1;  // padded slots meet zero rows of R
+      const float* src = Q + arow + (int64_t)col * ldq;
+      if (!TAIL) {
+        const f32x4 vv = *reinterpret_cast<const f32x4*>(src);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[j][v] = vv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const float x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
+          a[j][v] = in ? x : 0.f;
+        }
+      }
+    }
+  };
+  auto mma8 = [&](const float (&a)[8][VEC], int s) {
+    bf16x8 bh[NB], bl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int o = (((s * NB + nb) * 4 + kk) * 16 + li) * 8;
+      bh[nb] = *reinterpret_cast<const bf16x8*>(Rb + o);
+      bl[nb] = *reinterpret_cast<const bf16x8*>(Rb + PIECE + o);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      bf16x8 ah, al;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const __bf16 h = (__bf16)a[j][v];
+        ah[j] = h;
+        al[j] = (__bf16)(a[j][v] - (float)h);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[nb], acc[v][nb], 0, 0, 0);
+        acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[nb], acc[v][nb], 0, 0, 0);
+        acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[nb], acc[v][nb], 0, 0, 0);
+      }
+    }
+  };
+  for (int kc0 = 0; kc0 < K; kc0 += kKC) {
+    const int kc = min(kKC, K - kc0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < PIECE; e += kUpThreads) {
+      // e = (((s NB + nb) 4 + g) 16 + nn) 8 + j
+      const int j = e & 7, nn = (e >> 3) & 15, g = (e >> 7) & 3, snb = e >> 9;
+      const int nb = snb % NB, st = snb / NB;
+      const int r = 32 * st + g + 4 * j, c = 16 * nb + nn;
+      const bool in = r < kc && c < bw;
+      const double b = Rk[(kc0 + (in ? r : 0)) + (int64_t)(in ? c : 0) * ldr];
+      const double bv = in ? b : 0.0;
+      const __bf16 h = (__bf16)(float)bv;
+      Rb[e] = h;
+      Rb[PIECE + e] = (__bf16)(float)(bv - (double)(float)h);
+    }
+    __syncthreads();
+    // ping-pong over 32-column steps: the loads of step s+1 are in flight
+    // during the products of step s
+    float a0[8][VEC], a1[8][VEC];
+    load8(a0, kc0, 0);
+    for (int ks0 = 0; ks0 < kc; ks0 += 64) {
+      if (ks0 + 32 < kc) load8(a1, kc0, ks0 + 32);
+      mma8(a0, ks0 >> 5);
+      if (ks0 + 32 < kc) {
+        if (ks0 + 64 < kc) load8(a0, kc0, ks0 + 64);
+        mma8(a1, (ks0 >> 5) + 1);
+      }
+    }
+  }
+}
 
 template <typename T, typename C, int NB, bool TAIL>
 __device__ __forceinline__ void update_tile(
     const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
     const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t tile_row0,
     int64_t n, int K, int bw, unsigned char* ubuf_raw, double* Rd) {
-  typedef Mfma<C> M;
   typedef UpdateShape<T, C, NB> Sh;
+  typedef typename Sh::CE CE;
+  typedef Mfma<CE> M;
   constexpr int VEC = Sh::VEC;
   constexpr int WROWS = Sh::WROWS;
   constexpr int NCOL = Sh::NCOL;
   constexpr int CT_LD = Sh::CT_LD;
-  C* ubuf = reinterpret_cast<C*>(ubuf_raw);
+  CE* ubuf = reinterpret_cast<CE*>(ubuf_raw);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t wrow0 = tile_row0 + (int64_t)wave * WROWS;
@@ -164,6 +275,10 @@ __device__ __forceinline__ void update_tile(
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[v][nb] = (typename M::acc_t){0, 0, 0, 0};
 
+  if constexpr (Sh::BF3) {
+    static_assert(std::is_same<T, float>::value, "BF16x3 products need FP32 storage");
+    product_bf16x3<NB, TAIL>(acc, Q, ldq, Rk, ldr, arow, n, K, bw, ubuf_raw);
+  } else {
   constexpr int kUnroll = UpUnroll<T>::N;
   // A operand group: kUnroll K-steps of 4 columns, one 16-byte load per step.
   auto load_group = [&](T (&a)[kUnroll][VEC], int kc0, int ks0) {
@@ -192,9 +307,9 @@ __device__ __forceinline__ void update_tile(
       if (ks0 + 4 * u < kc) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          const C b = ubuf[(ks0 + 4 * u + kk) * NCOL + nb * 16 + li];
+          const CE b = ubuf[(ks0 + 4 * u + kk) * NCOL + nb * 16 + li];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma((C)a[u][v], b, acc[v][nb]);
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma((CE)a[u][v], b, acc[v][nb]);
         }
       }
     }
@@ -207,7 +322,7 @@ __device__ __forceinline__ void update_tile(
       const int r = e / NCOL, c = e % NCOL;
       const bool in = r < kc && c < bw;
       const double v = Rk[(kc0 + (in ? r : 0)) + (int64_t)(in ? c : 0) * ldr];
-      ubuf[e] = in ? (C)v : (C)0;
+      ubuf[e] = in ? (CE)v : (CE)0;
     }
     __syncthreads();
     constexpr int GS = 4 * kUnroll;
@@ -223,10 +338,11 @@ __device__ __forceinline__ void update_tile(
       }
     }
   }
+  }
   // Epilogue: lane owns row wrow0 + lane (lanes >= WROWS idle); the product is
   // moved through LDS one slab of SLAB columns at a time.
   constexpr int SLAB = Sh::SLAB;
-  C* ct = ubuf + wave * WROWS * CT_LD;
+  CE* ct = ubuf + wave * WROWS * CT_LD;
   double x[NCOL];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -250,7 +366,7 @@ __device__ __forceinline__ void update_tile(
       for (int c = 0; c < SLAB; ++c) {
         // step 3: Q' = W - Q R in the arithmetic C, from storage T
         const int cc = nb * 16 + h * SLAB + c;
-        const C qp = (C)wrow[cc] - ct[lr * CT_LD + c];
+        const CE qp = (CE)wrow[cc] - ct[lr * CT_LD + c];
         x[cc] = (double)qp;
       }
     }
@@ -691,11 +807,13 @@ static hipError_t launch_update_t(const void* W, int64_t ldw, const void* Q, int
   return launch_update_nb<T, C, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
 }
 
-hipError_t launch_update(bool f32, bool f32_math, const void* W, int64_t ldw, const void* Q,
+hipError_t launch_update(bool f32, int math, const void* W, int64_t ldw, const void* Q,
                          int64_t ldq, void* Qout, int64_t ldqo, const double* Rk,
                          const double* Rii, int64_t ldr, int64_t n, int64_t K, int bw,
                          hipStream_t st) {
-  if (f32 && f32_math)
+  if (f32 && math == kMathBf16x3)
+    return launch_update_t<float, Bf16x3>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+  if (f32 && math == kMathF32)
     return launch_update_t<float, float>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   if (f32)
     return launch_update_t<float, double>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
@@ -711,7 +829,7 @@ bool update_vec_ok(bool f32, const void* Q, int64_t ldq) {
   return ((ldq % VEC) == 0) && ((reinterpret_cast<uintptr_t>(Q) % 16) == 0);
 }
 
-hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items, int nprob,
+hipError_t launch_update_batched(bool f32, int math, const BatchItem* items, int nprob,
                                  int64_t total_tiles, int64_t K, int bw, hipStream_t st) {
   if (bw > kMaxB) return hipErrorInvalidValue;
   dim3 grid((unsigned)total_tiles);
@@ -719,11 +837,13 @@ hipError_t launch_update_batched(bool f32, bool f32_math, const BatchItem* items
   hipLaunchKernelGGL((update_batched_kernel<T, C, NB>), grid, dim3(kUpThreads), 0, st, items, \
                      nprob, (int)K, bw)
   if (bw <= 16) {
-    if (f32 && f32_math) RBGS_UPB(float, float, 1);
+    if (f32 && math == kMathBf16x3) RBGS_UPB(float, Bf16x3, 1);
+    else if (f32 && math == kMathF32) RBGS_UPB(float, float, 1);
     else if (f32) RBGS_UPB(float, double, 1);
     else RBGS_UPB(double, double, 1);
   } else {
-    if (f32 && f32_math) RBGS_UPB(float, float, 2);
+    if (f32 && math == kMathBf16x3) RBGS_UPB(float, Bf16x3, 2);
+    else if (f32 && math == kMathF32) RBGS_UPB(float, float, 2);
     else if (f32) RBGS_UPB(float, double, 2);
     else RBGS_UPB(double, double, 2);
   }

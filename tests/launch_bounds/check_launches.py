@@ -318,6 +318,16 @@ def _template_args(name):
         if c in "fd":
             out.append(c)
             p += 1
+        elif c == "N":                 # a nested class name, e.g. NS_6Bf16x3E
+            q = body.find("E", p)
+            k = p + 1
+            while k < q and not body[k].isdigit():
+                k += 1
+            m = k
+            while m < q and body[m].isdigit():
+                m += 1
+            out.append(body[m:m + int(body[k:m])] if m > k else body[p + 1:q])
+            p = q + 1
         elif c == "b":                 # bool in a literal: Lb0E / Lb1E handled below
             p += 1
         elif c == "L":

@@ -66,6 +66,7 @@ def _qr(lib, h, n=100, m=8, p=4, k=32, kind=0, zeta=8, store=0, math=0, variant=
     (dict(kind=7), B.RBGS_EINVAL),
     (dict(store=0, math=1), B.RBGS_EINVAL),       # FP64 storage needs FP64 arithmetic
     (dict(math=5), B.RBGS_EINVAL),
+    (dict(store=0, math=2), B.RBGS_EINVAL),       # BF16x3 products need FP32 storage
     (dict(store=2), B.RBGS_EINVAL),
     (dict(variant=4), B.RBGS_EINVAL),
     (dict(iters=0), B.RBGS_EINVAL),

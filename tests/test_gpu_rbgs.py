@@ -203,6 +203,57 @@ def test_fp32_arithmetic(gpu_lib, variant):
                           W8.shape[0])
 
 
+EPS_BF3 = 3 * 2.0**-16
+
+
+@pytest.mark.parametrize("variant", ["lowsync", "plain"])
+@pytest.mark.parametrize("m,b,k", [(64, 8, 256), (70, 16, 256), (96, 32, 384)])
+def test_bf16x3_arithmetic(gpu_lib, variant, m, b, k):
+    """Split BF16x3 products with FP32 accumulation on a well-conditioned W
+    (cond 1e2), against the oracle run on the same FP32-rounded input.
+    Tolerances: each split product a_hi b_hi + a_hi b_lo + a_lo b_hi differs
+    from a b by at most about EPS_BF3 = 3 2^-16 |a b| (the dropped a_lo b_lo and
+    the parts of a and b beyond two bf16 pieces), more than the FP32
+    accumulation (at most (K/32 + 3) u32) and the FP32 storage of Q (u32), so
+    * ||W - QR||_F <= EPS_BF3 || |Q| |R| ||_F (the update error of every block
+      is the factorization error of that block);
+    * entry-wise, the update error EPS_BF3 |Q| |R| reaches Q through R^{-1} and
+      later blocks through the least-squares step, so |x - x_or| <= EPS_BF3
+      cond(W) scale as for FP32 storage (tests/parity_checks.py);
+    * the first diagonal block involves no update: R_(1,1) to 4096 u;
+    * the certificates equal the oracle's routine on the GPU's S and R.
+    (A product missing one of its cross terms errs by about 2^-9 |a b| and
+    breaks the first bound by a factor of 7 or more.)"""
+    W = svd_matrix(10_000, m, np.logspace(0, -2, m), seed=41).astype(np.float32).astype(np.float64)
+    say("bf16x3 math", variant, m, b, k)
+    Q, R, S, cert = gpu_qr(W, b, "gaussian", k, THETA_SEED_SMALL, variant, store="f32", math="bf16x3")
+    o = oracle_qr(W, b, "gaussian", k, THETA_SEED_SMALL, variant)
+    err = factorization_error(W, Q, R)
+    bound = EPS_BF3 * np.linalg.norm(np.abs(Q) @ np.abs(R)) / np.linalg.norm(W)
+    say("bf16x3 factorization error", err, "bound", bound)
+    assert err <= bound
+    check_entrywise(W, Q, R, S, cert, o, EPS_BF3 * 1e2)
+    pc.assert_entrywise(R[:b, :b], o["R"][:b, :b], pc.scale_R(o["R"][:b, :b]), TOL64, "R_(1,1)")
+    assert cond2(Q) <= 10 and cert["delta"] < 1e-2
+
+
+def test_bf16x3_certificate_on_rank_deficient_input(gpu_lib):
+    """cond(W) = 1e8, numerically rank deficient at the precision of the split
+    products: the factorization error stays at the products' level, the
+    sketched orthogonality is lost, and the certificate Delta reports it (equal
+    to the oracle's certificate routine on the GPU's S and R)."""
+    W8 = svd_matrix(10_000, 64, np.logspace(0, -8, 64), seed=31).astype(np.float32).astype(np.float64)
+    Q, R, S, cert = gpu_qr(W8, 8, "sparse", 256, THETA_SEED_SMALL, "lowsync", store="f32",
+                           math="bf16x3")
+    err = factorization_error(W8, Q, R)
+    say("bf16x3 rank deficient", err, cert["delta"], cond2(Q))
+    assert err <= EPS_BF3 * np.linalg.norm(np.abs(Q) @ np.abs(R)) / np.linalg.norm(W8)
+    assert cert["delta"] > 0.1 and cond2(Q) > 10
+    th8 = Sketch("sparse", 256, seed=THETA_SEED_SMALL).materialize(W8.shape[0])
+    pc.check_certificates(cert, S, R, th8(W8), pc.abs_theta_w_fro(pc.abs_theta(th8, W8.shape[0]), W8),
+                          W8.shape[0])
+
+
 @pytest.mark.parametrize("variant", ["twice", "l2qr"])
 @pytest.mark.parametrize("kind,k", [("gaussian", 256), ("sparse", 256)])
 def test_two_pass_forms_fp64_elementwise(gpu_lib, variant, kind, k):

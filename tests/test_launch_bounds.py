@@ -31,6 +31,10 @@ CASES = [
     (4_000_000, 512, 32, 2048, SPARSE, F64, 0, LOWSYNC, 4, 0, 1),
     (4_000_000, 512, 32, 2048, SPARSE, F64, 0, LOWSYNC, 4, 1, 1),
     (4_000_000, 512, 32, 2048, SPARSE, F32, 1, LOWSYNC, 4, 0, 1),
+    (4_000_000, 512, 32, 2048, SPARSE, F32, 2, LOWSYNC, 4, 0, 1),
+    (1_000_000, 256, 16, 1024, SPARSE, F32, 2, LOWSYNC, 4, 1, 1),
+    (10_000, 64, 8, 256, GAUSS, F32, 2, PLAIN, 2, 1, 1),
+    (4097, 70, 32, 256, SPARSE, F32, 2, LOWSYNC, 2, 1, 1),
     (4_000_000, 512, 32, 2048, GAUSS, F64, 0, LOWSYNC, 4, 1, 1),
     (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 4, 1, 1),
     (1_000_000, 256, 16, 1024, SPARSE, F64, 0, LOWSYNC, 4, 1, 1),
