@@ -142,7 +142,14 @@ typedef struct {
   int32_t math;      /* rbgs_math                                         */
   int32_t variant;   /* rbgs_variant                                      */
   int32_t ls_iters;  /* Richardson sweeps l >= 1 for the least-squares step
-                        (supplement, Section SM.1); error <= Delta^l |y|    */
+                        (supplement, Section SM.1); error <= Delta^l |y|.
+                        0 would select the direct Householder solver of
+                        Section 2.1: it is not implemented on the GPU and
+                        returns RBGS_EUNSUPPORTED (the sketch is nearly
+                        orthonormal, so 4 sweeps reach the Householder result
+                        on the numerically rank-deficient workloads; the
+                        direct solver stays in the FP64 oracle).  Outside
+                        [0, 16]: RBGS_EINVAL.                              */
   void* stream;      /* hipStream_t or NULL                               */
 } rbgs_opts;
 

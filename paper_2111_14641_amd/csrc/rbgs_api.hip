@@ -284,7 +284,11 @@ static rbgs_status validate_qr(rbgs_handle h, const void* W, int64_t ldw, int64_
     return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
   if (opts->variant < RBGS_VARIANT_PLAIN || opts->variant > RBGS_VARIANT_L2QR)
     return fail(h, RBGS_EINVAL, "unknown variant");
-  if (opts->ls_iters < 1 || opts->ls_iters > 16)
+  if (opts->ls_iters == 0)
+    return fail(h, RBGS_EUNSUPPORTED,
+                "ls_iters = 0 (Householder least squares) is not implemented on the GPU; "
+                "use ls_iters >= 1 Richardson sweeps");
+  if (opts->ls_iters < 0 || opts->ls_iters > 16)
     return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
   if (p > 32) return fail(h, RBGS_EUNSUPPORTED, "block width p > 32 is not implemented");
   const size_t es = opts->store == RBGS_STORE_F32 ? 4 : 8;

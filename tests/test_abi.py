@@ -69,7 +69,9 @@ def _qr(lib, h, n=100, m=8, p=4, k=32, kind=0, zeta=8, store=0, math=0, variant=
     (dict(store=0, math=2), B.RBGS_EINVAL),       # BF16x3 products need FP32 storage
     (dict(store=2), B.RBGS_EINVAL),
     (dict(variant=4), B.RBGS_EINVAL),
-    (dict(iters=0), B.RBGS_EINVAL),
+    (dict(iters=0), B.RBGS_EUNSUPPORTED),         # Householder least squares: not on the GPU
+    (dict(iters=-1), B.RBGS_EINVAL),
+    (dict(iters=17), B.RBGS_EINVAL),
     (dict(ldw=50), B.RBGS_EINVAL),
     (dict(ldr=4), B.RBGS_EINVAL),
     (dict(Q=0x1000 + 8 * 50), B.RBGS_EINVAL),     # Q partially overlaps W
