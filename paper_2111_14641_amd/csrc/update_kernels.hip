@@ -424,33 +424,90 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form for FP64 arithmetic, bw <= 16 and K <= kUpPMaxK: each
-// workgroup stages R_(1:i-1,i) in LDS once and walks tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ... without further barriers.  The product is formed
-// transposed, (Q R)^T = R^T Q^T (the R entry is the A operand, the Q element
-// the B operand), so lane (kk, li) ends with rows VEC li + v of the wave's
-// strip and columns kk + 4 e: each row is spread over the four lanes
+// Persistent form for FP64 arithmetic, bw <= 16 NB and K <= UpPShape::MAXK
+// (NB = 1: one 16-column group, four 256-thread workgroups per CU; NB = 2: two
+// groups for blocks of 17..32 columns, one 512-thread workgroup per CU, whose
+// R_(1:i-1,i) fills most of the CU's LDS): each workgroup stages
+// R_(1:i-1,i) in LDS once and walks tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... without further barriers.  The product is formed transposed,
+// (Q R)^T = R^T Q^T (the R entry is the A operand, the Q element the B
+// operand), so lane (kk, li) ends with rows VEC li + v of the wave's strip and
+// columns 16 nb + kk + 4 e: each row is spread over the four lanes
 // (0..3, li).  The forward substitution of steps 4-5 runs on those registers
 // column by column, the solved entry handed across the four lanes by a lane
 // shuffle, so W, the result and the stores stay in registers: no LDS round
 // trip, no epilogue barrier.
 // ---------------------------------------------------------------------------
-constexpr int kUpPMaxK = 512;   // rows of R_(1:i-1,i) held in LDS (64 KB)
+constexpr int kUpPMaxK = 512;   // NB = 1: rows of R_(1:i-1,i) held in LDS (64 KB)
+constexpr int kUpP2MaxK = 480;  // NB = 2: 480 x 32 FP64 (120 KB)
 #ifndef RBGS_UP_PUNROLL32
 #define RBGS_UP_PUNROLL32 2
 #endif
 #ifndef RBGS_UP_PUNROLL64
 #define RBGS_UP_PUNROLL64 2
 #endif
-// K-steps of loads issued together (measured)
-template <typename T>
+#ifndef RBGS_UP_P2UNROLL
+#define RBGS_UP_P2UNROLL 4      // NB = 2: K-steps of loads issued together
+#endif
+// K-steps of loads issued together (measured for NB = 1)
+template <typename T, int NB = 1>
 struct UpPUnroll {
-  static constexpr int N = sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64;
+  static constexpr int N =
+      NB == 2 ? RBGS_UP_P2UNROLL : (sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64);
 };
+template <typename T, int NB>
+struct UpPShape {
+  static constexpr int VEC = Vec16<T>::N;
+  static constexpr int WAVES = NB == 1 ? 4 : 8;            // waves per workgroup
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int TILE = WAVES * 16 * VEC;           // rows per tile
+  static constexpr int NCOL = 16 * NB;
+  static constexpr int MAXK = NB == 1 ? kUpPMaxK : kUpP2MaxK;
+  static constexpr int MINW = NB == 1 ? 4 : 2;            // waves per SIMD asked of the compiler
+};
+
+// Forward substitution of steps 4-5 on the transposed-layout registers
+// acc[v][nb][e] (row VEC li + v, column 16 nb + kk + 4 e), FP64:
+// x_c = q'_c / R_cc (as q'_c (1 / R_cc)), then q'_c' -= x_c R_cc' for c' > c.
+// Column c of this lane's rows sits in lane (c % 4, li), group c / 16,
+// element (c % 16) / 4; it is handed to the lanes holding the other columns of
+// the same rows by a lane shuffle.  Ru holds the strictly upper part of
+// R_(i,i) (column-major, ld 16 NB; zero elsewhere and past bw), so the update
+// needs no mask.
+template <int VEC, int NB>
+__device__ __forceinline__ void p_substitute(double4_t (&acc)[VEC][NB], const double* Ru,
+                                             const double* Rinv, int bw, int kk, int li) {
+  constexpr int NCOL = 16 * NB;
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    if (c < bw) {
+      const int nbc = c >> 4, kc = c & 3, ec = (c & 15) >> 2;
+      const double rinv = Rinv[c];
+      double xb[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][nbc][ec] * rinv, 16 * kc + li, 64);
+      if (kk == kc) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v][nbc][ec] = xb[v];
+      }
+      // columns below c in every lane (earlier groups, e < ec) need nothing
+#pragma unroll
+      for (int nb = nbc; nb < NB; ++nb) {
+        double ru[4];
+#pragma unroll
+        for (int e = (nb == nbc ? ec : 0); e < 4; ++e) ru[e] = Ru[c + NCOL * (16 * nb + kk + 4 * e)];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+#pragma unroll
+          for (int e = (nb == nbc ? ec : 0); e < 4; ++e) acc[v][nb][e] = fma(-xb[v], ru[e], acc[v][nb][e]);
+      }
+    }
+  }
+}
 
 // One tile with guarded element loads and stores (rows >= n are neither read
 // nor written; any alignment).  Same arithmetic as update_p_full_tiles.
-template <typename T>
+template <typename T, int NB>
 __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
                                                       const T* __restrict__ Q, int64_t ldq,
                                                       T* Qout, int64_t ldqo, const double* Rs,
@@ -458,17 +515,19 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
                                                       bool subst, int64_t tile0, int64_t n,
                                                       int K, int bw) {
   typedef Mfma<double> M;
-  constexpr int VEC = Vec16<T>::N;
+  typedef UpPShape<T, NB> Sh;
+  constexpr int VEC = Sh::VEC;
   constexpr int WROWS = 16 * VEC;
+  constexpr int NCOL = Sh::NCOL;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, li = lane & 15;
   const int64_t arow = tile0 + (int64_t)wave * WROWS + (int64_t)VEC * li;  // this lane's rows
   const int bwc = bw - 1;
 
-  // The accumulators start at -W_(i) (transposed layout: acc[v][e] holds
-  // row arow + v, column kk + 4 e), so W is not held through the product; its
-  // loads are issued together with the first group of Q.
-  constexpr int kUnroll = UpPUnroll<T>::N;
+  // The accumulators start at -W_(i) (transposed layout: acc[v][nb][e] holds
+  // row arow + v, column 16 nb + kk + 4 e), so W is not held through the
+  // product; its loads are issued together with the first group of Q.
+  constexpr int kUnroll = UpPUnroll<T, NB>::N;
   constexpr int GS = 4 * kUnroll;
   auto load_group = [&](T (&a)[kUnroll][VEC], int ks0) {
 #pragma unroll
@@ -483,34 +542,43 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
       }
     }
   };
-  M::acc_t acc[VEC];
+  M::acc_t acc[VEC][NB];
   auto mma_group = [&](const T (&a)[kUnroll][VEC], int ks0) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (ks0 + 4 * u < K) {
-        const double b = Rs[(ks0 + 4 * u + kk) * 16 + li];  // R[ks + kk][li] = R^T[li][ks + kk]
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = M::mma(b, (double)a[u][v], acc[v]);
+        for (int nb = 0; nb < NB; ++nb) {
+          // R[ks + kk][16 nb + li] = R^T[li][ks + kk]
+          const double b = Rs[(ks0 + 4 * u + kk) * NCOL + 16 * nb + li];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
+        }
       }
     }
   };
   T a0[kUnroll][VEC], a1[kUnroll][VEC];
   {
-    T w[4][VEC];
+    T w[NB][4][VEC];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = kk + 4 * e < bw ? kk + 4 * e : bwc;
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const bool in = arow + v < n;
-        const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
-        w[e][v] = in ? x : (T)0;
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
+          w[nb][e][v] = in ? x : (T)0;
+        }
       }
-    }
     if (K > 0) load_group(a0, 0);
 #pragma unroll
     for (int v = 0; v < VEC; ++v)
-      acc[v] = (M::acc_t){-(double)w[0][v], -(double)w[1][v], -(double)w[2][v], -(double)w[3][v]};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v][nb] = (M::acc_t){-(double)w[nb][0][v], -(double)w[nb][1][v], -(double)w[nb][2][v],
+                                -(double)w[nb][3][v]};
   }
   for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
     if (ks0 + GS < K) load_group(a1, ks0 + GS);
@@ -522,47 +590,22 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
   }
   // step 3: acc = Q R - W = -Q'_(i) (FP64)
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) acc[v] = -acc[v];
-  // steps 4-5: forward substitution x R_(i,i) = q' for every row, column by
-  // column in FP64: x_c = q'_c / R_cc (as q'_c (1 / R_cc)), then
-  // q'_c' -= x_c R_cc' for c' > c.  Column c of this lane's rows sits in lane
-  // (c % 4, li), element c / 4; it is handed to the lanes holding the other
-  // columns of the same rows by a lane shuffle.  Ru holds the strictly upper
-  // part of R_(i,i) (zero elsewhere and past bw), so the update needs no mask.
-  if (subst) {
+  for (int v = 0; v < VEC; ++v)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
+    for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+  if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = 16 * nb + kk + 4 * e;
       if (c < bw) {
-        const int kc = c & 3, ec = c >> 2;
-        const double rinv = Rinv[c];
-        double xb[VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][ec] * rinv, 16 * kc + li, 64);
-        if (kk == kc) {
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v][ec] = xb[v];
-        }
-        // columns kk + 4 e with e < ec are below c in every lane: nothing to do
-        double ru[4];
-#pragma unroll
-        for (int e = ec; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
+        T* dst = Qout + arow + (int64_t)c * ldqo;
 #pragma unroll
         for (int v = 0; v < VEC; ++v)
-#pragma unroll
-          for (int e = ec; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
+          if (arow + v < n) dst[v] = (T)acc[v][nb][e];
       }
     }
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int c = kk + 4 * e;
-    if (c < bw) {
-      T* dst = Qout + arow + (int64_t)c * ldqo;
-#pragma unroll
-      for (int v = 0; v < VEC; ++v)
-        if (arow + v < n) dst[v] = (T)acc[v][e];
-    }
-  }
 }
 
 // The full tiles of one workgroup (tile = first, first + stride, .. < nfull),
@@ -570,8 +613,8 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
 // the next tile are loaded before the substitution and stores of the current
 // one, so the wait for them does not also wait for those stores (stores share
 // the vector-memory counter on this target).  Same arithmetic, in the same
-// order, as update_p_tile<T, false>.
-template <typename T>
+// order, as update_p_guarded_tile.
+template <typename T, int NB>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     const T* __restrict__ Q, int64_t ldq,
                                                     T* Qout, int64_t ldqo, const double* Rs,
@@ -579,23 +622,27 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     bool subst, int64_t first, int64_t stride,
                                                     int64_t nfull, int K, int bw) {
   typedef Mfma<double> M;
-  constexpr int VEC = Vec16<T>::N;
+  typedef UpPShape<T, NB> Sh;
+  constexpr int VEC = Sh::VEC;
   constexpr int WROWS = 16 * VEC;
-  constexpr int TILE = 4 * WROWS;
+  constexpr int TILE = Sh::TILE;
+  constexpr int NCOL = Sh::NCOL;
   typedef typename Vec16<T>::t VT;
-  constexpr int kUnroll = UpPUnroll<T>::N;
+  constexpr int kUnroll = UpPUnroll<T, NB>::N;
   constexpr int GS = 4 * kUnroll;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, li = lane & 15;
   const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;  // row of this lane in a tile
   const int bwc = bw - 1;
 
-  auto load_w = [&](VT (&wv)[4], int64_t arow) {
+  auto load_w = [&](VT (&wv)[NB][4], int64_t arow) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = kk + 4 * e < bw ? kk + 4 * e : bwc;
-      wv[e] = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
-    }
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc;
+        wv[nb][e] = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
+      }
   };
   auto load_group = [&](VT (&a)[kUnroll], int64_t arow, int ks0) {
 #pragma unroll
@@ -605,29 +652,34 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
       a[u] = *reinterpret_cast<const VT*>(Q + arow + (int64_t)col * ldq);
     }
   };
-  M::acc_t acc[VEC];
+  M::acc_t acc[VEC][NB];
   auto mma_group = [&](const VT (&a)[kUnroll], int ks0) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (ks0 + 4 * u < K) {
-        const double b = Rs[(ks0 + 4 * u + kk) * 16 + li];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) acc[v] = M::mma(b, (double)a[u][v], acc[v]);
+        for (int nb = 0; nb < NB; ++nb) {
+          const double b = Rs[(ks0 + 4 * u + kk) * NCOL + 16 * nb + li];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
+        }
       }
     }
   };
 
   int64_t tile = first;
   if (tile >= nfull) return;
-  VT wv[4], a0[kUnroll], a1[kUnroll];
+  VT wv[NB][4], a0[kUnroll], a1[kUnroll];
   load_w(wv, tile * TILE + roff);
   if (K > 0) load_group(a0, tile * TILE + roff, 0);
   for (;;) {
     const int64_t arow = tile * TILE + roff;
 #pragma unroll
     for (int v = 0; v < VEC; ++v)
-      acc[v] = (M::acc_t){-(double)wv[0][v], -(double)wv[1][v], -(double)wv[2][v],
-                          -(double)wv[3][v]};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v][nb] = (M::acc_t){-(double)wv[nb][0][v], -(double)wv[nb][1][v],
+                                -(double)wv[nb][2][v], -(double)wv[nb][3][v]};
     for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
       if (ks0 + GS < K) load_group(a1, arow, ks0 + GS);
       mma_group(a0, ks0);
@@ -643,86 +695,70 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
       if (K > 0) load_group(a0, next * TILE + roff, 0);
     }
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] = -acc[v];
-    if (subst) {
+    for (int v = 0; v < VEC; ++v)
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
+      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+    if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e;
         if (c < bw) {
-          const int kc = c & 3, ec = c >> 2;
-          const double rinv = Rinv[c];
-          double xb[VEC];
+          VT vv;
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][ec] * rinv, 16 * kc + li, 64);
-          if (kk == kc) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v][ec] = xb[v];
-          }
-          double ru[4];
-#pragma unroll
-          for (int e = ec; e < 4; ++e) ru[e] = Ru[c + 16 * (kk + 4 * e)];
-#pragma unroll
-          for (int v = 0; v < VEC; ++v)
-#pragma unroll
-            for (int e = ec; e < 4; ++e) acc[v][e] = fma(-xb[v], ru[e], acc[v][e]);
+          for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
+          *reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo) = vv;
         }
       }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = kk + 4 * e;
-      if (c < bw) {
-        VT vv;
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][e];
-        *reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo) = vv;
-      }
-    }
     if (!more) break;
     tile = next;
   }
 }
 
-// LDS: Rs [Kp][16] (rows >= K zero); Ru [16][16] (column-major) = strictly
-// upper part of R_(i,i), zero past bw; Rinv [16] = 1 / R_cc (1 past bw).  FP64.
-template <typename T>
-__global__ __launch_bounds__(kUpThreads, 4) void update_p_kernel(
+// LDS: Rs [Kp][16 NB] (rows >= K zero); Ru [16 NB][16 NB] (column-major) =
+// strictly upper part of R_(i,i), zero past bw; Rinv [16 NB] = 1 / R_cc (1 past
+// bw).  FP64.
+template <typename T, int NB>
+__global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)) void update_p_kernel(
     const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
     const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t ntiles,
     int64_t nfull, int64_t n, int K, int Kp, int bw) {
+  typedef UpPShape<T, NB> Sh;
+  constexpr int NCOL = Sh::NCOL;
   extern __shared__ __attribute__((aligned(16))) double up_lds[];
   double* Rs = up_lds;
-  double* Ru = up_lds + (int64_t)Kp * 16;
-  double* Rinv = Ru + 256;
-  constexpr int TILE = 4 * 16 * Vec16<T>::N;
-  for (int e = threadIdx.x; e < Kp * 16; e += kUpThreads) {
-    const int r = e >> 4, c = e & 15;
+  double* Ru = up_lds + (int64_t)Kp * NCOL;
+  double* Rinv = Ru + NCOL * NCOL;
+  constexpr int TILE = Sh::TILE;
+  for (int e = threadIdx.x; e < Kp * NCOL; e += Sh::THREADS) {
+    const int r = e / NCOL, c = e % NCOL;
     const bool in = r < K && c < bw;
     const double v = Rk[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
     Rs[e] = in ? v : 0.0;
   }
   const bool subst = Rii != nullptr;
   if (subst) {
-    {
-      const int e = threadIdx.x;  // 256 threads, one entry each
-      const int r = e & 15, c = e >> 4;
+    for (int e = threadIdx.x; e < NCOL * NCOL; e += Sh::THREADS) {
+      const int r = e % NCOL, c = e / NCOL;
       const bool in = r < c && c < bw;
       const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
       Ru[e] = in ? v : 0.0;
     }
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < NCOL) {
       const int c = threadIdx.x;
       Rinv[c] = c < bw ? 1.0 / Rii[c + (int64_t)c * ldr] : 1.0;
     }
   }
   __syncthreads();
-  update_p_full_tiles<T>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x, gridDim.x,
-                         nfull, K, bw);
+  update_p_full_tiles<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x, gridDim.x,
+                             nfull, K, bw);
   // the guarded tiles (a ragged last tile, or every tile when a pointer or
   // leading dimension is not 16-byte aligned) come after the full ones
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     if (tile >= nfull)
-      update_p_guarded_tile<T>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
-                               bw);
+      update_p_guarded_tile<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n,
+                                   K, bw);
 }
 
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
@@ -774,26 +810,40 @@ static bool aligned16(const void* p, int64_t ld, int vec) {
   return (ld % vec) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
 }
 
-template <typename T>
+template <typename T, int NB>
 static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int64_t ldq,
                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
                                   int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
-  constexpr int VEC = Vec16<T>::N;
-  constexpr int TILE = 4 * 16 * VEC;
+  typedef UpPShape<T, NB> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int TILE = Sh::TILE;
   const bool vec_ok = aligned16(W, ldw, VEC) && aligned16(Qout, ldqo, VEC) &&
                       (K == 0 || aligned16(Q, ldq, VEC));
   const int64_t ntiles = ceil_div(n, TILE);
   const int64_t nfull = vec_ok ? n / TILE : 0;
   const int Kp = (int)((K + 3) / 4 * 4);
-  const size_t lds = ((size_t)Kp * 16 + 256 + 16) * sizeof(double);
-  // FP32 storage: as many workgroups as give every one the same number of
-  // tiles (no partly empty last round; measured -0.6 % on the step, while
-  // FP64 storage, with twice the tiles, is better with all 1024)
-  const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS);
-  const unsigned grid = sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
-                                       : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
-  hipLaunchKernelGGL((update_p_kernel<T>), dim3(grid), dim3(kUpThreads), lds, st, (const T*)W, ldw,
-                     (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, (int)K, Kp, bw);
+  const size_t lds = ((size_t)Kp * Sh::NCOL + (size_t)Sh::NCOL * Sh::NCOL + Sh::NCOL) * sizeof(double);
+  unsigned grid;
+  if (NB == 1) {
+    // FP32 storage: as many workgroups as give every one the same number of
+    // tiles (no partly empty last round; measured -0.6 % on the step, while
+    // FP64 storage, with twice the tiles, is better with all 1024)
+    const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS);
+    grid = sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
+                          : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
+  } else {
+    // one workgroup per CU (its R_(1:i-1,i) fills most of the LDS)
+    const int64_t per = ceil_div(ntiles, 256);
+    grid = (unsigned)ceil_div(ntiles, per);
+  }
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&update_p_kernel<T, NB>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((update_p_kernel<T, NB>), dim3(grid), dim3(Sh::THREADS), lds, st, (const T*)W,
+                     ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, (int)K,
+                     Kp, bw);
   return hipGetLastError();
 }
 
@@ -802,7 +852,9 @@ static hipError_t launch_update_t(const void* W, int64_t ldw, const void* Q, int
                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
                                   int64_t ldr, int64_t n, int64_t K, int bw, hipStream_t st) {
   if (std::is_same<C, double>::value && bw <= 16 && K <= kUpPMaxK)
-    return launch_update_p<T>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+    return launch_update_p<T, 1>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+  if (std::is_same<C, double>::value && bw <= 32 && K <= kUpP2MaxK)
+    return launch_update_p<T, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   if (bw <= 16) return launch_update_nb<T, C, 1>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   return launch_update_nb<T, C, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
 }

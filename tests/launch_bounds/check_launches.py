@@ -187,15 +187,20 @@ def _update_general(L, T, NB):
     return out
 
 
-def _update_persistent(L, T):
+def _update_persistent(L, T, NB=1):
     # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, K, Kp, bw)
     es = 4 if T == "f" else 8
     VEC = 16 // es
-    TILE = 4 * 16 * VEC
+    WAVES = 4 if NB == 1 else 8
+    TILE = WAVES * 16 * VEC
+    NCOL = 16 * NB
     ldw, ldq, ldqo, ldr = L.i(1), L.i(3), L.i(5), L.i(8)
     ntiles, nfull, n, K, Kp, bw = L.i(9), L.i(10), L.i(11), L.i(12), L.i(13), L.i(14)
-    assert ntiles == cdiv(n, TILE) and nfull * TILE <= n and bw <= 16 and K <= Kp <= 512
-    assert L.shmem >= (Kp * 16 + 256 + 16) * 8
+    assert L.block[0] == 64 * WAVES
+    assert ntiles == cdiv(n, TILE) and nfull * TILE <= n and bw <= NCOL
+    assert K <= Kp <= (512 if NB == 1 else 480) and Kp % 4 == 0
+    assert L.shmem >= (Kp * NCOL + NCOL * NCOL + NCOL) * 8
+    assert L.shmem <= 160 * 1024
     last = n - 1
     out = [acc(0, es, 0, last + (bw - 1) * ldw), acc(4, es, 0, last + (bw - 1) * ldqo),
            acc(6, 8, 0, max(0, (K - 1) + (bw - 1) * ldr))]
@@ -358,7 +363,7 @@ MIRRORS = {
 }
 TEMPLATED = {
     "update_kernel": lambda L, t: _update_general(L, t[0], t[2]),
-    "update_p_kernel": lambda L, t: _update_persistent(L, t[0]),
+    "update_p_kernel": lambda L, t: _update_persistent(L, t[0], t[1] if len(t) > 1 else 1),
     "trsm_kernel": lambda L, t: _trsm(L, t[0]),
     "sketch_gauss_kernel": lambda L, t: _sketch_gauss(L, t[0], t[2]),
     "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),

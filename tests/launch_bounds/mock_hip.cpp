@@ -184,6 +184,7 @@ hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKin
   return copy(dst, src, bytes, kind);
 }
 
+hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 hipError_t hipGetLastError(void) { return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { return "mock"; }
 hipError_t hipSetDevice(int) { return hipSuccess; }

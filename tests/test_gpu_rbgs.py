@@ -132,6 +132,8 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (5000, 17, 1, 64, "gaussian", "l2qr"),          # TSQR of single columns
     (3000, 70, 32, 512, "sparse", "l2qr"),          # 32-wide TSQR over four tree levels
     (4000, 72, 24, 256, "rademacher", "twice"),
+    (4097, 75, 24, 256, "sparse", "lowsync"),       # 24-wide blocks: the 32-column update form
+    (9000, 96, 32, 512, "gaussian", "plain"),
     (64, 16, 4, 64, "identity", "l2qr"),
     (300, 20, 6, 300, "identity", "twice"),
     (4097, 30, 8, 128, "srht", "lowsync"),          # SRHT: ragged chunk, transform of 2^13
@@ -395,11 +397,13 @@ def test_rank_deficient_in_fp64(gpu_lib, store):
                         "R_(1,1)")
 
 
-def test_update_falls_back_past_lds_capacity(gpu_lib):
+@pytest.mark.parametrize("b,m", [(16, 560), (32, 544)])
+def test_update_falls_back_past_lds_capacity(gpu_lib, b, m):
     """Blocks whose K = c0 exceeds the rows of R the persistent update keeps in
-    LDS (512) take the general update kernel; both forms in one factorization
-    agree with the oracle at the FP64 tolerance."""
-    n, m, b, k = 3000, 560, 16, 576
+    LDS (512 for 16-column blocks, 480 for 32-column blocks) take the general
+    update kernel; both forms in one factorization agree with the oracle at the
+    FP64 tolerance."""
+    n, k = 3000, 576
     W = svd_matrix(n, m, np.logspace(0, -2, m), seed=91)
     say("update forms", n, m, b, k)
     Q, R, S, cert = gpu_qr(W, b, "sparse", k, 29, "lowsync")
@@ -410,16 +414,17 @@ def test_update_falls_back_past_lds_capacity(gpu_lib):
     assert factorization_error(W, Q, R) < 1e-14
 
 
+@pytest.mark.parametrize("b", [16, 32])
 @pytest.mark.parametrize("store", ["f64", "f32"])
 @pytest.mark.parametrize("ldw_pad,ldq_pad", [(0, 0), (8, 4), (3, 5), (4, 1)])
-def test_leading_dimensions_give_identical_results(gpu_lib, store, ldw_pad, ldq_pad):
+def test_leading_dimensions_give_identical_results(gpu_lib, store, ldw_pad, ldq_pad, b):
     """W and Q inside larger column-major buffers (ld > n): 16-byte aligned
     leading dimensions keep the vector path, others take the guarded path for
     every tile.  Every element is computed by the same operations in the same
     order either way, so the results equal those with ld = n bit for bit."""
     import torch
     from paper_2111_14641_amd import binding as B
-    n, m, b, k = 5000, 48, 16, 256
+    n, m, k = 5000, 48, 256
     W = svd_matrix(n, m, np.logspace(0, -3, m), seed=5)
     dt = torch.float64 if store == "f64" else torch.float32
     say("leading dimensions", store, ldw_pad, ldq_pad)
