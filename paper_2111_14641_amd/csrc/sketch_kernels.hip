@@ -164,9 +164,12 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 // across tiles.  The next tile is prefetched into registers while the current
 // one is summed; every prefetch load is unconditional (clamped index).  The
 // shape is chosen per storage type and width (measured): 1024 threads with 8
-// FP32 columns (68 KB of LDS, two workgroups per CU) or 4 FP64 columns (1024
-// threads for a 16-column sketch, 512 for all of W at once), so several
-// workgroups share a CU and hide one another's latency and barriers.  The slices of
+// FP32 columns (68 KB of LDS, two workgroups per CU) for a sketch of at most 16
+// columns, 16 FP32 columns (100 KB, one per CU, the plan of a tile read once
+// for twice the columns) for wider ones, or 4 FP64 columns (1024 threads for a
+// 16-column sketch, 512 for wider ones), so several workgroups share a CU and
+// hide one another's latency and barriers.  Staging two tiles per barrier (so
+// that each barrier waits on the sum of two buckets) measured slower.  The slices of
 // one row range are G apart in blockIdx.x (a multiple of 8 when G is), so
 // they run on the same XCD and share the plan through its L2.
 #ifndef RBGS_SPQ_NT32
@@ -185,13 +188,25 @@ __global__ __launch_bounds__(kSpThreads) void sparse_plan_batched_kernel(const B
 #define RBGS_SPQ_NT32M 1024  // FP32 storage, sketches of more than 16 columns
 #endif
 #ifndef RBGS_SPQ_NC32M
-#define RBGS_SPQ_NC32M 8
+#define RBGS_SPQ_NC32M 16   // measured: 4e6 x 512 sketches 10.2 -> 8.6 ms per QR, 1e6 x 256 unchanged
 #endif
 #ifndef RBGS_SPQ_NT64M
 #define RBGS_SPQ_NT64M 512   // FP64 storage, sketches of more than 16 columns
 #endif
 #ifndef RBGS_SPQ_NC64M
 #define RBGS_SPQ_NC64M 4
+#endif
+#ifndef RBGS_SPQ_TPB32
+#define RBGS_SPQ_TPB32 1     // FP32 storage: tiles staged per barrier
+#endif
+#ifndef RBGS_SPQ_TPB32M
+#define RBGS_SPQ_TPB32M 1
+#endif
+#ifndef RBGS_SPQ_TPB64
+#define RBGS_SPQ_TPB64 1
+#endif
+#ifndef RBGS_SPQ_TPB64M
+#define RBGS_SPQ_TPB64M 1
 #endif
 // MANY: the sketch has more than one 16-column group (all of W at once)
 template <typename T, bool MANY = false>
@@ -200,6 +215,8 @@ struct SpqShape {
                                            : (MANY ? RBGS_SPQ_NT64M : RBGS_SPQ_NT64);
   static constexpr int NC = sizeof(T) == 4 ? (MANY ? RBGS_SPQ_NC32M : RBGS_SPQ_NC32)
                                            : (MANY ? RBGS_SPQ_NC64M : RBGS_SPQ_NC64);
+  static constexpr int TPB = sizeof(T) == 4 ? (MANY ? RBGS_SPQ_TPB32M : RBGS_SPQ_TPB32)
+                                            : (MANY ? RBGS_SPQ_TPB64M : RBGS_SPQ_TPB64);
 };
 
 template <typename T, int TPT, bool MANY = false>
@@ -209,18 +226,18 @@ __device__ __forceinline__ void sketch_sparse_q_body(
     int64_t tiles_per_wg, double* __restrict__ partial, int g, int cs) {
   constexpr int NT = SpqShape<T, MANY>::NT;
   constexpr int NC = SpqShape<T, MANY>::NC;
+  constexpr int TB = SpqShape<T, MANY>::TPB;           // tiles staged per barrier
   static_assert(NC % 4 == 0, "columns per workgroup: a multiple of 4");
   typedef T V4 __attribute__((ext_vector_type(4)));
   typedef unsigned short U8 __attribute__((ext_vector_type(8)));
-  constexpr int RPT = kSpTile / NT;                    // staged rows per thread
-  constexpr int EVT = kSpTile * kSpMaxZeta / 8 / NT;   // entry vectors per thread
+  constexpr int RPT = kSpTile / NT;                    // staged rows per thread and tile
+  constexpr int EVT = kSpTile * kSpMaxZeta / 8 / NT;   // entry vectors per thread and tile
   // row stride: FP32 rows of 8 or more columns are padded by 16 bytes so that
   // rows gathered at random start on more distinct banks
   constexpr int XC = NC + ((sizeof(T) == 4 && NC >= 8) ? 4 : 0);
-  __shared__ __attribute__((aligned(32))) T xs[kSpTile * XC];  // [rr][c]
-  __shared__ __attribute__((aligned(16))) U8 ent8[kSpTile * kSpMaxZeta / 8];
-  __shared__ uint16_t off[kSpMaxK + 1];
-  const uint16_t* ent = (const uint16_t*)ent8;
+  __shared__ __attribute__((aligned(32))) T xs[TB][kSpTile * XC];  // [tile][rr][c]
+  __shared__ __attribute__((aligned(16))) U8 ent8[TB][kSpTile * kSpMaxZeta / 8];
+  __shared__ uint16_t off[TB][kSpMaxK + 1];
 
   const int tid = threadIdx.x;
   const int col0 = cs * NC;
@@ -237,73 +254,90 @@ __device__ __forceinline__ void sketch_sparse_q_body(
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[j][c] = 0.0;
 
-  T px[RPT][NC];
-  U8 pe[EVT];
-  uint16_t po[TPT + 1];
-  auto fetch = [&](int64_t tile) {
-    const int64_t r0 = tile * kSpTile;
-    const int trows = (int)min((int64_t)kSpTile, n - r0);
-    // clamped, unmasked loads: no plan entry names a row past the end, and
-    // the sums of columns past nc are never stored
+  T px[TB][RPT][NC];
+  U8 pe[TB][EVT];
+  uint16_t po[TB][TPT + 1];
+  // group of TB consecutive tiles from `tile` (tiles >= tend are clamped to
+  // tend - 1 and never summed)
+  auto fetch = [&](int64_t tile0) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int rr = tid + NT * q;
-      const int64_t r = r0 + (rr < trows ? rr : trows - 1);
+    for (int b = 0; b < TB; ++b) {
+      const int64_t tile = tile0 + b < tend ? tile0 + b : tend - 1;
+      const int64_t r0 = tile * kSpTile;
+      const int trows = (int)min((int64_t)kSpTile, n - r0);
+      // clamped, unmasked loads: no plan entry names a row past the end, and
+      // the sums of columns past nc are never stored
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        px[q][c] = X[r + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
-    }
-    const U8* pv = (const U8*)(plan_ent + tile * (int64_t)E);
+      for (int q = 0; q < RPT; ++q) {
+        const int rr = tid + NT * q;
+        const int64_t r = r0 + (rr < trows ? rr : trows - 1);
 #pragma unroll
-    for (int q = 0; q < EVT; ++q) {
-      const int v = tid + NT * q;
-      pe[q] = pv[v < nvec ? v : nvec - 1];
-    }
-    const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
+        for (int c = 0; c < NC; ++c)
+          px[b][q][c] = X[r + (int64_t)(col0 + (c < nc ? c : nc - 1)) * ldx];
+      }
+      const U8* pv = (const U8*)(plan_ent + tile * (int64_t)E);
 #pragma unroll
-    for (int i = 0; i <= TPT; ++i) {
-      const int t = tid + i * NT;
-      po[i] = so[t <= k ? t : k];
+      for (int q = 0; q < EVT; ++q) {
+        const int v = tid + NT * q;
+        pe[b][q] = pv[v < nvec ? v : nvec - 1];
+      }
+      const uint16_t* so = plan_off + tile * (int64_t)(k + 1);
+#pragma unroll
+      for (int i = 0; i <= TPT; ++i) {
+        const int t = tid + i * NT;
+        po[b][i] = so[t <= k ? t : k];
+      }
     }
   };
   if (tbeg < tend) fetch(tbeg);
-  for (int64_t tile = tbeg; tile < tend; ++tile) {
+  for (int64_t tile = tbeg; tile < tend; tile += TB) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      V4* xw = (V4*)(xs + (tid + NT * q) * XC);
+    for (int b = 0; b < TB; ++b) {
 #pragma unroll
-      for (int w = 0; w < NC / 4; ++w)
-        xw[w] = (V4){px[q][4 * w], px[q][4 * w + 1], px[q][4 * w + 2], px[q][4 * w + 3]};
+      for (int q = 0; q < RPT; ++q) {
+        V4* xw = (V4*)(xs[b] + (tid + NT * q) * XC);
+#pragma unroll
+        for (int w = 0; w < NC / 4; ++w)
+          xw[w] = (V4){px[b][q][4 * w], px[b][q][4 * w + 1], px[b][q][4 * w + 2], px[b][q][4 * w + 3]};
+      }
+#pragma unroll
+      for (int q = 0; q < EVT; ++q) {
+        const int v = tid + NT * q;
+        if (v < nvec) ent8[b][v] = pe[b][q];
+      }
+#pragma unroll
+      for (int i = 0; i <= TPT; ++i) {
+        const int t = tid + i * NT;
+        if (t <= k) off[b][t] = po[b][i];
+      }
     }
-#pragma unroll
-    for (int q = 0; q < EVT; ++q) {
-      const int v = tid + NT * q;
-      if (v < nvec) ent8[v] = pe[q];
-    }
-#pragma unroll
-    for (int i = 0; i <= TPT; ++i) {
-      const int t = tid + i * NT;
-      if (t <= k) off[t] = po[i];
-    }
-    if (tile + 1 < tend) fetch(tile + 1);   // in flight while this tile is summed
+    if (tile + TB < tend) fetch(tile + TB);   // in flight while these tiles are summed
     __syncthreads();
+    const int nb = (int)min((int64_t)TB, tend - tile);
 #pragma unroll
     for (int j = 0; j < TPT; ++j) {
       const int t = tid + j * NT;
       if (t < k) {
-        // one entry per pass; the next entry is read while this one is summed
-        const int b = off[t], e = off[t + 1];
-        uint32_t vn = ent[b < e ? b : 0];
-        for (int i = b; i < e; ++i) {
-          const uint32_t v = vn;
-          vn = ent[i + 1 < e ? i + 1 : i];
-          const V4* xr = (const V4*)(xs + (v >> 1) * XC);
-          const double sg = (v & 1u) ? -1.0 : 1.0;
+        // the staged tiles in order; in each, one entry per pass, the next
+        // entry read while this one is summed
 #pragma unroll
-          for (int w = 0; w < NC / 4; ++w) {
-            const V4 x = xr[w];
+        for (int b = 0; b < TB; ++b) {
+          if (b < nb) {
+            const uint16_t* ent = (const uint16_t*)ent8[b];
+            const int bb = off[b][t], e = off[b][t + 1];
+            uint32_t vn = ent[bb < e ? bb : 0];
+            for (int i = bb; i < e; ++i) {
+              const uint32_t v = vn;
+              vn = ent[i + 1 < e ? i + 1 : i];
+              const V4* xr = (const V4*)(xs[b] + (v >> 1) * XC);
+              const double sg = (v & 1u) ? -1.0 : 1.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[j][4 * w + u] = fma(sg, (double)x[u], acc[j][4 * w + u]);
+              for (int w = 0; w < NC / 4; ++w) {
+                const V4 x = xr[w];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[j][4 * w + u] = fma(sg, (double)x[u], acc[j][4 * w + u]);
+              }
+            }
           }
         }
       }
@@ -752,6 +786,12 @@ __global__ void theta_dense_kernel(int kind, int64_t k, int zeta, uint32_t key0,
 // Host launchers
 // ---------------------------------------------------------------------------
 
+#ifndef RBGS_SP_WGS
+#define RBGS_SP_WGS 256    // sparse sign, one 16-column group: row ranges
+#endif
+#ifndef RBGS_SP_WGSM
+#define RBGS_SP_WGSM 256   // sparse sign, several groups: row ranges x groups
+#endif
 int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_groups) {
   // Sparse sign: one 1024-thread workgroup per CU in total (256 CUs) spread
   // over the column groups.  Dense (Gaussian, Rademacher): about RBGS_GA_WGS
@@ -768,7 +808,8 @@ int sketch_num_partials(const SketchDesc& sk, int64_t n, int64_t ncols, int max_
     if (max_groups > 0) G = std::min<int64_t>(G, max_groups);
     return (int)std::max<int64_t>(1, G);
   } else {
-    G = ceil_div(256, groups);
+    // RBGS_SP_WGS: row ranges x 16-column groups (one per CU by default)
+    G = ceil_div(groups > 1 ? RBGS_SP_WGSM : RBGS_SP_WGS, groups);
     tile = kSpTile;
   }
   G = std::min<int64_t>(G, ceil_div(n, tile));

@@ -249,7 +249,7 @@ def _sketch_sparse_q(L, T, TPT, MANY):
     es = 4 if T == "f" else 8
     ldx, n, ncols, k, zeta, tpw, G = L.i(1), L.i(2), L.i(3), L.i(4), L.i(5), L.i(8), L.i(10)
     if es == 4:
-        NT, NC = 1024, 8
+        NT, NC = (1024, 16) if MANY else (1024, 8)
     else:
         NT, NC = (512, 4) if MANY else (1024, 4)
     assert L.block[0] == NT
