@@ -443,7 +443,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   const size_t o_stack = carve(qr_stack_size(k, b));
   const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
-  const size_t o_cnt = carve(1);
+  const size_t o_cnt = carve((size_t)(2 + kQrTreeCounters) / 2);  // [0] spare, [1 ..] QR tree
   const size_t o_G = carve((size_t)m * m);   // Gram matrix S^T S of the blocks done
   const size_t o_C = carve((size_t)m * b);   // c = S^T P_(i)
   const size_t o_Y = carve((size_t)m * b);   // Richardson iterate
@@ -485,7 +485,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.Rt = twice ? (double*)(base + o_Rt) : nullptr;
   r.tall = tall_need ? (double*)(base + o_tall) : nullptr;
   hipStream_t st = r.st;
-  HIP_TRY(h, launch_qr_init(R, ldr, m, r.flag, r.counters, 2, st), "init");
+  HIP_TRY(h, launch_qr_init(R, ldr, m, r.flag, r.counters, 1 + kQrTreeCounters, st), "init");
   if (r.plan) {
     ProfScope ps(h, kProfSketch, 0.0, st);
     HIP_TRY(h, launch_sparse_plan(d, n, 0, r.plan, st), "sketch plan");
@@ -872,7 +872,7 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
       std::vector<size_t> o;
       for (size_t doubles : {(size_t)(k * m), (size_t)(k * m), (size_t)(k * b), (size_t)(m * m),
                              (size_t)(m * b), (size_t)(m * b), (size_t)(G * k * m), (size_t)1,
-                             qr_stack_size(k, (int)b), (size_t)1}) {
+                             qr_stack_size(k, (int)b), (size_t)(kQrTreeCounters + 1) / 2}) {
         o.push_back(off);
         off += r256(doubles * 8);
       }

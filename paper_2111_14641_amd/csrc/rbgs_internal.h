@@ -368,9 +368,10 @@ hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const doub
 hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
                         int64_t ldy, double* E, int bw, hipStream_t st);
 // R_(i,i) (positive diagonal) of src (k x bw, ld k) in one launch (tree of
-// Householder QRs; *counter must be 0 and is left at 0; stack:
-// qr_stack_size(k, bw) doubles; flag[0] is set to the first column col0 + j whose
-// diagonal entry is zero or not finite, if it is still -1).
+// Householder QRs; counter[0 .. kQrTreeCounters) must be 0 and are left at 0;
+// stack: qr_stack_size(k, bw) doubles; flag[0] is set to the first column
+// col0 + j whose diagonal entry is zero or not finite, if it is still -1).
+constexpr int kQrTreeCounters = 62;
 hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, unsigned* counter,
                            double* Rii, int64_t ldr, int64_t* flag, int64_t col0, hipStream_t st);
 // R factor (positive diagonal) of the l2 QR of a tall rows x bw matrix (FP32 or

@@ -218,6 +218,9 @@ __device__ void qr_chunk(const T* __restrict__ src, int64_t ld_in, int64_t rows_
 #undef RBGS_QRC
 }
 
+// Stack of the tree levels: the larger of the one-group form (levels of
+// re-chunked stacked rows) and the grouped form (level l holds n_l R factors,
+// n_0 = chunks, n_(l+1) = ceil(n_l / FAN)).
 size_t qr_stack_size(int64_t k, int bw) {
   const int64_t CH = qr_chunk_rows(bw);
   int64_t rows = k, total = 0;
@@ -226,7 +229,10 @@ size_t qr_stack_size(int64_t k, int bw) {
     total += nch * bw;
     rows = nch * bw;
   }
-  return (size_t)total * bw + 1;
+  int64_t tree = 0;
+  const int64_t fan = CH / bw;
+  for (int64_t n = ceil_div(k, CH); n > 1; n = ceil_div(n, fan)) tree += n * bw;
+  return (size_t)std::max(total, tree) * bw + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -419,12 +425,31 @@ __device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned t
   return last;
 }
 
-// R_(i,i) (positive diagonal) of the k x bw matrix src (ld k): workgroup g
-// factors chunk g in LDS; the last workgroup factors the stack of chunk R
-// factors (all remaining levels of the tree) and writes R_(i,i).
+// Arrival counters the grouped tree needs for a k x bw sketch (0: one chunk),
+// and the number of R factors one chunk of a tree level takes (FAN).
+__host__ __device__ __forceinline__ int64_t qr_tree_fan(int bw) { return qr_chunk_rows(bw) / bw; }
+__host__ __device__ __forceinline__ int64_t qr_tree_counters(int64_t k, int bw) {
+  const int64_t fan = qr_tree_fan(bw);
+  int64_t need = 0;
+  for (int64_t n = (k + qr_chunk_rows(bw) - 1) / qr_chunk_rows(bw); n > 1; n = (n + fan - 1) / fan)
+    need += (n + fan - 1) / fan;
+  return need;
+}
+
+// R_(i,i) (positive diagonal) of the k x bw matrix src (ld k) by a Householder
+// TSQR tree in one launch: workgroup g factors chunk g (level 0) and writes
+// its R factor to the level-1 stack.  The R factors of a level are taken in
+// groups of FAN (as many as one chunk holds); the last workgroup of a group
+// to arrive (an arrival counter per group, reset to zero by that workgroup)
+// factors the group's stacked R factors into one R of the next level, so the
+// groups of a level proceed in parallel and the last arrival of the single
+// group of the top level writes R_(i,i).  The critical path is one chunk
+// factorization per level.  counters: ncnt zeroed counters; if the tree needs
+// more, the last of all level-0 workgroups factors every further level
+// itself (counters[0]).
 __device__ __forceinline__ void qr_fused_body(const double* __restrict__ src, int64_t k, int bw,
-                                              double* __restrict__ stack, unsigned* counter,
-                                              double* __restrict__ Rii, int64_t ldr,
+                                              double* __restrict__ stack, unsigned* counters,
+                                              int ncnt, double* __restrict__ Rii, int64_t ldr,
                                               int64_t* flag, int64_t col0, int64_t chunk) {
   __shared__ double xb[2 * (kQrThreads / 4) * kQrRpt];
   __shared__ double sg[2 + kQrMaxB];
@@ -436,7 +461,34 @@ __device__ __forceinline__ void qr_fused_body(const double* __restrict__ src, in
   }
   const int64_t ld1 = nch * bw;
   qr_chunk(src, k, k, bw, stack, ld1, 0, nullptr, 0, chunk, xb, sg);
-  if (!last_block_arrives(counter, (unsigned)nch)) return;
+  if (qr_tree_counters(k, bw) <= ncnt) {
+    const int64_t fan = qr_tree_fan(bw);
+    const double* buf = stack;
+    double* next = stack + ld1 * bw;
+    int64_t ld = ld1, n = nch, pos = chunk;
+    unsigned* cnt = counters;
+    for (;;) {
+      const int64_t ng = (n + fan - 1) / fan;  // groups (R factors of the next level)
+      const int64_t g = pos / fan;
+      const int64_t gs = min(fan, n - g * fan);
+      if (!last_block_arrives(cnt + g, (unsigned)gs)) return;
+      if (threadIdx.x == 0) cnt[g] = 0u;     // every other arrival has happened
+      const double* gsrc = buf + g * fan * bw;
+      if (ng == 1) {
+        qr_chunk(gsrc, ld, gs * bw, bw, Rii, ldr, 1, flag, col0, 0, xb, sg);
+        return;
+      }
+      const int64_t ld2 = ng * bw;
+      qr_chunk(gsrc, ld, gs * bw, bw, next + g * bw, ld2, 0, nullptr, 0, 0, xb, sg);
+      cnt += ng;
+      buf = next;
+      next += ld2 * bw;
+      ld = ld2;
+      n = ng;
+      pos = g;
+    }
+  }
+  if (!last_block_arrives(counters, (unsigned)nch)) return;
   // remaining levels in this workgroup
   const double* lsrc = stack;
   int64_t ld_in = ld1, lrows = ld1;
@@ -452,13 +504,14 @@ __device__ __forceinline__ void qr_fused_body(const double* __restrict__ src, in
     buf += out_rows * bw;
   }
   qr_chunk(lsrc, ld_in, lrows, bw, Rii, ldr, 1, flag, col0, 0, xb, sg);
-  if (threadIdx.x == 0) *counter = 0u;
+  if (threadIdx.x == 0) *counters = 0u;
 }
 
 __global__ __launch_bounds__(kQrThreads) void qr_fused_kernel(
     const double* __restrict__ src, int64_t k, int bw, double* __restrict__ stack,
-    unsigned* counter, double* __restrict__ Rii, int64_t ldr, int64_t* flag, int64_t col0) {
-  qr_fused_body(src, k, bw, stack, counter, Rii, ldr, flag, col0, blockIdx.x);
+    unsigned* counters, int ncnt, double* __restrict__ Rii, int64_t ldr, int64_t* flag,
+    int64_t col0) {
+  qr_fused_body(src, k, bw, stack, counters, ncnt, Rii, ldr, flag, col0, blockIdx.x);
 }
 
 // Lock-step batch (blockIdx.y = problem): the Householder tree of S'_(i).
@@ -466,8 +519,8 @@ __global__ __launch_bounds__(kQrThreads) void qr_fused_batched_kernel(const Batc
                                                                       int64_t k, int bw,
                                                                       int64_t c0) {
   const BatchItem& it = items[blockIdx.y];
-  qr_fused_body(c0 == 0 ? it.P : it.E, k, bw, it.stack, it.counter, it.R + c0 + c0 * it.ldr,
-                it.ldr, it.flag, c0, blockIdx.x);
+  qr_fused_body(c0 == 0 ? it.P : it.E, k, bw, it.stack, it.counter, kQrTreeCounters,
+                it.R + c0 + c0 * it.ldr, it.ldr, it.flag, c0, blockIdx.x);
 }
 
 // One level of a Householder TSQR tree over a tall rows_in x bw matrix:
@@ -632,10 +685,8 @@ __global__ void init_batched_kernel(const BatchItem* items, int64_t m) {
   const BatchItem& it = items[blockIdx.y];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < m * m) it.R[(idx % m) + it.ldr * (idx / m)] = 0.0;
-  if (idx == 0) {
-    *it.flag = -1;
-    *it.counter = 0u;
-  }
+  if (idx == 0) *it.flag = -1;
+  if (idx < kQrTreeCounters) it.counter[idx] = 0u;
 }
 
 // Deterministic test matrix for the autotuner: x[r][c] = a hash of (r, c)
@@ -751,7 +802,7 @@ hipError_t launch_qr_fused(const double* src, int64_t k, int bw, double* stack, 
   }
   const int64_t CH = qr_chunk_rows(bw);
   hipLaunchKernelGGL(qr_fused_kernel, dim3((unsigned)ceil_div(k, CH)), dim3(kQrThreads), 0, st, src,
-                     k, bw, stack, counter, Rii, ldr, flag, col0);
+                     k, bw, stack, counter, kQrTreeCounters, Rii, ldr, flag, col0);
   return hipGetLastError();
 }
 

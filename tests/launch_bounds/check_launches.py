@@ -138,16 +138,31 @@ def qr_chunk_rows(bw):
 
 
 def _qr_fused(L):
-    # (src, k, bw, stack, counter, Rii, ldr, flag, col0)
-    k, bw, ldr = L.i(1), L.i(2), L.i(6)
+    # (src, k, bw, stack, counters, ncnt, Rii, ldr, flag, col0)
+    k, bw, ncnt, ldr = L.i(1), L.i(2), L.i(5), L.i(7)
     CH = qr_chunk_rows(bw)
     nch = cdiv(k, CH)
     assert L.grid[0] == nch and L.block[0] == 256
-    out = [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(5, 8, 0, (bw - 1) + (bw - 1) * ldr),
-           acc(7, 8, 0, 0)]
+    out = [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(6, 8, 0, (bw - 1) + (bw - 1) * ldr),
+           acc(8, 8, 0, 0)]
     if nch == 1:
         return out
-    # level 1: chunk b writes rows [b bw, b bw + bw) of a (nch bw) x bw stack
+    # grouped tree: level l holds n_l R factors (n_0 = nch), n_(l+1) = ceil(n_l / fan),
+    # a counter per group of each level
+    fan = CH // bw
+    need, n = 0, nch
+    while n > 1:
+        need += cdiv(n, fan)
+        n = cdiv(n, fan)
+    if need <= ncnt:
+        hi, n, off = -1, nch, 0
+        while n > 1:
+            hi = max(hi, off + n * bw * bw - 1)
+            off += n * bw * bw
+            n = cdiv(n, fan)
+        return out + [acc(3, 8, 0, hi), acc(4, 4, 0, need - 1)]
+    # one group: level 1 rows [b bw, b bw + bw) of a (nch bw) x bw stack, then
+    # the further levels of re-chunked stacked rows
     ld1 = nch * bw
     hi = ld1 * bw - 1
     lrows, off = ld1, ld1 * bw
@@ -159,6 +174,14 @@ def _qr_fused(L):
         lrows = out_rows
     out += [acc(3, 8, 0, hi), acc(4, 4, 0, 0)]
     return out
+
+
+def _sketch_identity(L, T):
+    # (X, ldx, n, ncols, out, ldo)
+    es = 4 if T == "f" else 8
+    ldx, n, ncols, ldo = L.i(1), L.i(2), L.i(3), L.i(5)
+    assert L.grid[0] * L.block[0] >= n * ncols
+    return [acc(0, es, 0, (n - 1) + (ncols - 1) * ldx), acc(4, 8, 0, (n - 1) + (ncols - 1) * ldo)]
 
 
 def _qr_wave(L):
@@ -369,6 +392,7 @@ TEMPLATED = {
     "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),
     "sketch_srht_kernel": lambda L, t: _sketch_srht(L, t[0], t[1]),
     "qr_wave_kernel": lambda L, t: _qr_wave(L),
+    "sketch_identity_kernel": lambda L, t: _sketch_identity(L, t[0]),
 }
 
 

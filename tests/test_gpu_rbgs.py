@@ -133,6 +133,9 @@ def test_well_conditioned_fp64_elementwise(gpu_lib, variant, kind, k):
     (3000, 70, 32, 512, "sparse", "l2qr"),          # 32-wide TSQR over four tree levels
     (4000, 72, 24, 256, "rademacher", "twice"),
     (4097, 75, 24, 256, "sparse", "lowsync"),       # 24-wide blocks: the 32-column update form
+    (6000, 64, 32, 2048, "sparse", "lowsync"),      # QR tree of the sketch: 16 chunks, 4 groups, 2 levels
+    (5000, 72, 24, 1536, "gaussian", "lowsync"),    # ragged groups (5 R factors of 24 rows per chunk)
+    (8192, 40, 32, 8192, "identity", "plain"),      # 64 chunks, three levels of groups
     (9000, 96, 32, 512, "gaussian", "plain"),
     (64, 16, 4, 64, "identity", "l2qr"),
     (300, 20, 6, 300, "identity", "twice"),

@@ -47,6 +47,9 @@ CASES = [
     (5000, 96, 32, 256, GAUSS, F64, 0, LOWSYNC, 2, 1, 1),
     (9000, 40, 16, 2048, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
     (3000, 560, 16, 576, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (6000, 64, 32, 2048, SPARSE, F64, 0, LOWSYNC, 2, 1, 1),
+    (5000, 72, 24, 1536, GAUSS, F64, 0, LOWSYNC, 2, 1, 1),
+    (8192, 40, 32, 8192, 2, F64, 0, PLAIN, 2, 1, 1),
     (4097, 30, 8, 132, RADEM, F64, 0, LOWSYNC, 2, 1, 1),
     (10_000, 64, 8, 256, GAUSS, F32, 1, PLAIN, 2, 1, 1),
 ]
