@@ -182,7 +182,9 @@ RBGS_API rbgs_status rbgs_destroy(rbgs_handle h);
  *        ldq == ldw) factorizes in place; any other overlap is invalid.
  *   R    device, m x m FP64 (ld ldr >= m); upper triangular with positive
  *        diagonal on return; the strictly lower part is set to zero.
- *   S_out device or NULL, k x m FP64 (ld k): the sketch S = Theta Q.
+ *   S_out device or NULL, k x m FP64 (ld k): the sketch S = Theta Q.  (Without
+ *        S_out and cert the sketch of the last block, which only they use, is
+ *        not taken.)
  *   cert host or NULL.  When given, the call also computes Delta and Delta~,
  *        waits for the stream, and returns RBGS_EBREAKDOWN if a diagonal entry
  *        of R is zero or not finite (cert->breakdown_col names it; Q and R are

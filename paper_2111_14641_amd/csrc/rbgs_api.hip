@@ -387,6 +387,7 @@ struct QrRun {
   int64_t* flag;
   unsigned* counters;
   bool pair;     // dense sketches: W_(i+1) sketched together with Q_(i) (rbgs_qr only)
+  bool last_s = true;  // take S_(i) = Theta Q_(i) of the last block (for S_out or certificates)
 };
 
 // Workspace, zeroed R, breakdown flag, sketch plan.  `hoist` says whether all
@@ -640,6 +641,8 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
             "sketch reduction");
     return RBGS_OK;
   }
+  // the sketch of the last block is used only by S_out and the certificates
+  if (!r.last_s && c0 + bw >= m) return RBGS_OK;
   return do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.S + c0 * k, k, r.part, r.plan, st);
 }
 
@@ -690,6 +693,7 @@ rbgs_status rbgs_qr(rbgs_handle h, const void* W, int64_t ldw, int64_t n, int64_
   QrRun r;
   rbgs_status rs = qr_begin(r, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, true);
   if (rs != RBGS_OK) return rs;
+  r.last_s = S_out != nullptr || cert != nullptr;
   for (int64_t c0 = 0; c0 < m; c0 += p) {
     rs = qr_block(r, c0, r.Wb + r.es * (size_t)(c0 * ldw), ldw, false);
     if (rs != RBGS_OK) return rs;
@@ -717,6 +721,7 @@ rbgs_status rbgs_qr_noalloc(rbgs_handle h, const void* W, int64_t ldw, int64_t n
   h->prof_mask = 0;
   QrRun r;
   rs = qr_begin(r, h, W, ldw, n, m, p, sk, opts, Q, ldq, R, ldr, S_out, true, ws, kScratchBytes);
+  r.last_s = S_out != nullptr;
   for (int64_t c0 = 0; rs == RBGS_OK && c0 < m; c0 += p)
     rs = qr_block(r, c0, r.Wb + r.es * (size_t)(c0 * ldw), ldw, false);
   h->prof_mask = mask;

@@ -415,13 +415,22 @@ __global__ __launch_bounds__(256) void resid_batched_kernel(const BatchItem* ite
   resid_body(it.P + K * k, it.S, k, K, it.R + K * it.ldr, it.ldr, it.E, bw, blockIdx.x);
 }
 
+// Arrival of a workgroup at a counter shared with total workgroups; true in
+// the last one to arrive, which then sees every other workgroup's global
+// writes.  Every wave first waits until its own stores have reached the L2;
+// one thread then makes them visible device-wide (release: L2 write-back) and
+// counts, and the last workgroup's waves acquire (L2 invalidate).  A
+// device-scope fence in every wave would write back the L2 once per wave.
 __device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned total) {
   __shared__ bool last;
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == total - 1;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    last = atomicAdd(counter, 1u) == total - 1;
+  }
   __syncthreads();
-  if (last) __threadfence();
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return last;
 }
 

@@ -400,6 +400,29 @@ def test_rank_deficient_in_fp64(gpu_lib, store):
                         "R_(1,1)")
 
 
+@pytest.mark.parametrize("kind,store", [("sparse", "f32"), ("gaussian", "f64"), ("srht", "f32")])
+def test_last_sketch_skipped_without_outputs(gpu_lib, kind, store):
+    """Without S_out and a certificate the sketch of the last block (used by
+    nothing else) is not taken: Q and R are bit for bit those of the call that
+    returns S, which equals the oracle's sketch of the GPU's Q."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    n, m, b, k = 6000, 40, 16, 256
+    W = svd_matrix(n, m, np.logspace(0, -3, m), seed=77)
+    dt = torch.float64 if store == "f64" else torch.float32
+    Wt = B.colmajor(n, m, dt)
+    Wt.copy_(torch.from_numpy(W))
+    Q1, R1, S1, _ = B.rbgs_qr(Wt, b, kind, k, 9, None, "lowsync", 4, want_S=True)
+    Q2, R2, _, _ = B.rbgs_qr(Wt, b, kind, k, 9, None, "lowsync", 4)
+    torch.cuda.synchronize()
+    assert torch.equal(Q1, Q2) and torch.equal(R1, R2)
+    th = Sketch(kind, k, seed=9).materialize(n)
+    Qh = np.asfortranarray(Q1.double().cpu().numpy())
+    So = th(Qh[:, 32:])
+    scale = np.abs(Qh[:, 32:]).sum(axis=0) if kind != "sparse" else np.linalg.norm(Qh[:, 32:], axis=0)
+    assert np.all(np.abs(S1.cpu().numpy()[:, 32:] - So) <= 1e-12 * scale[None, :])
+
+
 @pytest.mark.parametrize("b,m", [(16, 560), (32, 544)])
 def test_update_falls_back_past_lds_capacity(gpu_lib, b, m):
     """Blocks whose K = c0 exceeds the rows of R the persistent update keeps in
