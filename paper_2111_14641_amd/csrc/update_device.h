@@ -1,0 +1,380 @@
+// Device-side bodies of the persistent update form (FP64 arithmetic, the
+// substitution fused), shared by the update kernel and the persistent batch
+// kernel, and the matrix-core and vector helpers of every update form.
+#ifndef RBGS_UPDATE_DEVICE_H
+#define RBGS_UPDATE_DEVICE_H
+
+#include "rbgs_internal.h"
+
+namespace rbgs {
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Matrix-core operations by compute type.  Output layout of the 16x16x4
+// instructions (lane l, accumulator register e, column l % 16):
+//   f32: row 4 (l / 16) + e        f64: row l / 16 + 4 e
+template <typename C>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  typedef float4_t acc_t;
+  __device__ static __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int kk, int e) { return 4 * kk + e; }
+};
+
+template <>
+struct Mfma<double> {
+  typedef double4_t acc_t;
+  __device__ static __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int kk, int e) { return kk + 4 * e; }
+};
+
+template <typename T>
+struct Vec16;  // 16-byte vector of storage elements
+template <>
+struct Vec16<float> {
+  static constexpr int N = 4;
+  typedef f32x4 t;
+};
+template <>
+struct Vec16<double> {
+  static constexpr int N = 2;
+  typedef f64x2 t;
+};
+
+// ---------------------------------------------------------------------------
+// Persistent form for FP64 arithmetic, bw <= 16 NB and K <= UpPShape::MAXK
+// (NB = 1: one 16-column group, four 256-thread workgroups per CU; NB = 2: two
+// groups for blocks of 17..32 columns, one 512-thread workgroup per CU, whose
+// R_(1:i-1,i) fills most of the CU's LDS): each workgroup stages
+// R_(1:i-1,i) in LDS once and walks tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... without further barriers.  The product is formed transposed,
+// (Q R)^T = R^T Q^T (the R entry is the A operand, the Q element the B
+// operand), so lane (kk, li) ends with rows VEC li + v of the wave's strip and
+// columns 16 nb + kk + 4 e: each row is spread over the four lanes
+// (0..3, li).  The forward substitution of steps 4-5 runs on those registers
+// column by column, the solved entry handed across the four lanes by a lane
+// shuffle, so W, the result and the stores stay in registers: no LDS round
+// trip, no epilogue barrier.
+// ---------------------------------------------------------------------------
+constexpr int kUpPMaxK = 512;   // NB = 1: rows of R_(1:i-1,i) held in LDS (64 KB)
+constexpr int kUpP2MaxK = 480;  // NB = 2: 480 x 32 FP64 (120 KB)
+#ifndef RBGS_UP_PUNROLL32
+#define RBGS_UP_PUNROLL32 2
+#endif
+#ifndef RBGS_UP_PUNROLL64
+#define RBGS_UP_PUNROLL64 2
+#endif
+#ifndef RBGS_UP_P2UNROLL
+#define RBGS_UP_P2UNROLL 4      // NB = 2: K-steps of loads issued together
+#endif
+// K-steps of loads issued together (measured for NB = 1)
+template <typename T, int NB = 1>
+struct UpPUnroll {
+  static constexpr int N =
+      NB == 2 ? RBGS_UP_P2UNROLL : (sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64);
+};
+// WV: waves per workgroup (the update kernel: 4 for NB = 1, 8 for NB = 2; the
+// persistent batch kernel: 16)
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+struct UpPShape {
+  static constexpr int VEC = Vec16<T>::N;
+  static constexpr int WAVES = WV;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int TILE = WAVES * 16 * VEC;           // rows per tile
+  static constexpr int NCOL = 16 * NB;
+  static constexpr int MAXK = NB == 1 ? kUpPMaxK : kUpP2MaxK;
+  static constexpr int MINW = NB == 1 ? 4 : 2;            // waves per SIMD asked of the compiler
+};
+
+// Forward substitution of steps 4-5 on the transposed-layout registers
+// acc[v][nb][e] (row VEC li + v, column 16 nb + kk + 4 e), FP64:
+// x_c = q'_c / R_cc (as q'_c (1 / R_cc)), then q'_c' -= x_c R_cc' for c' > c.
+// Column c of this lane's rows sits in lane (c % 4, li), group c / 16,
+// element (c % 16) / 4; it is handed to the lanes holding the other columns of
+// the same rows by a lane shuffle.  Ru holds the strictly upper part of
+// R_(i,i) (column-major, ld 16 NB; zero elsewhere and past bw), so the update
+// needs no mask.
+template <int VEC, int NB>
+__device__ __forceinline__ void p_substitute(double4_t (&acc)[VEC][NB], const double* Ru,
+                                             const double* Rinv, int bw, int kk, int li) {
+  constexpr int NCOL = 16 * NB;
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    if (c < bw) {
+      const int nbc = c >> 4, kc = c & 3, ec = (c & 15) >> 2;
+      const double rinv = Rinv[c];
+      double xb[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) xb[v] = __shfl(acc[v][nbc][ec] * rinv, 16 * kc + li, 64);
+      if (kk == kc) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v][nbc][ec] = xb[v];
+      }
+      // columns below c in every lane (earlier groups, e < ec) need nothing
+#pragma unroll
+      for (int nb = nbc; nb < NB; ++nb) {
+        double ru[4];
+#pragma unroll
+        for (int e = (nb == nbc ? ec : 0); e < 4; ++e) ru[e] = Ru[c + NCOL * (16 * nb + kk + 4 * e)];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+#pragma unroll
+          for (int e = (nb == nbc ? ec : 0); e < 4; ++e) acc[v][nb][e] = fma(-xb[v], ru[e], acc[v][nb][e]);
+      }
+    }
+  }
+}
+
+// One tile with guarded element loads and stores (rows >= n are neither read
+// nor written; any alignment).  Same arithmetic as update_p_full_tiles.
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+__device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
+                                                      const T* __restrict__ Q, int64_t ldq,
+                                                      T* Qout, int64_t ldqo, const double* Rs,
+                                                      const double* Ru, const double* Rinv,
+                                                      bool subst, int64_t tile0, int64_t n,
+                                                      int K, int bw) {
+  typedef Mfma<double> M;
+  typedef UpPShape<T, NB, WV> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int WROWS = 16 * VEC;
+  constexpr int NCOL = Sh::NCOL;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t arow = tile0 + (int64_t)wave * WROWS + (int64_t)VEC * li;  // this lane's rows
+  const int bwc = bw - 1;
+
+  // The accumulators start at -W_(i) (transposed layout: acc[v][nb][e] holds
+  // row arow + v, column 16 nb + kk + 4 e), so W is not held through the
+  // product; its loads are issued together with the first group of Q.
+  constexpr int kUnroll = UpPUnroll<T, NB>::N;
+  constexpr int GS = 4 * kUnroll;
+  auto load_group = [&](T (&a)[kUnroll][VEC], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      int col = ks0 + 4 * u + kk;
+      col = col < K ? col : K - 1;  // padded steps are skipped
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const bool in = arow + v < n;
+        const T x = Q[(in ? arow + v : n - 1) + (int64_t)col * ldq];
+        a[u][v] = in ? x : (T)0;
+      }
+    }
+  };
+  M::acc_t acc[VEC][NB];
+  auto mma_group = [&](const T (&a)[kUnroll][VEC], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ks0 + 4 * u < K) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          // R[ks + kk][16 nb + li] = R^T[li][ks + kk]
+          const double b = Rs[(ks0 + 4 * u + kk) * NCOL + 16 * nb + li];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
+        }
+      }
+    }
+  };
+  T a0[kUnroll][VEC], a1[kUnroll][VEC];
+  {
+    T w[NB][4][VEC];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool in = arow + v < n;
+          const T x = W[(in ? arow + v : n - 1) + (int64_t)c * ldw];
+          w[nb][e][v] = in ? x : (T)0;
+        }
+      }
+    if (K > 0) load_group(a0, 0);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v][nb] = (M::acc_t){-(double)w[nb][0][v], -(double)w[nb][1][v], -(double)w[nb][2][v],
+                                -(double)w[nb][3][v]};
+  }
+  for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
+    if (ks0 + GS < K) load_group(a1, ks0 + GS);
+    mma_group(a0, ks0);
+    if (ks0 + GS < K) {
+      if (ks0 + 2 * GS < K) load_group(a0, ks0 + 2 * GS);
+      mma_group(a1, ks0 + GS);
+    }
+  }
+  // step 3: acc = Q R - W = -Q'_(i) (FP64)
+#pragma unroll
+  for (int v = 0; v < VEC; ++v)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+  if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = 16 * nb + kk + 4 * e;
+      if (c < bw) {
+        T* dst = Qout + arow + (int64_t)c * ldqo;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if (arow + v < n) dst[v] = (T)acc[v][nb][e];
+      }
+    }
+}
+
+// The full tiles of one workgroup (tile = first, first + stride, .. < nfull),
+// software-pipelined across tiles: the W vectors and the first group of Q of
+// the next tile are loaded before the substitution and stores of the current
+// one, so the wait for them does not also wait for those stores (stores share
+// the vector-memory counter on this target).  Same arithmetic, in the same
+// order, as update_p_guarded_tile.
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+__device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
+                                                    const T* __restrict__ Q, int64_t ldq,
+                                                    T* Qout, int64_t ldqo, const double* Rs,
+                                                    const double* Ru, const double* Rinv,
+                                                    bool subst, int64_t first, int64_t stride,
+                                                    int64_t nfull, int K, int bw) {
+  typedef Mfma<double> M;
+  typedef UpPShape<T, NB, WV> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int WROWS = 16 * VEC;
+  constexpr int TILE = Sh::TILE;
+  constexpr int NCOL = Sh::NCOL;
+  typedef typename Vec16<T>::t VT;
+  constexpr int kUnroll = UpPUnroll<T, NB>::N;
+  constexpr int GS = 4 * kUnroll;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;  // row of this lane in a tile
+  const int bwc = bw - 1;
+
+  auto load_w = [&](VT (&wv)[NB][4], int64_t arow) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc;
+        wv[nb][e] = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
+      }
+  };
+  auto load_group = [&](VT (&a)[kUnroll], int64_t arow, int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      int col = ks0 + 4 * u + kk;
+      col = col < K ? col : K - 1;
+      a[u] = *reinterpret_cast<const VT*>(Q + arow + (int64_t)col * ldq);
+    }
+  };
+  M::acc_t acc[VEC][NB];
+  auto mma_group = [&](const VT (&a)[kUnroll], int ks0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (ks0 + 4 * u < K) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const double b = Rs[(ks0 + 4 * u + kk) * NCOL + 16 * nb + li];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
+        }
+      }
+    }
+  };
+
+  int64_t tile = first;
+  if (tile >= nfull) return;
+  VT wv[NB][4], a0[kUnroll], a1[kUnroll];
+  load_w(wv, tile * TILE + roff);
+  if (K > 0) load_group(a0, tile * TILE + roff, 0);
+  for (;;) {
+    const int64_t arow = tile * TILE + roff;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v][nb] = (M::acc_t){-(double)wv[nb][0][v], -(double)wv[nb][1][v],
+                                -(double)wv[nb][2][v], -(double)wv[nb][3][v]};
+    for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
+      if (ks0 + GS < K) load_group(a1, arow, ks0 + GS);
+      mma_group(a0, ks0);
+      if (ks0 + GS < K) {
+        if (ks0 + 2 * GS < K) load_group(a0, arow, ks0 + 2 * GS);
+        mma_group(a1, ks0 + GS);
+      }
+    }
+    const int64_t next = tile + stride;
+    const bool more = next < nfull;
+    if (more) {
+      load_w(wv, next * TILE + roff);
+      if (K > 0) load_group(a0, next * TILE + roff, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+    if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e;
+        if (c < bw) {
+          VT vv;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
+          *reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo) = vv;
+        }
+      }
+    if (!more) break;
+    tile = next;
+  }
+}
+
+// Stages the factors of block i in LDS for the persistent form (NCOL = 16 NB
+// columns, NT threads): Rs [Kp][NCOL] = R_(1:i-1,i) (rows >= K and columns >=
+// bw zero); with Rii given, Ru [NCOL][NCOL] (column-major) = the strictly upper
+// part of R_(i,i), zero past bw, and Rinv [NCOL] = 1 / R_cc (1 past bw).  FP64.
+// Every load is unconditional (clamped index).  The caller synchronizes.
+template <int NCOL, int NT>
+__device__ __forceinline__ void update_p_stage(const double* __restrict__ Rk,
+                                               const double* __restrict__ Rii, int64_t ldr, int K,
+                                               int Kp, int bw, double* Rs, double* Ru,
+                                               double* Rinv) {
+  for (int e = threadIdx.x; e < Kp * NCOL; e += NT) {
+    const int r = e / NCOL, c = e % NCOL;
+    const bool in = r < K && c < bw;
+    const double v = Rk[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
+    Rs[e] = in ? v : 0.0;
+  }
+  if (Rii != nullptr) {
+    for (int e = threadIdx.x; e < NCOL * NCOL; e += NT) {
+      const int r = e % NCOL, c = e / NCOL;
+      const bool in = r < c && c < bw;
+      const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
+      Ru[e] = in ? v : 0.0;
+    }
+    if (threadIdx.x < NCOL) {
+      const int c = threadIdx.x;
+      Rinv[c] = c < bw ? 1.0 / Rii[c + (int64_t)c * ldr] : 1.0;
+    }
+  }
+}
+
+}  // namespace rbgs
+
+#endif  // RBGS_UPDATE_DEVICE_H
