@@ -240,27 +240,46 @@ typedef struct {
   int32_t reserved;
 } rbgs_problem;
 
+/* Flags of rbgs_qr_batched. */
+#define RBGS_BATCH_GRAPH 1
+#define RBGS_BATCH_PERSISTENT 2
+
 /* Independent RBGS QR factorizations (Algorithm RBGS of Section 2) of a batch
  * of problems with their own n, m, p and k.
  *   probs host, `count` problems.  Problem i uses the sketch (sk->kind,
  *         sk->zeta, seed sk->seed + i, its own k); sk->k is ignored.
  *   opts  host; store, math, variant and ls_iters apply to every problem; the
  *         batch is enqueued on opts->stream.
- *   graph 1: the first call with a given batch (same pointers, sizes, options)
- *         runs it and records the whole enqueue sequence as a HIP graph; a later
- *         call with the identical batch launches that graph, one launch for the
- *         batch.  The graph reads W at run time, so W may change between calls.
- *         0: no graph.
- * Problems that share m, p and k (low-sync form, sparse sign, p <= 32,
- * k <= 2048; two or more of them) run in lock step on opts->stream: block by
- * block, one launch per kernel and block step for the whole group, from a
- * device array of per-problem descriptors and workspaces in the handle's
- * batch arena (laid out, uploaded and -- if an earlier batch may still use
- * it -- waited for on the host before anything is enqueued).  The other
- * problems are spread over four internal streams (largest first, each to the
- * least loaded stream), joined back to opts->stream.  A call that lays the
- * arena out again drops the recorded graph.  Problems with p or k equal to 0
- * are tuned first (rbgs_autotune, which waits for the device).
+ *   graph RBGS_BATCH_GRAPH: the first call with a given batch (same pointers,
+ *         sizes, options, flags) runs it and records the whole enqueue
+ *         sequence as a HIP graph; a later call with the identical batch
+ *         launches that graph, one launch for the batch.  The graph reads W at
+ *         run time, so W may change between calls.
+ *         RBGS_BATCH_PERSISTENT (may be combined with RBGS_BATCH_GRAPH): every
+ *         problem the persistent queue takes (FP32 storage, FP64 arithmetic,
+ *         low-sync form, sparse sign with zeta <= 8, p <= 32, k <= 1024, and
+ *         (K_last + 3) / 4 * 4 * w + w * w + w <= 18432 with K_last the columns
+ *         before the last block and w = 16 for p <= 16, 32 otherwise) runs in
+ *         ONE launch of one workgroup per compute unit that works through a
+ *         device queue of the problems' stages (plan of Theta, sketch of W and
+ *         its reduction, then per block the small factors, the update, the
+ *         sketch of Q_(i) and its reduction), after an initialisation launch;
+ *         stages of different problems run at the same time.  The call then
+ *         waits for opts->stream and returns RBGS_EDEVICE if the queue did not
+ *         drain (a workgroup waited more than 4 s for a stage; no such wait is
+ *         expected).  Calls that overlap on one handle race.
+ *         0: no graph, lock-step groups.
+ * Without RBGS_BATCH_PERSISTENT, problems that share m, p and k (low-sync
+ * form, sparse sign, p <= 32, k <= 2048; two or more of them) run in lock step
+ * on opts->stream: block by block, one launch per kernel and block step for
+ * the whole group, from a device array of per-problem descriptors and
+ * workspaces in the handle's batch arena (laid out, uploaded and -- if an
+ * earlier batch may still use it -- waited for on the host before anything is
+ * enqueued).  The other problems are spread over four internal streams
+ * (largest first, each to the least loaded stream), joined back to
+ * opts->stream.  A call that lays the arena out again drops the recorded
+ * graph.  Problems with p or k equal to 0 are tuned first (rbgs_autotune,
+ * which waits for the device).
  * Every problem is validated before anything is enqueued: on an invalid
  * problem the call returns RBGS_EINVAL (or RBGS_EUNSUPPORTED) with that
  * problem's status set and enqueues nothing.  No certificate is computed. */

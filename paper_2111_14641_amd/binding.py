@@ -18,6 +18,7 @@ RBGS_OK, RBGS_EINVAL, RBGS_ENOMEM, RBGS_EDEVICE, RBGS_EBREAKDOWN, RBGS_ENOTCONV,
 # rbgs_store / rbgs_math / rbgs_sketch_kind / rbgs_variant
 STORE = {"f64": 0, "f32": 1}
 MATH = {"f64": 0, "f32": 1, "bf16x3": 2}
+RBGS_BATCH_GRAPH, RBGS_BATCH_PERSISTENT = 1, 2   # flags of rbgs_qr_batched
 SKETCH = {"gaussian": 0, "sparse": 1, "identity": 2, "rademacher": 3, "srht": 4}
 VARIANT = {"plain": 0, "lowsync": 1, "twice": 2, "l2qr": 3}
 PROFILE = {"update": 0, "sketch": 1, "reduce": 2, "small": 3, "trsm": 4}
@@ -271,10 +272,12 @@ def rbgs_qr(W, p, kind="sparse", k=None, seed=0, zeta=None, variant="lowsync", l
 
 
 def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=None, variant="lowsync",
-                    ls_iters=4, Qs=None, Rs=None, math="f64", graph=False):
+                    ls_iters=4, Qs=None, Rs=None, math="f64", graph=False, persistent=False):
     """Independent RBGS QRs of column-major CUDA tensors Ws (same dtype and
     device) in one call; problem i uses sketch seed `seed + i`.  ps / ks: block
-    widths and sketch sizes per problem (None or 0 = autotuned).
+    widths and sketch sizes per problem (None or 0 = autotuned).  persistent:
+    the problems the persistent queue takes run in one launch (the call then
+    waits for the device).
 
     Returns (Qs, Rs, ps, ks) with the block widths and sketch sizes used."""
     torch = _torch()
@@ -301,7 +304,9 @@ def rbgs_qr_batched(Ws, ps=None, ks=None, kind="sparse", seed=0, zeta=None, vari
         arr[i] = rbgs_problem(wp, ldw, W.shape[0], W.shape[1], qp, ldq, rp, ldr, p, k, 0, 0)
     sk = make_sketch(kind, 0, seed, zeta)
     opts = rbgs_opts(STORE[store], MATH[math], VARIANT[variant], int(ls_iters), _stream_ptr(Ws[0]))
-    st = lib.rbgs_qr_batched(h, count, arr, sk, opts, 1 if graph else 0)
+    st = lib.rbgs_qr_batched(h, count, arr, sk, opts,
+                             (RBGS_BATCH_GRAPH if graph else 0) |
+                             (RBGS_BATCH_PERSISTENT if persistent else 0))
     lib.check(st, h)
     return Qs, Rs, [arr[i].p for i in range(count)], [arr[i].k for i in range(count)]
 

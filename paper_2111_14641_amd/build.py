@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "librbgs.so")
 ARCH = "gfx950"
 
 SOURCES = ["rbgs_api.hip", "sketch_kernels.hip", "update_kernels.hip", "small_kernels.hip",
-           "krylov_kernels.hip", "post_kernels.hip"]
+           "krylov_kernels.hip", "post_kernels.hip", "batch_kernels.hip"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form
 # v_pk_* FP32 operations from scalar code.

@@ -54,9 +54,11 @@ struct rbgs_handle_s {
   size_t kry_bytes = 0;
   // autotuner: (m, ceil log2 n, store, math, kind, variant) -> (p, k)
   std::vector<std::pair<std::vector<int64_t>, std::pair<int64_t, int64_t>>> tuned;
-  // lock-step batches: workspace of every problem and the device descriptors
+  // lock-step and persistent batches: workspace of every problem and the
+  // device descriptors
   void* bws = nullptr;
   size_t bws_bytes = 0;
+  PbCtl* pb_ctl = nullptr;  // control word of the last persistent batch (in bws)
 };
 
 namespace {
@@ -771,6 +773,26 @@ double batch_bytes(const rbgs_problem& pr, size_t es) {
   return tot;
 }
 
+// Grows the batch arena to `bytes` (waiting for the device and dropping the
+// old contents when it must move).
+rbgs_status arena_reserve(rbgs_handle h, size_t bytes) {
+  if (bytes <= h->bws_bytes) return RBGS_OK;
+  if (h->bws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->bws);
+    h->bws = nullptr;
+    h->bws_bytes = 0;
+    h->pb_ctl = nullptr;
+  }
+  if (hipMalloc(&h->bws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    h->bws = nullptr;
+    return fail(h, RBGS_ENOMEM, "batch workspace of " + std::to_string(bytes) + " bytes");
+  }
+  h->bws_bytes = bytes;
+  return RBGS_OK;
+}
+
 // Enqueue every problem on its lane; lanes fork from and join back to st.
 // ---------------------------------------------------------------------------
 // Lock-step groups: problems with the same m, p and k (low-sync form, sparse
@@ -887,20 +909,9 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
       offs[gi].insert(offs[gi].end(), o.begin(), o.end());
     }
   }
-  if (off > h->bws_bytes) {
-    if (h->bws) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(h->bws);
-      h->bws = nullptr;
-      h->bws_bytes = 0;
-    }
-    if (hipMalloc(&h->bws, off) != hipSuccess) {
-      (void)hipGetLastError();
-      h->bws = nullptr;
-      return fail(h, RBGS_ENOMEM, "batch workspace of " + std::to_string(off) + " bytes");
-    }
-    h->bws_bytes = off;
-  }
+  h->pb_ctl = nullptr;
+  const rbgs_status rs = arena_reserve(h, off);
+  if (rs != RBGS_OK) return rs;
   char* base = (char*)h->bws;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     LockGroup& g = groups[gi];
@@ -928,6 +939,186 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
     HIP_TRY(h, hipMemcpy(g.items, host[gi].data(), sizeof(BatchItem) * np, hipMemcpyHostToDevice),
             "upload batch descriptors");
   }
+  return RBGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batch: every problem it can take (FP32 storage, FP64
+// arithmetic, low-sync form, sparse sign, p <= 32, k <= 1024, the factors of
+// the last block within the kernel's LDS) runs in one launch that works
+// through a device queue of stages (batch_kernels.hip).  The descriptors, the
+// queue and every problem's workspace live in the batch arena.
+// ---------------------------------------------------------------------------
+struct PersistBatch {
+  std::vector<int64_t> idx;  // problem indices
+  PbProb* probs = nullptr;   // device arrays in the arena
+  int32_t* order = nullptr;
+  PbStage* stages = nullptr;
+  unsigned *claimed = nullptr, *finished = nullptr, *valid = nullptr;
+  PbCtl* ctl = nullptr;
+  unsigned total = 0;
+  int64_t max_mm = 0;
+};
+
+bool persist_ok(const rbgs_problem& pr, const rbgs_sketch* sk, const rbgs_opts* opts) {
+  if (opts->variant != RBGS_VARIANT_LOWSYNC || sk->kind != RBGS_SKETCH_SPARSE_SIGN ||
+      opts->store != RBGS_STORE_F32 || opts->math != RBGS_MATH_F64 || sk->zeta > 8)
+    return false;
+  if (pr.p > kPbMaxP || pr.k > kPbMaxK) return false;
+  const int64_t last_c0 = ((pr.m - 1) / pr.p) * pr.p;  // columns before the last block
+  return pb_update_lds(last_c0, pr.p) <= kPbLdsBytes;
+}
+
+bool aligned16(const void* ptr, int64_t ld) {
+  return (reinterpret_cast<uintptr_t>(ptr) % 16) == 0 && ld % 4 == 0;
+}
+
+// Arena layout and descriptor upload (waits for the copy).
+rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* probs,
+                          const rbgs_sketch* sk, const rbgs_opts* opts, PersistBatch& pb,
+                          std::vector<int64_t>& rest) {
+  pb = PersistBatch();
+  rest.clear();
+  h->pb_ctl = nullptr;
+  for (int64_t i = 0; i < count; ++i)
+    (persist_ok(probs[i], sk, opts) ? pb.idx : rest).push_back(i);
+  if (pb.idx.empty()) return RBGS_OK;
+  if ((int64_t)pb.idx.size() >= 65535)
+    return fail(h, RBGS_EUNSUPPORTED, "persistent batch of more than 65534 problems");
+  if (h->bws) HIP_TRY(h, hipDeviceSynchronize(), "synchronize before batch setup");
+  const int64_t np = (int64_t)pb.idx.size();
+  auto r256 = [](size_t bytes) { return ((bytes + 255) / 256) * 256; };
+  std::vector<PbProb> host(np);
+  std::vector<size_t> offs;  // per problem: S, P, E, G, Cb, Yb, part, flag, plan
+  size_t off = 0;
+  const size_t o_probs = off;
+  off += r256(sizeof(PbProb) * np);
+  const size_t o_order = off;
+  off += r256(sizeof(int32_t) * np);
+  int64_t total = 0;
+  for (int64_t q = 0; q < np; ++q) total += pb_stage_count(probs[pb.idx[q]].m, probs[pb.idx[q]].p);
+  if (total >= (int64_t)1 << 31) return fail(h, RBGS_EUNSUPPORTED, "persistent batch too large");
+  const size_t o_stages = off;
+  off += r256(sizeof(PbStage) * total);
+  const size_t o_claimed = off;
+  off += r256(sizeof(unsigned) * total);
+  const size_t o_finished = off;
+  off += r256(sizeof(unsigned) * total);
+  const size_t o_valid = off;
+  off += r256(sizeof(unsigned) * total);
+  const size_t o_ctl = off;
+  off += r256(sizeof(PbCtl));
+  std::vector<double> work(np);
+  for (int64_t q = 0; q < np; ++q) {
+    const int64_t i = pb.idx[q];
+    const rbgs_problem& pr = probs[i];
+    rbgs_sketch ski = *sk;
+    ski.k = pr.k;
+    ski.seed = sk->seed + (uint64_t)i;
+    const SketchDesc d = make_desc(&ski, pr.n);
+    PbProb& P = host[q];
+    memset(&P, 0, sizeof P);
+    P.W = (const float*)pr.W;
+    P.Q = (float*)pr.Q;
+    P.R = pr.R;
+    P.n = pr.n;
+    P.ldw = pr.ldw;
+    P.ldq = pr.ldq;
+    P.ldr = pr.ldr;
+    P.key0 = d.key0;
+    P.key1 = d.key1;
+    P.m = (int32_t)pr.m;
+    P.p = (int32_t)pr.p;
+    P.k = (int32_t)pr.k;
+    P.nb = (int32_t)((pr.m + pr.p - 1) / pr.p);
+    const int64_t tiles = sparse_plan_tiles(pr.n);
+    P.plan_tiles = (int32_t)tiles;
+    const int64_t tpw = (tiles + kPbSkG - 1) / kPbSkG;
+    P.sk_tpw = (int32_t)tpw;
+    P.sk_G = (int32_t)((tiles + tpw - 1) / tpw);
+    const int64_t rows = pr.p <= 16 ? kPbTileRows : kPbTileRows / 2;
+    P.up_tiles = (int32_t)((pr.n + rows - 1) / rows);
+    P.up_nfull = aligned16(pr.W, pr.ldw) && aligned16(pr.Q, pr.ldq) ? (int32_t)(pr.n / rows) : 0;
+    pb.max_mm = std::max<int64_t>(pb.max_mm, pr.m * pr.m);
+    work[q] = batch_bytes(pr, 4);
+    const int64_t m = pr.m, k = pr.k, b = pr.p;
+    for (size_t doubles : {(size_t)(k * m), (size_t)(k * m), (size_t)(k * b), (size_t)(m * m),
+                           (size_t)(m * b), (size_t)(m * b), (size_t)(P.sk_G * k * m), (size_t)1}) {
+      offs.push_back(off);
+      off += r256(doubles * 8);
+    }
+    offs.push_back(off);
+    off += r256(sparse_plan_bytes(d, pr.n));
+    offs.push_back((size_t)plan_offsets_len(d, pr.n));  // entry offset (elements)
+  }
+  rbgs_status rs = arena_reserve(h, off);
+  if (rs != RBGS_OK) return rs;
+  char* base = (char*)h->bws;
+  for (int64_t q = 0; q < np; ++q) {
+    PbProb& P = host[q];
+    const size_t* o = &offs[q * 10];
+    P.S = (double*)(base + o[0]);
+    P.P = (double*)(base + o[1]);
+    P.E = (double*)(base + o[2]);
+    P.G = (double*)(base + o[3]);
+    P.Cb = (double*)(base + o[4]);
+    P.Yb = (double*)(base + o[5]);
+    P.part = (double*)(base + o[6]);
+    P.flag = (int64_t*)(base + o[7]);
+    P.plan_off = (uint16_t*)(base + o[8]);
+    P.plan_ent = P.plan_off + o[9];
+  }
+  // the first stage of the largest problem is taken first
+  std::vector<int32_t> order(np);
+  for (int64_t q = 0; q < np; ++q) order[q] = (int32_t)q;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+  pb.probs = (PbProb*)(base + o_probs);
+  pb.order = (int32_t*)(base + o_order);
+  pb.stages = (PbStage*)(base + o_stages);
+  pb.claimed = (unsigned*)(base + o_claimed);
+  pb.finished = (unsigned*)(base + o_finished);
+  pb.valid = (unsigned*)(base + o_valid);
+  pb.ctl = (PbCtl*)(base + o_ctl);
+  pb.total = (unsigned)total;
+  HIP_TRY(h, hipMemcpy(pb.probs, host.data(), sizeof(PbProb) * np, hipMemcpyHostToDevice),
+          "upload batch descriptors");
+  HIP_TRY(h, hipMemcpy(pb.order, order.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice),
+          "upload batch order");
+  h->pb_ctl = pb.ctl;
+  return RBGS_OK;
+}
+
+rbgs_status enqueue_persistent(rbgs_handle h, const PersistBatch& pb, const rbgs_sketch* sk,
+                               const rbgs_opts* opts, hipStream_t st) {
+  int cus = 0, rate_khz = 0;
+  HIP_TRY(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device),
+          "compute unit count");
+  HIP_TRY(h, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, h->device),
+          "wall clock rate");
+  // every wait of a workgroup: at most 4 s (a stage takes milliseconds)
+  const uint64_t limit = (uint64_t)std::max(rate_khz, 1) * 4000ull;
+  HIP_TRY(h, launch_persistent_batch(pb.probs, pb.order, (int)pb.idx.size(), pb.max_mm, pb.stages,
+                                     pb.claimed, pb.finished, pb.valid, pb.ctl, pb.total,
+                                     (int)sk->zeta, (int)opts->ls_iters, limit, cus, st),
+          "persistent batch");
+  return RBGS_OK;
+}
+
+// Waits for st and reads the persistent queue's control word.
+rbgs_status persist_check(rbgs_handle h, hipStream_t st) {
+  if (!h->pb_ctl) return RBGS_OK;
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  HIP_TRY(h, hipMemcpyAsync(h->host_cert, h->pb_ctl, sizeof(PbCtl), hipMemcpyDeviceToHost, st),
+          "copy queue state");
+  HIP_TRY(h, hipStreamSynchronize(st), "persistent batch");
+  PbCtl c;
+  memcpy(&c, h->host_cert, sizeof c);
+  if (c.error == 1u)
+    return fail(h, RBGS_EDEVICE, "persistent batch: a workgroup waited too long for a stage");
+  if (c.error != 0u) return fail(h, RBGS_EDEVICE, "persistent batch: queue overflow");
+  if (c.head != c.tail)
+    return fail(h, RBGS_EDEVICE, "persistent batch: " + std::to_string(c.tail - c.head) +
+                                     " stages left in the queue");
   return RBGS_OK;
 }
 
@@ -971,7 +1162,7 @@ rbgs_status enqueue_group(rbgs_handle h, const LockGroup& g, const rbgs_sketch* 
 rbgs_status enqueue_batch(rbgs_handle h, int64_t count, rbgs_problem* probs,
                           const rbgs_sketch* sk, const rbgs_opts* opts,
                           const std::vector<std::vector<int64_t>>& lane_items,
-                          const std::vector<LockGroup>& groups) {
+                          const std::vector<LockGroup>& groups, const PersistBatch& pb) {
   hipStream_t st = (hipStream_t)opts->stream;
   const int L = (int)lane_items.size();
   if (L > 0) HIP_TRY(h, hipEventRecord(h->lane_ev[L], st), "event record");
@@ -996,6 +1187,11 @@ rbgs_status enqueue_batch(rbgs_handle h, int64_t count, rbgs_problem* probs,
     const rbgs_status rs = enqueue_group(h, g, sk, opts, st);
     if (rs != RBGS_OK) return rs;
     for (int64_t i : g.idx) probs[i].status = RBGS_OK;
+  }
+  if (!pb.idx.empty()) {
+    const rbgs_status rs = enqueue_persistent(h, pb, sk, opts, st);
+    if (rs != RBGS_OK) return rs;
+    for (int64_t i : pb.idx) probs[i].status = RBGS_OK;
   }
   for (int l = 0; l < L; ++l) {
     HIP_TRY(h, hipEventRecord(h->lane_ev[l], h->lane_streams[l]), "event record");
@@ -1110,7 +1306,8 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   if (!h) return RBGS_EINVAL;
   h->last_error.clear();
   if (count < 1 || !probs || !sk || !opts) return fail(h, RBGS_EINVAL, "empty batch or NULL argument");
-  if (graph != 0 && graph != 1) return fail(h, RBGS_EINVAL, "graph must be 0 or 1");
+  if (graph < 0 || graph > 3) return fail(h, RBGS_EINVAL, "graph must be 0, 1, 2 or 3");
+  const bool persistent = (graph & 2) != 0;
   // tune the problems that ask for it, then validate every problem
   for (int64_t i = 0; i < count; ++i) {
     rbgs_problem& pr = probs[i];
@@ -1147,9 +1344,9 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   DeviceGuard guard(h->device);
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)opts->stream;
-  const bool use_graph = graph == 1 && st != nullptr;
+  const bool use_graph = (graph & 1) != 0 && st != nullptr;
   std::vector<int64_t> key = {count, opts->store, opts->math, opts->variant, opts->ls_iters,
-                              (int64_t)(intptr_t)st, sk->kind, sk->zeta, (int64_t)sk->seed};
+                              (int64_t)(intptr_t)st, sk->kind, sk->zeta, (int64_t)sk->seed, graph};
   for (int64_t i = 0; i < count; ++i) {
     const rbgs_problem& pr = probs[i];
     for (int64_t v : {(int64_t)(intptr_t)pr.W, pr.ldw, pr.n, pr.m, (int64_t)(intptr_t)pr.Q, pr.ldq,
@@ -1159,7 +1356,7 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   if (use_graph && h->graph_exec && key == h->graph_key) {
     HIP_TRY(h, hipGraphLaunch(h->graph_exec, st), "hipGraphLaunch");
     for (int64_t i = 0; i < count; ++i) probs[i].status = RBGS_OK;
-    return RBGS_OK;
+    return persistent ? persist_check(h, st) : RBGS_OK;
   }
   // a recorded graph refers to the batch arena, which the setup below lays out anew
   if (h->graph_exec) {
@@ -1174,7 +1371,9 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   // lock-step groups on the caller's stream; the other problems on the lanes
   std::vector<LockGroup> groups;
   std::vector<int64_t> rest;
-  rbgs_status rs = lockstep_setup(h, count, probs, sk, opts, groups, rest);
+  PersistBatch pb;
+  rbgs_status rs = persistent ? persist_setup(h, count, probs, sk, opts, pb, rest)
+                              : lockstep_setup(h, count, probs, sk, opts, groups, rest);
   if (rs != RBGS_OK) return rs;
   // largest problem first, each to the least loaded lane
   const int L = (int)std::min<int64_t>(kBatchLanes, (int64_t)rest.size());
@@ -1192,7 +1391,8 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
     lane_items[l].push_back(i);
     load[l] += batch_bytes(probs[i], es);
   }
-  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups);
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups, pb);
+  if (rs == RBGS_OK && !pb.idx.empty()) rs = persist_check(h, st);
   if (rs != RBGS_OK || !use_graph) return rs;
   // record the same enqueue sequence as a graph for later identical calls
   if (h->graph_exec) {
@@ -1205,7 +1405,7 @@ rbgs_status rbgs_qr_batched(rbgs_handle h, int64_t count, rbgs_problem* probs,
   }
   h->graph_key.clear();
   HIP_TRY(h, hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups);
+  rs = enqueue_batch(h, count, probs, sk, opts, lane_items, groups, pb);
   hipGraph_t g = nullptr;
   const hipError_t ce = hipStreamEndCapture(st, &g);
   if (rs != RBGS_OK) {

@@ -266,6 +266,61 @@ hipError_t launch_qr_batched(const BatchItem* items, int nprob, int64_t k, int b
 hipError_t launch_update_batched(bool f32, int math, const BatchItem* items, int nprob,
                                  int64_t total_tiles, int64_t K, int bw, hipStream_t st);
 hipError_t launch_init_batched(const BatchItem* items, int nprob, int64_t m, hipStream_t st);
+// ---------------------------------------------------------------------------
+// Persistent batch: one launch runs a device queue of stages (plan, sketch of
+// W, its reduction, and per block the small factors, the update, the sketch
+// of Q_(i) and its reduction) for every problem of a batch; FP32 storage,
+// FP64 arithmetic, low-synchronization form, sparse sign.
+// ---------------------------------------------------------------------------
+constexpr int kPbThreads = 1024;            // threads per workgroup (one per CU)
+constexpr int kPbMaxK = 1024;               // sketch rows
+constexpr int kPbMaxP = 32;                 // block width
+constexpr int kPbLdsBytes = 144 * 1024;     // LDS pool shared by the stages
+constexpr int kPbTileRows = 1024;           // rows per update tile for p <= 16 (half for p > 16)
+constexpr int kPbSkG = 16;                  // row groups of a sketch, at most
+
+// Stage kinds, in the order they follow one another for one problem.
+enum PbKind : int32_t { kPbPlan = 0, kPbWsk, kPbRedw, kPbSmall, kPbUpd, kPbQsk, kPbReds };
+
+struct PbProb {
+  const float* W;
+  float* Q;
+  double *R, *S, *P, *E, *G, *Cb, *Yb, *part;
+  int64_t* flag;
+  uint16_t* plan_off;
+  uint16_t* plan_ent;
+  int64_t n, ldw, ldq, ldr;
+  uint32_t key0, key1;
+  int32_t m, p, k, nb;        // nb = ceil(m / p) blocks
+  int32_t plan_tiles;         // tiles of kSpTile rows
+  int32_t sk_G, sk_tpw;       // sketch row groups and tiles per group
+  int32_t up_tiles, up_nfull; // update tiles (kPbTileRows rows, half for p > 16)
+                              // and those on the vector path
+};
+struct PbStage {
+  int32_t prob, kind, block, nitems;
+};
+struct PbCtl {
+  unsigned head, tail, error, pad;
+};
+// Stages of one problem with m columns and block width p.
+inline int64_t pb_stage_count(int64_t m, int64_t p) { return 4 * ((m + p - 1) / p) + 1; }
+// LDS bytes the update of a block of width bw after K columns needs.
+inline int64_t pb_update_lds(int64_t K, int64_t bw) {
+  const int64_t ncol = bw <= 16 ? 16 : 32, Kp = (K + 3) / 4 * 4;
+  return (Kp * ncol + ncol * ncol + ncol) * 8;
+}
+// Initializes the queue (the first stage of problem order[i] in slot i) and,
+// per problem, R = 0 and the breakdown flag; then runs the queue.  Both on st;
+// no host synchronization.  `limit` bounds every wait of a workgroup, in
+// ticks of the device's constant-rate clock (on expiry ctl->error = 1 and the
+// workgroups leave).
+hipError_t launch_persistent_batch(const PbProb* probs, const int32_t* order, int nprob,
+                                   int64_t max_mm, PbStage* stages, unsigned* claimed,
+                                   unsigned* finished, unsigned* valid, PbCtl* ctl,
+                                   unsigned total, int zeta, int ls_iters, uint64_t limit,
+                                   int grid, hipStream_t st);
+
 // rows per update tile (for the flattened prefix) and the unguarded tile count
 int64_t update_tile_rows(bool f32);
 bool update_vec_ok(bool f32, const void* Q, int64_t ldq);

@@ -241,11 +241,16 @@ __device__ __forceinline__ void qr_wave_body(const double* __restrict__ src, int
     for (int q = 0; q < CPW; ++q) right |= w + 16 * q > j && w + 16 * q < bw;
     if (right && beta != 0.0) {
       // rows lane + 64 i with i >= 1 are >= 64 > j: only i = 0 needs the mask
-      double v[RPT];
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
+      auto vi = [&](int i) {
         const double x = xj[lane + 64 * i];
-        v[i] = i > 0 ? x : (lane < j ? 0.0 : (lane == j ? v0 : x));
+        return i > 0 ? x : (lane < j ? 0.0 : (lane == j ? v0 : x));
+      };
+      // one column per wave: the reflector is held in registers; with more,
+      // it is read from LDS again for each use (register budget)
+      double v[CPW == 1 ? RPT : 1];
+      if constexpr (CPW == 1) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) v[i] = vi(i);
       }
 #pragma unroll
       for (int q = 0; q < CPW; ++q) {
@@ -254,12 +259,16 @@ __device__ __forceinline__ void qr_wave_body(const double* __restrict__ src, int
           double d0 = 0.0, d1 = 0.0;
 #pragma unroll
           for (int i = 0; i < RPT; ++i) {
-            if (i & 1) d1 = fma(v[i], a[q][i], d1);
-            else d0 = fma(v[i], a[q][i], d0);
+            const double vv = CPW == 1 ? v[CPW == 1 ? i : 0] : vi(i);
+            if (i & 1) d1 = fma(vv, a[q][i], d1);
+            else d0 = fma(vv, a[q][i], d0);
           }
           const double wt = beta * wave_total(d0 + d1);
 #pragma unroll
-          for (int i = 0; i < RPT; ++i) a[q][i] = fma(-wt, v[i], a[q][i]);
+          for (int i = 0; i < RPT; ++i) {
+            const double vv = CPW == 1 ? v[CPW == 1 ? i : 0] : vi(i);
+            a[q][i] = fma(-wt, vv, a[q][i]);
+          }
         }
       }
     }

@@ -83,10 +83,12 @@ struct UpPUnroll {
       NB == 2 ? RBGS_UP_P2UNROLL : (sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64);
 };
 // WV: waves per workgroup (the update kernel: 4 for NB = 1, 8 for NB = 2; the
-// persistent batch kernel: 16)
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+// persistent batch kernel: 16).  VE: rows per lane, read as one vector of VE
+// elements (the update kernel: 16 bytes; the persistent batch kernel halves it
+// for NB = 2, to fit its register budget).
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
 struct UpPShape {
-  static constexpr int VEC = Vec16<T>::N;
+  static constexpr int VEC = VE;
   static constexpr int WAVES = WV;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int TILE = WAVES * 16 * VEC;           // rows per tile
@@ -136,7 +138,7 @@ __device__ __forceinline__ void p_substitute(double4_t (&acc)[VEC][NB], const do
 
 // One tile with guarded element loads and stores (rows >= n are neither read
 // nor written; any alignment).  Same arithmetic as update_p_full_tiles.
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
                                                       const T* __restrict__ Q, int64_t ldq,
                                                       T* Qout, int64_t ldqo, const double* Rs,
@@ -144,7 +146,7 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
                                                       bool subst, int64_t tile0, int64_t n,
                                                       int K, int bw) {
   typedef Mfma<double> M;
-  typedef UpPShape<T, NB, WV> Sh;
+  typedef UpPShape<T, NB, WV, VE> Sh;
   constexpr int VEC = Sh::VEC;
   constexpr int WROWS = 16 * VEC;
   constexpr int NCOL = Sh::NCOL;
@@ -243,7 +245,7 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
 // one, so the wait for them does not also wait for those stores (stores share
 // the vector-memory counter on this target).  Same arithmetic, in the same
 // order, as update_p_guarded_tile.
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8)>
+template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     const T* __restrict__ Q, int64_t ldq,
                                                     T* Qout, int64_t ldqo, const double* Rs,
@@ -251,12 +253,12 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     bool subst, int64_t first, int64_t stride,
                                                     int64_t nfull, int K, int bw) {
   typedef Mfma<double> M;
-  typedef UpPShape<T, NB, WV> Sh;
+  typedef UpPShape<T, NB, WV, VE> Sh;
   constexpr int VEC = Sh::VEC;
   constexpr int WROWS = 16 * VEC;
   constexpr int TILE = Sh::TILE;
   constexpr int NCOL = Sh::NCOL;
-  typedef typename Vec16<T>::t VT;
+  typedef T VT __attribute__((ext_vector_type(VE)));
   constexpr int kUnroll = UpPUnroll<T, NB>::N;
   constexpr int GS = 4 * kUnroll;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

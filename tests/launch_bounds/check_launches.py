@@ -61,6 +61,8 @@ def parse_log(path):
                 events.append(("launch", Launch(name, grid, block, shmem, raw)))
             elif parts[0] == "copy":
                 events.append(("copy", int(parts[1]), int(parts[2]), int(parts[3]), int(parts[4])))
+            elif parts[0] == "data":
+                events.append(("data", int(parts[1]), bytes.fromhex(parts[2]) if len(parts) > 2 else b""))
     return events
 
 
@@ -332,6 +334,164 @@ def _sketch_srht(L, T, TPT):
     return [acc(0, es, 0, (n - 1) + (ncols - 1) * ldx), acc(10, 8, 0, G * ncols * k - 1)]
 
 
+# ---------------------------------------------------------------------------
+# Persistent batch.  The descriptors are read from the bytes the host uploaded
+# (the "data" events); every access is returned as ("abs", first byte, end
+# byte) of device memory.
+# ---------------------------------------------------------------------------
+MEM = {}          # device address -> uploaded bytes (set by check_events)
+PB_FMT = "<13Q4q2I10i"   # struct PbProb: 13 pointers, n, ldw, ldq, ldr, key0, key1, 10 int32
+PB_SIZE = struct.calcsize(PB_FMT) + (-struct.calcsize(PB_FMT)) % 8
+PB_FIELDS = ("W Q R S P E G Cb Yb part flag plan_off plan_ent n ldw ldq ldr key0 key1 "
+             "m p k nb plan_tiles sk_G sk_tpw up_tiles up_nfull pad").split()
+PB_LDS = 144 * 1024
+PB_TILE = 1024
+
+
+def uploaded(addr):
+    assert addr in MEM, f"no upload at {addr:#x}"
+    return MEM[addr]
+
+
+def pb_problems(addr, count=None):
+    raw = uploaded(addr)
+    assert len(raw) % PB_SIZE == 0, "descriptor array size"
+    np_ = len(raw) // PB_SIZE if count is None else count
+    out = []
+    for q in range(np_):
+        vals = struct.unpack_from(PB_FMT[:-3] + "9i", raw, q * PB_SIZE)
+        out.append(dict(zip(PB_FIELDS, vals)))
+    return out
+
+
+def absacc(ptr, es, lo, hi):
+    return ("abs", ptr + int(lo) * es, ptr + (int(hi) + 1) * es)
+
+
+def pb_items(P, kind, block):
+    """Items of a stage (restated from the device code)."""
+    bw = min(P["p"], P["m"] - block * P["p"])
+    red = 4 * 1024
+    if kind == "plan":
+        return cdiv(P["plan_tiles"], 2)
+    if kind == "wsk":
+        return P["sk_G"] * cdiv(P["m"], 16)
+    if kind == "redw":
+        return cdiv(P["k"] * P["m"], red)
+    if kind == "small":
+        return 1
+    if kind == "upd":
+        return cdiv(P["up_tiles"], 2)
+    if kind == "qsk":
+        return P["sk_G"] * cdiv(bw, 16 if bw > 8 else 8)
+    return cdiv(P["k"] * bw, red)
+
+
+def pb_chain(P):
+    """Stages of one problem in the order the queue runs them."""
+    out = [("plan", 0), ("wsk", 0), ("redw", 0)]
+    for b in range(P["nb"]):
+        out += [("small", b), ("upd", b)]
+        if b + 1 < P["nb"]:
+            out += [("qsk", b), ("reds", b)]
+    return out
+
+
+def pb_problem_accesses(P, zeta, ls):
+    n, m, p, k = P["n"], P["m"], P["p"], P["k"]
+    ldw, ldq, ldr = P["ldw"], P["ldq"], P["ldr"]
+    G, tpw = P["sk_G"], P["sk_tpw"]
+    assert 1 <= p <= 32 and 1 <= m <= n and m <= k <= 1024 and zeta <= 8 and k % zeta == 0
+    assert P["nb"] == cdiv(m, p)
+    tiles = cdiv(n, 1024)
+    assert P["plan_tiles"] == tiles
+    assert G * tpw >= tiles and (G - 1) * tpw < tiles, "sketch row groups"
+    rows = PB_TILE if p <= 16 else PB_TILE // 2
+    assert P["up_tiles"] == cdiv(n, rows)
+    assert P["up_nfull"] * rows <= n
+    if P["up_nfull"] > 0:
+        assert P["W"] % 16 == 0 and P["Q"] % 16 == 0 and ldw % 4 == 0 and ldq % 4 == 0
+    ncol = 16 if p <= 16 else 32
+    out = [absacc(P["plan_off"], 2, 0, tiles * (k + 1) - 1),
+           absacc(P["plan_ent"], 2, 0, tiles * 1024 * zeta - 1),
+           absacc(P["flag"], 8, 0, 0)]
+    for kind, b in pb_chain(P):
+        assert pb_items(P, kind, b) >= 1
+        c0 = b * p
+        K = c0
+        bw = min(p, m - c0)
+        if kind == "wsk":
+            out += [absacc(P["W"], 4, 0, (n - 1) + (m - 1) * ldw),
+                    absacc(P["part"], 8, 0, G * m * k - 1)]
+        elif kind == "redw":
+            out += [absacc(P["part"], 8, 0, G * m * k - 1), absacc(P["P"], 8, 0, k * m - 1)]
+        elif kind == "small":
+            if K > 0:
+                bp = p
+                out += [absacc(P["S"], 8, 0, K * k - 1),                       # S_(1:i-1)
+                        absacc(P["P"], 8, K * k, K * k + bw * k - 1),          # P_(i)
+                        absacc(P["G"], 8, (K - bp) * m, (K - bp) * m + (K - 1) + (bp - 1) * m),
+                        absacc(P["G"], 8, K - bp, (K - bp) + (bp - 1) + (K - 1) * m),
+                        absacc(P["G"], 8, 0, (K - 1) * m + K - 1),             # sweeps
+                        absacc(P["R"], 8, K * ldr, K * ldr + (K - 1) + (bw - 1) * ldr),
+                        absacc(P["E"], 8, 0, k * bw - 1)]
+                if ls > 1:
+                    out += [absacc(P["Cb"], 8, 0, K * bw - 1), absacc(P["Yb"], 8, 0, K * bw - 1)]
+            out.append(absacc(P["R"], 8, c0 + c0 * ldr, c0 + c0 * ldr + (bw - 1) + (bw - 1) * ldr))
+            out.append(absacc(P["P"] if K == 0 else P["E"], 8, 0, k * bw - 1))
+        elif kind == "upd":
+            Kp = cdiv(K, 4) * 4
+            assert (Kp * ncol + ncol * ncol + ncol) * 8 <= PB_LDS, "update factors exceed the LDS pool"
+            assert bw <= ncol
+            out += [absacc(P["W"], 4, c0 * ldw, (n - 1) + (c0 + bw - 1) * ldw),
+                    absacc(P["Q"], 4, c0 * ldq, (n - 1) + (c0 + bw - 1) * ldq),
+                    absacc(P["R"], 8, c0 + c0 * ldr, c0 + c0 * ldr + (bw - 1) + (bw - 1) * ldr)]
+            if K > 0:
+                out += [absacc(P["Q"], 4, 0, (n - 1) + (K - 1) * ldq),
+                        absacc(P["R"], 8, c0 * ldr, c0 * ldr + (K - 1) + (bw - 1) * ldr)]
+        elif kind == "qsk":
+            out += [absacc(P["Q"], 4, c0 * ldq, (n - 1) + (c0 + bw - 1) * ldq),
+                    absacc(P["part"], 8, 0, G * bw * k - 1)]
+        elif kind == "reds":
+            out += [absacc(P["part"], 8, 0, G * bw * k - 1),
+                    absacc(P["S"], 8, c0 * k, c0 * k + bw * k - 1)]
+    return out
+
+
+def _persistent_init(L):
+    # (probs, order, nprob, stages, claimed, finished, valid, ctl, total)
+    nprob, total = L.i(2), L.u(8)
+    probs = pb_problems(L.u(0))
+    assert len(probs) == nprob
+    order = struct.unpack("<%di" % nprob, uploaded(L.u(1)))
+    assert sorted(order) == list(range(nprob)), "order is a permutation"
+    assert L.block[0] == 256 and L.grid[1] == nprob + 1
+    assert L.grid[0] * 256 >= total
+    out = [absacc(L.u(0), PB_SIZE, 0, nprob - 1), acc(1, 4, 0, nprob - 1),
+           acc(3, 16, 0, min(nprob, total) - 1), acc(4, 4, 0, total - 1),
+           acc(5, 4, 0, total - 1), acc(6, 4, 0, total - 1), acc(7, 16, 0, 0)]
+    for P in probs:
+        m = P["m"]
+        assert L.grid[0] * 256 >= m * m
+        out += [absacc(P["R"], 8, 0, (m - 1) + (m - 1) * P["ldr"]), absacc(P["flag"], 8, 0, 0)]
+    return out
+
+
+def _persistent_batch(L):
+    # (probs, stages, claimed, finished, valid, ctl, total, zeta, ls, limit)
+    total, zeta, ls = L.u(6), L.i(7), L.i(8)
+    probs = pb_problems(L.u(0))
+    assert L.block[0] == 1024 and L.grid[0] >= 1 and L.shmem == 0
+    assert total == sum(len(pb_chain(P)) for P in probs) == sum(4 * P["nb"] + 1 for P in probs)
+    assert L.u(9) > 0, "wait limit"
+    out = [absacc(L.u(0), PB_SIZE, 0, len(probs) - 1), acc(1, 16, 0, total - 1),
+           acc(2, 4, 0, total - 1), acc(3, 4, 0, total - 1), acc(4, 4, 0, total - 1),
+           acc(5, 16, 0, 0)]
+    for P in probs:
+        out += pb_problem_accesses(P, zeta, ls)
+    return out
+
+
 def _template_args(name):
     """Template arguments of a mangled kernel name, e.g. IfdLi2EE -> ['f', 'd', 2]."""
     base = kernel_base(name)
@@ -383,6 +543,8 @@ MIRRORS = {
     "sketch_resid_kernel": _sketch_resid,
     "sum_kernel": _sum,
     "finite_kernel": _finite,
+    "persistent_init_kernel": _persistent_init,
+    "persistent_batch_kernel": _persistent_batch,
 }
 TEMPLATED = {
     "update_kernel": lambda L, t: _update_general(L, t[0], t[2]),
@@ -413,8 +575,11 @@ def check_events(events):
     violations = []
     seen = set()
     n = 0
+    MEM.clear()
     for ev in events:
-        if ev[0] == "alloc":
+        if ev[0] == "data":
+            MEM[ev[1]] = ev[2]
+        elif ev[0] == "alloc":
             live[ev[1]] = ev[2]
         elif ev[0] == "free":
             live.pop(ev[1], None)
@@ -430,9 +595,13 @@ def check_events(events):
                 violations.append(f"no bounds mirror for kernel {base}")
                 continue
             n += 1
-            for (j, es, lo, hi) in accesses:
-                ptr = L.u(j)
-                a0, a1 = ptr + lo * es, ptr + (hi + 1) * es
+            for a in accesses:
+                if a[0] == "abs":
+                    j, (a0, a1) = "(descriptor)", a[1:]
+                else:
+                    j, es, lo, hi = a
+                    ptr = L.u(j)
+                    a0, a1 = ptr + lo * es, ptr + (hi + 1) * es
                 ok = any(b <= a0 and a1 <= b + sz for b, sz in live.items())
                 if not ok:
                     violations.append(f"{base} grid {L.grid}: argument {j} touches "

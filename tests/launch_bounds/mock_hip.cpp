@@ -4,12 +4,14 @@
 // real host code of the library run: every device allocation returns an address
 // in a reserved range that is never dereferenced, every kernel launch is
 // recorded (kernel name, grid, block, dynamic LDS, raw argument bytes) instead
-// of executed, and copies from the device fill the host buffer with 0xFF bytes.
+// of executed, and copies from the device fill the host buffer with 0xFF bytes
+// (or the byte RBGS_MOCK_D2H_FILL names).
 // The record is written to the file named by RBGS_LAUNCH_LOG, one line per
 // event:
 //   alloc <base> <bytes>
 //   launch <mangled name> <gx> <gy> <gz> <bx> <by> <bz> <shmem> <nargs> <hex bytes of each arg>
 //   copy <dst> <src> <bytes> <kind>
+//   data <dst> <hex bytes>      (the bytes of a host -> device copy)
 #include <cxxabi.h>
 #include <hip/hip_runtime_api.h>
 #include <stdio.h>
@@ -174,7 +176,19 @@ hipError_t hipHostFree(void* p) {
 static hipError_t copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
   fprintf(log_file(), "copy %llu %llu %zu %d\n", (unsigned long long)(uint64_t)dst,
           (unsigned long long)(uint64_t)src, bytes, (int)kind);
-  if (kind == hipMemcpyDeviceToHost) memset(dst, 0xFF, bytes);
+  if (kind == hipMemcpyDeviceToHost) {
+    // 0xFF bytes (a flag of -1: no breakdown), or the byte RBGS_MOCK_D2H_FILL names
+    const char* fill = getenv("RBGS_MOCK_D2H_FILL");
+    memset(dst, fill ? atoi(fill) : 0xFF, bytes);
+  }
+  // host -> device uploads of up to 8 MiB (descriptor arrays): their bytes
+  if (kind == hipMemcpyHostToDevice && bytes <= (8u << 20)) {
+    FILE* f = log_file();
+    fprintf(f, "data %llu ", (unsigned long long)(uint64_t)dst);
+    const unsigned char* b = (const unsigned char*)src;
+    for (size_t i = 0; i < bytes; ++i) fprintf(f, "%02x", b[i]);
+    fprintf(f, "\n");
+  }
   return hipSuccess;
 }
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
@@ -185,6 +199,12 @@ hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKin
 }
 
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t attr, int) {
+  *v = attr == hipDeviceAttributeMultiprocessorCount ? 256
+       : attr == hipDeviceAttributeWallClockRate    ? 100000
+                                                    : 0;
+  return hipSuccess;
+}
 hipError_t hipGetLastError(void) { return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { return "mock"; }
 hipError_t hipSetDevice(int) { return hipSuccess; }

@@ -112,7 +112,8 @@ def test_batched_validation_on_host(lib_and_handle):
     assert arr[1].status == B.RBGS_EINVAL
     assert "problem 1" in lib.rbgs_last_error(h).decode()
     assert lib.rbgs_qr_batched(h, 0, arr, ctypes.byref(sk), ctypes.byref(op), 0) == B.RBGS_EINVAL
-    assert lib.rbgs_qr_batched(h, 1, arr, ctypes.byref(sk), ctypes.byref(op), 2) == B.RBGS_EINVAL
+    for flags in (4, -1):  # graph: RBGS_BATCH_GRAPH | RBGS_BATCH_PERSISTENT at most
+        assert lib.rbgs_qr_batched(h, 1, arr, ctypes.byref(sk), ctypes.byref(op), flags) == B.RBGS_EINVAL
     arr[0].p = 33
     assert lib.rbgs_qr_batched(h, 1, arr, ctypes.byref(sk), ctypes.byref(op), 0) == B.RBGS_EUNSUPPORTED
     p, k = ctypes.c_int64(), ctypes.c_int64()

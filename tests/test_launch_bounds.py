@@ -122,6 +122,85 @@ def test_noalloc_launches_stay_in_the_scratch_array(driver, case):
     assert not violations, "\n".join(violations[:20])
 
 
+BATCH_CASES = [
+    # count, p, k / m, ragged leading dimensions
+    (24, 16, 4, 0),
+    (24, 32, 2, 1),
+    (9, 32, 4, 0),
+    (16, 8, 3, 1),
+]
+
+
+@pytest.mark.parametrize("case", BATCH_CASES, ids=lambda c: "batch-%d-p%d-k%d-ld%d" % c)
+def test_persistent_batch_launches_stay_in_bounds(driver, case):
+    """rbgs_qr_batched with the persistent queue: the descriptors the host
+    uploads are read back from the log, and every stage of every problem
+    (restated from the kernel) stays inside its arrays; the queue holds
+    exactly the stages the problems' chains need."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / ("batch_%d_%d_%d_%d.txt" % case))
+    r = subprocess.run([exe, "batch", *[str(v) for v in case]],
+                       env={**os.environ, "RBGS_LAUNCH_LOG": log, "RBGS_MOCK_D2H_FILL": "0"},
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    events = cl.parse_log(log)
+    names = [cl.kernel_base(e[1].name) for e in events if e[0] == "launch"]
+    assert names.count("persistent_batch_kernel") == 1 and names.count("persistent_init_kernel") == 1
+    violations, n, seen = cl.check_events(events)
+    assert n > 0
+    assert not violations, "\n".join(violations[:20])
+
+
+def test_persistent_batch_gpu_test_shapes_stay_in_bounds(driver):
+    """The shapes the GPU tests of the persistent batch run."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_gpu_persistent as tp
+    exe, out = driver
+    for name, shapes in (("oracle", tp.SHAPES), ("streams", tp.STREAM_SHAPES)):
+        spec = ";".join(",".join(str(v) for v in s) for s in shapes)
+        log = str(out / ("batchs_%s.txt" % name))
+        r = subprocess.run([exe, "batchs", spec], capture_output=True, text=True,
+                           env={**os.environ, "RBGS_LAUNCH_LOG": log, "RBGS_MOCK_D2H_FILL": "0"})
+        assert r.returncode == 0, r.stdout + r.stderr
+        events = cl.parse_log(log)
+        names = [cl.kernel_base(e[1].name) for e in events if e[0] == "launch"]
+        assert names.count("persistent_batch_kernel") == 1, name
+        violations, n, seen = cl.check_events(events)
+        assert n > 0 and not violations, "\n".join(violations[:20])
+
+
+def test_persistent_batch_checker_catches_a_short_array(driver):
+    """A problem's R one row short (leading dimension m - 1) must be flagged."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / "batch_planted.txt")
+    subprocess.run([exe, "batch", "9", "32", "4", "0"], check=True, capture_output=True,
+                   env={**os.environ, "RBGS_LAUNCH_LOG": log, "RBGS_MOCK_D2H_FILL": "0"})
+    events = cl.parse_log(log)
+    assert not cl.check_events(events)[0]
+    il = next(i for i, e in enumerate(events) if e[0] == "launch" and
+              cl.kernel_base(e[1].name) == "persistent_batch_kernel")
+    pa = events[il][1].u(0)
+    idx = next(i for i, e in enumerate(events) if e[0] == "data" and e[1] == pa)
+    raw = bytearray(events[idx][2])
+    off = cl.PB_FIELDS.index("ldr")
+    # ldr is the 17th 8-byte field; make it one larger for problem 3
+    pos = 3 * cl.PB_SIZE + 8 * off
+    ldr = int.from_bytes(raw[pos:pos + 8], "little")
+    raw[pos:pos + 8] = (ldr + 1).to_bytes(8, "little")
+    bad = list(events)
+    bad[idx] = ("data", pa, bytes(raw))
+    assert any("descriptor" in v for v in cl.check_events(bad)[0])
+
+
 def test_noalloc_rejects_a_workspace_beyond_the_scratch_array(driver):
     exe, out = driver
     log = str(out / "noalloc_big.txt")
