@@ -225,8 +225,10 @@ def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
 
 def batched_form(count=512, reps=3):
     """The batched workload: `count` FP32 problems of uneven n and m, tuned p
-    and k, one graph launch per batch, against the same QRs launched one by
-    one.  Aggregate algorithmic GB/s over all problems."""
+    and k: the lock-step groups replayed as one graph per batch, the same QRs
+    in one persistent launch (a device queue of the problems' stages), and the
+    same QRs launched one by one.  Aggregate algorithmic GB/s over all
+    problems."""
     import numpy as np
     import torch
     from paper_2111_14641_amd import binding as B
@@ -257,19 +259,45 @@ def batched_form(count=512, reps=3):
         e1.record(stream)
         torch.cuda.synchronize()
         ms_single = e0.elapsed_time(e1)
-    tot = sum(alg_bytes(W.shape[0], W.shape[1], ps[i], 4) for i, W in enumerate(Ws))
-    errs, conds = [], []
-    for W, Q, R in zip(Ws, Qs, Rs):
-        Wd, Qd = W.double(), Q.double()
-        errs.append((torch.linalg.norm(Wd - Qd @ R) / torch.linalg.norm(Wd)).item())
-        ev = np.linalg.eigvalsh((Qd.t() @ Qd).cpu().numpy())
-        conds.append(float(np.sqrt(ev[-1] / ev[0])))
     del Q1, R1
+    # the same factorizations in one persistent launch (device queue of stages),
+    # recorded as a graph by the first call; each call waits for the device
+    Qp = [B.colmajor(W.shape[0], W.shape[1], torch.float32) for W in Ws]
+    Rp = [B.colmajor(W.shape[1], W.shape[1], torch.float64) for W in Ws]
+    with torch.cuda.stream(stream):
+        B.rbgs_qr_batched(Ws, ps, ks, seed=0x2111146414, Qs=Qp, Rs=Rp, graph=True, persistent=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            B.rbgs_qr_batched(Ws, ps, ks, seed=0x2111146414, Qs=Qp, Rs=Rp, graph=True,
+                              persistent=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_pers = e0.elapsed_time(e1) / reps
+    tot = sum(alg_bytes(W.shape[0], W.shape[1], ps[i], 4) for i, W in enumerate(Ws))
+
+    def metrics(Qs_, Rs_):
+        errs, conds = [], []
+        for W, Q, R in zip(Ws, Qs_, Rs_):
+            Wd, Qd = W.double(), Q.double()
+            errs.append((torch.linalg.norm(Wd - Qd @ R) / torch.linalg.norm(Wd)).item())
+            ev = np.linalg.eigvalsh((Qd.t() @ Qd).cpu().numpy())
+            conds.append(float(np.sqrt(ev[-1] / ev[0])))
+        return float(f"{max(errs):.3g}"), float(f"{max(conds):.4g}")
+
+    err_l, cond_l = metrics(Qs, Rs)
+    err_p, cond_p = metrics(Qp, Rp)
+    # persistent vs lock-step R (the sketches' partial sums are grouped differently)
+    dR = max((torch.linalg.norm(R1 - R0) / torch.linalg.norm(R0)).item() for R0, R1 in zip(Rs, Rp))
     return dict(problems=count, alg_GB=round(tot / 1e9, 3), ms_graph=round(ms_graph, 3),
-                GBps_graph=round(tot / (ms_graph * 1e-3) / 1e9, 1), ms_one_by_one=round(ms_single, 3),
+                GBps_graph=round(tot / (ms_graph * 1e-3) / 1e9, 1),
+                ms_persistent=round(ms_pers, 3), GBps_persistent=round(tot / (ms_pers * 1e-3) / 1e9, 1),
+                persistent_speedup_vs_graph=round(ms_graph / ms_pers, 3),
+                ms_one_by_one=round(ms_single, 3),
                 GBps_one_by_one=round(tot / (ms_single * 1e-3) / 1e9, 1),
                 speedup=round(ms_single / ms_graph, 3), first_call_s=round(first_s, 3),
-                max_rel_err=float(f"{max(errs):.3g}"), max_cond2_Q=float(f"{max(conds):.4g}"),
+                max_rel_err=err_l, max_cond2_Q=cond_l, max_rel_err_persistent=err_p,
+                max_cond2_Q_persistent=cond_p, max_rel_dR_persistent_vs_lockstep=float(f"{dR:.3g}"),
                 p_used=sorted(set(ps)), k_over_m=sorted(set(round(k / W.shape[1], 2)
                                                           for k, W in zip(ks, Ws))))
 

@@ -5,19 +5,20 @@
 //
 // The work of one problem is a chain of stages, each a set of independent
 // items:
-//   plan of Theta (per pair of 1024-row tiles) -> partial sums of Theta W
+//   plan of Theta (per 8 tiles of 1024 rows) -> partial sums of Theta W
 //   (row group x 16-column slice) -> their reduction into P = Theta W ->
 //   for each block i: small factors (step 2 by Richardson sweeps in Gram
-//   form, Theta-QR of the sketched residual; one item) -> update and
-//   substitution of steps 3-5 (pairs of 1024-row tiles) -> partial sums of
+//   form on the FP64 matrix cores, Theta-QR of the sketched residual; one
+//   item) -> update and substitution of steps 3-5 (16 tiles of 1024 rows,
+//   512 for p > 16, per item) -> partial sums of
 //   Theta Q_(i) -> their reduction into S_(i) (the last two not for the last
 //   block).
 // Stage s + 1 of a problem reads what every item of stage s wrote, so a stage
 // enters the queue when the last item of its predecessor finishes; the first
 // stage of every problem is queued at the start, largest problem first.
-// Workgroups take items from the stage at the head of the queue (a counter of
-// claimed items per stage); the head moves on once every item of its stage is
-// claimed.  Different problems, and different stages of them, are in flight
+// Workgroups take items from the first queued stage that still has items (a
+// counter of claimed items per stage), walking forward from the head, which
+// moves on past stages whose items are all taken.  Different problems, and different stages of them, are in flight
 // at once, so one problem's small factors (one workgroup, no HBM traffic)
 // overlap the others' HBM-bound updates and sketches.
 //
@@ -42,9 +43,21 @@ namespace rbgs {
 
 namespace {
 
-constexpr int kPbRedOut = 4 * kPbThreads;  // sketch outputs per reduction item
-constexpr int kPbPlanTiles = 2;            // plan tiles per item
-constexpr int kPbUpdTiles = 2;             // update tiles per item
+#ifndef RBGS_PB_RED
+#define RBGS_PB_RED 4          // sketch outputs per thread of a reduction item
+#endif
+// Measured on 512 problems (n 16k..262k, m 32..256, p = 32, k = 4m): update
+// items of 4, 8, 16 and 32 tiles gave 87.4, 83.4, 82.0 and 81.4 ms (plan items
+// of half as many tiles); 16 keeps more items per stage for small problems.
+#ifndef RBGS_PB_PLAN_TILES
+#define RBGS_PB_PLAN_TILES 8   // plan tiles per item
+#endif
+#ifndef RBGS_PB_UPD_TILES
+#define RBGS_PB_UPD_TILES 16   // update tiles per item
+#endif
+constexpr int kPbRedOut = RBGS_PB_RED * kPbThreads;
+constexpr int kPbPlanTiles = RBGS_PB_PLAN_TILES;
+constexpr int kPbUpdTiles = RBGS_PB_UPD_TILES;
 
 static_assert(UpPShape<float, 1, kPbThreads / 64, 4>::TILE == kPbTileRows, "update tile");
 static_assert(UpPShape<float, 2, kPbThreads / 64, 2>::TILE == kPbTileRows / 2, "update tile");
@@ -121,39 +134,67 @@ __device__ __forceinline__ void st_agent(int32_t* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One thread: the next item, or -1 when the queue is drained, after an error,
-// or when the wait for a stage exceeds `limit` ticks (then the error word is
-// set).  Acquires before returning an item.
+// The first wave: the next item (in lane 0's `item` and `out`), or -1 when
+// the queue is drained, after an error, or when a wait for a stage exceeds
+// `limit` ticks (then the error word is set).  The 64 lanes look at 64 stages
+// from the head at once (queued?, all items taken?); the first stage with an
+// item left is tried with one atomic add, and the winner acquires.  Every
+// stage before the first one not known to be exhausted has all its items taken
+// (claim counts only grow), so the head moves there (atomic max).
 __device__ int pb_claim(const PbStage* stages, unsigned* claimed, const unsigned* valid,
                         PbCtl* ctl, unsigned total, uint64_t limit, int& item, PbStage& out) {
+  const int lane = threadIdx.x & 63;
   uint64_t t0 = wall_clock64();
   for (;;) {
-    const unsigned h = ld_agent(&ctl->head);
-    if (h >= total) return -1;
-    if (ld_agent(&ctl->error) != 0u) return -1;
-    if (ld_agent(&valid[h]) == 0u) {
+    const unsigned h0 = (unsigned)__builtin_amdgcn_readfirstlane((int)ld_agent(&ctl->head));
+    if (h0 >= total) return -1;
+    const unsigned slot = h0 + lane;
+    const bool in = slot < total;
+    const bool queued = in && ld_agent(&valid[in ? slot : 0]) != 0u;
+    unsigned n = 0;
+    bool left = false;
+    if (queued) {
+      n = (unsigned)ld_agent(&stages[slot].nitems);
+      left = ld_agent(&claimed[slot]) < n;
+    }
+    const uint64_t m_left = __ballot(left);
+    const uint64_t m_done = __ballot(queued && !left);  // queued, every item taken
+    // the exhausted prefix: stages h0 .. h0 + g - 1 (a stage not queued yet,
+    // or one with items left, ends it)
+    const unsigned g = ~m_done == 0 ? 64u : (unsigned)__builtin_ctzll(~m_done);
+    if (m_left == 0) {
+      if (g > 0 && lane == 0) atomicMax(&ctl->head, h0 + g);
+      if (g == 64 || h0 + g >= total) continue;
+      // stage h0 + g is not queued yet: wait for it
+      if (__builtin_amdgcn_readfirstlane((int)ld_agent(&ctl->error)) != 0) return -1;
       if (wall_clock64() - t0 > limit) {
-        atomicCAS(&ctl->error, 0u, 1u);
+        if (lane == 0) atomicCAS(&ctl->error, 0u, 1u);
         return -1;
       }
       __builtin_amdgcn_s_sleep(4);
       continue;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    PbStage e;
-    e.prob = ld_agent(&stages[h].prob);
-    e.kind = ld_agent(&stages[h].kind);
-    e.block = ld_agent(&stages[h].block);
-    e.nitems = ld_agent(&stages[h].nitems);
-    const unsigned c = atomicAdd(&claimed[h], 1u);
-    if (c + 1 >= (unsigned)e.nitems) atomicCAS(&ctl->head, h, h + 1);  // stage fully claimed
-    if (c >= (unsigned)e.nitems) {
-      t0 = wall_clock64();
-      continue;
+    const unsigned f = (unsigned)__builtin_ctzll(m_left);
+    const unsigned hs = h0 + f;
+    const unsigned nf = (unsigned)__shfl((int)n, (int)f, 64);
+    unsigned c = 0;
+    if (lane == 0) c = atomicAdd(&claimed[hs], 1u);
+    c = (unsigned)__shfl((int)c, 0, 64);
+    if (c >= nf) continue;  // taken meanwhile
+    t0 = wall_clock64();
+    if (lane == 0) {
+      // past the stage taken only when it is the end of the exhausted prefix
+      // and its last item was taken here; never past a stage not queued yet
+      const unsigned next = f == g && c + 1 == nf ? hs + 1 : h0 + g;
+      if (next > h0) atomicMax(&ctl->head, next);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      out.prob = ld_agent(&stages[hs].prob);
+      out.kind = ld_agent(&stages[hs].kind);
+      out.block = ld_agent(&stages[hs].block);
+      out.nitems = (int)nf;
+      item = (int)c;
     }
-    item = (int)c;
-    out = e;
-    return (int)h;
+    return (int)hs;
   }
 }
 
@@ -167,7 +208,10 @@ __device__ void pb_finish(const PbProb* probs, const PbStage& st, int slot, PbSt
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const PbProb& P = probs[st.prob];
   int nk, nblk;
-  if (!pb_next(P, st.kind, st.block, nk, nblk)) return;
+  if (!pb_next(P, st.kind, st.block, nk, nblk)) {
+    atomicAdd(&ctl->done, 1u);
+    return;
+  }
   const unsigned t = atomicAdd(&ctl->tail, 1u);
   if (t >= total) {  // more stages than counted on the host: cannot happen
     atomicCAS(&ctl->error, 0u, 2u);
@@ -233,8 +277,65 @@ __device__ __forceinline__ void pb_reduce(const double* __restrict__ part, int G
   }
 }
 
-// Steps 2 and the Theta-QR of block i (one item): the same products, sweeps
-// and QR as the lock-step batch, in one workgroup.
+// out[i, j] = add1[i, j] + (add2[i, j] + sgn sum_d op(A)[i, d] B[d, j]) for
+// i < M, j < N (the addends when given), and outT[j, i] the same value when
+// outT is given; op(A)[i, d] = A[d + i lda] (TA, A^T) or A[i + d lda].  One
+// workgroup: each wave takes 16 x 16 output tiles in turn and accumulates them
+// on the FP64 matrix cores over d in steps of 4 (lane (kk, li) supplies
+// op(A)[i0 + li, d + kk] and B[d + kk, j0 + li] and ends with rows
+// i0 + kk + 4 e, column j0 + li).  Loads past M, N or D are clamped and their
+// values replaced by zero.  Columns of A and B are read in 32-byte runs per
+// lane group, so one pass over a 128-byte line serves four steps.
+template <bool TA>
+__device__ __forceinline__ void pb_gemm(int M, int N, int D, const double* __restrict__ A,
+                                        int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                        double sgn, const double* add1, int64_t ld1,
+                                        const double* add2, int64_t ld2, double* out,
+                                        int64_t ldo, double* outT, int64_t ldt) {
+  typedef Mfma<double> Mm;
+  constexpr int U = 4;  // steps of 4 whose operands are loaded together
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  for (int tile = w; tile < tm * tn; tile += kPbThreads / 64) {
+    const int i0 = (tile % tm) * 16, j0 = (tile / tm) * 16;
+    const bool oka = i0 + li < M, okb = j0 + li < N;
+    const int64_t ia = oka ? i0 + li : M - 1, jb = okb ? j0 + li : N - 1;
+    Mm::acc_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int d0 = 0; d0 < D; d0 += 4 * U) {
+      double a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int d = d0 + 4 * u + kk;
+        const bool okd = d < D;
+        const int64_t dc = okd ? d : D - 1;
+        const double av = TA ? A[dc + ia * lda] : A[ia + dc * lda];
+        const double bv = B[dc + jb * ldb];
+        a[u] = oka && okd ? av : 0.0;
+        b[u] = okb && okd ? bv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc = Mm::mma(a[u], b[u], acc);
+    }
+    const int64_t j = j0 + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + Mm::row(kk, e);
+      if (i < M && j < N) {
+        double v = sgn * acc[e];
+        if (add2) v = add2[i + j * ld2] + v;
+        if (add1) v = add1[i + j * ld1] + v;
+        out[i + j * ldo] = v;
+        if (outT) outT[j + i * ldt] = v;
+      }
+    }
+  }
+}
+
+// Steps 2 and the Theta-QR of block i (one item), in one workgroup: the least
+// squares of step 2 in Gram form as the lock-step batch (c = S^T P_(i) and the
+// new block column of G = S^T S, sweeps Y <- Y + c - G Y, S' = P_(i) - S Y),
+// its products on the matrix cores, then the QR of S'.
 __device__ __forceinline__ void pb_small(const PbProb& P, int block, int ls) {
   const int64_t k = P.k, m = P.m, ldr = P.ldr;
   const int64_t c0 = (int64_t)block * P.p, K = c0;
@@ -244,10 +345,10 @@ __device__ __forceinline__ void pb_small(const PbProb& P, int block, int ls) {
     double* const RK = P.R + K * ldr;
     double* out0 = ls > 1 ? P.Cb : RK;
     const int64_t ldo0 = ls > 1 ? K : ldr;
-    const int64_t nsty = K * (bw + bprev) * 64;
-    for (int64_t bx = 0; bx * kPbThreads < nsty; ++bx)
-      gram_sty_body(P.S, k, K, P.P + K * k, bw, P.S + (K - bprev) * k, bprev, out0, ldo0,
-                    P.G + (K - bprev) * m, m, P.G + (K - bprev), m, bx);
+    pb_gemm<true>((int)K, bw, (int)k, P.S, k, P.P + K * k, k, 1.0, nullptr, 0, nullptr, 0, out0,
+                  ldo0, nullptr, 0);
+    pb_gemm<true>((int)K, bprev, (int)k, P.S, k, P.S + (K - bprev) * k, k, 1.0, nullptr, 0,
+                  nullptr, 0, P.G + (K - bprev) * m, m, P.G + (K - bprev), m);
     __syncthreads();
     int cur = 0;  // iterate in Cb (0), Yb (1) or R_(1:i-1,i) (2); the last one in R
     for (int it = 1; it < ls; ++it) {
@@ -256,15 +357,13 @@ __device__ __forceinline__ void pb_small(const PbProb& P, int block, int ls) {
       const int64_t ldy = cur == 2 ? ldr : K;
       double* Yn = dst == 1 ? P.Yb : RK;
       const int64_t ldyn = dst == 2 ? ldr : K;
-      const int64_t nsw = K * bw * 16;
-      for (int64_t bx = 0; bx * kPbThreads < nsw; ++bx)
-        gram_sweep_body(P.G, m, K, P.Cb, Y, ldy, Yn, ldyn, bw, bx);
+      pb_gemm<false>((int)K, bw, (int)K, P.G, m, Y, ldy, -1.0, Y, ldy, P.Cb, K, Yn, ldyn,
+                     nullptr, 0);
       __syncthreads();
       cur = dst;
     }
-    const int64_t nres = k * bw * 16;
-    for (int64_t bx = 0; bx * kPbThreads < nres; ++bx)
-      resid_body(P.P + K * k, P.S, k, K, RK, ldr, P.E, bw, bx);
+    pb_gemm<false>((int)k, bw, (int)K, P.S, k, RK, ldr, -1.0, P.P + K * k, k, nullptr, 0, P.E, k,
+                   nullptr, 0);
     __syncthreads();
   }
   const double* src = K == 0 ? P.P : P.E;
@@ -377,12 +476,15 @@ __global__ __launch_bounds__(kPbThreads, 1) void persistent_batch_kernel(
   }
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
       int item = 0;
       PbStage e;
-      s_slot = pb_claim(a.stages, a.claimed, a.valid, a.ctl, a.total, a.limit, item, e);
-      s_item = item;
-      s_st = e;
+      const int slot = pb_claim(a.stages, a.claimed, a.valid, a.ctl, a.total, a.limit, item, e);
+      if (threadIdx.x == 0) {
+        s_slot = slot;
+        s_item = item;
+        s_st = e;
+      }
     }
     __syncthreads();
     const int slot = uni(s_slot);
@@ -451,7 +553,7 @@ __global__ __launch_bounds__(256) void persistent_init_kernel(const PbProb* __re
     ctl->head = 0u;
     ctl->tail = (unsigned)nprob;
     ctl->error = 0u;
-    ctl->pad = 0u;
+    ctl->done = 0u;
   }
 }
 

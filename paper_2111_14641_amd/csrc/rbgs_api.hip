@@ -58,7 +58,8 @@ struct rbgs_handle_s {
   // device descriptors
   void* bws = nullptr;
   size_t bws_bytes = 0;
-  PbCtl* pb_ctl = nullptr;  // control word of the last persistent batch (in bws)
+  PbCtl* pb_ctl = nullptr;  // control words of the last persistent batch (in bws)
+  unsigned pb_nprob = 0, pb_total = 0;  // its problems and stages
 };
 
 namespace {
@@ -1033,7 +1034,8 @@ rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* prob
     P.nb = (int32_t)((pr.m + pr.p - 1) / pr.p);
     const int64_t tiles = sparse_plan_tiles(pr.n);
     P.plan_tiles = (int32_t)tiles;
-    const int64_t tpw = (tiles + kPbSkG - 1) / kPbSkG;
+    const int64_t tpw = std::min(tiles, std::max<int64_t>((tiles + kPbSkG - 1) / kPbSkG,
+                                                          kPbSkMinTiles));
     P.sk_tpw = (int32_t)tpw;
     P.sk_G = (int32_t)((tiles + tpw - 1) / tpw);
     const int64_t rows = pr.p <= 16 ? kPbTileRows : kPbTileRows / 2;
@@ -1085,6 +1087,8 @@ rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* prob
   HIP_TRY(h, hipMemcpy(pb.order, order.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice),
           "upload batch order");
   h->pb_ctl = pb.ctl;
+  h->pb_nprob = (unsigned)np;
+  h->pb_total = pb.total;
   return RBGS_OK;
 }
 
@@ -1116,9 +1120,9 @@ rbgs_status persist_check(rbgs_handle h, hipStream_t st) {
   if (c.error == 1u)
     return fail(h, RBGS_EDEVICE, "persistent batch: a workgroup waited too long for a stage");
   if (c.error != 0u) return fail(h, RBGS_EDEVICE, "persistent batch: queue overflow");
-  if (c.head != c.tail)
-    return fail(h, RBGS_EDEVICE, "persistent batch: " + std::to_string(c.tail - c.head) +
-                                     " stages left in the queue");
+  if (c.tail != h->pb_total || c.done != h->pb_nprob)
+    return fail(h, RBGS_EDEVICE, "persistent batch: " + std::to_string(h->pb_nprob - c.done) +
+                                     " problems not finished");
   return RBGS_OK;
 }
 

@@ -278,6 +278,7 @@ constexpr int kPbMaxP = 32;                 // block width
 constexpr int kPbLdsBytes = 144 * 1024;     // LDS pool shared by the stages
 constexpr int kPbTileRows = 1024;           // rows per update tile for p <= 16 (half for p > 16)
 constexpr int kPbSkG = 16;                  // row groups of a sketch, at most
+constexpr int kPbSkMinTiles = 4;            // tiles per row group, at least (but one group)
 
 // Stage kinds, in the order they follow one another for one problem.
 enum PbKind : int32_t { kPbPlan = 0, kPbWsk, kPbRedw, kPbSmall, kPbUpd, kPbQsk, kPbReds };
@@ -301,7 +302,7 @@ struct PbStage {
   int32_t prob, kind, block, nitems;
 };
 struct PbCtl {
-  unsigned head, tail, error, pad;
+  unsigned head, tail, error, done;  // done: problems whose last stage has finished
 };
 // Stages of one problem with m columns and block width p.
 inline int64_t pb_stage_count(int64_t m, int64_t p) { return 4 * ((m + p - 1) / p) + 1; }

@@ -373,7 +373,7 @@ def pb_items(P, kind, block):
     bw = min(P["p"], P["m"] - block * P["p"])
     red = 4 * 1024
     if kind == "plan":
-        return cdiv(P["plan_tiles"], 2)
+        return cdiv(P["plan_tiles"], 8)
     if kind == "wsk":
         return P["sk_G"] * cdiv(P["m"], 16)
     if kind == "redw":
@@ -381,7 +381,7 @@ def pb_items(P, kind, block):
     if kind == "small":
         return 1
     if kind == "upd":
-        return cdiv(P["up_tiles"], 2)
+        return cdiv(P["up_tiles"], 16)
     if kind == "qsk":
         return P["sk_G"] * cdiv(bw, 16 if bw > 8 else 8)
     return cdiv(P["k"] * bw, red)
@@ -406,6 +406,7 @@ def pb_problem_accesses(P, zeta, ls):
     tiles = cdiv(n, 1024)
     assert P["plan_tiles"] == tiles
     assert G * tpw >= tiles and (G - 1) * tpw < tiles, "sketch row groups"
+    assert G <= 16 and (tpw >= 4 or tpw == tiles)
     rows = PB_TILE if p <= 16 else PB_TILE // 2
     assert P["up_tiles"] == cdiv(n, rows)
     assert P["up_nfull"] * rows <= n

@@ -4,8 +4,7 @@
 // real host code of the library run: every device allocation returns an address
 // in a reserved range that is never dereferenced, every kernel launch is
 // recorded (kernel name, grid, block, dynamic LDS, raw argument bytes) instead
-// of executed, and copies from the device fill the host buffer with 0xFF bytes
-// (or the byte RBGS_MOCK_D2H_FILL names).
+// of executed, and copies from the device fill the host buffer with 0xFF bytes.
 // The record is written to the file named by RBGS_LAUNCH_LOG, one line per
 // event:
 //   alloc <base> <bytes>
@@ -176,11 +175,7 @@ hipError_t hipHostFree(void* p) {
 static hipError_t copy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
   fprintf(log_file(), "copy %llu %llu %zu %d\n", (unsigned long long)(uint64_t)dst,
           (unsigned long long)(uint64_t)src, bytes, (int)kind);
-  if (kind == hipMemcpyDeviceToHost) {
-    // 0xFF bytes (a flag of -1: no breakdown), or the byte RBGS_MOCK_D2H_FILL names
-    const char* fill = getenv("RBGS_MOCK_D2H_FILL");
-    memset(dst, fill ? atoi(fill) : 0xFF, bytes);
-  }
+  if (kind == hipMemcpyDeviceToHost) memset(dst, 0xFF, bytes);
   // host -> device uploads of up to 8 MiB (descriptor arrays): their bytes
   if (kind == hipMemcpyHostToDevice && bytes <= (8u << 20)) {
     FILE* f = log_file();
