@@ -135,21 +135,24 @@ __device__ __forceinline__ void st_agent(int32_t* p, int v) {
 }
 
 // The first wave: the next item (in lane 0's `item` and `out`), or -1 when
-// the queue is drained, after an error, or when a wait for a stage exceeds
-// `limit` ticks (then the error word is set).  The 64 lanes look at 64 stages
-// from the head at once (queued?, all items taken?); the first stage with an
-// item left is tried with one atomic add, and the winner acquires.  Every
-// stage before the first one not known to be exhausted has all its items taken
-// (claim counts only grow), so the head moves there (atomic max).
+// every level is drained, after an error, or when a wait for a stage exceeds
+// `limit` ticks (then the error word is set).  Each group of 16 lanes looks at
+// 16 slots from the head of one level (the first group at the highest level)
+// at once: queued?, every item taken?  The first stage with an item left, in
+// that order, is tried with one atomic add, and the winner acquires.  In each
+// level every stage before the first one not known to be exhausted has all its
+// items taken (claim counts only grow), so that level's head moves there
+// (atomic max); it never passes a stage that is not queued yet.
 __device__ int pb_claim(const PbStage* stages, unsigned* claimed, const unsigned* valid,
-                        PbCtl* ctl, unsigned total, uint64_t limit, int& item, PbStage& out) {
-  const int lane = threadIdx.x & 63;
+                        PbCtl* ctl, uint64_t limit, int& item, PbStage& out) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4, i = lane & 15;
+  const int lev = kPbLevels - 1 - grp;
+  const unsigned end = ld_agent(&ctl->end[lev]);
   uint64_t t0 = wall_clock64();
   for (;;) {
-    const unsigned h0 = (unsigned)__builtin_amdgcn_readfirstlane((int)ld_agent(&ctl->head));
-    if (h0 >= total) return -1;
-    const unsigned slot = h0 + lane;
-    const bool in = slot < total;
+    const unsigned hl = ld_agent(&ctl->head[lev]);  // the same in the 16 lanes of a group
+    const unsigned slot = hl + i;
+    const bool in = slot < end;
     const bool queued = in && ld_agent(&valid[in ? slot : 0]) != 0u;
     unsigned n = 0;
     bool left = false;
@@ -159,13 +162,14 @@ __device__ int pb_claim(const PbStage* stages, unsigned* claimed, const unsigned
     }
     const uint64_t m_left = __ballot(left);
     const uint64_t m_done = __ballot(queued && !left);  // queued, every item taken
-    // the exhausted prefix: stages h0 .. h0 + g - 1 (a stage not queued yet,
-    // or one with items left, ends it)
-    const unsigned g = ~m_done == 0 ? 64u : (unsigned)__builtin_ctzll(~m_done);
+    if (__ballot(hl < end) == 0) return -1;             // every level drained
+    // this group's exhausted prefix: slots hl .. hl + g - 1
+    const unsigned gd = (unsigned)(m_done >> (16 * grp)) & 0xFFFFu;
+    const unsigned g = gd == 0xFFFFu ? 16u : (unsigned)__builtin_ctz(~gd);
     if (m_left == 0) {
-      if (g > 0 && lane == 0) atomicMax(&ctl->head, h0 + g);
-      if (g == 64 || h0 + g >= total) continue;
-      // stage h0 + g is not queued yet: wait for it
+      if (i == 0 && g > 0) atomicMax(&ctl->head[lev], hl + g);
+      // a group whose 16 slots were all exhausted looks again at once
+      if (__ballot(i == 0 && g == 16u) != 0) continue;
       if (__builtin_amdgcn_readfirstlane((int)ld_agent(&ctl->error)) != 0) return -1;
       if (wall_clock64() - t0 > limit) {
         if (lane == 0) atomicCAS(&ctl->error, 0u, 1u);
@@ -174,19 +178,22 @@ __device__ int pb_claim(const PbStage* stages, unsigned* claimed, const unsigned
       __builtin_amdgcn_s_sleep(4);
       continue;
     }
-    const unsigned f = (unsigned)__builtin_ctzll(m_left);
-    const unsigned hs = h0 + f;
-    const unsigned nf = (unsigned)__shfl((int)n, (int)f, 64);
+    const int f = __builtin_ctzll(m_left);
+    const unsigned hs = (unsigned)__shfl((int)slot, f, 64);
+    const unsigned nf = (unsigned)__shfl((int)n, f, 64);
+    const unsigned gf = (unsigned)__shfl((int)g, f, 64);
+    const unsigned hf = (unsigned)__shfl((int)hl, f, 64);
+    const int lf = kPbLevels - 1 - (f >> 4);
     unsigned c = 0;
     if (lane == 0) c = atomicAdd(&claimed[hs], 1u);
     c = (unsigned)__shfl((int)c, 0, 64);
     if (c >= nf) continue;  // taken meanwhile
     t0 = wall_clock64();
     if (lane == 0) {
-      // past the stage taken only when it is the end of the exhausted prefix
-      // and its last item was taken here; never past a stage not queued yet
-      const unsigned next = f == g && c + 1 == nf ? hs + 1 : h0 + g;
-      if (next > h0) atomicMax(&ctl->head, next);
+      // past the stage taken only when it ends the exhausted prefix of its
+      // level and its last item was taken here
+      const unsigned next = (unsigned)(f & 15) == gf && c + 1 == nf ? hs + 1 : hf + gf;
+      if (next > hf) atomicMax(&ctl->head[lf], next);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       out.prob = ld_agent(&stages[hs].prob);
       out.kind = ld_agent(&stages[hs].kind);
@@ -199,9 +206,9 @@ __device__ int pb_claim(const PbStage* stages, unsigned* claimed, const unsigned
 }
 
 // One thread, after the workgroup's writes of the item are complete: count
-// the item; the last one of its stage queues the successor.
+// the item; the last one of its stage queues the successor in its level.
 __device__ void pb_finish(const PbProb* probs, const PbStage& st, int slot, PbStage* stages,
-                          unsigned* finished, unsigned* valid, PbCtl* ctl, unsigned total) {
+                          unsigned* finished, unsigned* valid, PbCtl* ctl) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const unsigned f = atomicAdd(&finished[slot], 1u);
   if (f + 1 != (unsigned)st.nitems) return;
@@ -212,8 +219,9 @@ __device__ void pb_finish(const PbProb* probs, const PbStage& st, int slot, PbSt
     atomicAdd(&ctl->done, 1u);
     return;
   }
-  const unsigned t = atomicAdd(&ctl->tail, 1u);
-  if (t >= total) {  // more stages than counted on the host: cannot happen
+  const int lev = pb_level(P.nb, nk, nblk);
+  const unsigned t = atomicAdd(&ctl->tail[lev], 1u);
+  if (t >= ld_agent(&ctl->end[lev])) {  // more stages than counted on the host: cannot happen
     atomicCAS(&ctl->error, 0u, 2u);
     return;
   }
@@ -237,6 +245,7 @@ __device__ __forceinline__ T* uni(T* p) {
 
 // LDS shared by the stages (one stage at a time per workgroup).
 __shared__ __attribute__((aligned(32))) char pb_pool[kPbLdsBytes];
+
 
 // ---- the stages ------------------------------------------------------------
 
@@ -479,7 +488,7 @@ __global__ __launch_bounds__(kPbThreads, 1) void persistent_batch_kernel(
     if (threadIdx.x < 64) {
       int item = 0;
       PbStage e;
-      const int slot = pb_claim(a.stages, a.claimed, a.valid, a.ctl, a.total, a.limit, item, e);
+      const int slot = pb_claim(a.stages, a.claimed, a.valid, a.ctl, a.limit, item, e);
       if (threadIdx.x == 0) {
         s_slot = slot;
         s_item = item;
@@ -519,17 +528,16 @@ __global__ __launch_bounds__(kPbThreads, 1) void persistent_batch_kernel(
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0)
-      pb_finish(a.probs, s_st, s_slot, a.stages, a.finished, a.valid, a.ctl, a.total);
+      pb_finish(a.probs, s_st, s_slot, a.stages, a.finished, a.valid, a.ctl);
   }
 }
 
-// y < nprob: R = 0 and the breakdown flag of problem y; y = nprob: the queue.
-__global__ __launch_bounds__(256) void persistent_init_kernel(const PbProb* __restrict__ probs,
-                                                              const int32_t* __restrict__ order,
-                                                              int nprob, PbStage* stages,
-                                                              unsigned* claimed,
-                                                              unsigned* finished, unsigned* valid,
-                                                              PbCtl* ctl, unsigned total) {
+// y < nprob: R = 0 and the breakdown flag of problem y; y = nprob: the queue,
+// from the host's template.
+__global__ __launch_bounds__(256) void persistent_init_kernel(
+    const PbProb* __restrict__ probs, int nprob, const PbStage* __restrict__ stages0,
+    const unsigned* __restrict__ valid0, const PbCtl* __restrict__ ctl0, PbStage* stages,
+    unsigned* claimed, unsigned* finished, unsigned* valid, PbCtl* ctl, unsigned total) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((int)blockIdx.y < nprob) {
     const PbProb& P = probs[blockIdx.y];
@@ -540,27 +548,19 @@ __global__ __launch_bounds__(256) void persistent_init_kernel(const PbProb* __re
   if (idx < total) {
     claimed[idx] = 0u;
     finished[idx] = 0u;
-    if (idx < nprob) {
-      const int q = order[idx];
-      stages[idx].prob = q;
-      stages[idx].kind = kPbPlan;
-      stages[idx].block = 0;
-      stages[idx].nitems = pb_items(probs[q], kPbPlan, 0);
-    }
-    valid[idx] = idx < nprob ? 1u : 0u;
+    PbStage e = stages0[idx];
+    if (valid0[idx] != 0u) e.nitems = pb_items(probs[e.prob], e.kind, e.block);
+    stages[idx] = e;
+    valid[idx] = valid0[idx];
   }
-  if (idx == 0) {
-    ctl->head = 0u;
-    ctl->tail = (unsigned)nprob;
-    ctl->error = 0u;
-    ctl->done = 0u;
-  }
+  if (idx == 0) *ctl = *ctl0;
 }
 
 static int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-hipError_t launch_persistent_batch(const PbProb* probs, const int32_t* order, int nprob,
-                                   int64_t max_mm, PbStage* stages, unsigned* claimed,
+hipError_t launch_persistent_batch(const PbProb* probs, int nprob, int64_t max_mm,
+                                   const PbStage* stages0, const unsigned* valid0,
+                                   const PbCtl* ctl0, PbStage* stages, unsigned* claimed,
                                    unsigned* finished, unsigned* valid, PbCtl* ctl,
                                    unsigned total, int zeta, int ls_iters, uint64_t limit,
                                    int grid, hipStream_t st) {
@@ -568,7 +568,8 @@ hipError_t launch_persistent_batch(const PbProb* probs, const int32_t* order, in
     return hipErrorInvalidValue;
   const int64_t gx = std::max(ceil_div64(max_mm, 256), ceil_div64(total, 256));
   hipLaunchKernelGGL(persistent_init_kernel, dim3((unsigned)gx, (unsigned)nprob + 1), dim3(256), 0,
-                     st, probs, order, nprob, stages, claimed, finished, valid, ctl, total);
+                     st, probs, nprob, stages0, valid0, ctl0, stages, claimed, finished, valid,
+                     ctl, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(persistent_batch_kernel, dim3((unsigned)grid), dim3(kPbThreads), 0, st, probs,

@@ -29,6 +29,9 @@ struct ProfRec {
 
 }  // namespace
 
+constexpr int kHostWords = 16;  // pinned host words of a handle
+static_assert(sizeof(rbgs::PbCtl) <= kHostWords * sizeof(double), "queue state");
+
 struct rbgs_handle_s {
   int device = 0;
   std::string last_error;
@@ -40,7 +43,7 @@ struct rbgs_handle_s {
   double prof_ms[kProfClasses] = {0};
   int64_t prof_cnt[kProfClasses] = {0};
   double prof_bytes[kProfClasses] = {0};
-  double* host_cert = nullptr;  // pinned, 4 doubles + flag
+  double* host_cert = nullptr;  // pinned, kHostWords doubles (certificates, queue state)
   // batched calls: lanes (child handles with their own stream and workspace)
   std::vector<rbgs_handle> lanes;
   std::vector<hipStream_t> lane_streams;
@@ -59,7 +62,7 @@ struct rbgs_handle_s {
   void* bws = nullptr;
   size_t bws_bytes = 0;
   PbCtl* pb_ctl = nullptr;  // control words of the last persistent batch (in bws)
-  unsigned pb_nprob = 0, pb_total = 0;  // its problems and stages
+  unsigned pb_nprob = 0;  // its problems
 };
 
 namespace {
@@ -655,7 +658,7 @@ rbgs_status qr_certify(QrRun& r, rbgs_cert* cert) {
   hipStream_t st = r.st;
   HIP_TRY(h, launch_certificates(r.S, r.P, r.R, r.ldr, r.k, r.m, r.cscratch, r.cout, st),
           "certificates");
-  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, kHostWords * sizeof(double)), "hipHostMalloc");
   HIP_TRY(h, hipMemcpyAsync(h->host_cert, r.cout, 4 * sizeof(double), hipMemcpyDeviceToHost, st),
           "copy certificate");
   HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, r.flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
@@ -953,7 +956,9 @@ rbgs_status lockstep_setup(rbgs_handle h, int64_t count, const rbgs_problem* pro
 struct PersistBatch {
   std::vector<int64_t> idx;  // problem indices
   PbProb* probs = nullptr;   // device arrays in the arena
-  int32_t* order = nullptr;
+  PbStage* stages0 = nullptr;  // the queue at the start (template)
+  unsigned* valid0 = nullptr;
+  PbCtl* ctl0 = nullptr;
   PbStage* stages = nullptr;
   unsigned *claimed = nullptr, *finished = nullptr, *valid = nullptr;
   PbCtl* ctl = nullptr;
@@ -994,11 +999,35 @@ rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* prob
   size_t off = 0;
   const size_t o_probs = off;
   off += r256(sizeof(PbProb) * np);
-  const size_t o_order = off;
-  off += r256(sizeof(int32_t) * np);
+  // stages per priority level: the kinds of a problem's chain in order
+  auto chain = [](int nb, auto&& visit) {
+    visit(kPbPlan, 0);
+    visit(kPbWsk, 0);
+    visit(kPbRedw, 0);
+    for (int b = 0; b < nb; ++b) {
+      visit(kPbSmall, b);
+      visit(kPbUpd, b);
+      if (b + 1 < nb) {
+        visit(kPbQsk, b);
+        visit(kPbReds, b);
+      }
+    }
+  };
+  int64_t per_level[kPbLevels] = {0};
+  for (int64_t q = 0; q < np; ++q) {
+    const rbgs_problem& pr = probs[pb.idx[q]];
+    const int nb = (int)((pr.m + pr.p - 1) / pr.p);
+    chain(nb, [&](int kind, int b) { ++per_level[pb_level(nb, kind, b)]; });
+  }
   int64_t total = 0;
-  for (int64_t q = 0; q < np; ++q) total += pb_stage_count(probs[pb.idx[q]].m, probs[pb.idx[q]].p);
+  for (int l = 0; l < kPbLevels; ++l) total += per_level[l];
   if (total >= (int64_t)1 << 31) return fail(h, RBGS_EUNSUPPORTED, "persistent batch too large");
+  const size_t o_stages0 = off;
+  off += r256(sizeof(PbStage) * total);
+  const size_t o_valid0 = off;
+  off += r256(sizeof(unsigned) * total);
+  const size_t o_ctl0 = off;
+  off += r256(sizeof(PbCtl));
   const size_t o_stages = off;
   off += r256(sizeof(PbStage) * total);
   const size_t o_claimed = off;
@@ -1070,12 +1099,30 @@ rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* prob
     P.plan_off = (uint16_t*)(base + o[8]);
     P.plan_ent = P.plan_off + o[9];
   }
-  // the first stage of the largest problem is taken first
+  // the queue at the start: the first stage of every problem in its level,
+  // the largest problem of a level first
   std::vector<int32_t> order(np);
   for (int64_t q = 0; q < np; ++q) order[q] = (int32_t)q;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+  PbCtl c0;
+  memset(&c0, 0, sizeof c0);
+  for (int l = 0, b = 0; l < kPbLevels; b += (int)per_level[l], ++l) {
+    c0.base[l] = c0.head[l] = c0.tail[l] = (unsigned)b;
+    c0.end[l] = (unsigned)(b + per_level[l]);
+  }
+  std::vector<PbStage> stages0((size_t)total);
+  std::vector<unsigned> valid0((size_t)total, 0u);
+  for (auto& e : stages0) e = PbStage{-1, -1, -1, 0};
+  for (int32_t q : order) {
+    const int l = pb_level(host[q].nb, kPbPlan, 0);
+    const unsigned t = c0.tail[l]++;
+    stages0[t] = PbStage{q, kPbPlan, 0, 0};  // items: filled in on the device
+    valid0[t] = 1u;
+  }
   pb.probs = (PbProb*)(base + o_probs);
-  pb.order = (int32_t*)(base + o_order);
+  pb.stages0 = (PbStage*)(base + o_stages0);
+  pb.valid0 = (unsigned*)(base + o_valid0);
+  pb.ctl0 = (PbCtl*)(base + o_ctl0);
   pb.stages = (PbStage*)(base + o_stages);
   pb.claimed = (unsigned*)(base + o_claimed);
   pb.finished = (unsigned*)(base + o_finished);
@@ -1084,11 +1131,13 @@ rbgs_status persist_setup(rbgs_handle h, int64_t count, const rbgs_problem* prob
   pb.total = (unsigned)total;
   HIP_TRY(h, hipMemcpy(pb.probs, host.data(), sizeof(PbProb) * np, hipMemcpyHostToDevice),
           "upload batch descriptors");
-  HIP_TRY(h, hipMemcpy(pb.order, order.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice),
-          "upload batch order");
+  HIP_TRY(h, hipMemcpy(pb.stages0, stages0.data(), sizeof(PbStage) * total, hipMemcpyHostToDevice),
+          "upload queue");
+  HIP_TRY(h, hipMemcpy(pb.valid0, valid0.data(), sizeof(unsigned) * total, hipMemcpyHostToDevice),
+          "upload queue");
+  HIP_TRY(h, hipMemcpy(pb.ctl0, &c0, sizeof c0, hipMemcpyHostToDevice), "upload queue");
   h->pb_ctl = pb.ctl;
   h->pb_nprob = (unsigned)np;
-  h->pb_total = pb.total;
   return RBGS_OK;
 }
 
@@ -1101,9 +1150,9 @@ rbgs_status enqueue_persistent(rbgs_handle h, const PersistBatch& pb, const rbgs
           "wall clock rate");
   // every wait of a workgroup: at most 4 s (a stage takes milliseconds)
   const uint64_t limit = (uint64_t)std::max(rate_khz, 1) * 4000ull;
-  HIP_TRY(h, launch_persistent_batch(pb.probs, pb.order, (int)pb.idx.size(), pb.max_mm, pb.stages,
-                                     pb.claimed, pb.finished, pb.valid, pb.ctl, pb.total,
-                                     (int)sk->zeta, (int)opts->ls_iters, limit, cus, st),
+  HIP_TRY(h, launch_persistent_batch(pb.probs, (int)pb.idx.size(), pb.max_mm, pb.stages0, pb.valid0,
+                                     pb.ctl0, pb.stages, pb.claimed, pb.finished, pb.valid, pb.ctl,
+                                     pb.total, (int)sk->zeta, (int)opts->ls_iters, limit, cus, st),
           "persistent batch");
   return RBGS_OK;
 }
@@ -1111,7 +1160,7 @@ rbgs_status enqueue_persistent(rbgs_handle h, const PersistBatch& pb, const rbgs
 // Waits for st and reads the persistent queue's control word.
 rbgs_status persist_check(rbgs_handle h, hipStream_t st) {
   if (!h->pb_ctl) return RBGS_OK;
-  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, kHostWords * sizeof(double)), "hipHostMalloc");
   HIP_TRY(h, hipMemcpyAsync(h->host_cert, h->pb_ctl, sizeof(PbCtl), hipMemcpyDeviceToHost, st),
           "copy queue state");
   HIP_TRY(h, hipStreamSynchronize(st), "persistent batch");
@@ -1120,7 +1169,9 @@ rbgs_status persist_check(rbgs_handle h, hipStream_t st) {
   if (c.error == 1u)
     return fail(h, RBGS_EDEVICE, "persistent batch: a workgroup waited too long for a stage");
   if (c.error != 0u) return fail(h, RBGS_EDEVICE, "persistent batch: queue overflow");
-  if (c.tail != h->pb_total || c.done != h->pb_nprob)
+  bool full = true;
+  for (int l = 0; l < kPbLevels; ++l) full = full && c.tail[l] == c.end[l] && c.head[l] == c.end[l];
+  if (!full || c.done != h->pb_nprob)
     return fail(h, RBGS_EDEVICE, "persistent batch: " + std::to_string(h->pb_nprob - c.done) +
                                      " problems not finished");
   return RBGS_OK;
@@ -1591,7 +1642,7 @@ rbgs_status rbgs_block_gmres(rbgs_handle h, const rbgs_csr* A, const double* B, 
   if (!guard.ok) return fail(h, RBGS_EDEVICE, "hipSetDevice failed");
   rbgs_status rs = ensure_kry(h, off);
   if (rs != RBGS_OK) return rs;
-  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, kHostWords * sizeof(double)), "hipHostMalloc");
   char* base = (char*)h->kry;
   void* Qb = base + o_Q;
   double* Rm = (double*)(base + o_R);
@@ -1714,7 +1765,7 @@ rbgs_status rbgs_cholqr_post(rbgs_handle h, int32_t store, void* Q, int64_t ldq,
   }
   HIP_TRY(h, launch_trmm_full(G, m, R, ldr, m, T, st), "R' R");
   if (!breakdown_col) return RBGS_OK;
-  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, 8 * sizeof(double)), "hipHostMalloc");
+  if (!h->host_cert) HIP_TRY(h, hipHostMalloc((void**)&h->host_cert, kHostWords * sizeof(double)), "hipHostMalloc");
   HIP_TRY(h, hipMemcpyAsync(h->host_cert + 4, flag, sizeof(int64_t), hipMemcpyDeviceToHost, st),
           "copy flag");
   HIP_TRY(h, hipStreamSynchronize(st), "stream synchronize");

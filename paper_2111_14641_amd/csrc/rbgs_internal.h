@@ -301,23 +301,39 @@ struct PbProb {
 struct PbStage {
   int32_t prob, kind, block, nitems;
 };
+// The queue has kPbLevels priority levels, each a FIFO over its own range of
+// slots [base, end); a stage's level grows with the blocks its problem has
+// left (pb_level), and workgroups take from the highest level with work.
+constexpr int kPbLevels = 4;
 struct PbCtl {
-  unsigned head, tail, error, done;  // done: problems whose last stage has finished
+  unsigned head[kPbLevels], tail[kPbLevels], base[kPbLevels], end[kPbLevels];
+  unsigned error, done, pad[2];  // done: problems whose last stage has finished
 };
 // Stages of one problem with m columns and block width p.
 inline int64_t pb_stage_count(int64_t m, int64_t p) { return 4 * ((m + p - 1) / p) + 1; }
+// Priority level of a stage of a problem of nb blocks: blocks left (the
+// stages before the first block count as all nb) 1-2 -> 0, 3-4 -> 1, 5-6 -> 2,
+// 7 or more -> 3.
+__host__ __device__ inline int pb_level(int nb, int kind, int block) {
+  const int rem = kind <= kPbRedw ? nb : nb - block;
+  const int l = (rem - 1) / 2;
+  return l < kPbLevels - 1 ? l : kPbLevels - 1;
+}
 // LDS bytes the update of a block of width bw after K columns needs.
 inline int64_t pb_update_lds(int64_t K, int64_t bw) {
   const int64_t ncol = bw <= 16 ? 16 : 32, Kp = (K + 3) / 4 * 4;
   return (Kp * ncol + ncol * ncol + ncol) * 8;
 }
-// Initializes the queue (the first stage of problem order[i] in slot i) and,
-// per problem, R = 0 and the breakdown flag; then runs the queue.  Both on st;
-// no host synchronization.  `limit` bounds every wait of a workgroup, in
-// ticks of the device's constant-rate clock (on expiry ctl->error = 1 and the
-// workgroups leave).
-hipError_t launch_persistent_batch(const PbProb* probs, const int32_t* order, int nprob,
-                                   int64_t max_mm, PbStage* stages, unsigned* claimed,
+// Initializes the queue from the host's template (stages0 / valid0: the first
+// stage of every problem in its level's range, item counts filled in on the
+// device; ctl0: heads, tails, ranges)
+// and, per problem, R = 0 and the breakdown flag; then runs the queue.  Both
+// on st; no host synchronization.  `limit` bounds every wait of a workgroup,
+// in ticks of the device's constant-rate clock (on expiry ctl->error = 1 and
+// the workgroups leave).
+hipError_t launch_persistent_batch(const PbProb* probs, int nprob, int64_t max_mm,
+                                   const PbStage* stages0, const unsigned* valid0,
+                                   const PbCtl* ctl0, PbStage* stages, unsigned* claimed,
                                    unsigned* finished, unsigned* valid, PbCtl* ctl,
                                    unsigned total, int zeta, int ls_iters, uint64_t limit,
                                    int grid, hipStream_t st);

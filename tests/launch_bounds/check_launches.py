@@ -459,18 +459,56 @@ def pb_problem_accesses(P, zeta, ls):
     return out
 
 
+PB_LEVELS = 4
+PB_CTL = 16 * PB_LEVELS + 16   # struct PbCtl
+
+
+def pb_level(nb, kind, block):
+    rem = nb if kind in ("plan", "wsk", "redw") else nb - block
+    return min(PB_LEVELS - 1, (rem - 1) // 2)
+
+
+def pb_queue0(L, probs, total):
+    """The queue the host uploads: every problem's first stage once, in its
+    level's range; ranges that partition [0, total) with room for each level's
+    stages."""
+    st = struct.unpack("<%di" % (4 * total), uploaded(L.u(2)))
+    va = struct.unpack("<%dI" % total, uploaded(L.u(3)))
+    c0 = struct.unpack("<20I", uploaded(L.u(4)))
+    head, tail, base, end = c0[0:4], c0[4:8], c0[8:12], c0[12:16]
+    need = [0] * PB_LEVELS
+    for P in probs:
+        for kind, b in pb_chain(P):
+            need[pb_level(P["nb"], kind, b)] += 1
+    assert base[0] == 0 and end[PB_LEVELS - 1] == total
+    firsts = {}
+    for lv in range(PB_LEVELS):
+        assert end[lv] - base[lv] == need[lv], "level range"
+        if lv:
+            assert base[lv] == end[lv - 1]
+        assert head[lv] == base[lv] <= tail[lv] <= end[lv]
+        for t in range(base[lv], end[lv]):
+            q, kind, blk = st[4 * t:4 * t + 3]
+            assert bool(va[t]) == (t < tail[lv])
+            if va[t]:
+                assert kind == 0 and blk == 0 and q not in firsts
+                assert pb_level(probs[q]["nb"], "plan", 0) == lv
+                firsts[q] = t
+    assert sorted(firsts) == list(range(len(probs)))
+
+
 def _persistent_init(L):
-    # (probs, order, nprob, stages, claimed, finished, valid, ctl, total)
-    nprob, total = L.i(2), L.u(8)
+    # (probs, nprob, stages0, valid0, ctl0, stages, claimed, finished, valid, ctl, total)
+    nprob, total = L.i(1), L.u(10)
     probs = pb_problems(L.u(0))
     assert len(probs) == nprob
-    order = struct.unpack("<%di" % nprob, uploaded(L.u(1)))
-    assert sorted(order) == list(range(nprob)), "order is a permutation"
+    pb_queue0(L, probs, total)
     assert L.block[0] == 256 and L.grid[1] == nprob + 1
     assert L.grid[0] * 256 >= total
-    out = [absacc(L.u(0), PB_SIZE, 0, nprob - 1), acc(1, 4, 0, nprob - 1),
-           acc(3, 16, 0, min(nprob, total) - 1), acc(4, 4, 0, total - 1),
-           acc(5, 4, 0, total - 1), acc(6, 4, 0, total - 1), acc(7, 16, 0, 0)]
+    out = [absacc(L.u(0), PB_SIZE, 0, nprob - 1), acc(2, 16, 0, total - 1),
+           acc(3, 4, 0, total - 1), acc(4, PB_CTL, 0, 0), acc(5, 16, 0, total - 1),
+           acc(6, 4, 0, total - 1), acc(7, 4, 0, total - 1), acc(8, 4, 0, total - 1),
+           acc(9, PB_CTL, 0, 0)]
     for P in probs:
         m = P["m"]
         assert L.grid[0] * 256 >= m * m
@@ -487,7 +525,7 @@ def _persistent_batch(L):
     assert L.u(9) > 0, "wait limit"
     out = [absacc(L.u(0), PB_SIZE, 0, len(probs) - 1), acc(1, 16, 0, total - 1),
            acc(2, 4, 0, total - 1), acc(3, 4, 0, total - 1), acc(4, 4, 0, total - 1),
-           acc(5, 16, 0, 0)]
+           acc(5, PB_CTL, 0, 0)]
     for P in probs:
         out += pb_problem_accesses(P, zeta, ls)
     return out

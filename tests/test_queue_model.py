@@ -1,15 +1,17 @@
 """Model of the persistent batch's device queue (CPU, no GPU).
 
 The protocol of persistent_batch_kernel (paper_2111_14641_amd/csrc/
-batch_kernels.hip), restated step by step: each workgroup reads the head,
-looks at 64 slots from it at once (queued?, every item taken?), takes an item
-of the first stage with items left by an atomic add, and moves the head by an
-atomic max to the end of the exhausted prefix (past the stage taken when it is
-that end and its last item was taken); the workgroup that finishes a stage's
-last item reserves a slot (atomic add on the tail) and publishes the successor
-stage later.  A random scheduler interleaves the workgroups' steps, with the
-gap between a slot's reservation and its publication, and between a
-workgroup's look at the slots and its atomic add, as wide as it likes.  Every
+batch_kernels.hip), restated step by step.  The queue has priority levels, each
+a FIFO over its own range of slots.  Each workgroup reads every level's head,
+looks at 16 slots from each at once (queued?, every item taken?), takes an item
+of the first stage with items left (highest level first) by an atomic add, and
+moves that level's head by an atomic max to the end of its exhausted prefix
+(past the stage taken when it is that end and its last item was taken); the
+workgroup that finishes a stage's last item reserves a slot in the successor's
+level (atomic add on that level's tail) and publishes the successor later.
+A random scheduler interleaves the workgroups' steps, with the gap between a
+slot's reservation and its publication, and between a workgroup's look at the
+slots and its atomic add, as wide as it likes.  Every
 item of every stage must be taken exactly once, every problem must finish,
 and the head must never pass a stage that is not queued or has items left."""
 import random
@@ -17,29 +19,48 @@ import random
 import pytest
 
 
+LEVELS = 4
+WINDOW = 16
+
+
+def level_of(chain, i):
+    """Priority of stage i of a chain: grows with the stages left."""
+    return min(LEVELS - 1, (len(chain) - i - 1) // 4)
+
+
 class Queue:
     def __init__(self, chains):
         self.chains = chains                     # per problem: item counts of its stages
         self.total = sum(len(c) for c in chains)
+        need = [0] * LEVELS
+        for c in chains:
+            for i in range(len(c)):
+                need[level_of(c, i)] += 1
+        self.base, self.end = [], []
+        b = 0
+        for lv in range(LEVELS):
+            self.base.append(b)
+            b += need[lv]
+            self.end.append(b)
+        self.head = list(self.base)
+        self.tail = list(self.base)
         self.stage = [None] * self.total         # (problem, index in chain)
         self.valid = [0] * self.total
         self.claimed = [0] * self.total
         self.finished = [0] * self.total
         self.taken = [0] * self.total            # successful claims (checked)
-        self.head = 0
-        self.tail = 0
         self.done = 0
         for q in range(len(chains)):
-            self.publish(self.reserve(), (q, 0))
+            self.publish(self.reserve(level_of(chains[q], 0)), (q, 0))
 
     def n(self, slot):
         q, i = self.stage[slot]
         return self.chains[q][i]
 
-    def reserve(self):
-        t = self.tail
-        self.tail += 1
-        assert t < self.total
+    def reserve(self, lv):
+        t = self.tail[lv]
+        self.tail[lv] += 1
+        assert t < self.end[lv]
         return t
 
     def publish(self, t, st):
@@ -47,8 +68,9 @@ class Queue:
         self.valid[t] = 1
 
     def check_head(self):
-        for s in range(min(self.head, self.total)):
-            assert self.valid[s] and self.claimed[s] >= self.n(s), f"head passed slot {s}"
+        for lv in range(LEVELS):
+            for s in range(self.base[lv], min(self.head[lv], self.end[lv])):
+                assert self.valid[s] and self.claimed[s] >= self.n(s), f"head passed slot {s}"
 
 
 def workgroup(Q, rng):
@@ -56,39 +78,43 @@ def workgroup(Q, rng):
     while True:
         # --- claim --------------------------------------------------------
         while True:
-            h0 = Q.head
+            heads = list(Q.head)
             yield
-            if h0 >= Q.total:
+            if all(heads[lv] >= Q.end[lv] for lv in range(LEVELS)):
                 return
-            window = []
-            for lane in range(64):
-                s = h0 + lane
-                if s >= Q.total:
-                    window.append((False, False, 0))
-                    continue
-                queued = bool(Q.valid[s])
-                n = Q.n(s) if queued else 0
-                left = queued and Q.claimed[s] < n
-                window.append((queued, left, n))
+            window = []          # (level, slot, queued, left, n), highest level first
+            for lv in reversed(range(LEVELS)):
+                for i in range(WINDOW):
+                    s = heads[lv] + i
+                    if s >= Q.end[lv]:
+                        window.append((lv, s, False, False, 0))
+                        continue
+                    queued = bool(Q.valid[s])
+                    n = Q.n(s) if queued else 0
+                    window.append((lv, s, queued, queued and Q.claimed[s] < n, n))
             yield
-            g = next((i for i, (qd, lf, _) in enumerate(window) if not (qd and not lf)), 64)
-            f = next((i for i, (_, lf, _) in enumerate(window) if lf), None)
-            if f is None:
-                if g > 0:
-                    Q.head = max(Q.head, h0 + g)
-                    Q.check_head()
+            g = {}
+            for lv in range(LEVELS):
+                grp = [w for w in window if w[0] == lv]
+                g[lv] = next((i for i, w in enumerate(grp) if not (w[2] and not w[3])), WINDOW)
+            pick = next((w for w in window if w[3]), None)
+            if pick is None:
+                for lv in range(LEVELS):
+                    if g[lv] > 0:
+                        Q.head[lv] = max(Q.head[lv], heads[lv] + g[lv])
+                Q.check_head()
                 yield
                 continue
-            hs, nf = h0 + f, window[f][2]
+            lv, hs, _, _, nf = pick
             c = Q.claimed[hs]
             Q.claimed[hs] += 1
             yield
             if c >= nf:
                 continue
             Q.taken[hs] += 1
-            nxt = hs + 1 if (f == g and c + 1 == nf) else h0 + g
-            if nxt > h0:
-                Q.head = max(Q.head, nxt)
+            nxt = hs + 1 if (hs - heads[lv] == g[lv] and c + 1 == nf) else heads[lv] + g[lv]
+            if nxt > heads[lv]:
+                Q.head[lv] = max(Q.head[lv], nxt)
                 Q.check_head()
             yield
             break
@@ -102,7 +128,7 @@ def workgroup(Q, rng):
         if last:
             q, i = Q.stage[hs]
             if i + 1 < len(Q.chains[q]):
-                t = Q.reserve()
+                t = Q.reserve(level_of(Q.chains[q], i + 1))
                 for _ in range(rng.randrange(0, 8)):   # reserved, not yet published
                     yield
                 Q.publish(t, (q, i + 1))
@@ -138,41 +164,45 @@ def test_queue_takes_every_item_once(seed):
         steps += 1
         assert steps < 5_000_000, "no progress"
     assert Q.done == nprob
-    assert Q.tail == Q.total
+    assert Q.tail == Q.end
     for s in range(Q.total):
         assert Q.taken[s] == Q.n(s), (s, Q.taken[s], Q.n(s))
-    assert Q.head == Q.total
+    assert Q.head == Q.end
 
 
 def test_model_catches_a_head_moved_past_an_unqueued_stage():
-    """The model must flag the mistake of moving the head to the stage taken
-    (past every slot before it) without checking that those slots are
+    """The model must flag the mistake of moving a level's head to the stage
+    taken (past every slot before it) without checking that those slots are
     exhausted: with reservations published late, some seed makes a workgroup
     take a later stage while an earlier slot is still unpublished."""
     def bad_workgroup(Q, rng):
         while True:
             while True:
-                h0 = Q.head
+                heads = list(Q.head)
                 yield
-                if h0 >= Q.total:
+                if all(heads[lv] >= Q.end[lv] for lv in range(LEVELS)):
                     return
-                f = None
-                for lane in range(64):
-                    s = h0 + lane
-                    if s < Q.total and Q.valid[s] and Q.claimed[s] < Q.n(s):
-                        f = lane
+                pick = None
+                for lv in reversed(range(LEVELS)):
+                    for i in range(WINDOW):
+                        s = heads[lv] + i
+                        if s < Q.end[lv] and Q.valid[s] and Q.claimed[s] < Q.n(s):
+                            pick = (lv, s)
+                            break
+                    if pick:
                         break
                 yield
-                if f is None:
+                if pick is None:
                     yield
                     continue
-                hs, nf = h0 + f, Q.n(h0 + f)
+                lv, hs = pick
+                nf = Q.n(hs)
                 c = Q.claimed[hs]
                 Q.claimed[hs] += 1
                 if c >= nf:
                     continue
                 Q.taken[hs] += 1
-                Q.head = max(Q.head, hs + 1 if c + 1 == nf else hs)   # the mistake
+                Q.head[lv] = max(Q.head[lv], hs + 1 if c + 1 == nf else hs)   # the mistake
                 Q.check_head()
                 yield
                 break
@@ -181,7 +211,7 @@ def test_model_catches_a_head_moved_past_an_unqueued_stage():
             if Q.finished[hs] == nf:
                 q, i = Q.stage[hs]
                 if i + 1 < len(Q.chains[q]):
-                    t = Q.reserve()
+                    t = Q.reserve(level_of(Q.chains[q], i + 1))
                     for _ in range(rng.randrange(0, 8)):
                         yield
                     Q.publish(t, (q, i + 1))
