@@ -223,6 +223,24 @@ def kernel_breakdown(W, p, kind, k, seed, variant, reps=2, math="f64"):
     return out
 
 
+def targets(roofline, speedup, forms):
+    """The workload's targets beside what this run measured (met or missed)."""
+    out = {"update_hbm_frac": dict(target=0.70, measured=roofline["frac"],
+                                   met=roofline["frac"] >= 0.70)}
+    if speedup is not None:
+        out["f32_storage_speedup_vs_f64"] = dict(target=2.0, measured=round(speedup, 3),
+                                                 met=speedup >= 2.0)
+    g = forms.get("gmres_convdiff_1024_f32basis")
+    if g is not None:
+        out["gmres_relres"] = dict(target=1e-8, measured=g["relres"], met=bool(g["converged"]))
+    b = forms.get("batched_512_f32")
+    if b is not None:
+        out["batched_persistent_vs_lockstep_graph"] = dict(
+            target=1.0, measured=b["persistent_speedup_vs_graph"],
+            met=b["persistent_speedup_vs_graph"] > 1.0)
+    return out
+
+
 def batched_form(count=512, reps=3):
     """The batched workload: `count` FP32 problems of uneven n and m, tuned p
     and k: the lock-step groups replayed as one graph per batch, the same QRs
@@ -571,6 +589,7 @@ def main():
                   for name, f in forms.items()},
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
+        "targets": targets(roofline, speedup, forms),
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
