@@ -164,7 +164,8 @@ def test_persistent_batch_gpu_test_shapes_stay_in_bounds(driver):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import test_gpu_persistent as tp
     exe, out = driver
-    for name, shapes in (("oracle", tp.SHAPES), ("streams", tp.STREAM_SHAPES)):
+    for name, shapes in (("oracle", tp.SHAPES), ("streams", tp.STREAM_SHAPES),
+                         ("random", tp.RANDOM_SHAPES)):
         spec = ";".join(",".join(str(v) for v in s) for s in shapes)
         log = str(out / ("batchs_%s.txt" % name))
         r = subprocess.run([exe, "batchs", spec], capture_output=True, text=True,
