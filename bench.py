@@ -101,7 +101,7 @@ def accuracy_chunked(W, Q, R, cert, chunk=1 << 20):
 
 
 def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False, math="f64",
-              profile_sketch=False, chunked_metrics=False, keep_R=False):
+              profile_sketch=False, chunked_metrics=False, keep_R=False, ls_iters=LS_ITERS):
     """Times `steps` QRs on a dedicated stream.  With profile_update, a second
     timed region of `steps` QRs follows in which HIP events bracket every
     update launch on its stream (the roofline figure); the events themselves
@@ -115,7 +115,8 @@ def time_form(W, p, kind, k, seed, variant, steps, warmup, profile_update=False,
     n, m = W.shape
     Q = B.colmajor(n, m, W.dtype, W.device)
     R = B.colmajor(m, m, torch.float64, W.device)
-    run = lambda **kw: B.rbgs_qr(W, p, kind, k, seed, None, variant, LS_ITERS, Q=Q, R=R, math=math, **kw)
+    run = lambda **kw: B.rbgs_qr(W, p, kind, k, seed, None, variant, ls_iters, Q=Q, R=R, math=math,
+                                 **kw)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         # accuracy run (with certificate) outside the timed region
@@ -525,6 +526,9 @@ def main():
                                                  max(3, args.steps // 4), 1)
         forms["f32_sparse_l2qr"], _ = time_form(W32, p, "sparse", k, THETA_SEED_LARGE, "l2qr",
                                                 max(3, args.steps // 4), 1)
+        # the direct (Householder) least squares in place of the sweeps
+        forms["f32_sparse_lowsync_householder_ls"], _ = time_form(
+            W32, p, "sparse", k, THETA_SEED_LARGE, "lowsync", max(3, args.steps // 4), 1, ls_iters=0)
         if not args.no_gaussian:
             print("[bench] gaussian forms", file=sys.stderr, flush=True)
             forms["f32_gauss_lowsync"], _ = time_form(W32, p, "gaussian", k, THETA_SEED_LARGE,

@@ -141,14 +141,16 @@ typedef struct {
   int32_t store;     /* rbgs_store                                        */
   int32_t math;      /* rbgs_math                                         */
   int32_t variant;   /* rbgs_variant                                      */
-  int32_t ls_iters;  /* Richardson sweeps l >= 1 for the least-squares step
-                        (supplement, Section SM.1); error <= Delta^l |y|.
-                        0 would select the direct Householder solver of
-                        Section 2.1: it is not implemented on the GPU and
-                        returns RBGS_EUNSUPPORTED (the sketch is nearly
-                        orthonormal, so 4 sweeps reach the Householder result
-                        on the numerically rank-deficient workloads; the
-                        direct solver stays in the FP64 oracle).  Outside
+  int32_t ls_iters;  /* Least-squares step (step 2).  l >= 1: Richardson
+                        sweeps (supplement, Section SM.1); error <=
+                        Delta^l |y|.  0: the direct Householder solver of
+                        Section 2.1: a Householder QR of the sketch
+                        S_(1:i-1), extended by each block's S_(i), applied
+                        to P_(i) and solved with its R (one workgroup, FP64;
+                        slower, for checking the sweeps); it needs k <= 1024,
+                        at most 1024 columns before the last block and
+                        p <= 16 when k > 512 (else RBGS_EUNSUPPORTED), and
+                        batched calls run such problems one by one.  Outside
                         [0, 16]: RBGS_EINVAL.                              */
   void* stream;      /* hipStream_t or NULL                               */
 } rbgs_opts;

@@ -290,12 +290,13 @@ static rbgs_status validate_qr(rbgs_handle h, const void* W, int64_t ldw, int64_
     return fail(h, RBGS_EINVAL, "FP64 storage needs FP64 arithmetic");
   if (opts->variant < RBGS_VARIANT_PLAIN || opts->variant > RBGS_VARIANT_L2QR)
     return fail(h, RBGS_EINVAL, "unknown variant");
-  if (opts->ls_iters == 0)
-    return fail(h, RBGS_EUNSUPPORTED,
-                "ls_iters = 0 (Householder least squares) is not implemented on the GPU; "
-                "use ls_iters >= 1 Richardson sweeps");
   if (opts->ls_iters < 0 || opts->ls_iters > 16)
-    return fail(h, RBGS_EINVAL, "ls_iters must be in [1, 16]");
+    return fail(h, RBGS_EINVAL, "ls_iters must be in [0, 16]");
+  if (opts->ls_iters == 0 && p <= 32 &&
+      !hh_supported(sk->k, ((m - 1) / p) * p, (int)std::min<int64_t>(p, m)))
+    return fail(h, RBGS_EUNSUPPORTED,
+                "ls_iters = 0 (Householder least squares) needs k <= 1024, at most 1024 columns "
+                "before the last block, and p <= 16 when k > 512");
   if (p > 32) return fail(h, RBGS_EUNSUPPORTED, "block width p > 32 is not implemented");
   const size_t es = opts->store == RBGS_STORE_F32 ? 4 : 8;
   {
@@ -389,6 +390,7 @@ struct QrRun {
   double* R;
   int64_t ldr;
   double *S, *P, *E, *part, *stack, *G, *Cb, *Yb, *cscratch, *cout, *Rt, *tall;
+  double *HS, *tau;  // Householder factorization of S_(1:i-1) (ls_iters = 0)
   uint16_t* plan;
   int64_t* flag;
   unsigned* counters;
@@ -464,6 +466,9 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
     if (m % b) tall_need = std::max(tall_need, qr_stack_size(n, (int)(m % b)));
   }
   const size_t o_tall = tall_need ? carve(tall_need) : 0;
+  const bool hh = r.l == 0;
+  const size_t o_HS = hh ? carve((size_t)k * m) : 0;
+  const size_t o_tau = hh ? carve((size_t)m) : 0;
   char* base;
   if (ext_ws) {
     if (off > ext_bytes)
@@ -491,6 +496,8 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.cout = (double*)(base + o_cout);
   r.Rt = twice ? (double*)(base + o_Rt) : nullptr;
   r.tall = tall_need ? (double*)(base + o_tall) : nullptr;
+  r.HS = hh ? (double*)(base + o_HS) : nullptr;
+  r.tau = hh ? (double*)(base + o_tau) : nullptr;
   hipStream_t st = r.st;
   HIP_TRY(h, launch_qr_init(R, ldr, m, r.flag, r.counters, 1 + kQrTreeCounters, st), "init");
   if (r.plan) {
@@ -526,10 +533,17 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     rs = do_sketch(h, d, r.f32, Wi, ldwi, n, bw, 0, Pi, k, r.part, r.plan, st);
     if (rs != RBGS_OK) return rs;
   }
-  // ---- step 2: sketched least squares by l Richardson sweeps ----------
-  // One pass over S gives c = S^T P_(i) (sweep 1: R_(1:i-1,i) = c) and the
-  // Gram block S^T S_(i-1); sweeps 2..l use the Gram matrix.
-  if (K > 0) {
+  // ---- step 2: sketched least squares ----------------------------------
+  // l = 0: Householder (the factorization of S_(1:i-1) is kept up to date).
+  if (K > 0 && l == 0) {
+    ProfScope ps(h, kProfSmall, 0.0, st);
+    HIP_TRY(h, launch_hh_solve(r.HS, r.tau, Pi, k, K, bw, Rk, ldr, st),
+            "least squares: Householder");
+  }
+  // l >= 1 Richardson sweeps: one pass over S gives c = S^T P_(i) (sweep 1:
+  // R_(1:i-1,i) = c) and the Gram block S^T S_(i-1); sweeps 2..l use the Gram
+  // matrix.
+  if (K > 0 && l > 0) {
     ProfScope ps(h, kProfSmall, 0.0, st);
     const int bprev = b;  // width of block i-1 (only the last block can be narrower)
     const double* Sprev = r.S + (K - bprev) * k;
@@ -645,11 +659,18 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     HIP_TRY(h, launch_sketch_reduce(r.part + (slots - bw1) * k, G, k, bw1, sc, r.P + (c0 + b) * k, k,
                                     st, slots),
             "sketch reduction");
-    return RBGS_OK;
+  } else {
+    // the sketch of the last block is used only by S_out and the certificates
+    if (!r.last_s && c0 + bw >= m) return RBGS_OK;
+    rs = do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.S + c0 * k, k, r.part, r.plan, st);
+    if (rs != RBGS_OK) return rs;
   }
-  // the sketch of the last block is used only by S_out and the certificates
-  if (!r.last_s && c0 + bw >= m) return RBGS_OK;
-  return do_sketch(h, d, r.f32, Qi, r.ldq, n, bw, 0, r.S + c0 * k, k, r.part, r.plan, st);
+  if (l == 0 && c0 + bw < m) {
+    ProfScope ps(h, kProfSmall, 0.0, st);
+    HIP_TRY(h, launch_hh_absorb(r.S + c0 * k, k, c0, bw, r.HS, r.tau, st),
+            "least squares: Householder update");
+  }
+  return RBGS_OK;
 }
 
 // Step 6: certificates; the host waits for the stream.
@@ -815,7 +836,7 @@ struct LockGroup {
 
 bool lockstep_ok(const rbgs_problem& pr, const rbgs_sketch* sk, const rbgs_opts* opts) {
   return opts->variant == RBGS_VARIANT_LOWSYNC && sk->kind == RBGS_SKETCH_SPARSE_SIGN &&
-         pr.p <= 32 && pr.k <= 2048;
+         opts->ls_iters >= 1 && pr.p <= 32 && pr.k <= 2048;
 }
 
 // Groups, arena layout and descriptor upload (waits for the copy).
@@ -968,7 +989,8 @@ struct PersistBatch {
 
 bool persist_ok(const rbgs_problem& pr, const rbgs_sketch* sk, const rbgs_opts* opts) {
   if (opts->variant != RBGS_VARIANT_LOWSYNC || sk->kind != RBGS_SKETCH_SPARSE_SIGN ||
-      opts->store != RBGS_STORE_F32 || opts->math != RBGS_MATH_F64 || sk->zeta > 8)
+      opts->store != RBGS_STORE_F32 || opts->math != RBGS_MATH_F64 || sk->zeta > 8 ||
+      opts->ls_iters < 1)
     return false;
   if (pr.p > kPbMaxP || pr.k > kPbMaxK) return false;
   const int64_t last_c0 = ((pr.m - 1) / pr.p) * pr.p;  // columns before the last block

@@ -468,6 +468,17 @@ hipError_t launch_trmm_full(const double* A, int64_t lda, double* R, int64_t ldr
                             double* T, hipStream_t st);
 // Fill an m x m column-major matrix (ld) with zeros.
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+// Householder least squares of step 2 (one workgroup; hh_supported: k <= 1024,
+// K <= 1024, bw <= 32 for k <= 512 and bw <= 16 above):
+// absorb: columns c0 .. c0 + bw - 1 of the sketch (Snew, k x bw, ld k) into
+// the factorization HS (k x m, ld k: R_S on and above the diagonal, reflector
+// vectors below) and tau (m); solve: Y (K x bw, ld ldy) = the least-squares
+// solution of S_(1:K) Y = P (k x bw, ld k), K <= 1024.
+bool hh_supported(int64_t k, int64_t K, int bw);
+hipError_t launch_hh_absorb(const double* Snew, int64_t k, int64_t c0, int bw, double* HS,
+                            double* tau, hipStream_t st);
+hipError_t launch_hh_solve(const double* HS, const double* tau, const double* P, int64_t k,
+                           int64_t K, int bw, double* Y, int64_t ldy, hipStream_t st);
 // R = 0 (m x m), *flag = -1, counters[0 .. ncnt) = 0, in one launch.
 hipError_t launch_qr_init(double* R, int64_t ldr, int64_t m, int64_t* flag, unsigned* counters,
                           int ncnt, hipStream_t st);

@@ -439,6 +439,179 @@ __global__ void init_batched_kernel(const BatchItem* items, int64_t m) {
   if (idx < kQrTreeCounters) it.counter[idx] = 0u;
 }
 
+// ---------------------------------------------------------------------------
+// Direct least squares of step 2 (Section 2.1): Householder QR of the sketch
+// S_(1:i-1), kept up to date block by block in the form of LAPACK's geqrf (R
+// on and above the diagonal of HS, the reflectors' vectors below it with a
+// unit leading entry, their scalars in tau), so R_(1:i-1,i) = R_S^{-1}
+// (H_(K-1) .. H_0 P_(i))[0:K].  FP64; one workgroup of 16 waves, each holding
+// one or two columns of k <= 64 RPT rows in registers (lane l: rows l + 64 i).
+// ---------------------------------------------------------------------------
+constexpr int kHhMaxK = 1024;  // rows of the sketch and columns of S_(1:i-1)
+
+// x <- H_j x for the column held in a[] (rows j.. of reflector j; v_j[j] = 1).
+// The vector is read twice (for the dot product, then for the update; the
+// second read hits the cache) rather than held, to keep the registers for the
+// columns.
+template <int RPT>
+__device__ __forceinline__ void hh_reflect(double (&a)[RPT], const double* __restrict__ v,
+                                           double t, int j, int k, int lane) {
+  auto vi = [&](int i) {
+    const int row = lane + 64 * i;
+    const bool below = row > j && row < k;
+    const double x = v[below ? row : j];
+    return below ? x : (row == j ? 1.0 : 0.0);
+  };
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    if (i & 1) d1 = fma(vi(i), a[i], d1);
+    else d0 = fma(vi(i), a[i], d0);
+  }
+  const double w = t * wave_total(d0 + d1);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) a[i] = fma(-w, vi(i), a[i]);
+}
+
+// New columns c0 .. c0 + bw - 1 of the sketch (Snew, k x bw, ld k) into the
+// factorization: the reflectors 0 .. c0 - 1 applied to them, then their own
+// Householder QR on rows c0 .. k - 1 (LAPACK's sign convention: beta =
+// -sign(alpha) ||x||, tau = (beta - alpha) / beta, tau = 0 for a zero tail).
+// Wave w holds columns w + 16 q, q < CPW (bw <= 16 CPW).
+template <int RPT, int CPW>
+__global__ __launch_bounds__(kQwThreads) void hh_absorb_kernel(const double* __restrict__ Snew,
+                                                               int k, int c0, int bw,
+                                                               double* HS, double* tau) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a[CPW][RPT];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = w + 16 * q;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = lane + 64 * i;
+      const bool ok = c < bw && row < k;
+      const double x = Snew[ok ? row + (int64_t)c * k : 0];
+      a[q][i] = ok ? x : 0.0;
+    }
+  }
+  for (int j = 0; j < c0; ++j) {
+    const double t = tau[j];
+    if (t == 0.0) continue;
+#pragma unroll
+    for (int q = 0; q < CPW; ++q)
+      if (w + 16 * q < bw) hh_reflect<RPT>(a[q], HS + (int64_t)j * k, t, j, k, lane);
+  }
+  for (int jj = 0; jj < bw; ++jj) {
+    const int j = c0 + jj;
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      if (w + 16 * q != jj) continue;  // the pivot column's wave
+      double xs = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = lane + 64 * i;
+        if (row == j) xs = a[q][i];
+        if (row > j && row < k) s2 = fma(a[q][i], a[q][i], s2);
+      }
+      const double alpha = wave_total(xs);   // one nonzero term: exact
+      const double sigma = wave_total(s2);
+      double beta = alpha, t = 0.0, scale = 0.0;
+      if (sigma != 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, sigma));
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      double* col = HS + (int64_t)j * k;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int row = lane + 64 * i;
+        if (row < k) col[row] = row < j ? a[q][i] : (row == j ? beta : a[q][i] * scale);
+      }
+      if (lane == 0) tau[j] = t;
+    }
+    __syncthreads();
+    const double t = tau[j];
+    if (t != 0.0) {
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        const int c = w + 16 * q;
+        if (c < bw && c > jj) hh_reflect<RPT>(a[q], HS + (int64_t)j * k, t, j, k, lane);
+      }
+    }
+  }
+}
+
+// Y (K x bw, ld ldy) = R_S^{-1} (H_(K-1) .. H_0 P)[0:K] for P (k x bw, ld k):
+// wave w takes columns w, w + 16; the back substitution runs on the wave's
+// column in LDS (y_r = c_r / R_rr, then c_l -= y_r R_lr for l < r).
+template <int RPT>
+__global__ __launch_bounds__(kQwThreads) void hh_solve_kernel(const double* __restrict__ HS,
+                                                              const double* __restrict__ tau,
+                                                              const double* __restrict__ P, int k,
+                                                              int K, int bw, double* Y,
+                                                              int64_t ldy) {
+  __shared__ double cs[16][kHhMaxK];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c = w; c - w < bw; c += 16) {
+    if (c >= bw) continue;  // wave-uniform
+    double a[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = lane + 64 * i;
+      const double x = P[(row < k ? row : 0) + (int64_t)c * k];
+      a[i] = row < k ? x : 0.0;
+    }
+    for (int j = 0; j < K; ++j) {
+      const double t = tau[j];
+      if (t != 0.0) hh_reflect<RPT>(a, HS + (int64_t)j * k, t, j, k, lane);
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int row = lane + 64 * i;
+      if (row < K) cs[w][row] = a[i];
+    }
+    for (int r = K - 1; r >= 0; --r) {
+      const double y = cs[w][r] / HS[r + (int64_t)r * k];
+      const double* Rr = HS + (int64_t)r * k;
+      for (int l = lane; l < r; l += 64) cs[w][l] = fma(-y, Rr[l], cs[w][l]);
+      if (lane == 0) cs[w][r] = y;
+    }
+    for (int l = lane; l < K; l += 64) Y[l + (int64_t)c * ldy] = cs[w][l];
+  }
+}
+
+bool hh_supported(int64_t k, int64_t K, int bw) {
+  return k <= kHhMaxK && K <= kHhMaxK && K >= 0 && bw >= 1 && bw <= (k <= 512 ? 32 : 16);
+}
+
+hipError_t launch_hh_absorb(const double* Snew, int64_t k, int64_t c0, int bw, double* HS,
+                            double* tau, hipStream_t st) {
+  if (!hh_supported(k, c0, bw)) return hipErrorInvalidValue;
+#define RBGS_HHA(R, C)                                                                           \
+  hipLaunchKernelGGL((hh_absorb_kernel<R, C>), dim3(1), dim3(kQwThreads), 0, st, Snew, (int)k,   \
+                     (int)c0, bw, HS, tau)
+  if (k <= 256) RBGS_HHA(4, 2);
+  else if (k <= 512) RBGS_HHA(8, 2);
+  else RBGS_HHA(16, 1);
+#undef RBGS_HHA
+  return hipGetLastError();
+}
+
+hipError_t launch_hh_solve(const double* HS, const double* tau, const double* P, int64_t k,
+                           int64_t K, int bw, double* Y, int64_t ldy, hipStream_t st) {
+  if (!hh_supported(k, K, bw) || K < 1) return hipErrorInvalidValue;
+#define RBGS_HHS(R)                                                                              \
+  hipLaunchKernelGGL(hh_solve_kernel<R>, dim3(1), dim3(kQwThreads), 0, st, HS, tau, P, (int)k,    \
+                     (int)K, bw, Y, ldy)
+  if (k <= 256) RBGS_HHS(4);
+  else if (k <= 512) RBGS_HHS(8);
+  else RBGS_HHS(16);
+#undef RBGS_HHS
+  return hipGetLastError();
+}
+
 // Deterministic test matrix for the autotuner: x[r][c] = a hash of (r, c)
 // mapped to [-1, 1) (full rank with overwhelming probability).
 __global__ void fill_test_kernel(void* X, int f32, int64_t n, int64_t m, int64_t ld) {

@@ -193,6 +193,31 @@ def _qr_wave(L):
             acc(5, 8, 0, 0)]
 
 
+def _trmm_upper(L):
+    # (A, lda, R, ldr, bw): thread (i, j) = (t % 32, t / 32)
+    lda, ldr, bw = L.i(1), L.i(3), L.i(4)
+    assert L.grid[0] == 1 and L.block[0] == 1024 and 1 <= bw <= 32
+    return [acc(0, 8, 0, (bw - 1) + (bw - 1) * lda), acc(2, 8, 0, (bw - 1) + (bw - 1) * ldr)]
+
+
+def _hh_absorb(L, RPT, CPW):
+    # (Snew, k, c0, bw, HS, tau)
+    k, c0, bw = L.i(1), L.i(2), L.i(3)
+    assert L.grid[0] == 1 and L.block[0] == 1024
+    assert 64 * RPT >= k and 16 * CPW >= bw >= 1 and c0 >= 0
+    return [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(4, 8, 0, (c0 + bw) * k - 1),
+            acc(5, 8, 0, c0 + bw - 1)]
+
+
+def _hh_solve(L, RPT):
+    # (HS, tau, P, k, K, bw, Y, ldy)
+    k, K, bw, ldy = L.i(3), L.i(4), L.i(5), L.i(7)
+    assert L.grid[0] == 1 and L.block[0] == 1024
+    assert 64 * RPT >= k and 1 <= K <= 1024 and 1 <= bw <= 32
+    return [acc(0, 8, 0, K * k - 1), acc(1, 8, 0, K - 1), acc(2, 8, 0, (k - 1) + (bw - 1) * k),
+            acc(6, 8, 0, (K - 1) + (bw - 1) * ldy)]
+
+
 def _update_general(L, T, NB):
     # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, nfull, n, K, bw)
     es = 4 if T == "f" else 8
@@ -582,6 +607,7 @@ MIRRORS = {
     "sketch_resid_kernel": _sketch_resid,
     "sum_kernel": _sum,
     "finite_kernel": _finite,
+    "trmm_upper_kernel": _trmm_upper,
     "persistent_init_kernel": _persistent_init,
     "persistent_batch_kernel": _persistent_batch,
 }
@@ -594,6 +620,8 @@ TEMPLATED = {
     "sketch_srht_kernel": lambda L, t: _sketch_srht(L, t[0], t[1]),
     "qr_wave_kernel": lambda L, t: _qr_wave(L),
     "sketch_identity_kernel": lambda L, t: _sketch_identity(L, t[0]),
+    "hh_absorb_kernel": lambda L, t: _hh_absorb(L, t[0], t[1]),
+    "hh_solve_kernel": lambda L, t: _hh_solve(L, t[0]),
 }
 
 

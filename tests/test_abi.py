@@ -69,7 +69,8 @@ def _qr(lib, h, n=100, m=8, p=4, k=32, kind=0, zeta=8, store=0, math=0, variant=
     (dict(store=0, math=2), B.RBGS_EINVAL),       # BF16x3 products need FP32 storage
     (dict(store=2), B.RBGS_EINVAL),
     (dict(variant=4), B.RBGS_EINVAL),
-    (dict(iters=0), B.RBGS_EUNSUPPORTED),         # Householder least squares: not on the GPU
+    (dict(iters=0, k=1032, n=2000), B.RBGS_EUNSUPPORTED),           # Householder: k <= 1024
+    (dict(iters=0, k=600, n=2000, m=64, p=32), B.RBGS_EUNSUPPORTED),  # and p <= 16 past k = 512
     (dict(iters=-1), B.RBGS_EINVAL),
     (dict(iters=17), B.RBGS_EINVAL),
     (dict(ldw=50), B.RBGS_EINVAL),

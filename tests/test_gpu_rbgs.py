@@ -470,3 +470,87 @@ def test_leading_dimensions_give_identical_results(gpu_lib, store, ldw_pad, ldq_
     assert torch.equal(Q1, Q0)
     if ldq_pad:
         assert bool((Qb[n:] == 7.0).all())   # nothing written past row n
+
+
+# ---------------------------------------------------------------------------
+# Direct (Householder) least squares of step 2: ls_iters = 0
+# ---------------------------------------------------------------------------
+def oracle_qr_householder(W, b, kind, k, seed, variant, zeta=None):
+    th = Sketch(kind, k, seed=seed, zeta=zeta).materialize(W.shape[0])
+    o = orb.rbgs(W, b, th, variant, "householder")
+    o["absT"] = pc.abs_theta(th, W.shape[0])
+    return o
+
+
+@pytest.mark.parametrize("n,m,b,k,kind,variant", [
+    (10_000, 64, 8, 256, "gaussian", "lowsync"),
+    (10_000, 64, 8, 256, "gaussian", "plain"),
+    (7777, 70, 16, 1024, "sparse", "lowsync"),      # k = 1024: 16 rows per lane, ragged last block
+    (5000, 96, 32, 512, "sparse", "lowsync"),       # 32-wide blocks (two columns per wave)
+    (4097, 40, 32, 132, "rademacher", "plain"),     # Rademacher, k not a multiple of 64
+    (4097, 30, 8, 128, "sparse", "twice"),
+    (3000, 70, 16, 256, "srht", "lowsync"),
+    (2000, 1, 4, 8, "sparse", "lowsync"),           # m = 1: no least squares at all
+    (3000, 24, 24, 96, "gaussian", "lowsync"),      # one block
+    (5000, 17, 1, 64, "sparse", "plain"),           # single-column blocks: 16 factorization updates
+])
+def test_householder_least_squares_fp64(gpu_lib, n, m, b, k, kind, variant):
+    """The GPU's Householder least squares (QR of S_(1:i-1) extended block by
+    block) against the oracle's direct solver (LAPACK QR of S_(1:i-1))."""
+    W = svd_matrix(n, m, np.logspace(0, -2, m), seed=n + m + 3 * b)
+    say("householder", n, m, b, k, kind, variant)
+    Q, R, S, cert = gpu_qr(W, b, kind, k, 31, variant, ls_iters=0)
+    o = oracle_qr_householder(W, b, kind, k, 31, variant)
+    assert rel(R, o["R"]) < 1e-12
+    assert rel(Q, o["Q"]) < 1e-11
+    check_entrywise(W, Q, R, S, cert, o, TOL64)
+    assert factorization_error(W, Q, R) < 1e-14
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_householder_matches_sweeps_on_rank_deficient_input(gpu_lib, store):
+    """On a numerically rank-deficient W (cond 1e14) the direct solver and 4
+    Richardson sweeps give the same factorization quality (the sweeps' error
+    Delta^4 |y| is below the rounding of step 3), and the direct GPU result
+    matches the oracle's direct result in the metrics."""
+    n, m, b, k = 20_000, 96, 16, 512
+    W = svd_matrix(n, m, np.logspace(0, -14, m), seed=77)
+    if store == "f32":
+        W = W.astype(np.float32).astype(np.float64)
+    say("householder rank deficient", store)
+    Qh, Rh, Sh, ch = gpu_qr(W, b, "sparse", k, 5, "lowsync", store=store, ls_iters=0)
+    Qr, Rr, Sr, cr = gpu_qr(W, b, "sparse", k, 5, "lowsync", store=store, ls_iters=4)
+    o = oracle_qr_householder(W, b, "sparse", k, 5, "lowsync")
+    target = 1e-14 if store == "f64" else 1e-6
+    for Q, R in ((Qh, Rh), (Qr, Rr)):
+        assert factorization_error(W, Q, R) < target
+        assert cond2(Q) <= 10
+    assert abs(cond2(Qh) - cond2(o["Q"])) <= 0.05 * cond2(o["Q"])
+    assert abs(cond2(Qh) - cond2(Qr)) <= 0.05 * cond2(Qr)
+
+
+def test_householder_in_a_batch(gpu_lib):
+    """Batched problems with ls_iters = 0 run one by one (the lock-step and
+    persistent forms use the sweeps) and each matches the oracle."""
+    import torch
+    from paper_2111_14641_amd import binding as B
+    say("householder batch")
+    shapes = [(3000, 32, 16, 96), (5000, 48, 8, 128), (4097, 40, 32, 160)]
+    Wh, Ws = [], []
+    for i, (n, m, b, k) in enumerate(shapes):
+        W = svd_matrix(n, m, np.logspace(0, -2, m), seed=400 + i)
+        Wt = B.colmajor(n, m, torch.float64)
+        Wt.copy_(torch.from_numpy(W))
+        Wh.append(W)
+        Ws.append(Wt)
+    for persistent in (False, True):
+        Qs, Rs, _, _ = B.rbgs_qr_batched(Ws, [s[2] for s in shapes], [s[3] for s in shapes],
+                                         seed=50, ls_iters=0, persistent=persistent)
+        torch.cuda.synchronize()
+        for i, (W, Q, R) in enumerate(zip(Wh, Qs, Rs)):
+            n, m, b, k = shapes[i]
+            o = oracle_qr_householder(W, b, "sparse", k, 50 + i, "lowsync")
+            Rg = np.ascontiguousarray(R.cpu().numpy())
+            Qg = np.ascontiguousarray(Q.cpu().numpy())
+            assert rel(Rg, o["R"]) < 1e-12, (persistent, i)
+            pc.assert_qrs_entrywise(Qg, Rg, None, o, None, TOL64, TOL64)

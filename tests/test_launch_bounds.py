@@ -52,6 +52,12 @@ CASES = [
     (8192, 40, 32, 8192, 2, F64, 0, PLAIN, 2, 1, 1),
     (4097, 30, 8, 132, RADEM, F64, 0, LOWSYNC, 2, 1, 1),
     (10_000, 64, 8, 256, GAUSS, F32, 1, PLAIN, 2, 1, 1),
+    # Householder least squares (ls_iters = 0)
+    (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 0, 1, 1),
+    (10_000, 64, 8, 256, GAUSS, F64, 0, PLAIN, 0, 1, 1),
+    (5000, 96, 32, 512, SPARSE, F64, 0, LOWSYNC, 0, 1, 1),
+    (4097, 70, 32, 256, GAUSS, F64, 0, TWICE, 0, 1, 1),
+    (3000, 150, 16, 1024, RADEM, F64, 0, LOWSYNC, 0, 0, 0),
 ]
 
 
