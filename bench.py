@@ -36,7 +36,9 @@ LS_ITERS = 4   # Richardson sweeps of the least-squares step
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernel_hbm_traffic_n1e6_m256_p16_k1024_f32.md")
-UPDATE_SRC = os.path.join(ROOT, "paper_2111_14641_amd", "csrc", "update_kernels.hip")
+# the update kernel's source: its launcher file and the header with its device bodies
+UPDATE_SRC = [os.path.join(ROOT, "paper_2111_14641_amd", "csrc", f)
+              for f in ("update_kernels.hip", "update_device.h")]
 
 
 def measured_traffic(n, m, p, k):
@@ -46,7 +48,7 @@ def measured_traffic(n, m, p, k):
         return None
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(UPDATE_SRC, "rb").read()).hexdigest()
+        src = hashlib.sha256(b"".join(open(f, "rb").read() for f in UPDATE_SRC)).hexdigest()
     except OSError:
         return None
     mt = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
