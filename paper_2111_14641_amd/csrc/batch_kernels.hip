@@ -388,14 +388,14 @@ __device__ __forceinline__ void pb_small(const PbProb& P, int block, int ls) {
 // Steps 3-5 of block i for update tiles item, item + nitems, ...  NB = 2
 // (block width p > 16) reads two rows per lane instead of four (512-row
 // tiles), which keeps it within the register budget of 16 waves per CU.
-template <int NB>
+template <int NB, int FORM>
 __device__ __forceinline__ void pb_update(const PbProb& P, int block, int item, int nitems) {
   constexpr int WV = kPbThreads / 64;
   constexpr int VE = NB == 1 ? 4 : 2;
   constexpr int NCOL = 16 * NB;
   constexpr int TROWS = UpPShape<float, NB, WV, VE>::TILE;
   const int64_t c0 = (int64_t)block * P.p;
-  const int K = (int)c0, Kp = (K + 3) / 4 * 4;
+  const int K = (int)c0, Kp = up_p_rows(K, NB);
   const int bw = pb_bw(P, block);
   double* Rs = reinterpret_cast<double*>(pb_pool);
   double* Ru = Rs + (int64_t)Kp * NCOL;
@@ -405,8 +405,8 @@ __device__ __forceinline__ void pb_update(const PbProb& P, int block, int item, 
   __syncthreads();
   const float* Wi = P.W + c0 * P.ldw;
   float* Qi = P.Q + c0 * P.ldq;
-  update_p_full_tiles<float, NB, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru, Rinv, true,
-                                         item, nitems, P.up_nfull, K, bw);
+  update_p_full_tiles<float, NB, FORM, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru, Rinv,
+                                               true, item, nitems, P.up_nfull, K, bw);
   for (int64_t tile = item; tile < P.up_tiles; tile += nitems)
     if (tile >= P.up_nfull)
       update_p_guarded_tile<float, NB, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru, Rinv,
@@ -446,9 +446,20 @@ __device__ __noinline__ void pb_run_reduce(const PbProb* Pp, int block, int item
 __device__ __noinline__ void pb_run_small(const PbProb* P, int block, int ls) {
   pb_small(*uni(P), uni(block), uni(ls));
 }
-template <int NB>
+template <int NB, int FORM>
 __device__ __noinline__ void pb_run_update(const PbProb* P, int block, int item, int nitems) {
-  pb_update<NB>(*uni(P), uni(block), uni(item), uni(nitems));
+  pb_update<NB, FORM>(*uni(P), uni(block), uni(item), uni(nitems));
+}
+// the update in the form its block needs (up_p_form), each a function of its own
+template <int NB>
+__device__ __forceinline__ void pb_run_update_form(const PbProb* P, int block, int item,
+                                                   int nitems) {
+  switch (up_p_form(block * P->p, pb_bw(*P, block), NB)) {
+    case 0: pb_run_update<NB, 0>(P, block, item, nitems); break;
+    case 1: pb_run_update<NB, 1>(P, block, item, nitems); break;
+    case 2: pb_run_update<NB, 2>(P, block, item, nitems); break;
+    default: pb_run_update<NB, 3>(P, block, item, nitems); break;
+  }
 }
 
 }  // namespace
@@ -514,8 +525,8 @@ __global__ __launch_bounds__(kPbThreads, 1) void persistent_batch_kernel(
         pb_run_small(P, block, a.ls);
         break;
       case kPbUpd:
-        if (P->p <= 16) pb_run_update<1>(P, block, item, uni(s_st.nitems));
-        else pb_run_update<2>(P, block, item, uni(s_st.nitems));
+        if (P->p <= 16) pb_run_update_form<1>(P, block, item, uni(s_st.nitems));
+        else pb_run_update_form<2>(P, block, item, uni(s_st.nitems));
         break;
       case kPbQsk:
         if (pb_bw(*P, block) > 8) pb_run_sketch_q<16>(P, block, item, a.zeta);

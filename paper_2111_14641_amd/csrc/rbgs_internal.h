@@ -319,9 +319,17 @@ __host__ __device__ inline int pb_level(int nb, int kind, int block) {
   const int l = (rem - 1) / 2;
   return l < kPbLevels - 1 ? l : kPbLevels - 1;
 }
+// Rows of R_(1:i-1,i) staged by the persistent update form for 16 nb columns:
+// K rounded up to whole pairs of the K loop's load groups (the loop has no
+// partial pair; rows >= K are zero).
+__host__ __device__ constexpr int up_p_kalign(int nb) { return nb == 1 ? 16 : 32; }
+__host__ __device__ inline int up_p_rows(int K, int nb) {
+  return (K + up_p_kalign(nb) - 1) / up_p_kalign(nb) * up_p_kalign(nb);
+}
 // LDS bytes the update of a block of width bw after K columns needs.
 inline int64_t pb_update_lds(int64_t K, int64_t bw) {
-  const int64_t ncol = bw <= 16 ? 16 : 32, Kp = (K + 3) / 4 * 4;
+  const int nb = bw <= 16 ? 1 : 2;
+  const int64_t ncol = 16 * nb, Kp = up_p_rows((int)K, nb);
   return (Kp * ncol + ncol * ncol + ncol) * 8;
 }
 // Initializes the queue from the host's template (stages0 / valid0: the first

@@ -50,6 +50,21 @@ struct Vec16<double> {
   typedef f64x2 t;
 };
 
+// Streaming accesses of the persistent update: Q_(1:i-1) and W_(i) are read
+// once per launch and Q_(i) written once, all far larger than the caches, so
+// they carry the nontemporal hint (measured on the 1e6 x 256 workload, loads:
+// 242 -> 225 us per launch at K = 240, 119 -> 109 us at K = 96, the QR 3.91 ->
+// 3.70 ms; stores: the update a further 2 % faster, the sketch of Q_(i) that
+// reads it back unchanged).
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename V>
+__device__ __forceinline__ void st_result(V v, V* p) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---------------------------------------------------------------------------
 // Persistent form for FP64 arithmetic, bw <= 16 NB and K <= UpPShape::MAXK
 // (NB = 1: one 16-column group, four 256-thread workgroups per CU; NB = 2: two
@@ -95,6 +110,9 @@ struct UpPShape {
   static constexpr int NCOL = 16 * NB;
   static constexpr int MAXK = NB == 1 ? kUpPMaxK : kUpP2MaxK;
   static constexpr int MINW = NB == 1 ? 4 : 2;            // waves per SIMD asked of the compiler
+  static constexpr int GS = 4 * UpPUnroll<T, NB>::N;      // K-steps of one load group
+  static_assert(up_p_kalign(NB) % (2 * GS) == 0, "staged rows: whole pairs of load groups");
+  static_assert(MAXK % up_p_kalign(NB) == 0, "largest K: whole pairs of load groups");
 };
 
 // Forward substitution of steps 4-5 on the transposed-layout registers
@@ -240,18 +258,27 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
 }
 
 // The full tiles of one workgroup (tile = first, first + stride, .. < nfull),
-// software-pipelined across tiles: the W vectors and the first group of Q of
-// the next tile are loaded before the substitution and stores of the current
-// one, so the wait for them does not also wait for those stores (stores share
-// the vector-memory counter on this target).  Same arithmetic, in the same
-// order, as update_p_guarded_tile.
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
-__device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
-                                                    const T* __restrict__ Q, int64_t ldq,
-                                                    T* Qout, int64_t ldqo, const double* Rs,
-                                                    const double* Ru, const double* Rinv,
-                                                    bool subst, int64_t first, int64_t stride,
-                                                    int64_t nfull, int K, int bw) {
+// software-pipelined as a ring of two load groups (GS K-steps each): group
+// g + 2 is loaded into the registers of group g right after g's products, so
+// every load has a whole group of products to arrive in; the ring runs on
+// across tiles (the last pair of a tile loads the next tile's groups 0 and 1),
+// and the next tile's W is loaded as soon as the current tile's W has been
+// taken into the accumulators.  No load is issued under a branch: loads and
+// stores share one in-order counter on this target, and where paths with
+// different numbers of accesses meet the compiler waits for all of them.  So
+// R_(1:i-1,i) is staged with Kp = up_p_rows(K, NB) rows (zero past K), a
+// K-step at or past Kf = K - K % 4 reads column min(Kf + kk, K - 1) (a
+// column of Q_(1:i-1), multiplied by zero rows where it is padding), and a
+// workgroup's last tile prefetches that column of its own rows again (cached)
+// instead of a next tile.  FULL: bw = 16 NB (every column stored
+// unconditionally).  Same arithmetic, in the same order, as
+// update_p_guarded_tile, up to products by the zero rows of the padding.
+template <typename T, int NB, int WV, int VE, bool FULL>
+__device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const T* __restrict__ Q,
+                                                 int64_t ldq, T* Qout, int64_t ldqo,
+                                                 const double* Rs, const double* Ru,
+                                                 const double* Rinv, bool subst, int64_t first,
+                                                 int64_t stride, int64_t nfull, int K, int bw) {
   typedef Mfma<double> M;
   typedef UpPShape<T, NB, WV, VE> Sh;
   constexpr int VEC = Sh::VEC;
@@ -260,40 +287,46 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
   constexpr int NCOL = Sh::NCOL;
   typedef T VT __attribute__((ext_vector_type(VE)));
   constexpr int kUnroll = UpPUnroll<T, NB>::N;
-  constexpr int GS = 4 * kUnroll;
+  constexpr int GS = Sh::GS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, li = lane & 15;
   const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;  // row of this lane in a tile
   const int bwc = bw - 1;
+  const int ngroups = up_p_rows(K, NB) / GS;  // even, >= 2 (K > 0)
+  const int Kf = K & ~3;
+  const int64_t kko = (int64_t)kk * ldq;                      // column kk
+  const int64_t klo = (int64_t)min(Kf + kk, K - 1) * ldq;     // column of the steps >= Kf
 
-  auto load_w = [&](VT (&wv)[NB][4], int64_t arow) {
+  // column c of W at rows wp.. (clamped past bw); cs = 0 reads one vector
+  // 4 NB times (the prefetch without a next tile)
+  auto load_w = [&](VT (&wv)[NB][4], const T* wp, int64_t cs) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int c = 16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc;
-        wv[nb][e] = *reinterpret_cast<const VT*>(W + arow + (int64_t)c * ldw);
+        const int c = FULL ? 16 * nb + kk + 4 * e
+                           : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
+        wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * cs));
       }
   };
-  auto load_group = [&](VT (&a)[kUnroll], int64_t arow, int ks0) {
+  // group g of Q: step s = g GS + 4 u reads column s + kk from qk (stride cs)
+  // below Kf, else the vector at ql
+  auto load_group = [&](VT (&a)[kUnroll], const T* qk, const T* ql, int64_t cs, int g) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      int col = ks0 + 4 * u + kk;
-      col = col < K ? col : K - 1;
-      a[u] = *reinterpret_cast<const VT*>(Q + arow + (int64_t)col * ldq);
+      const int s = g * GS + 4 * u;
+      a[u] = ld_stream(reinterpret_cast<const VT*>(s < Kf ? qk + (int64_t)s * cs : ql));
     }
   };
   M::acc_t acc[VEC][NB];
-  auto mma_group = [&](const VT (&a)[kUnroll], int ks0) {
+  auto mma_group = [&](const VT (&a)[kUnroll], int g) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      if (ks0 + 4 * u < K) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const double b = Rs[(ks0 + 4 * u + kk) * NCOL + 16 * nb + li];
+      for (int nb = 0; nb < NB; ++nb) {
+        const double b = Rs[(g * GS + 4 * u + kk) * NCOL + 16 * nb + li];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
-        }
+        for (int v = 0; v < VEC; ++v) acc[v][nb] = M::mma(b, (double)a[u][v], acc[v][nb]);
       }
     }
   };
@@ -301,8 +334,11 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
   int64_t tile = first;
   if (tile >= nfull) return;
   VT wv[NB][4], a0[kUnroll], a1[kUnroll];
-  load_w(wv, tile * TILE + roff);
-  if (K > 0) load_group(a0, tile * TILE + roff, 0);
+  const T* qk = Q + tile * TILE + roff + kko;
+  const T* ql = Q + tile * TILE + roff + klo;
+  load_w(wv, W + tile * TILE + roff, ldw);
+  load_group(a0, qk, ql, ldq, 0);
+  load_group(a1, qk, ql, ldq, 1);
   for (;;) {
     const int64_t arow = tile * TILE + roff;
 #pragma unroll
@@ -311,20 +347,24 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
       for (int nb = 0; nb < NB; ++nb)
         acc[v][nb] = (M::acc_t){-(double)wv[nb][0][v], -(double)wv[nb][1][v],
                                 -(double)wv[nb][2][v], -(double)wv[nb][3][v]};
-    for (int ks0 = 0; ks0 < K; ks0 += 2 * GS) {
-      if (ks0 + GS < K) load_group(a1, arow, ks0 + GS);
-      mma_group(a0, ks0);
-      if (ks0 + GS < K) {
-        if (ks0 + 2 * GS < K) load_group(a0, arow, ks0 + 2 * GS);
-        mma_group(a1, ks0 + GS);
-      }
-    }
     const int64_t next = tile + stride;
     const bool more = next < nfull;
-    if (more) {
-      load_w(wv, next * TILE + roff);
-      if (K > 0) load_group(a0, next * TILE + roff, 0);
+    const T* hot = ql;  // read by this tile's last group
+    load_w(wv, more ? W + next * TILE + roff : hot, more ? ldw : 0);
+    int g = 0;
+    for (; g + 2 < ngroups; g += 2) {
+      mma_group(a0, g);
+      load_group(a0, qk, ql, ldq, g + 2);
+      mma_group(a1, g + 1);
+      load_group(a1, qk, ql, ldq, g + 3);
     }
+    const T* qkn = more ? Q + next * TILE + roff + kko : hot;
+    const T* qln = more ? Q + next * TILE + roff + klo : hot;
+    const int64_t csn = more ? ldq : 0;
+    mma_group(a0, g);
+    load_group(a0, qkn, qln, csn, 0);
+    mma_group(a1, g + 1);
+    load_group(a1, qkn, qln, csn, 1);
 #pragma unroll
     for (int v = 0; v < VEC; ++v)
 #pragma unroll
@@ -335,16 +375,107 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int c = 16 * nb + kk + 4 * e;
-        if (c < bw) {
+        if (FULL || c < bw) {
           VT vv;
 #pragma unroll
           for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
-          *reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo) = vv;
+          st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+        }
+      }
+    if (!more) break;
+    tile = next;
+    qk = qkn;
+    ql = qln;
+  }
+}
+
+// K = 0 (the first block): W and the substitution only; the next tile's W is
+// loaded ahead of the current one's substitution and stores (without a next
+// tile: the current tile's W again, cached).
+template <typename T, int NB, int WV, int VE, bool FULL>
+__device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qout, int64_t ldqo,
+                                                 const double* Ru, const double* Rinv, bool subst,
+                                                 int64_t first, int64_t stride, int64_t nfull,
+                                                 int bw) {
+  typedef Mfma<double> M;
+  typedef UpPShape<T, NB, WV, VE> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int WROWS = 16 * VEC;
+  constexpr int TILE = Sh::TILE;
+  typedef T VT __attribute__((ext_vector_type(VE)));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, li = lane & 15;
+  const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;
+  const int bwc = bw - 1;
+  auto load_w = [&](VT (&wv)[NB][4], const T* wp) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = FULL ? 16 * nb + kk + 4 * e
+                           : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
+        wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
+      }
+  };
+  int64_t tile = first;
+  if (tile >= nfull) return;
+  VT wv[NB][4];
+  M::acc_t acc[VEC][NB];
+  load_w(wv, W + tile * TILE + roff);
+  for (;;) {
+    const int64_t arow = tile * TILE + roff;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v][nb] = (M::acc_t){(double)wv[nb][0][v], (double)wv[nb][1][v], (double)wv[nb][2][v],
+                                (double)wv[nb][3][v]};
+    const int64_t next = tile + stride;
+    const bool more = next < nfull;
+    load_w(wv, W + (more ? next : tile) * TILE + roff);
+    if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * nb + kk + 4 * e;
+        if (FULL || c < bw) {
+          VT vv;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
+          st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
         }
       }
     if (!more) break;
     tile = next;
   }
+}
+
+// Forms of the full-tile walk: K = 0 or K > 0, and all 16 NB columns of the
+// block stored or only bw < 16 NB of them.  Each form is instantiated on its
+// own (a kernel, or a function of its own), so that its registers are
+// allocated for it alone: with the forms in one function the compiler kept
+// values of one live across the other and spilled.
+__host__ __device__ inline int up_p_form(int K, int bw, int nb) {
+  return (K > 0 ? 2 : 0) + (bw == 16 * nb ? 1 : 0);
+}
+
+// The full tiles of one workgroup (tile = first, first + stride, .. < nfull)
+// in form FORM = up_p_form(K, bw, NB).  Rs holds up_p_rows(K, NB) rows.
+template <typename T, int NB, int FORM, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
+__device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
+                                                    const T* __restrict__ Q, int64_t ldq,
+                                                    T* Qout, int64_t ldqo, const double* Rs,
+                                                    const double* Ru, const double* Rinv,
+                                                    bool subst, int64_t first, int64_t stride,
+                                                    int64_t nfull, int K, int bw) {
+  constexpr bool FULL = (FORM & 1) != 0;
+  if constexpr (FORM >= 2)
+    update_p_tiles_k<T, NB, WV, VE, FULL>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, first,
+                                          stride, nfull, K, bw);
+  else
+    update_p_tiles_0<T, NB, WV, VE, FULL>(W, ldw, Qout, ldqo, Ru, Rinv, subst, first, stride,
+                                          nfull, bw);
 }
 
 // Stages the factors of block i in LDS for the persistent form (NCOL = 16 NB

@@ -381,10 +381,10 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
                                 tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
 }
 
-// LDS: Rs [Kp][16 NB] (rows >= K zero); Ru [16 NB][16 NB] (column-major) =
+// LDS: Rs [Kp][16 NB] (Kp = up_p_rows(K, NB); rows >= K zero); Ru [16 NB][16 NB] (column-major) =
 // strictly upper part of R_(i,i), zero past bw; Rinv [16 NB] = 1 / R_cc (1 past
 // bw).  FP64.
-template <typename T, int NB>
+template <typename T, int NB, int FORM>
 __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)) void update_p_kernel(
     const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
     const double* __restrict__ Rk, const double* __restrict__ Rii, int64_t ldr, int64_t ntiles,
@@ -399,8 +399,8 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
   update_p_stage<NCOL, Sh::THREADS>(Rk, Rii, ldr, K, Kp, bw, Rs, Ru, Rinv);
   const bool subst = Rii != nullptr;
   __syncthreads();
-  update_p_full_tiles<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x, gridDim.x,
-                             nfull, K, bw);
+  update_p_full_tiles<T, NB, FORM>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x,
+                                   gridDim.x, nfull, K, bw);
   // the guarded tiles (a ragged last tile, or every tile when a pointer or
   // leading dimension is not 16-byte aligned) come after the full ones
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
@@ -458,6 +458,24 @@ static bool aligned16(const void* p, int64_t ld, int vec) {
   return (ld % vec) == 0 && (reinterpret_cast<uintptr_t>(p) % 16) == 0;
 }
 
+template <typename T, int NB, int FORM>
+static hipError_t launch_update_p_form(unsigned grid, size_t lds, const void* W, int64_t ldw,
+                                       const void* Q, int64_t ldq, void* Qout, int64_t ldqo,
+                                       const double* Rk, const double* Rii, int64_t ldr,
+                                       int64_t ntiles, int64_t nfull, int64_t n, int64_t K, int Kp,
+                                       int bw, hipStream_t st) {
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&update_p_kernel<T, NB, FORM>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((update_p_kernel<T, NB, FORM>), dim3(grid), dim3(UpPShape<T, NB>::THREADS),
+                     lds, st, (const T*)W, ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr,
+                     ntiles, nfull, n, (int)K, Kp, bw);
+  return hipGetLastError();
+}
+
 template <typename T, int NB>
 static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int64_t ldq,
                                   void* Qout, int64_t ldqo, const double* Rk, const double* Rii,
@@ -469,7 +487,7 @@ static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int
                       (K == 0 || aligned16(Q, ldq, VEC));
   const int64_t ntiles = ceil_div(n, TILE);
   const int64_t nfull = vec_ok ? n / TILE : 0;
-  const int Kp = (int)((K + 3) / 4 * 4);
+  const int Kp = up_p_rows((int)K, NB);
   const size_t lds = ((size_t)Kp * Sh::NCOL + (size_t)Sh::NCOL * Sh::NCOL + Sh::NCOL) * sizeof(double);
   unsigned grid;
   if (NB == 1) {
@@ -484,15 +502,20 @@ static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int
     const int64_t per = ceil_div(ntiles, 256);
     grid = (unsigned)ceil_div(ntiles, per);
   }
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&update_p_kernel<T, NB>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  switch (up_p_form((int)K, bw, NB)) {
+    case 0:
+      return launch_update_p_form<T, NB, 0>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,
+                                            ntiles, nfull, n, K, Kp, bw, st);
+    case 1:
+      return launch_update_p_form<T, NB, 1>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,
+                                            ntiles, nfull, n, K, Kp, bw, st);
+    case 2:
+      return launch_update_p_form<T, NB, 2>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,
+                                            ntiles, nfull, n, K, Kp, bw, st);
+    default:
+      return launch_update_p_form<T, NB, 3>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,
+                                            ntiles, nfull, n, K, Kp, bw, st);
   }
-  hipLaunchKernelGGL((update_p_kernel<T, NB>), dim3(grid), dim3(Sh::THREADS), lds, st, (const T*)W,
-                     ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, (int)K,
-                     Kp, bw);
-  return hipGetLastError();
 }
 
 template <typename T, typename C>

@@ -237,7 +237,7 @@ def _update_general(L, T, NB):
     return out
 
 
-def _update_persistent(L, T, NB=1):
+def _update_persistent(L, T, NB=1, form=None):
     # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, K, Kp, bw)
     es = 4 if T == "f" else 8
     VEC = 16 // es
@@ -248,7 +248,9 @@ def _update_persistent(L, T, NB=1):
     ntiles, nfull, n, K, Kp, bw = L.i(9), L.i(10), L.i(11), L.i(12), L.i(13), L.i(14)
     assert L.block[0] == 64 * WAVES
     assert ntiles == cdiv(n, TILE) and nfull * TILE <= n and bw <= NCOL
-    assert K <= Kp <= (512 if NB == 1 else 480) and Kp % 4 == 0
+    align = 16 if NB == 1 else 32    # whole pairs of the K loop's load groups
+    assert Kp == cdiv(K, align) * align <= (512 if NB == 1 else 480)
+    assert form == (2 if K > 0 else 0) + (1 if bw == NCOL else 0), "form does not match K, bw"
     assert L.shmem >= (Kp * NCOL + NCOL * NCOL + NCOL) * 8
     assert L.shmem <= 160 * 1024
     last = n - 1
@@ -466,7 +468,8 @@ def pb_problem_accesses(P, zeta, ls):
             out.append(absacc(P["R"], 8, c0 + c0 * ldr, c0 + c0 * ldr + (bw - 1) + (bw - 1) * ldr))
             out.append(absacc(P["P"] if K == 0 else P["E"], 8, 0, k * bw - 1))
         elif kind == "upd":
-            Kp = cdiv(K, 4) * 4
+            align = 16 if ncol == 16 else 32
+            Kp = cdiv(K, align) * align
             assert (Kp * ncol + ncol * ncol + ncol) * 8 <= PB_LDS, "update factors exceed the LDS pool"
             assert bw <= ncol
             out += [absacc(P["W"], 4, c0 * ldw, (n - 1) + (c0 + bw - 1) * ldw),
@@ -613,7 +616,7 @@ MIRRORS = {
 }
 TEMPLATED = {
     "update_kernel": lambda L, t: _update_general(L, t[0], t[2]),
-    "update_p_kernel": lambda L, t: _update_persistent(L, t[0], t[1] if len(t) > 1 else 1),
+    "update_p_kernel": lambda L, t: _update_persistent(L, t[0], int(t[1]), int(t[2])),
     "trsm_kernel": lambda L, t: _trsm(L, t[0]),
     "sketch_gauss_kernel": lambda L, t: _sketch_gauss(L, t[0], t[2]),
     "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),
