@@ -121,8 +121,9 @@ struct UpPShape {
 // Column c of this lane's rows sits in lane (c % 4, li), group c / 16,
 // element (c % 16) / 4; it is handed to the lanes holding the other columns of
 // the same rows by a lane shuffle.  Ru holds the strictly upper part of
-// R_(i,i) (column-major, ld 16 NB; zero elsewhere and past bw), so the update
-// needs no mask.
+// R_(i,i) (row-major, 16 NB per row; zero elsewhere and past bw), so the
+// update needs no mask.  (The 16-column forms with four rows per lane use
+// rows_substitute instead: same operations, in the same order.)
 template <int VEC, int NB>
 __device__ __forceinline__ void p_substitute(double4_t (&acc)[VEC][NB], const double* Ru,
                                              const double* Rinv, int bw, int kk, int li) {
@@ -144,12 +145,62 @@ __device__ __forceinline__ void p_substitute(double4_t (&acc)[VEC][NB], const do
       for (int nb = nbc; nb < NB; ++nb) {
         double ru[4];
 #pragma unroll
-        for (int e = (nb == nbc ? ec : 0); e < 4; ++e) ru[e] = Ru[c + NCOL * (16 * nb + kk + 4 * e)];
+        for (int e = (nb == nbc ? ec : 0); e < 4; ++e) ru[e] = Ru[c * NCOL + 16 * nb + kk + 4 * e];
 #pragma unroll
         for (int v = 0; v < VEC; ++v)
 #pragma unroll
           for (int e = (nb == nbc ? ec : 0); e < 4; ++e) acc[v][nb][e] = fma(-xb[v], ru[e], acc[v][nb][e]);
       }
+    }
+  }
+}
+
+// 4 x 4 transpose across the four 16-lane rows of a wave, on doubles: after
+// it, register s of lane (row r, li) holds what register r of lane (row s, li)
+// held.  Two rounds of gfx950 lane swaps on each 32-bit half: rows 2-3 of x[s]
+// with rows 0-1 of x[s + 2], then rows 1 and 3 of x[s] with rows 0 and 2 of
+// x[s + 1].
+__device__ __forceinline__ void rows_transpose4(double (&x)[4]) {
+  unsigned h[2][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x[s]);
+    h[0][s] = (unsigned)b;
+    h[1][s] = (unsigned)(b >> 32);
+  }
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const auto t = __builtin_amdgcn_permlane32_swap(h[w][s], h[w][s + 2], false, false);
+      h[w][s] = t[0];
+      h[w][s + 2] = t[1];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s += 2) {
+      const auto t = __builtin_amdgcn_permlane16_swap(h[w][s], h[w][s + 1], false, false);
+      h[w][s] = t[0];
+      h[w][s + 1] = t[1];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    x[s] = __longlong_as_double((long long)(((unsigned long long)h[1][s] << 32) | h[0][s]));
+}
+
+// Forward substitution of steps 4-5 on one row held by this lane, y[c] =
+// column c (NCOL = 16 NB): x_c = q'_c (1 / R_cc), then q'_c' -= x_c R_cc' for
+// c' > c, column after column (Ru row-major as in p_substitute; rows of R are
+// read as LDS broadcasts).
+template <int NCOL>
+__device__ __forceinline__ void rows_substitute(double (&y)[NCOL], const double* Ru,
+                                                const double* Rinv, int bw) {
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    if (c < bw) {
+      y[c] = y[c] * Rinv[c];
+#pragma unroll
+      for (int c2 = c + 1; c2 < NCOL; ++c2) y[c2] = fma(-y[c], Ru[c * NCOL + c2], y[c2]);
     }
   }
 }
@@ -365,23 +416,44 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
     load_group(a0, qkn, qln, csn, 0);
     mma_group(a1, g + 1);
     load_group(a1, qkn, qln, csn, 1);
+    if constexpr (VEC == 4 && NB == 1) {
+      // rows to lanes: lane (kk, li) takes row 4 li + kk, all 16 columns
+      // (measured: 1e6 x 256 QR 3.68 -> 3.63 ms; for 32 columns the shuffle form
+      // below stays, the row form measured 1 % slower there)
+      double y[NCOL];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
-    if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+        for (int e = 0; e < 4; ++e) {
+          double x[4] = {acc[0][nb][e], acc[1][nb][e], acc[2][nb][e], acc[3][nb][e]};
+          rows_transpose4(x);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 16 * nb + kk + 4 * e;
-        if (FULL || c < bw) {
-          VT vv;
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
-          st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+          for (int s = 0; s < 4; ++s) y[16 * nb + 4 * e + s] = -x[s];
         }
-      }
+      if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
+      T* dst = Qout + tile * TILE + (int64_t)wave * WROWS + 4 * li + kk;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c)
+        if (FULL || c < bw) st_result((T)y[c], dst + (int64_t)c * ldqo);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+      if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 16 * nb + kk + 4 * e;
+          if (FULL || c < bw) {
+            VT vv;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
+            st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+          }
+        }
+    }
     if (!more) break;
     tile = next;
     qk = qkn;
@@ -391,7 +463,9 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
 
 // K = 0 (the first block): W and the substitution only; the next tile's W is
 // loaded ahead of the current one's substitution and stores (without a next
-// tile: the current tile's W again, cached).
+// tile: the current tile's W again, cached).  With four rows per lane and 16
+// columns the tile is read row-wise from the start (lane (kk, li) takes row
+// 4 li + kk, one column per load), so the substitution needs no lane exchange.
 template <typename T, int NB, int WV, int VE, bool FULL>
 __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qout, int64_t ldqo,
                                                  const double* Ru, const double* Rinv, bool subst,
@@ -402,52 +476,79 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
   constexpr int VEC = Sh::VEC;
   constexpr int WROWS = 16 * VEC;
   constexpr int TILE = Sh::TILE;
+  constexpr int NCOL = Sh::NCOL;
   typedef T VT __attribute__((ext_vector_type(VE)));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, li = lane & 15;
-  const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;
   const int bwc = bw - 1;
-  auto load_w = [&](VT (&wv)[NB][4], const T* wp) {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = FULL ? 16 * nb + kk + 4 * e
-                           : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
-        wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
-      }
-  };
   int64_t tile = first;
   if (tile >= nfull) return;
-  VT wv[NB][4];
-  M::acc_t acc[VEC][NB];
-  load_w(wv, W + tile * TILE + roff);
-  for (;;) {
-    const int64_t arow = tile * TILE + roff;
+  if constexpr (VEC == 4 && NB == 1) {
+    const int64_t rrow = (int64_t)wave * WROWS + 4 * li + kk;  // this lane's row in a tile
+    auto load_row = [&](T (&w)[NCOL], const T* wp) {
 #pragma unroll
-    for (int v = 0; v < VEC; ++v)
+      for (int c = 0; c < NCOL; ++c)
+        w[c] = ld_stream(wp + (int64_t)(FULL ? c : (c < bw ? c : bwc)) * ldw);
+    };
+    T w[NCOL];
+    load_row(w, W + tile * TILE + rrow);
+    for (;;) {
+      double y[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) y[c] = (double)w[c];
+      const int64_t next = tile + stride;
+      const bool more = next < nfull;
+      load_row(w, W + (more ? next : tile) * TILE + rrow);
+      if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
+      T* dst = Qout + tile * TILE + rrow;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c)
+        if (FULL || c < bw) st_result((T)y[c], dst + (int64_t)c * ldqo);
+      if (!more) break;
+      tile = next;
+    }
+  } else {
+    const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;
+    auto load_w = [&](VT (&wv)[NB][4], const T* wp) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[v][nb] = (M::acc_t){(double)wv[nb][0][v], (double)wv[nb][1][v], (double)wv[nb][2][v],
-                                (double)wv[nb][3][v]};
-    const int64_t next = tile + stride;
-    const bool more = next < nfull;
-    load_w(wv, W + (more ? next : tile) * TILE + roff);
-    if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 16 * nb + kk + 4 * e;
-        if (FULL || c < bw) {
-          VT vv;
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
-          st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+        for (int e = 0; e < 4; ++e) {
+          const int c = FULL ? 16 * nb + kk + 4 * e
+                             : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
+          wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
         }
-      }
-    if (!more) break;
-    tile = next;
+    };
+    VT wv[NB][4];
+    M::acc_t acc[VEC][NB];
+    load_w(wv, W + tile * TILE + roff);
+    for (;;) {
+      const int64_t arow = tile * TILE + roff;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[v][nb] = (M::acc_t){(double)wv[nb][0][v], (double)wv[nb][1][v],
+                                  (double)wv[nb][2][v], (double)wv[nb][3][v]};
+      const int64_t next = tile + stride;
+      const bool more = next < nfull;
+      load_w(wv, W + (more ? next : tile) * TILE + roff);
+      if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 16 * nb + kk + 4 * e;
+          if (FULL || c < bw) {
+            VT vv;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
+            st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+          }
+        }
+      if (!more) break;
+      tile = next;
+    }
   }
 }
 
@@ -480,7 +581,7 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
 
 // Stages the factors of block i in LDS for the persistent form (NCOL = 16 NB
 // columns, NT threads): Rs [Kp][NCOL] = R_(1:i-1,i) (rows >= K and columns >=
-// bw zero); with Rii given, Ru [NCOL][NCOL] (column-major) = the strictly upper
+// bw zero); with Rii given, Ru [NCOL][NCOL] (row-major) = the strictly upper
 // part of R_(i,i), zero past bw, and Rinv [NCOL] = 1 / R_cc (1 past bw).  FP64.
 // Every load is unconditional (clamped index).  The caller synchronizes.
 template <int NCOL, int NT>
@@ -496,7 +597,7 @@ __device__ __forceinline__ void update_p_stage(const double* __restrict__ Rk,
   }
   if (Rii != nullptr) {
     for (int e = threadIdx.x; e < NCOL * NCOL; e += NT) {
-      const int r = e % NCOL, c = e / NCOL;
+      const int r = e / NCOL, c = e % NCOL;
       const bool in = r < c && c < bw;
       const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
       Ru[e] = in ? v : 0.0;

@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
                                 tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
 }
 
-// LDS: Rs [Kp][16 NB] (Kp = up_p_rows(K, NB); rows >= K zero); Ru [16 NB][16 NB] (column-major) =
+// LDS: Rs [Kp][16 NB] (Kp = up_p_rows(K, NB); rows >= K zero); Ru [16 NB][16 NB] (row-major) =
 // strictly upper part of R_(i,i), zero past bw; Rinv [16 NB] = 1 / R_cc (1 past
 // bw).  FP64.
 template <typename T, int NB, int FORM>
