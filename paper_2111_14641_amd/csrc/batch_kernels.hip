@@ -405,8 +405,8 @@ __device__ __forceinline__ void pb_update(const PbProb& P, int block, int item, 
   __syncthreads();
   const float* Wi = P.W + c0 * P.ldw;
   float* Qi = P.Q + c0 * P.ldq;
-  update_p_full_tiles<float, NB, FORM, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru, Rinv,
-                                               true, item, nitems, P.up_nfull, K, bw);
+  update_p_full_tiles<float, NB, FORM, false, false, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru,
+                                                      Rinv, true, item, nitems, P.up_nfull, K, bw);
   for (int64_t tile = item; tile < P.up_tiles; tile += nitems)
     if (tile >= P.up_nfull)
       update_p_guarded_tile<float, NB, WV, VE>(Wi, P.ldw, P.Q, P.ldq, Qi, P.ldq, Rs, Ru, Rinv,

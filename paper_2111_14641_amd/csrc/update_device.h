@@ -50,19 +50,24 @@ struct Vec16<double> {
   typedef f64x2 t;
 };
 
-// Streaming accesses of the persistent update: Q_(1:i-1) and W_(i) are read
-// once per launch and Q_(i) written once, all far larger than the caches, so
-// they carry the nontemporal hint (measured on the 1e6 x 256 workload, loads:
-// 242 -> 225 us per launch at K = 240, 119 -> 109 us at K = 96, the QR 3.91 ->
-// 3.70 ms; stores: the update a further 2 % faster, the sketch of Q_(i) that
-// reads it back unchanged).
-template <typename V>
+// Streaming accesses of the persistent update (NT = true): for a single large
+// factorization Q_(1:i-1) and W_(i) are read once per launch and Q_(i)
+// written once, all far larger than the caches, so they carry the nontemporal
+// hint (measured on the 1e6 x 256 workload, loads: 242 -> 225 us per launch
+// at K = 240, 119 -> 109 us at K = 96, the QR 3.91 -> 3.70 ms; stores: the
+// update a further 2 % faster, the sketch of Q_(i) that reads it back
+// unchanged).  The persistent batch, whose problems stay in the caches
+// between stages, uses plain accesses (with the hint its 512-problem batch
+// went from 81 to 89 ms).
+template <bool NT, typename V>
 __device__ __forceinline__ V ld_stream(const V* p) {
-  return __builtin_nontemporal_load(p);
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
-template <typename V>
+template <bool NT, typename V>
 __device__ __forceinline__ void st_result(V v, V* p) {
-  __builtin_nontemporal_store(v, p);
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -324,7 +329,7 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
 // instead of a next tile.  FULL: bw = 16 NB (every column stored
 // unconditionally).  Same arithmetic, in the same order, as
 // update_p_guarded_tile, up to products by the zero rows of the padding.
-template <typename T, int NB, int WV, int VE, bool FULL>
+template <typename T, int NB, int WV, int VE, bool FULL, bool NT, bool ROWS>
 __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const T* __restrict__ Q,
                                                  int64_t ldq, T* Qout, int64_t ldqo,
                                                  const double* Rs, const double* Ru,
@@ -357,7 +362,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
       for (int e = 0; e < 4; ++e) {
         const int c = FULL ? 16 * nb + kk + 4 * e
                            : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
-        wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * cs));
+        wv[nb][e] = ld_stream<NT>(reinterpret_cast<const VT*>(wp + (int64_t)c * cs));
       }
   };
   // group g of Q: step s = g GS + 4 u reads column s + kk from qk (stride cs)
@@ -366,7 +371,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int s = g * GS + 4 * u;
-      a[u] = ld_stream(reinterpret_cast<const VT*>(s < Kf ? qk + (int64_t)s * cs : ql));
+      a[u] = ld_stream<NT>(reinterpret_cast<const VT*>(s < Kf ? qk + (int64_t)s * cs : ql));
     }
   };
   M::acc_t acc[VEC][NB];
@@ -416,7 +421,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
     load_group(a0, qkn, qln, csn, 0);
     mma_group(a1, g + 1);
     load_group(a1, qkn, qln, csn, 1);
-    if constexpr (VEC == 4 && NB == 1) {
+    if constexpr (ROWS && VEC == 4 && NB == 1) {
       // rows to lanes: lane (kk, li) takes row 4 li + kk, all 16 columns
       // (measured: 1e6 x 256 QR 3.68 -> 3.63 ms; for 32 columns the shuffle form
       // below stays, the row form measured 1 % slower there)
@@ -434,7 +439,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
       T* dst = Qout + tile * TILE + (int64_t)wave * WROWS + 4 * li + kk;
 #pragma unroll
       for (int c = 0; c < NCOL; ++c)
-        if (FULL || c < bw) st_result((T)y[c], dst + (int64_t)c * ldqo);
+        if (FULL || c < bw) st_result<NT>((T)y[c], dst + (int64_t)c * ldqo);
     } else {
 #pragma unroll
       for (int v = 0; v < VEC; ++v)
@@ -450,7 +455,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
             VT vv;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
-            st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+            st_result<NT>(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
           }
         }
     }
@@ -462,11 +467,13 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
 }
 
 // K = 0 (the first block): W and the substitution only; the next tile's W is
-// loaded ahead of the current one's substitution and stores (without a next
-// tile: the current tile's W again, cached).  With four rows per lane and 16
-// columns the tile is read row-wise from the start (lane (kk, li) takes row
-// 4 li + kk, one column per load), so the substitution needs no lane exchange.
-template <typename T, int NB, int WV, int VE, bool FULL>
+// loaded ahead of the current one's substitution and stores.  With four rows
+// per lane and 16 columns the tile is read row-wise from the start (lane
+// (kk, li) takes row 4 li + kk, one column per load), so the substitution
+// needs no lane exchange; the prefetch is skipped on a workgroup's last tile
+// (the loop has no later load whose wait it could lengthen).  The other shapes
+// prefetch the current tile's W again there.
+template <typename T, int NB, int WV, int VE, bool FULL, bool NT, bool ROWS>
 __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qout, int64_t ldqo,
                                                  const double* Ru, const double* Rinv, bool subst,
                                                  int64_t first, int64_t stride, int64_t nfull,
@@ -483,12 +490,12 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
   const int bwc = bw - 1;
   int64_t tile = first;
   if (tile >= nfull) return;
-  if constexpr (VEC == 4 && NB == 1) {
+  if constexpr (ROWS && VEC == 4 && NB == 1) {
     const int64_t rrow = (int64_t)wave * WROWS + 4 * li + kk;  // this lane's row in a tile
     auto load_row = [&](T (&w)[NCOL], const T* wp) {
 #pragma unroll
       for (int c = 0; c < NCOL; ++c)
-        w[c] = ld_stream(wp + (int64_t)(FULL ? c : (c < bw ? c : bwc)) * ldw);
+        w[c] = ld_stream<NT>(wp + (int64_t)(FULL ? c : (c < bw ? c : bwc)) * ldw);
     };
     T w[NCOL];
     load_row(w, W + tile * TILE + rrow);
@@ -498,12 +505,12 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
       for (int c = 0; c < NCOL; ++c) y[c] = (double)w[c];
       const int64_t next = tile + stride;
       const bool more = next < nfull;
-      load_row(w, W + (more ? next : tile) * TILE + rrow);
+      if (more) load_row(w, W + next * TILE + rrow);
       if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
       T* dst = Qout + tile * TILE + rrow;
 #pragma unroll
       for (int c = 0; c < NCOL; ++c)
-        if (FULL || c < bw) st_result((T)y[c], dst + (int64_t)c * ldqo);
+        if (FULL || c < bw) st_result<NT>((T)y[c], dst + (int64_t)c * ldqo);
       if (!more) break;
       tile = next;
     }
@@ -516,7 +523,7 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
         for (int e = 0; e < 4; ++e) {
           const int c = FULL ? 16 * nb + kk + 4 * e
                              : (16 * nb + kk + 4 * e < bw ? 16 * nb + kk + 4 * e : bwc);
-          wv[nb][e] = ld_stream(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
+          wv[nb][e] = ld_stream<NT>(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
         }
     };
     VT wv[NB][4];
@@ -543,7 +550,7 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
             VT vv;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) vv[v] = (T)acc[v][nb][e];
-            st_result(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+            st_result<NT>(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
           }
         }
       if (!more) break;
@@ -562,8 +569,13 @@ __host__ __device__ inline int up_p_form(int K, int bw, int nb) {
 }
 
 // The full tiles of one workgroup (tile = first, first + stride, .. < nfull)
-// in form FORM = up_p_form(K, bw, NB).  Rs holds up_p_rows(K, NB) rows.
-template <typename T, int NB, int FORM, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
+// in form FORM = up_p_form(K, bw, NB), streaming accesses if NT, the epilogue
+// of 16-column blocks with four rows per lane in row layout if ROWS (the update
+// kernel; in the persistent batch's stage functions, with their smaller
+// register budget, the row layout spilled: 192 -> 1356 bytes of scratch per
+// lane).  Rs holds up_p_rows(K, NB) rows.
+template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV = (NB == 1 ? 4 : 8),
+          int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     const T* __restrict__ Q, int64_t ldq,
                                                     T* Qout, int64_t ldqo, const double* Rs,
@@ -572,10 +584,10 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     int64_t nfull, int K, int bw) {
   constexpr bool FULL = (FORM & 1) != 0;
   if constexpr (FORM >= 2)
-    update_p_tiles_k<T, NB, WV, VE, FULL>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, first,
+    update_p_tiles_k<T, NB, WV, VE, FULL, NT, ROWS>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, first,
                                           stride, nfull, K, bw);
   else
-    update_p_tiles_0<T, NB, WV, VE, FULL>(W, ldw, Qout, ldqo, Ru, Rinv, subst, first, stride,
+    update_p_tiles_0<T, NB, WV, VE, FULL, NT, ROWS>(W, ldw, Qout, ldqo, Ru, Rinv, subst, first, stride,
                                           nfull, bw);
 }
 

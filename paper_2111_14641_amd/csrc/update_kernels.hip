@@ -399,8 +399,8 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
   update_p_stage<NCOL, Sh::THREADS>(Rk, Rii, ldr, K, Kp, bw, Rs, Ru, Rinv);
   const bool subst = Rii != nullptr;
   __syncthreads();
-  update_p_full_tiles<T, NB, FORM>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x,
-                                   gridDim.x, nfull, K, bw);
+  update_p_full_tiles<T, NB, FORM, true, true>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst,
+                                         blockIdx.x, gridDim.x, nfull, K, bw);
   // the guarded tiles (a ragged last tile, or every tile when a pointer or
   // leading dimension is not 16-byte aligned) come after the full ones
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
