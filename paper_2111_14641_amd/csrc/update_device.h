@@ -421,7 +421,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
     load_group(a0, qkn, qln, csn, 0);
     mma_group(a1, g + 1);
     load_group(a1, qkn, qln, csn, 1);
-    if constexpr (ROWS && VEC == 4 && NB == 1) {
+    if constexpr (ROWS && FULL && VEC == 4 && NB == 1) {
       // rows to lanes: lane (kk, li) takes row 4 li + kk, all 16 columns
       // (measured: 1e6 x 256 QR 3.68 -> 3.63 ms; for 32 columns the shuffle form
       // below stays, the row form measured 1 % slower there)
@@ -436,10 +436,19 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
           for (int s = 0; s < 4; ++s) y[16 * nb + 4 * e + s] = -x[s];
         }
       if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
-      T* dst = Qout + tile * TILE + (int64_t)wave * WROWS + 4 * li + kk;
+      // and back (the transpose is its own inverse): 16-byte stores of 4 rows
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c)
-        if (FULL || c < bw) st_result<NT>((T)y[c], dst + (int64_t)c * ldqo);
+      for (int e = 0; e < 4; ++e) {
+        double x[4] = {y[4 * e], y[4 * e + 1], y[4 * e + 2], y[4 * e + 3]};
+        rows_transpose4(x);
+        const int c = kk + 4 * e;
+        if (FULL || c < bw) {
+          VT vv;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) vv[v] = (T)x[v];
+          st_result<NT>(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+        }
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < VEC; ++v)
@@ -468,11 +477,13 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
 
 // K = 0 (the first block): W and the substitution only; the next tile's W is
 // loaded ahead of the current one's substitution and stores.  With four rows
-// per lane and 16 columns the tile is read row-wise from the start (lane
-// (kk, li) takes row 4 li + kk, one column per load), so the substitution
-// needs no lane exchange; the prefetch is skipped on a workgroup's last tile
-// (the loop has no later load whose wait it could lengthen).  The other shapes
-// prefetch the current tile's W again there.
+// per lane and all 16 columns (ROWS, FULL) the substitution runs in row layout
+// between two lane-swap transposes, the loads and stores staying 16-byte
+// vectors (in row layout, one 4-byte element per lane and instruction, the
+// K = 0 launch took 32 us instead of 23 without its substitution); the
+// prefetch is skipped on a workgroup's last tile (the loop has no later load
+// whose wait it could lengthen).  The other shapes prefetch the current
+// tile's W again there.
 template <typename T, int NB, int WV, int VE, bool FULL, bool NT, bool ROWS>
 __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qout, int64_t ldqo,
                                                  const double* Ru, const double* Rinv, bool subst,
@@ -490,27 +501,45 @@ __device__ __forceinline__ void update_p_tiles_0(const T* W, int64_t ldw, T* Qou
   const int bwc = bw - 1;
   int64_t tile = first;
   if (tile >= nfull) return;
-  if constexpr (ROWS && VEC == 4 && NB == 1) {
-    const int64_t rrow = (int64_t)wave * WROWS + 4 * li + kk;  // this lane's row in a tile
-    auto load_row = [&](T (&w)[NCOL], const T* wp) {
+  if constexpr (ROWS && FULL && VEC == 4 && NB == 1) {
+    // W as 16-byte vectors of 4 rows (lane (kk, li): rows 4 li + v of columns
+    // kk + 4 e), into row layout for the substitution and back for the stores
+    const int64_t roff = (int64_t)wave * WROWS + (int64_t)VEC * li;
+    auto load_w = [&](VT (&wv)[4], const T* wp) {
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c)
-        w[c] = ld_stream<NT>(wp + (int64_t)(FULL ? c : (c < bw ? c : bwc)) * ldw);
+      for (int e = 0; e < 4; ++e) {
+        const int c = FULL ? kk + 4 * e : (kk + 4 * e < bw ? kk + 4 * e : bwc);
+        wv[e] = ld_stream<NT>(reinterpret_cast<const VT*>(wp + (int64_t)c * ldw));
+      }
     };
-    T w[NCOL];
-    load_row(w, W + tile * TILE + rrow);
+    VT wv[4];
+    load_w(wv, W + tile * TILE + roff);
     for (;;) {
+      const int64_t arow = tile * TILE + roff;
       double y[NCOL];
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c) y[c] = (double)w[c];
+      for (int e = 0; e < 4; ++e) {
+        double x[4] = {(double)wv[e][0], (double)wv[e][1], (double)wv[e][2], (double)wv[e][3]};
+        rows_transpose4(x);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) y[4 * e + s] = x[s];
+      }
       const int64_t next = tile + stride;
       const bool more = next < nfull;
-      if (more) load_row(w, W + next * TILE + rrow);
+      if (more) load_w(wv, W + next * TILE + roff);
       if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
-      T* dst = Qout + tile * TILE + rrow;
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c)
-        if (FULL || c < bw) st_result<NT>((T)y[c], dst + (int64_t)c * ldqo);
+      for (int e = 0; e < 4; ++e) {
+        double x[4] = {y[4 * e], y[4 * e + 1], y[4 * e + 2], y[4 * e + 3]};
+        rows_transpose4(x);
+        const int c = kk + 4 * e;
+        if (FULL || c < bw) {
+          VT vv;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) vv[v] = (T)x[v];
+          st_result<NT>(vv, reinterpret_cast<VT*>(Qout + arow + (int64_t)c * ldqo));
+        }
+      }
       if (!more) break;
       tile = next;
     }
@@ -570,10 +599,11 @@ __host__ __device__ inline int up_p_form(int K, int bw, int nb) {
 
 // The full tiles of one workgroup (tile = first, first + stride, .. < nfull)
 // in form FORM = up_p_form(K, bw, NB), streaming accesses if NT, the epilogue
-// of 16-column blocks with four rows per lane in row layout if ROWS (the update
-// kernel; in the persistent batch's stage functions, with their smaller
+// of full 16-column blocks with four rows per lane in row layout if ROWS (the
+// update kernel; in the persistent batch's stage functions, with their smaller
 // register budget, the row layout spilled: 192 -> 1356 bytes of scratch per
-// lane).  Rs holds up_p_rows(K, NB) rows.
+// lane; narrower blocks keep the shuffle form, where the masked row form
+// spilled too).  Rs holds up_p_rows(K, NB) rows.
 template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV = (NB == 1 ? 4 : 8),
           int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
