@@ -402,11 +402,12 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
   update_p_full_tiles<T, NB, FORM, true, true>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst,
                                          blockIdx.x, gridDim.x, nfull, K, bw);
   // the guarded tiles (a ragged last tile, or every tile when a pointer or
-  // leading dimension is not 16-byte aligned) come after the full ones
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    if (tile >= nfull)
-      update_p_guarded_tile<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n,
-                                   K, bw);
+  // leading dimension is not 16-byte aligned) come after the full ones, dealt
+  // from the last workgroup backwards: the last workgroups have the fewest
+  // full tiles (workgroup b has those b + j gridDim.x < nfull)
+  for (int64_t tile = nfull + (gridDim.x - 1 - blockIdx.x); tile < ntiles; tile += gridDim.x)
+    update_p_guarded_tile<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
+                                 bw);
 }
 
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
