@@ -184,6 +184,31 @@ def test_fp32_storage_fp64_arithmetic(gpu_lib, variant, decades):
 
 
 @pytest.mark.parametrize("variant", ["plain", "lowsync"])
+@pytest.mark.parametrize("n,m,b", [
+    (7777, 40, 5),      # K = 5, 10, ..: steps past K - K % 4 read a clamped column
+    (7777, 42, 6),      # K % 4 = 2, ragged last block of 2 columns
+    (5000, 70, 10),     # partial 16-column group in every block
+    (9000, 100, 16),    # full 16-column blocks (row-layout epilogue) and a last block of 4
+    (300, 48, 16),      # one full tile and a ragged one: a workgroup's first tile is its last
+])
+def test_fp32_storage_update_block_widths(gpu_lib, variant, n, m, b):
+    """FP32 storage with FP64 arithmetic on the persistent update's forms:
+    block widths below 16 (partial column groups), K not a multiple of 4,
+    full 16-column blocks, ragged tiles; entry-wise against the oracle on the
+    same FP32 input."""
+    decades = 2
+    W = svd_matrix(n, m, np.logspace(0, -decades, m), seed=n + m + b).astype(np.float32)
+    W = W.astype(np.float64)
+    say("fp32 storage update widths", variant, n, m, b)
+    Q, R, S, cert = gpu_qr(W, b, "sparse", 256, THETA_SEED_SMALL, variant, store="f32", ls_iters=4)
+    o = oracle_qr(W, b, "sparse", 256, THETA_SEED_SMALL, variant, ls_iters=4)
+    assert factorization_error(W, Q, R) <= 1e-6
+    assert np.all(np.diag(R) > 0)
+    tol = 64 * U32 * 10**decades
+    check_entrywise(W, Q, R, S, cert, o, tol)
+
+
+@pytest.mark.parametrize("variant", ["plain", "lowsync"])
 def test_fp32_arithmetic(gpu_lib, variant):
     """FP32 products with FP32 accumulation: fine on a well-conditioned W,
     while on a W that is numerically rank deficient in FP32 the factorization
