@@ -452,7 +452,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   const size_t o_stack = carve(qr_stack_size(k, b));
   const size_t o_plan = d.kind == kSparse ? carve((sparse_plan_bytes(d, n) + 7) / 8) : 0;
   const size_t o_flag = carve(1);
-  const size_t o_cnt = carve((size_t)(2 + kQrTreeCounters) / 2);  // [0] spare, [1 ..] QR tree
+  const size_t o_cnt = carve((size_t)(2 + kQrTreeCounters) / 2);  // [0] R_(i,i) ready, [1 ..] QR tree
   const size_t o_G = carve((size_t)m * m);   // Gram matrix S^T S of the blocks done
   const size_t o_C = carve((size_t)m * b);   // c = S^T P_(i)
   const size_t o_Y = carve((size_t)m * b);   // Richardson iterate
@@ -488,7 +488,7 @@ rbgs_status qr_begin(QrRun& r, rbgs_handle h, const void* W, int64_t ldw, int64_
   r.stack = (double*)(base + o_stack);
   r.plan = d.kind == kSparse ? (uint16_t*)(base + o_plan) : nullptr;
   r.flag = (int64_t*)(base + o_flag);
-  r.counters = (unsigned*)(base + o_cnt);  // [1]: QR tree arrivals
+  r.counters = (unsigned*)(base + o_cnt);  // [0]: R_(i,i) ready (fused update), [1 ..]: QR tree
   r.G = (double*)(base + o_G);
   r.Cb = (double*)(base + o_C);
   r.Yb = (double*)(base + o_Y);
@@ -568,7 +568,20 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     }
   }
   const double ub = (double)r.es * (double)n * (double)(K + 2 * bw);
-  if (r.variant == RBGS_VARIANT_LOWSYNC) {
+  if (r.variant == RBGS_VARIANT_LOWSYNC && update_fused_ok(r.math, K, bw, k)) {
+    // ---- steps 4-5 with postponed sketching; the QR of S'_(i) runs inside
+    // the update launch (its first workgroup), overlapping the products
+    {
+      ProfScope ps(h, kProfSmall, 0.0, st);
+      HIP_TRY(h, launch_resid(Pi, r.S, k, K, Rk, ldr, r.E, bw, st), "S'");
+    }
+    {
+      ProfScope ps(h, kProfUpdate, ub, st);
+      HIP_TRY(h, launch_update_fused(r.f32, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, Rii, ldr, n, K,
+                                     bw, r.E, k, r.flag, c0, r.counters, st),
+              "update with the QR of the sketch");
+    }
+  } else if (r.variant == RBGS_VARIANT_LOWSYNC) {
     // ---- steps 4-5 with postponed sketching: S'_(i) = P_(i) - S R_(1:i-1,i)
     {
       ProfScope ps(h, kProfSmall, 0.0, st);

@@ -317,6 +317,139 @@ __device__ __forceinline__ void qr_wave_body(const double* __restrict__ src, int
   }
 }
 
+// The same factorization (bw <= 16, k <= 64 RPT) by the NW waves of one
+// workgroup (NW = 4 or 8; the update launch's first workgroup computes R_(i,i)
+// this way while the others start their products): wave w keeps columns
+// w + NW q (q < 16 / NW) and, in each step, the reflector in registers.  Every
+// column sees the same operations in the same order as in qr_wave_body (dot
+// product split by row parity, one wave_total, one fma per entry).
+template <int RPT>
+struct QwNLds {
+  double xb[2 * 64 * RPT];
+  double sg[2];
+  double diag[16];
+};
+
+template <int RPT, int NW>
+__device__ __forceinline__ void qr_waven_body(const double* __restrict__ src, int64_t k, int bw,
+                                              double* __restrict__ Rii, int64_t ldr, int64_t* flag,
+                                              int64_t col0, QwNLds<RPT>& L) {
+  constexpr int CH = 64 * RPT;
+  constexpr int CPW = 16 / NW;
+  static_assert(NW * CPW == 16, "16 columns over the waves");
+  double* xb = L.xb;
+  double* sg = L.sg;
+  double* diag = L.diag;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a[CPW][RPT];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = w + NW * q;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t r = lane + 64 * i;
+      const bool ok = c < bw && r < k;
+      const double v = src[ok ? r + (int64_t)c * k : 0];
+      a[q][i] = ok ? v : 0.0;
+    }
+  }
+  if (w == 0) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      xb[lane + 64 * i] = a[0][i];
+      s2 = fma(a[0][i], a[0][i], s2);
+    }
+    s2 = wave_total(s2);
+    if (lane == 0) sg[0] = s2;
+  }
+  __syncthreads();
+  for (int j = 0; j < bw; ++j) {
+    const double* xj = xb + (j & 1) * CH;
+    const double sigma = sg[j & 1];
+    const double x0 = xj[j];
+    double alpha = 0.0, beta = 0.0, v0 = x0;
+    if (sigma != 0.0) {
+      const double nrm = sqrt(sigma);
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      beta = 1.0 / (nrm * (nrm + fabs(x0)));
+      v0 = x0 - alpha;
+    }
+    bool right = false;
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) right |= w + NW * q > j && w + NW * q < bw;
+    if (right && beta != 0.0) {
+      double v[RPT];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const double x = xj[lane + 64 * i];
+        v[i] = i > 0 ? x : (lane < j ? 0.0 : (lane == j ? v0 : x));
+      }
+      double d[CPW];
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          if (i & 1) d1 = fma(v[i], a[q][i], d1);
+          else d0 = fma(v[i], a[q][i], d0);
+        }
+        d[q] = d0 + d1;
+      }
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        const int c = w + NW * q;
+        if (c > j && c < bw) {
+          const double wt = beta * wave_total(d[q]);
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) a[q][i] = fma(-wt, v[i], a[q][i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+      const int c = w + NW * q;
+      if (c == j && lane == j) a[q][0] = sigma != 0.0 ? alpha : 0.0;
+      if (c == j + 1 && c < bw) {
+        double* xn = xb + ((j + 1) & 1) * CH;
+        double s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          xn[lane + 64 * i] = a[q][i];
+          if (i > 0 || lane > j) s2 = fma(a[q][i], a[q][i], s2);
+        }
+        s2 = wave_total(s2);
+        if (lane == 0) sg[(j + 1) & 1] = s2;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = w + NW * q;
+    if (c < bw && lane == c) diag[c] = a[q][0];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = w + NW * q;
+    if (c < bw && lane < bw) {
+      const double sgn = diag[lane] < 0.0 ? -1.0 : 1.0;
+      Rii[lane + (int64_t)c * ldr] = lane <= c ? sgn * a[q][0] : 0.0;
+    }
+  }
+  if (threadIdx.x == 0 && flag != nullptr) {
+    for (int j = 0; j < bw; ++j) {
+      const double d = diag[j];
+      if (!(d != 0.0) || !isfinite(d)) {
+        atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL),
+                  (unsigned long long)(col0 + j));
+        break;
+      }
+    }
+  }
+}
+
 }  // namespace rbgs
 
 #endif  // RBGS_SMALL_DEVICE_H

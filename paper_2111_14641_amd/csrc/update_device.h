@@ -4,6 +4,8 @@
 #ifndef RBGS_UPDATE_DEVICE_H
 #define RBGS_UPDATE_DEVICE_H
 
+#include <type_traits>
+
 #include "rbgs_internal.h"
 
 namespace rbgs {
@@ -329,12 +331,14 @@ __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
 // instead of a next tile.  FULL: bw = 16 NB (every column stored
 // unconditionally).  Same arithmetic, in the same order, as
 // update_p_guarded_tile, up to products by the zero rows of the padding.
-template <typename T, int NB, int WV, int VE, bool FULL, bool NT, bool ROWS>
+template <typename T, int NB, int WV, int VE, bool FULL, bool NT, bool ROWS, bool HOOKED,
+          typename Hook>
 __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const T* __restrict__ Q,
                                                  int64_t ldq, T* Qout, int64_t ldqo,
                                                  const double* Rs, const double* Ru,
                                                  const double* Rinv, bool subst, int64_t first,
-                                                 int64_t stride, int64_t nfull, int K, int bw) {
+                                                 int64_t stride, int64_t nfull, int K, int bw,
+                                                 Hook& hook) {
   typedef Mfma<double> M;
   typedef UpPShape<T, NB, WV, VE> Sh;
   constexpr int VEC = Sh::VEC;
@@ -395,7 +399,8 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
   load_w(wv, W + tile * TILE + roff, ldw);
   load_group(a0, qk, ql, ldq, 0);
   load_group(a1, qk, ql, ldq, 1);
-  for (;;) {
+  // one tile; the first copy (HOOKED) calls hook() before its substitution
+  auto step = [&](auto hooked) -> bool {
     const int64_t arow = tile * TILE + roff;
 #pragma unroll
     for (int v = 0; v < VEC; ++v)
@@ -435,6 +440,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
 #pragma unroll
           for (int s = 0; s < 4; ++s) y[16 * nb + 4 * e + s] = -x[s];
         }
+      if constexpr (decltype(hooked)::value) hook();
       if (subst) rows_substitute<NCOL>(y, Ru, Rinv, FULL ? NCOL : bw);
       // and back (the transpose is its own inverse): 16-byte stores of 4 rows
 #pragma unroll
@@ -454,6 +460,7 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
       for (int v = 0; v < VEC; ++v)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[v][nb] = -acc[v][nb];
+      if constexpr (decltype(hooked)::value) hook();
       if (subst) p_substitute<VEC, NB>(acc, Ru, Rinv, bw, kk, li);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -468,10 +475,17 @@ __device__ __forceinline__ void update_p_tiles_k(const T* W, int64_t ldw, const 
           }
         }
     }
-    if (!more) break;
-    tile = next;
-    qk = qkn;
-    ql = qln;
+    if (more) {
+      tile = next;
+      qk = qkn;
+      ql = qln;
+    }
+    return more;
+  };
+  if constexpr (HOOKED) {
+    if (!step(std::true_type{})) return;
+  }
+  while (step(std::false_type{})) {
   }
 }
 
@@ -598,12 +612,37 @@ __host__ __device__ inline int up_p_form(int K, int bw, int nb) {
 }
 
 // The full tiles of one workgroup (tile = first, first + stride, .. < nfull)
-// in form FORM = up_p_form(K, bw, NB), streaming accesses if NT, the epilogue
+// in form FORM = up_p_form(K, bw, NB); with HOOKED (K > 0 forms) hook() runs
+// once, in the first tile, after its products and before its substitution
+// (it may synchronize the workgroup and stage Ru and Rinv); streaming
+// accesses if NT, the epilogue
 // of full 16-column blocks with four rows per lane in row layout if ROWS (the
 // update kernel; in the persistent batch's stage functions, with their smaller
 // register budget, the row layout spilled: 192 -> 1356 bytes of scratch per
 // lane; narrower blocks keep the shuffle form, where the masked row form
 // spilled too).  Rs holds up_p_rows(K, NB) rows.
+template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV, int VE, bool HOOKED,
+          typename Hook>
+__device__ __forceinline__ void update_p_full_tiles_h(const T* W, int64_t ldw,
+                                                      const T* __restrict__ Q, int64_t ldq,
+                                                      T* Qout, int64_t ldqo, const double* Rs,
+                                                      const double* Ru, const double* Rinv,
+                                                      bool subst, int64_t first, int64_t stride,
+                                                      int64_t nfull, int K, int bw, Hook& hook) {
+  constexpr bool FULL = (FORM & 1) != 0;
+  if constexpr (FORM >= 2)
+    update_p_tiles_k<T, NB, WV, VE, FULL, NT, ROWS, HOOKED>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru,
+                                                            Rinv, subst, first, stride, nfull, K,
+                                                            bw, hook);
+  else
+    update_p_tiles_0<T, NB, WV, VE, FULL, NT, ROWS>(W, ldw, Qout, ldqo, Ru, Rinv, subst, first, stride,
+                                          nfull, bw);
+}
+
+// Without a hook (R_(i,i) staged before the walk).
+struct NoHook {
+  __device__ void operator()() const {}
+};
 template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV = (NB == 1 ? 4 : 8),
           int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
@@ -612,13 +651,38 @@ __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     const double* Ru, const double* Rinv,
                                                     bool subst, int64_t first, int64_t stride,
                                                     int64_t nfull, int K, int bw) {
-  constexpr bool FULL = (FORM & 1) != 0;
-  if constexpr (FORM >= 2)
-    update_p_tiles_k<T, NB, WV, VE, FULL, NT, ROWS>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, first,
-                                          stride, nfull, K, bw);
-  else
-    update_p_tiles_0<T, NB, WV, VE, FULL, NT, ROWS>(W, ldw, Qout, ldqo, Ru, Rinv, subst, first, stride,
-                                          nfull, bw);
+  NoHook none;
+  update_p_full_tiles_h<T, NB, FORM, NT, ROWS, WV, VE, false>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru,
+                                                              Rinv, subst, first, stride, nfull, K,
+                                                              bw, none);
+}
+
+// Ru [NCOL][NCOL] (row-major) = the strictly upper part of R_(i,i), zero past
+// bw, and Rinv [NCOL] = 1 / R_cc (1 past bw), FP64, by NT threads.  COH: read
+// R_(i,i) with device-coherent loads (relaxed atomics at agent scope), for a
+// factor written during the same launch by a workgroup on another XCD; this
+// replaces an acquire fence, whose cache invalidation in every workgroup was
+// measured at about a tenth of the update's time.
+template <int NCOL, int NT, bool COH = false>
+__device__ __forceinline__ void update_p_stage_rii(const double* __restrict__ Rii, int64_t ldr,
+                                                   int bw, double* Ru, double* Rinv) {
+  auto ld = [&](int64_t i) -> double {
+    if constexpr (COH)
+      return __hip_atomic_load(const_cast<double*>(Rii) + i, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    else
+      return Rii[i];
+  };
+  for (int e = threadIdx.x; e < NCOL * NCOL; e += NT) {
+    const int r = e / NCOL, c = e % NCOL;
+    const bool in = r < c && c < bw;
+    const double v = ld((in ? r : 0) + (int64_t)(in ? c : 0) * ldr);
+    Ru[e] = in ? v : 0.0;
+  }
+  if (threadIdx.x < NCOL) {
+    const int c = threadIdx.x;
+    Rinv[c] = c < bw ? 1.0 / ld(c + (int64_t)c * ldr) : 1.0;
+  }
 }
 
 // Stages the factors of block i in LDS for the persistent form (NCOL = 16 NB
@@ -637,18 +701,7 @@ __device__ __forceinline__ void update_p_stage(const double* __restrict__ Rk,
     const double v = Rk[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
     Rs[e] = in ? v : 0.0;
   }
-  if (Rii != nullptr) {
-    for (int e = threadIdx.x; e < NCOL * NCOL; e += NT) {
-      const int r = e / NCOL, c = e % NCOL;
-      const bool in = r < c && c < bw;
-      const double v = Rii[(in ? r : 0) + (int64_t)(in ? c : 0) * ldr];
-      Ru[e] = in ? v : 0.0;
-    }
-    if (threadIdx.x < NCOL) {
-      const int c = threadIdx.x;
-      Rinv[c] = c < bw ? 1.0 / Rii[c + (int64_t)c * ldr] : 1.0;
-    }
-  }
+  if (Rii != nullptr) update_p_stage_rii<NCOL, NT>(Rii, ldr, bw, Ru, Rinv);
 }
 
 }  // namespace rbgs

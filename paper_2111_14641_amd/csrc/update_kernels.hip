@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "small_device.h"
 #include "update_device.h"
 
 namespace rbgs {
@@ -410,6 +411,80 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
                                  bw);
 }
 
+// Low-sync update with the QR of the sketch in the same launch (Section
+// 2.2.3: R_(i,i) is needed only by the substitution of each row, after the
+// product Q_(1:i-1) R_(1:i-1,i)).  Workgroup 0 factors the residual sketch E
+// with four waves and releases R_(i,i) (device-scope fence, then the ready
+// value); workgroups 1.. walk the tiles of the persistent form with R_(1:i-1,i)
+// staged, and in their first tile, between the products and the substitution,
+// wait for the ready value (polling with sleeps, bounded by `limit` ticks of
+// the 100 MHz clock; on expiry the block is reported as a breakdown), then
+// acquire and stage Ru and Rinv.  Workgroup 0 is dispatched first, so it is
+// resident before anyone waits for it.
+__device__ __forceinline__ void wait_ready(unsigned* ready, unsigned target, int64_t* flag,
+                                           int64_t col0, uint64_t limit) {
+  const uint64_t t0 = wall_clock64();
+  while (__hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (wall_clock64() - t0 > limit) {
+      atomicCAS((unsigned long long*)flag, (unsigned long long)(-1LL), (unsigned long long)col0);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Eight-wave workgroups (512-row tiles for FP32 storage, two per CU): the QR
+// of a 1024 x 16 sketch in four waves would need 64 doubles per lane for the
+// matrix alone, more than the update's register budget.
+template <typename T>
+using UpFShape = UpPShape<T, 1, 8>;
+
+template <typename T, int FORM, int RPT>
+__global__ __launch_bounds__((UpFShape<T>::THREADS), (UpFShape<T>::MINW)) void update_fused_kernel(
+    const T* W, int64_t ldw, const T* __restrict__ Q, int64_t ldq, T* Qout, int64_t ldqo,
+    const double* __restrict__ Rk, double* Rii, int64_t ldr, int64_t ntiles, int64_t nfull,
+    int64_t n, int K, int Kp, int bw, const double* __restrict__ E, int64_t k, int64_t* flag,
+    int64_t col0, unsigned* ready, uint64_t limit, int subst) {
+  typedef UpFShape<T> Sh;
+  constexpr int NCOL = Sh::NCOL;
+  constexpr int TILE = Sh::TILE;
+  extern __shared__ __attribute__((aligned(16))) double up_lds[];
+  const unsigned target = (unsigned)(col0 + 1);
+  if (blockIdx.x == 0) {
+    qr_waven_body<RPT, Sh::WAVES>(E, k, bw, Rii, ldr, flag, col0,
+                                  *reinterpret_cast<QwNLds<RPT>*>(up_lds));
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(ready, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  double* Rs = up_lds;
+  double* Ru = up_lds + (int64_t)Kp * NCOL;
+  double* Rinv = Ru + NCOL * NCOL;
+  update_p_stage<NCOL, Sh::THREADS>(Rk, nullptr, ldr, K, Kp, bw, Rs, Ru, Rinv);
+  __syncthreads();
+  bool staged = false;
+  auto hook = [&]() {
+    if (threadIdx.x == 0) wait_ready(ready, target, flag, col0, limit);
+    __syncthreads();
+    update_p_stage_rii<NCOL, Sh::THREADS, true>(Rii, ldr, bw, Ru, Rinv);
+    __syncthreads();
+    staged = true;
+  };
+  const int64_t b = blockIdx.x - 1, G = gridDim.x - 1;
+  // subst (always 1) is a launch argument on purpose: with a constant the
+  // compiler hoists the reads of R_(i,i) out of the tile loop (136 of them, in
+  // registers) and spills
+  update_p_full_tiles_h<T, 1, FORM, true, true, Sh::WAVES, Sh::VEC, true>(
+      W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst != 0, b, G, nfull, K, bw, hook);
+  const int64_t g0 = nfull + (G - 1 - b);
+  if (g0 < ntiles && !staged) hook();
+  for (int64_t tile = g0; tile < ntiles; tile += G)
+    update_p_guarded_tile<T, 1, Sh::WAVES, Sh::VEC>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv,
+                                                    subst != 0, tile * TILE, n, K, bw);
+}
+
 // Plain variant: in-place substitution Q_(i) = Q'_(i) R_(i,i)^{-1}, one row per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(T* __restrict__ Qb, int64_t ldq,
@@ -529,6 +604,76 @@ static hipError_t launch_update_t(const void* W, int64_t ldw, const void* Q, int
     return launch_update_p<T, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   if (bw <= 16) return launch_update_nb<T, C, 1>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
   return launch_update_nb<T, C, 2>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, st);
+}
+
+bool update_fused_ok(int math, int64_t K, int bw, int64_t k) {
+  return math == kMathF64 && bw == 16 && K >= 48 && K <= kUpPMaxK && k >= bw && k <= 1024;
+}
+
+template <typename T, int FORM, int RPT>
+static hipError_t launch_update_fused_t(unsigned grid, size_t lds, const void* W, int64_t ldw,
+                                        const void* Q, int64_t ldq, void* Qout, int64_t ldqo,
+                                        const double* Rk, double* Rii, int64_t ldr,
+                                        int64_t ntiles, int64_t nfull, int64_t n, int64_t K, int Kp,
+                                        int bw, const double* E, int64_t k, int64_t* flag,
+                                        int64_t col0, unsigned* ready, hipStream_t st) {
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&update_fused_kernel<T, FORM, RPT>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const uint64_t limit = 20000000;  // 0.2 s of the 100 MHz clock
+  hipLaunchKernelGGL((update_fused_kernel<T, FORM, RPT>), dim3(grid), dim3(UpFShape<T>::THREADS),
+                     lds, st, (const T*)W, ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr,
+                     ntiles, nfull, n, (int)K, Kp, bw, E, k, flag, col0, ready, limit, 1);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_update_fused_s(const void* W, int64_t ldw, const void* Q, int64_t ldq,
+                                        void* Qout, int64_t ldqo, const double* Rk, double* Rii,
+                                        int64_t ldr, int64_t n, int64_t K, int bw, const double* E,
+                                        int64_t k, int64_t* flag, int64_t col0, unsigned* ready,
+                                        hipStream_t st) {
+  typedef UpFShape<T> Sh;
+  constexpr int VEC = Sh::VEC;
+  constexpr int TILE = Sh::TILE;
+  const bool vec_ok = aligned16(W, ldw, VEC) && aligned16(Qout, ldqo, VEC) && aligned16(Q, ldq, VEC);
+  const int64_t ntiles = ceil_div(n, TILE);
+  const int64_t nfull = vec_ok ? n / TILE : 0;
+  const int Kp = up_p_rows((int)K, 1);
+  const int RPT = k <= 256 ? 4 : (k <= 512 ? 8 : 16);
+  const size_t lds_up = ((size_t)Kp * Sh::NCOL + (size_t)Sh::NCOL * Sh::NCOL + Sh::NCOL) * sizeof(double);
+  const size_t lds_qr = (size_t)(2 * 64 * RPT + 2 + 16) * sizeof(double);
+  const size_t lds = std::max(lds_up, lds_qr);
+  // as the persistent form (two workgroups of eight waves per CU): workgroups
+  // with the same number of tiles (FP32 storage) or all 512, plus the first
+  // workgroup for the QR
+  const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS / 2);
+  const unsigned grid = 1 + (sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
+                                            : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS / 2));
+  // full 16-column blocks only (form 3; the partial form spilled here)
+#define RBGS_UF(R)                                                                                 \
+  return launch_update_fused_t<T, 3, R>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,     \
+                                        ntiles, nfull, n, K, Kp, bw, E, k, flag, col0, ready, st)
+  if (RPT == 4) RBGS_UF(4);
+  if (RPT == 8) RBGS_UF(8);
+  RBGS_UF(16);
+#undef RBGS_UF
+}
+
+hipError_t launch_update_fused(bool f32, const void* W, int64_t ldw, const void* Q, int64_t ldq,
+                               void* Qout, int64_t ldqo, const double* Rk, double* Rii,
+                               int64_t ldr, int64_t n, int64_t K, int bw, const double* E,
+                               int64_t k, int64_t* flag, int64_t col0, unsigned* ready,
+                               hipStream_t st) {
+  if (!update_fused_ok(kMathF64, K, bw, k)) return hipErrorInvalidValue;
+  if (f32)
+    return launch_update_fused_s<float>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, E, k,
+                                        flag, col0, ready, st);
+  return launch_update_fused_s<double>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, E, k,
+                                       flag, col0, ready, st);
 }
 
 hipError_t launch_update(bool f32, int math, const void* W, int64_t ldw, const void* Q,

@@ -263,6 +263,30 @@ def _update_persistent(L, T, NB=1, form=None):
     return out
 
 
+def _update_fused(L, T, form, RPT):
+    # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, K, Kp, bw,
+    #  E, k, flag, col0, ready, limit, subst): the persistent update in eight-wave
+    # workgroups, the first of which factors the k x bw sketch E into R_(i,i)
+    es = 4 if T == "f" else 8
+    VEC = 16 // es
+    TILE = 8 * 16 * VEC
+    ldw, ldq, ldqo, ldr = L.i(1), L.i(3), L.i(5), L.i(8)
+    ntiles, nfull, n, K, Kp, bw = L.i(9), L.i(10), L.i(11), L.i(12), L.i(13), L.i(14)
+    k = L.i(16)
+    assert L.block[0] == 512 and L.grid[0] >= 2
+    assert ntiles == cdiv(n, TILE) and nfull * TILE <= n
+    assert form == 3 and bw == 16 and 48 <= K <= 512 and Kp == cdiv(K, 16) * 16
+    assert bw <= k <= 64 * RPT and RPT in (4, 8, 16)
+    assert L.shmem >= max((Kp * 16 + 16 * 16 + 16) * 8, (2 * 64 * RPT + 2 + 16) * 8)
+    assert L.shmem <= 160 * 1024
+    assert L.u(20) > 0 and L.i(21) == 1, "wait limit, substitution on"
+    last = n - 1
+    return [acc(0, es, 0, last + (bw - 1) * ldw), acc(4, es, 0, last + (bw - 1) * ldqo),
+            acc(2, es, 0, last + (K - 1) * ldq), acc(6, 8, 0, (K - 1) + (bw - 1) * ldr),
+            acc(7, 8, 0, (bw - 1) + (bw - 1) * ldr), acc(15, 8, 0, (k - 1) + (bw - 1) * k),
+            acc(17, 8, 0, 0), acc(19, 4, 0, 0)]
+
+
 def _trsm(L, T):
     # (Qb, ldq, Rii, ldr, n, bw)
     es = 4 if T == "f" else 8
@@ -617,6 +641,7 @@ MIRRORS = {
 TEMPLATED = {
     "update_kernel": lambda L, t: _update_general(L, t[0], t[2]),
     "update_p_kernel": lambda L, t: _update_persistent(L, t[0], int(t[1]), int(t[2])),
+    "update_fused_kernel": lambda L, t: _update_fused(L, t[0], int(t[1]), int(t[2])),
     "trsm_kernel": lambda L, t: _trsm(L, t[0]),
     "sketch_gauss_kernel": lambda L, t: _sketch_gauss(L, t[0], t[2]),
     "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),
