@@ -565,7 +565,9 @@ def main():
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(n, m, p, k),
                     traffic_unit="bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     alg_bytes_per_launch=round(upd_bytes / max(upd_cnt, 1)),
-                    kernel="update_p_kernel<float> (persistent; step 3 + substitution, low-sync)",
+                    kernel="update_p_kernel<float> / update_fused_kernel<float> (persistent; "
+                           "step 3 + substitution, low-sync; in the fused launches the first "
+                           "workgroup also factors the sketch of the block)",
                     launches=upd_cnt, avg_launch_us=round(upd_ms / max(upd_cnt, 1) * 1e3, 2),
                     share_of_step=round(upd_ms / args.steps / upd_step_ms, 3),
                     events_region_ms_per_step=round(upd_step_ms, 4),
