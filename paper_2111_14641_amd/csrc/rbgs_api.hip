@@ -34,6 +34,7 @@ static_assert(sizeof(rbgs::PbCtl) <= kHostWords * sizeof(double), "queue state")
 
 struct rbgs_handle_s {
   int device = 0;
+  int clock_khz = 0;  // rate of the device's wall clock (bounded waits); 0 if unknown
   std::string last_error;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -322,6 +323,12 @@ rbgs_status rbgs_create(rbgs_handle* h, int device) {
   rbgs_handle p = new (std::nothrow) rbgs_handle_s();
   if (!p) return RBGS_ENOMEM;
   p->device = device;
+  // queried once here, outside any stream capture; a device that cannot say
+  // leaves 0 (the bounded waits then assume 100 MHz) and no error behind
+  if (hipDeviceGetAttribute(&p->clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess) {
+    p->clock_khz = 0;
+    (void)hipGetLastError();
+  }
   *h = p;
   return RBGS_OK;
 }
@@ -528,6 +535,8 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
   double* Rii = r.R + c0 + c0 * r.ldr;    // R_(i,i)
   const int64_t ldr = r.ldr;
   void* Qi = r.Qb + r.es * (size_t)(c0 * r.ldq);
+  // the update's wait for R_(i,i) gives up after 4 s (the QR takes microseconds)
+  const uint64_t wait_limit = (uint64_t)(h->clock_khz > 0 ? h->clock_khz : 100000) * 4000ull;
   rbgs_status rs;
   if (sketch_w) {
     rs = do_sketch(h, d, r.f32, Wi, ldwi, n, bw, 0, Pi, k, r.part, r.plan, st);
@@ -578,7 +587,7 @@ rbgs_status qr_block(QrRun& r, int64_t c0, const void* Wi, int64_t ldwi, bool sk
     {
       ProfScope ps(h, kProfUpdate, ub, st);
       HIP_TRY(h, launch_update_fused(r.f32, Wi, ldwi, r.Q, r.ldq, Qi, r.ldq, Rk, Rii, ldr, n, K,
-                                     bw, r.E, k, r.flag, c0, r.counters, st),
+                                     bw, r.E, k, r.flag, c0, r.counters, wait_limit, st),
               "update with the QR of the sketch");
     }
   } else if (r.variant == RBGS_VARIANT_LOWSYNC) {

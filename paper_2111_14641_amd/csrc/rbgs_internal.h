@@ -405,15 +405,16 @@ hipError_t launch_update(bool f32, int math, const void* W, int64_t ldw, const v
 // workgroup factors the k x bw residual sketch E (ld k) into Rii (positive
 // diagonal, breakdown column into flag as the QR of a sketch does) and then
 // releases *ready = col0 + 1; the other workgroups run the update and wait for
-// that value before their first substitution (bounded by about 0.2 s, after
-// which col0 is put into flag).  *ready must start below col0 + 1.  Only where
+// that value before their first substitution (bounded by limit ticks of the
+// device's wall clock, limit > 0, after which col0 is put into flag and the
+// launch completes).  *ready must start below col0 + 1.  Only where
 // update_fused_ok holds: FP64 arithmetic, bw = 16, 48 <= K <= 512, k <= 1024.
 bool update_fused_ok(int math, int64_t K, int bw, int64_t k);
 hipError_t launch_update_fused(bool f32, const void* W, int64_t ldw, const void* Q, int64_t ldq,
                                void* Qout, int64_t ldqo, const double* Rk, double* Rii,
                                int64_t ldr, int64_t n, int64_t K, int bw, const double* E,
                                int64_t k, int64_t* flag, int64_t col0, unsigned* ready,
-                               hipStream_t st);
+                               uint64_t limit, hipStream_t st);
 // In place Q_(i) = Q'_(i) R_(i,i)^{-1} (forward substitution per row).
 hipError_t launch_trsm(bool f32, void* Q, int64_t ldq, const double* Rii, int64_t ldr, int64_t n,
                        int bw, hipStream_t st);

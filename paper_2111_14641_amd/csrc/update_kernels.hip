@@ -616,14 +616,14 @@ static hipError_t launch_update_fused_t(unsigned grid, size_t lds, const void* W
                                         const double* Rk, double* Rii, int64_t ldr,
                                         int64_t ntiles, int64_t nfull, int64_t n, int64_t K, int Kp,
                                         int bw, const double* E, int64_t k, int64_t* flag,
-                                        int64_t col0, unsigned* ready, hipStream_t st) {
+                                        int64_t col0, unsigned* ready, uint64_t limit,
+                                        hipStream_t st) {
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&update_fused_kernel<T, FORM, RPT>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const uint64_t limit = 20000000;  // 0.2 s of the 100 MHz clock
   hipLaunchKernelGGL((update_fused_kernel<T, FORM, RPT>), dim3(grid), dim3(UpFShape<T>::THREADS),
                      lds, st, (const T*)W, ldw, (const T*)Q, ldq, (T*)Qout, ldqo, Rk, Rii, ldr,
                      ntiles, nfull, n, (int)K, Kp, bw, E, k, flag, col0, ready, limit, 1);
@@ -635,7 +635,7 @@ static hipError_t launch_update_fused_s(const void* W, int64_t ldw, const void* 
                                         void* Qout, int64_t ldqo, const double* Rk, double* Rii,
                                         int64_t ldr, int64_t n, int64_t K, int bw, const double* E,
                                         int64_t k, int64_t* flag, int64_t col0, unsigned* ready,
-                                        hipStream_t st) {
+                                        uint64_t limit, hipStream_t st) {
   typedef UpFShape<T> Sh;
   constexpr int VEC = Sh::VEC;
   constexpr int TILE = Sh::TILE;
@@ -656,7 +656,8 @@ static hipError_t launch_update_fused_s(const void* W, int64_t ldw, const void* 
   // full 16-column blocks only (form 3; the partial form spilled here)
 #define RBGS_UF(R)                                                                                 \
   return launch_update_fused_t<T, 3, R>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,     \
-                                        ntiles, nfull, n, K, Kp, bw, E, k, flag, col0, ready, st)
+                                        ntiles, nfull, n, K, Kp, bw, E, k, flag, col0, ready,     \
+                                        limit, st)
   if (RPT == 4) RBGS_UF(4);
   if (RPT == 8) RBGS_UF(8);
   RBGS_UF(16);
@@ -667,13 +668,13 @@ hipError_t launch_update_fused(bool f32, const void* W, int64_t ldw, const void*
                                void* Qout, int64_t ldqo, const double* Rk, double* Rii,
                                int64_t ldr, int64_t n, int64_t K, int bw, const double* E,
                                int64_t k, int64_t* flag, int64_t col0, unsigned* ready,
-                               hipStream_t st) {
-  if (!update_fused_ok(kMathF64, K, bw, k)) return hipErrorInvalidValue;
+                               uint64_t limit, hipStream_t st) {
+  if (!update_fused_ok(kMathF64, K, bw, k) || limit == 0) return hipErrorInvalidValue;
   if (f32)
     return launch_update_fused_s<float>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, E, k,
-                                        flag, col0, ready, st);
+                                        flag, col0, ready, limit, st);
   return launch_update_fused_s<double>(W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, n, K, bw, E, k,
-                                       flag, col0, ready, st);
+                                       flag, col0, ready, limit, st);
 }
 
 hipError_t launch_update(bool f32, int math, const void* W, int64_t ldw, const void* Q,
