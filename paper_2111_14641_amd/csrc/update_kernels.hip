@@ -414,13 +414,15 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
 // Low-sync update with the QR of the sketch in the same launch (Section
 // 2.2.3: R_(i,i) is needed only by the substitution of each row, after the
 // product Q_(1:i-1) R_(1:i-1,i)).  Workgroup 0 factors the residual sketch E
-// with four waves and releases R_(i,i) (device-scope fence, then the ready
-// value); workgroups 1.. walk the tiles of the persistent form with R_(1:i-1,i)
-// staged, and in their first tile, between the products and the substitution,
-// wait for the ready value (polling with sleeps, bounded by `limit` ticks of
-// the 100 MHz clock; on expiry the block is reported as a breakdown), then
-// acquire and stage Ru and Rinv.  Workgroup 0 is dispatched first, so it is
-// resident before anyone waits for it.
+// with its eight waves and releases R_(i,i) (device-scope fence, then the
+// ready value); workgroups 1.. walk the tiles of the persistent form with
+// R_(1:i-1,i) staged, and in their first tile, between the products and the
+// substitution, wait for the ready value (polling with sleeps, bounded by
+// `limit` ticks of the device's wall clock; on expiry the block is reported as
+// a breakdown), then stage Ru and Rinv with device-coherent loads (no acquire
+// fence: its cache invalidation in every workgroup costs more than the QR).
+// Workgroup 0 is dispatched first, so it is resident before anyone waits for
+// it, and it waits for no one.
 __device__ __forceinline__ void wait_ready(unsigned* ready, unsigned target, int64_t* flag,
                                            int64_t col0, uint64_t limit) {
   const uint64_t t0 = wall_clock64();
