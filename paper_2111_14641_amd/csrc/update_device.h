@@ -104,11 +104,11 @@ struct UpPUnroll {
   static constexpr int N =
       NB == 2 ? RBGS_UP_P2UNROLL : (sizeof(T) == 4 ? RBGS_UP_PUNROLL32 : RBGS_UP_PUNROLL64);
 };
-// WV: waves per workgroup (the update kernel: 4 for NB = 1, 8 for NB = 2; the
-// persistent batch kernel: 16).  VE: rows per lane, read as one vector of VE
+// WV: waves per workgroup (the update kernels: 8; the persistent batch
+// kernel: 16).  VE: rows per lane, read as one vector of VE
 // elements (the update kernel: 16 bytes; the persistent batch kernel halves it
 // for NB = 2, to fit its register budget).
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
+template <typename T, int NB, int WV = 8, int VE = Vec16<T>::N>
 struct UpPShape {
   static constexpr int VEC = VE;
   static constexpr int WAVES = WV;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void rows_substitute(double (&y)[NCOL], const double*
 
 // One tile with guarded element loads and stores (rows >= n are neither read
 // nor written; any alignment).  Same arithmetic as update_p_full_tiles.
-template <typename T, int NB, int WV = (NB == 1 ? 4 : 8), int VE = Vec16<T>::N>
+template <typename T, int NB, int WV = 8, int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_guarded_tile(const T* W, int64_t ldw,
                                                       const T* __restrict__ Q, int64_t ldq,
                                                       T* Qout, int64_t ldqo, const double* Rs,
@@ -643,7 +643,7 @@ __device__ __forceinline__ void update_p_full_tiles_h(const T* W, int64_t ldw,
 struct NoHook {
   __device__ void operator()() const {}
 };
-template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV = (NB == 1 ? 4 : 8),
+template <typename T, int NB, int FORM, bool NT, bool ROWS, int WV = 8,
           int VE = Vec16<T>::N>
 __device__ __forceinline__ void update_p_full_tiles(const T* W, int64_t ldw,
                                                     const T* __restrict__ Q, int64_t ldq,

@@ -2,11 +2,12 @@
 // optionally followed in the same pass by the substitution of steps 4-5,
 // Q_(i) = Q'_(i) R_(i,i)^{-1} (FP64 arithmetic).
 //
-// Two forms.  The persistent form (update_p_kernel: FP64 arithmetic, bw <= 16,
-// K <= kUpPMaxK, the common case) keeps R_(1:i-1,i) in LDS for the whole
-// launch and applies the substitution as a second matrix-core product; it is
-// described where it is defined.  The general form (update_kernel: any width
-// up to 32, any K, and FP32 arithmetic) is below.
+// Two forms.  The persistent form (update_p_kernel: FP64 arithmetic, bw <= 32,
+// K <= kUpPMaxK, kUpP2MaxK for 32 columns, the common case; update_fused_kernel
+// adds the QR of the sketch) keeps R_(1:i-1,i) in LDS for the whole launch,
+// forms the product on FP64 matrix cores and runs the forward substitution in
+// its epilogue; its device bodies are in update_device.h.  The general form
+// (update_kernel: any width up to 32, any K, and FP32 arithmetic) is below.
 //
 // General form.  The product runs on matrix cores, in FP64
 // (v_mfma_f64_16x16x4f64; FP32 data are converted exactly) or, on request for
@@ -382,7 +383,10 @@ __global__ __launch_bounds__(kUpThreads, RBGS_UP_MINW) void update_batched_kerne
                                 tile * Sh::TILE, it.n, K, bw, ubuf_raw, Rd);
 }
 
-// LDS: Rs [Kp][16 NB] (Kp = up_p_rows(K, NB); rows >= K zero); Ru [16 NB][16 NB] (row-major) =
+// Persistent workgroups of eight waves (two per CU; measured faster than four
+// waves, four per CU, at large K, where R_(1:i-1,i) leaves LDS for two
+// workgroups either way) walk the tiles.  LDS: Rs [Kp][16 NB]
+// (Kp = up_p_rows(K, NB); rows >= K zero); Ru [16 NB][16 NB] (row-major) =
 // strictly upper part of R_(i,i), zero past bw; Rinv [16 NB] = 1 / R_cc (1 past
 // bw).  FP64.
 template <typename T, int NB, int FORM>
@@ -400,15 +404,15 @@ __global__ __launch_bounds__((UpPShape<T, NB>::THREADS), (UpPShape<T, NB>::MINW)
   update_p_stage<NCOL, Sh::THREADS>(Rk, Rii, ldr, K, Kp, bw, Rs, Ru, Rinv);
   const bool subst = Rii != nullptr;
   __syncthreads();
-  update_p_full_tiles<T, NB, FORM, true, true>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst,
-                                         blockIdx.x, gridDim.x, nfull, K, bw);
+  update_p_full_tiles<T, NB, FORM, true, true, Sh::WAVES, Sh::VEC>(
+      W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, blockIdx.x, gridDim.x, nfull, K, bw);
   // the guarded tiles (a ragged last tile, or every tile when a pointer or
   // leading dimension is not 16-byte aligned) come after the full ones, dealt
   // from the last workgroup backwards: the last workgroups have the fewest
   // full tiles (workgroup b has those b + j gridDim.x < nfull)
   for (int64_t tile = nfull + (gridDim.x - 1 - blockIdx.x); tile < ntiles; tile += gridDim.x)
-    update_p_guarded_tile<T, NB>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv, subst, tile * TILE, n, K,
-                                 bw);
+    update_p_guarded_tile<T, NB, Sh::WAVES, Sh::VEC>(W, ldw, Q, ldq, Qout, ldqo, Rs, Ru, Rinv,
+                                                     subst, tile * TILE, n, K, bw);
 }
 
 // Low-sync update with the QR of the sketch in the same launch (Section
@@ -529,7 +533,7 @@ static hipError_t launch_update_nb(const void* W, int64_t ldw, const void* Q, in
 }
 
 #ifndef RBGS_UP_PWGS
-#define RBGS_UP_PWGS 1024   // workgroups of the persistent form (4 per CU)
+#define RBGS_UP_PWGS 512    // workgroups of the persistent form (two of eight waves per CU)
 #endif
 
 static bool aligned16(const void* p, int64_t ld, int vec) {
@@ -571,7 +575,7 @@ static hipError_t launch_update_p(const void* W, int64_t ldw, const void* Q, int
   if (NB == 1) {
     // FP32 storage: as many workgroups as give every one the same number of
     // tiles (no partly empty last round; measured -0.6 % on the step, while
-    // FP64 storage, with twice the tiles, is better with all 1024)
+    // FP64 storage, with twice the tiles, is better with all of them)
     const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS);
     grid = sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
                           : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS);
@@ -652,9 +656,9 @@ static hipError_t launch_update_fused_s(const void* W, int64_t ldw, const void* 
   // as the persistent form (two workgroups of eight waves per CU): workgroups
   // with the same number of tiles (FP32 storage) or all 512, plus the first
   // workgroup for the QR
-  const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS / 2);
+  const int64_t per = ceil_div(ntiles, RBGS_UP_PWGS);
   const unsigned grid = 1 + (sizeof(T) == 4 ? (unsigned)ceil_div(ntiles, per)
-                                            : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS / 2));
+                                            : (unsigned)std::min<int64_t>(ntiles, RBGS_UP_PWGS));
   // full 16-column blocks only (form 3; the partial form spilled here)
 #define RBGS_UF(R)                                                                                 \
   return launch_update_fused_t<T, 3, R>(grid, lds, W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr,     \

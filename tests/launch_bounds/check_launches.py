@@ -241,12 +241,12 @@ def _update_persistent(L, T, NB=1, form=None):
     # (W, ldw, Q, ldq, Qout, ldqo, Rk, Rii, ldr, ntiles, nfull, n, K, Kp, bw)
     es = 4 if T == "f" else 8
     VEC = 16 // es
-    WAVES = 4 if NB == 1 else 8
+    WAVES = 8
     TILE = WAVES * 16 * VEC
     NCOL = 16 * NB
     ldw, ldq, ldqo, ldr = L.i(1), L.i(3), L.i(5), L.i(8)
     ntiles, nfull, n, K, Kp, bw = L.i(9), L.i(10), L.i(11), L.i(12), L.i(13), L.i(14)
-    assert L.block[0] == 64 * WAVES
+    assert L.block[0] == 64 * WAVES and L.grid[0] <= (512 if NB == 1 else 256)
     assert ntiles == cdiv(n, TILE) and nfull * TILE <= n and bw <= NCOL
     align = 16 if NB == 1 else 32    # whole pairs of the K loop's load groups
     assert Kp == cdiv(K, align) * align <= (512 if NB == 1 else 480)
