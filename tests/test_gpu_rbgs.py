@@ -472,10 +472,13 @@ def test_leading_dimensions_give_identical_results(gpu_lib, store, ldw_pad, ldq_
     """W and Q inside larger column-major buffers (ld > n): 16-byte aligned
     leading dimensions keep the vector path, others take the guarded path for
     every tile.  Every element is computed by the same operations in the same
-    order either way, so the results equal those with ld = n bit for bit."""
+    order either way, so the results equal those with ld = n bit for bit.  With
+    m = 64 and 16-column blocks the last block (K = 48) takes the update launch
+    that also factors the sketch, whose workgroups then reach the wait for
+    R_(i,i) from the guarded tiles."""
     import torch
     from paper_2111_14641_amd import binding as B
-    n, m, k = 5000, 48, 256
+    n, m, k = 5000, 64, 256
     W = svd_matrix(n, m, np.logspace(0, -3, m), seed=5)
     dt = torch.float64 if store == "f64" else torch.float32
     say("leading dimensions", store, ldw_pad, ldq_pad)
