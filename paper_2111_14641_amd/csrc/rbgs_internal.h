@@ -458,7 +458,7 @@ hipError_t launch_gram_sty(const double* S, int64_t k, int64_t K, const double* 
 hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const double* C,
                              const double* Y, int64_t ldy, double* Ynew, int64_t ldyn, int bw,
                              hipStream_t st);
-// E = P - S Y (k x bw, ld k; S: k x K, ld k; Y: K x bw, ld ldy).
+// E = P - S Y (k x bw, ld k; S: k x K, ld k; Y: K x bw, ld ldy; K >= 1).
 hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
                         int64_t ldy, double* E, int bw, hipStream_t st);
 // R_(i,i) (positive diagonal) of src (k x bw, ld k) in one launch (tree of

@@ -161,6 +161,49 @@ __device__ __forceinline__ void resid_body(const double* __restrict__ P,
   if (ok && q == 0) E[t + (int64_t)c * k] = P[t + (int64_t)c * k] - v;
 }
 
+// The same E, NC columns per group of 16 lanes (columns NC cc .. NC cc + NC - 1
+// of row t): one read of S[t][j] serves NC outputs.  Every output sees the
+// operations of resid_body in the same order, so the results are identical.
+template <int NC>
+__device__ __forceinline__ void resid_cols_body(const double* __restrict__ P,
+                                                const double* __restrict__ S, int64_t k,
+                                                int64_t K, const double* __restrict__ Y,
+                                                int64_t ldy, double* __restrict__ E, int bw,
+                                                int64_t bx) {
+  const int q = threadIdx.x & 15;
+  const int64_t o = (bx * blockDim.x + threadIdx.x) >> 4;
+  const int ncc = (bw + NC - 1) / NC;
+  const bool ok = o < k * ncc;
+  const int64_t t = ok ? o % k : 0;
+  const int c0 = ok ? (int)(o / k) * NC : 0;
+  const double* yc[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) yc[i] = Y + (int64_t)min(c0 + i, bw - 1) * ldy;  // clamped
+  double a0[NC], a1[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) a0[i] = a1[i] = 0.0;
+  int64_t j = q;
+  for (; j + 16 < K; j += 32) {
+    const double s0 = S[t + j * k], s1 = S[t + (j + 16) * k];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      a0[i] = fma(s0, yc[i][j], a0[i]);
+      a1[i] = fma(s1, yc[i][j + 16], a1[i]);
+    }
+  }
+  for (; j < K; j += 16) {
+    const double s0 = S[t + j * k];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) a0[i] = fma(s0, yc[i][j], a0[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const double v = group_sum<16>(a0[i] + a1[i]);
+    const int c = c0 + i;
+    if (ok && q == 0 && c < bw) E[t + (int64_t)c * k] = P[t + (int64_t)c * k] - v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // R_(i,i) of a k x bw sketch with k <= 1024 and bw <= 16 CPW in one workgroup
 // of 16 waves: wave w keeps columns w + 16 q (q < CPW) in registers (lane l

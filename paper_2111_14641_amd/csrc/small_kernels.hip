@@ -251,11 +251,17 @@ __global__ __launch_bounds__(256) void gram_sweep_batched_kernel(const BatchItem
   gram_sweep_body(it.G, m, K, it.Cb, Y, ldy, Yn, ldyn, bw, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ P,
-                                                    const double* __restrict__ S, int64_t k,
-                                                    int64_t K, const double* __restrict__ Y,
-                                                    int64_t ldy, double* __restrict__ E, int bw) {
-  resid_body(P, S, k, K, Y, ldy, E, bw, blockIdx.x);
+// NC columns per 16 lanes: 4 measured best for 16-column blocks (small
+// factors 0.454 / 0.445 / 0.47 ms per QR at NC = 2 / 4 / 8, 0.477 with one
+// column per 16 lanes; 16 leaves too few workgroups).
+constexpr int kResidCols = 4;
+template <int NC>
+__global__ __launch_bounds__(256) void resid_cols_kernel(const double* __restrict__ P,
+                                                         const double* __restrict__ S, int64_t k,
+                                                         int64_t K, const double* __restrict__ Y,
+                                                         int64_t ldy, double* __restrict__ E,
+                                                         int bw) {
+  resid_cols_body<NC>(P, S, k, K, Y, ldy, E, bw, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void resid_batched_kernel(const BatchItem* items, int64_t k,
@@ -655,9 +661,10 @@ hipError_t launch_gram_sweep(const double* G, int64_t ldg, int64_t K, const doub
 
 hipError_t launch_resid(const double* P, const double* S, int64_t k, int64_t K, const double* Y,
                         int64_t ldy, double* E, int bw, hipStream_t st) {
-  const int64_t threads = k * bw * 16;
-  hipLaunchKernelGGL(resid_kernel, dim3((unsigned)ceil_div(threads, 256)), dim3(256), 0, st, P,
-                     S, k, K, Y, ldy, E, bw);
+  if (bw < 1 || K < 1) return hipErrorInvalidValue;
+  const int64_t threads = k * ((bw + kResidCols - 1) / kResidCols) * 16;
+  hipLaunchKernelGGL(resid_cols_kernel<kResidCols>, dim3((unsigned)ceil_div(threads, 256)),
+                     dim3(256), 0, st, P, S, k, K, Y, ldy, E, bw);
   return hipGetLastError();
 }
 

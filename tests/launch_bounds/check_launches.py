@@ -122,11 +122,12 @@ def _gram_sweep(L):
             acc(4, 8, 0, (bw - 1) * ldy + K - 1), acc(6, 8, 0, (K - 1) + (bw - 1) * ldyn)]
 
 
-def _resid(L):
-    # (P, S, k, K, Y, ldy, E, bw)
+def _resid(L, NC):
+    # (P, S, k, K, Y, ldy, E, bw): 16 lanes per row and NC columns; columns of Y
+    # clamped to bw - 1
     k, K, ldy, bw = L.i(2), L.i(3), L.i(5), L.i(7)
-    assert K >= 1
-    assert L.grid[0] * L.block[0] // 16 >= k * bw
+    assert K >= 1 and bw >= 1
+    assert L.grid[0] * L.block[0] // 16 >= k * cdiv(bw, NC)
     return [acc(0, 8, 0, (k - 1) + (bw - 1) * k), acc(1, 8, 0, (k - 1) + (K - 1) * k),
             acc(4, 8, 0, (bw - 1) * ldy + K - 1), acc(6, 8, 0, (k - 1) + (bw - 1) * k)]
 
@@ -627,7 +628,6 @@ MIRRORS = {
     "sketch_reduce_kernel": _sketch_reduce,
     "gram_sty_kernel": _gram_sty,
     "gram_sweep_kernel": _gram_sweep,
-    "resid_kernel": _resid,
     "qr_fused_kernel": _qr_fused,
     "sparse_plan_kernel": _sparse_plan,
     "gram_defect_kernel": _gram_defect,
@@ -643,6 +643,7 @@ TEMPLATED = {
     "update_p_kernel": lambda L, t: _update_persistent(L, t[0], int(t[1]), int(t[2])),
     "update_fused_kernel": lambda L, t: _update_fused(L, t[0], int(t[1]), int(t[2])),
     "trsm_kernel": lambda L, t: _trsm(L, t[0]),
+    "resid_cols_kernel": lambda L, t: _resid(L, int(t[0])),
     "sketch_gauss_kernel": lambda L, t: _sketch_gauss(L, t[0], t[2]),
     "sketch_sparse_q_kernel": lambda L, t: _sketch_sparse_q(L, t[0], t[1], t[2]),
     "sketch_srht_kernel": lambda L, t: _sketch_srht(L, t[0], t[1]),
