@@ -96,6 +96,46 @@ def test_every_launch_stays_in_bounds(driver, case):
     assert not violations, "\n".join(violations[:20])
 
 
+FUSED_CASES = [
+    # case as above, then the blocks whose update launch also factors the sketch
+    ((20_000, 128, 16, 256, SPARSE, F32, 0, LOWSYNC, 4, 0, 0), [48, 64, 80, 96, 112]),
+    ((20_000, 128, 16, 256, SPARSE, F64, 0, LOWSYNC, 0, 0, 0), [48, 64, 80, 96, 112]),
+    ((3000, 600, 16, 1024, SPARSE, F64, 0, LOWSYNC, 2, 0, 0), list(range(48, 513, 16))),
+    ((20_000, 128, 16, 256, SPARSE, F32, 1, LOWSYNC, 4, 0, 0), []),     # FP32 arithmetic
+    ((20_000, 128, 16, 256, SPARSE, F32, 0, PLAIN, 4, 0, 0), []),       # plain variant
+    ((20_000, 128, 32, 256, SPARSE, F32, 0, LOWSYNC, 4, 0, 0), []),     # 32-column blocks
+    ((20_000, 128, 16, 2048, SPARSE, F32, 0, LOWSYNC, 4, 0, 0), []),    # k > 1024
+]
+
+
+@pytest.mark.parametrize("case,fused_K", FUSED_CASES,
+                         ids=lambda c: "x".join(str(v) for v in c[:4]) + "-math%d-var%d" % (c[6], c[7])
+                         if isinstance(c, tuple) else None)
+def test_fused_update_takes_exactly_the_eligible_blocks(driver, case, fused_K):
+    """Host dispatch of the update that also factors the sketch: low-sync, FP64
+    arithmetic, 16-column blocks with 48 <= K <= 512 and k <= 1024, and for
+    those blocks no separate QR launch; every other block keeps the QR launch
+    and the plain update."""
+    import sys
+    sys.path.insert(0, HERE)
+    import check_launches as cl
+    exe, out = driver
+    log = str(out / ("fused_" + "_".join(str(v) for v in case) + ".txt"))
+    r = subprocess.run([exe, *[str(v) for v in case]], env={**os.environ, "RBGS_LAUNCH_LOG": log},
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    launches = [e[1] for e in cl.parse_log(log) if e[0] == "launch"]
+    fused = [L for L in launches if cl.kernel_base(L.name) == "update_fused_kernel"]
+    assert sorted(L.i(12) for L in fused) == fused_K          # argument 12: K
+    n, m, p, k = case[:4]
+    blocks = -(-m // p)
+    updates = [L for L in launches if cl.kernel_base(L.name) in ("update_p_kernel", "update_kernel")]
+    assert len(updates) + len(fused) == blocks
+    if case[7] == LOWSYNC:
+        qrs = [L for L in launches if cl.kernel_base(L.name) in ("qr_wave_kernel", "qr_fused_kernel")]
+        assert len(qrs) == blocks - len(fused)
+
+
 NOALLOC_CASES = [
     # the no-allocation entry point (two calls, the second on half the rows)
     (1_000_000, 256, 16, 1024, SPARSE, F32, 0, LOWSYNC, 4, 1, 0),
